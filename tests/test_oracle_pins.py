@@ -1,0 +1,593 @@
+"""Pins for the CPU oracle: each check ties it to something other than itself
+(closed forms, conservation laws, finite differences, brute force, LAPACK,
+the paper's Table I)."""
+import numpy as np
+import pytest
+
+import gridgen
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+# --------------------------------------------------------------------------
+# helpers written independently of the oracle
+# --------------------------------------------------------------------------
+def two_bus(r=0.02, x=0.08, b=0.04, P=0.9, Q=0.3, E=1.0, pv=False, vs=1.0):
+    """Slack bus 0 and bus 1 joined by one branch (pi-model, total charging b)."""
+    bt = np.array([gridgen.BUS_SLACK, gridgen.BUS_PV if pv else gridgen.BUS_PQ], np.int8)
+    vset = np.array([E, vs if pv else 1.0])
+    g = gridgen.Grid(n=2, f=np.array([0], np.int32), t=np.array([1], np.int32),
+                     r=np.array([r]), x=np.array([x]), b=np.array([b]), bus_type=bt,
+                     vset=vset, Pd=np.array([0.0, P]), Qd=np.array([0.0, Q]),
+                     Pg=np.zeros(2), pts=np.zeros((2, 2)))
+    return g
+
+
+def closed_form_pq(r, x, b, P, Q, E=1.0):
+    """Load P+jQ at bus 1 behind z = r+jx with charging beta = b/2 at bus 1.
+
+    From V0 conj(V1) = v + z (P - j Q'), Q' = Q - beta v, v = |V1|^2:
+      (1 - 2 x beta + |z|^2 beta^2) v^2 + (2rP + 2xQ - E^2 - 2|z|^2 Q beta) v
+        + |z|^2 (P^2 + Q^2) = 0, larger root; theta1 = -atan2(xP - rQ', v + rP + xQ').
+    """
+    beta = b / 2.0
+    z2 = r * r + x * x
+    a2 = 1 - 2 * x * beta + z2 * beta * beta
+    a1 = 2 * r * P + 2 * x * Q - E * E - 2 * z2 * Q * beta
+    a0 = z2 * (P * P + Q * Q)
+    v = (-a1 + np.sqrt(a1 * a1 - 4 * a2 * a0)) / (2 * a2)
+    Qp = Q - beta * v
+    th = -np.arctan2(x * P - r * Qp, v + r * P + x * Qp)
+    return np.sqrt(v), th
+
+
+def closed_form_pv(r, x, Pinj, vs, E=1.0):
+    """PV bus 1 (|V1| = vs) injecting Pinj into the branch to the slack:
+    Re(V1 conj(V1 - V0) / conj(z)) = Pinj gives r cos t - x sin t = c,
+    c = (vs^2 r - Pinj |z|^2) / (vs E); small-angle root."""
+    R = np.hypot(r, x)
+    phi = np.arctan2(x, r)
+    c = (vs * vs * r - Pinj * R * R) / (vs * E)
+    return np.arccos(c / R) - phi
+
+
+def branch_currents(grid, Vm, Va):
+    V = Vm * np.exp(1j * Va)
+    z = grid.r + 1j * grid.x
+    return V, (V[grid.f] - V[grid.t]) / z
+
+
+def kcl_currents(grid, V):
+    """Bus current injections summed branch by branch (series + half charging)."""
+    I = np.zeros(grid.n, complex)
+    z = grid.r + 1j * grid.x
+    for e in range(grid.m):
+        a, b = grid.f[e], grid.t[e]
+        Is = (V[a] - V[b]) / z[e]
+        I[a] += Is + 1j * grid.b[e] / 2 * V[a]
+        I[b] += -Is + 1j * grid.b[e] / 2 * V[b]
+    return I
+
+
+def random_state(grid, rng, spread=0.3):
+    Vm = rng.uniform(0.9, 1.1, grid.n)
+    Va = rng.uniform(-spread, spread, grid.n)
+    return Vm, Va
+
+
+def reduced_residual(O, Y, grid, Vm, Va, Psp, Qsp):
+    """Residual vector over P(non-slack), Q(PQ) in ascending bus order."""
+    P, Q = O.injections(Y, Vm, Va)
+    FP, FQ, _ = O.mismatch(grid.bus_type, P, Q, Psp, Qsp)
+    ns = grid.bus_type != gridgen.BUS_SLACK
+    pq = grid.bus_type == gridgen.BUS_PQ
+    return np.concatenate([FP[ns], FQ[pq]])
+
+
+# --------------------------------------------------------------------------
+# admittance matrix and injections
+# --------------------------------------------------------------------------
+def test_ybus_matches_branchwise_kcl(oracle):
+    g = gridgen.make_grid(60, seed=11)
+    Y = oracle.grid_ybus(g)
+    rng = np.random.default_rng(0)
+    Vm, Va = random_state(g, rng)
+    V = Vm * np.exp(1j * Va)
+    np.testing.assert_allclose(Y.dense() @ V, kcl_currents(g, V), rtol=0, atol=1e-11)
+
+
+def test_ybus_parallel_branches_sum(oracle):
+    f = np.array([0, 0, 1], np.int32)
+    t = np.array([1, 1, 2], np.int32)
+    r = np.array([0.01, 0.03, 0.02])
+    x = np.array([0.1, 0.2, 0.05])
+    b = np.array([0.02, 0.0, 0.01])
+    Y = oracle.ybus(3, f, t, r, x, b).dense()
+    y = 1 / (r + 1j * x)
+    assert Y[0, 1] == pytest.approx(-(y[0] + y[1]))
+    assert Y[1, 1] == pytest.approx(y[0] + y[1] + y[2] + 1j * (0.01 + 0.005))
+    assert Y[0, 2] == 0
+
+
+def test_ybus_rejects_self_loop(oracle):
+    with pytest.raises(ValueError):
+        oracle.ybus(2, np.array([1], np.int32), np.array([1], np.int32), np.ones(1),
+                    np.ones(1), np.zeros(1))
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_power_balance_tellegen(oracle, seed):
+    """At any voltages: sum P_i = sum r|I|^2 and
+    sum Q_i = sum x|I|^2 - sum b/2 (|V_f|^2 + |V_t|^2)."""
+    g = gridgen.make_grid(80, seed=seed)
+    Y = oracle.grid_ybus(g)
+    rng = np.random.default_rng(seed)
+    Vm, Va = random_state(g, rng)
+    P, Q = oracle.injections(Y, Vm, Va)
+    V, I = branch_currents(g, Vm, Va)
+    loss_p = np.sum(g.r * np.abs(I) ** 2)
+    loss_q = np.sum(g.x * np.abs(I) ** 2) - np.sum(g.b / 2 * (np.abs(V[g.f]) ** 2 +
+                                                             np.abs(V[g.t]) ** 2))
+    assert np.sum(P) == pytest.approx(loss_p, rel=1e-11, abs=1e-11)
+    assert np.sum(Q) == pytest.approx(loss_q, rel=1e-11, abs=1e-11)
+    assert loss_p > 0
+
+
+def test_lossless_injections_sum_to_zero(oracle):
+    g = gridgen.make_grid(50, seed=5)
+    Y = oracle.ybus(g.n, g.f, g.t, np.zeros(g.m), g.x, g.b)
+    Vm, Va = random_state(g, np.random.default_rng(1))
+    P, _ = oracle.injections(Y, Vm, Va)
+    assert abs(np.sum(P)) < 1e-11
+
+
+def test_injection_single_bus_formula(oracle):
+    """S_i = V_i conj(I_i) with I from branch-wise KCL."""
+    g = gridgen.make_grid(40, seed=9)
+    Y = oracle.grid_ybus(g)
+    Vm, Va = random_state(g, np.random.default_rng(2))
+    P, Q = oracle.injections(Y, Vm, Va)
+    V = Vm * np.exp(1j * Va)
+    S = V * np.conj(kcl_currents(g, V))
+    np.testing.assert_allclose(P, S.real, atol=1e-11)
+    np.testing.assert_allclose(Q, S.imag, atol=1e-11)
+
+
+def test_mismatch_norm_excludes_slack_and_pv_q(oracle):
+    bt = np.array([3, 2, 1], np.int8)
+    P = np.array([5.0, 1.0, 2.0])
+    Q = np.array([7.0, 9.0, 3.0])
+    FP, FQ, nrm = oracle.mismatch(bt, P, Q, np.zeros(3), np.zeros(3))
+    assert FP.tolist() == [0.0, 1.0, 2.0]
+    assert FQ.tolist() == [0.0, 0.0, 3.0]
+    assert nrm == 3.0
+    _, _, nrm = oracle.mismatch(bt, np.array([0, np.nan, 0.0]), Q, np.zeros(3), np.zeros(3))
+    assert np.isnan(nrm)
+
+
+# --------------------------------------------------------------------------
+# Newton-Raphson: closed forms and agreement of the two formulations
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("sparse", [False, True])
+@pytest.mark.parametrize("case", [(0.02, 0.08, 0.04, 0.9, 0.3), (0.01, 0.12, 0.0, 1.5, 0.4),
+                                  (0.05, 0.05, 0.1, 0.3, -0.2)])
+def test_two_bus_pq_closed_form(oracle, case, sparse):
+    r, x, b, P, Q = case
+    g = two_bus(r, x, b, P, Q)
+    res = oracle.solve_grid(g, sparse=sparse, tol=1e-13, max_iter=30)
+    assert res.status == 0
+    vm, th = closed_form_pq(r, x, b, P, Q)
+    assert res.Vm[1] == pytest.approx(vm, abs=1e-12)
+    assert res.Va[1] == pytest.approx(th, abs=1e-12)
+
+
+@pytest.mark.parametrize("sparse", [False, True])
+def test_two_bus_pv_closed_form(oracle, sparse):
+    r, x, vs, Pinj = 0.02, 0.1, 1.03, 0.8
+    g = two_bus(r, x, 0.03, 0.0, 0.0, pv=True, vs=vs)
+    g.Pg[1] = Pinj
+    res = oracle.solve_grid(g, sparse=sparse, tol=1e-13, max_iter=30)
+    assert res.status == 0
+    assert res.Vm[1] == vs
+    assert res.Va[1] == pytest.approx(closed_form_pv(r, x, Pinj, vs), abs=1e-12)
+
+
+@pytest.mark.parametrize("n,seed", [(30, 1), (200, 1), (200, 2), (500, 3)])
+def test_sparse_paper_path_equals_dense_definition(oracle, n, seed):
+    g = gridgen.make_grid(n, seed)
+    d = oracle.solve_grid(g, sparse=False)
+    s = oracle.solve_grid(g, sparse=True)
+    nat = oracle.solve_grid(g, sparse=True, ordering=1)
+    assert d.status == s.status == nat.status == 0
+    assert d.iters == s.iters == nat.iters
+    for r in (s, nat):
+        np.testing.assert_allclose(r.Vm, d.Vm, atol=1e-12)
+        np.testing.assert_allclose(r.Va, d.Va, atol=1e-12)
+
+
+def test_solution_zeroes_independent_residual(oracle):
+    """The converged state satisfies S = V conj(I) = S_sp computed branch-wise."""
+    g = gridgen.make_grid(300, 7)
+    res = oracle.solve_grid(g)
+    assert res.status == 0
+    V = res.Vm * np.exp(1j * res.Va)
+    S = V * np.conj(kcl_currents(g, V))
+    ns = g.bus_type != gridgen.BUS_SLACK
+    pq = g.bus_type == gridgen.BUS_PQ
+    assert np.max(np.abs(S.real[ns] - g.Psp[ns])) < 1e-8
+    assert np.max(np.abs(S.imag[pq] - g.Qsp[pq])) < 1e-8
+    pv = g.bus_type == gridgen.BUS_PV
+    np.testing.assert_array_equal(res.Vm[pv], g.vset[pv])
+
+
+def test_quadratic_convergence(oracle):
+    g = gridgen.make_grid(200, 4)
+    Y = oracle.grid_ybus(g)
+    Vm0, Va0 = g.flat_start()
+    norms = []
+    for k in range(0, 5):
+        r = oracle.newton_dense(Y, g.bus_type, g.Psp, g.Qsp, Vm0, Va0, tol=0.0, max_iter=k)
+        norms.append(r.norm)
+    # e_{k+1} <= C e_k^2 once in the basin
+    for a, b in zip(norms[1:-1], norms[2:]):
+        if a < 1e-2 and b > 1e-14:
+            assert b < 10 * a * a
+
+
+def test_not_converged_and_nonfinite_status(oracle):
+    g = gridgen.make_grid(50, 2)
+    r = oracle.solve_grid(g, max_iter=1)
+    assert r.status == 6 and r.iters == 1
+    bad = gridgen.make_grid(50, 2)
+    bad.Pd[5] = np.nan
+    assert oracle.solve_grid(bad).status == 7
+
+
+# --------------------------------------------------------------------------
+# Jacobians against finite differences of the mismatch
+# --------------------------------------------------------------------------
+def test_dense_jacobian_fd(oracle):
+    g = gridgen.make_grid(40, 8)
+    Y = oracle.grid_ybus(g)
+    rng = np.random.default_rng(3)
+    Vm, Va = random_state(g, rng)
+    Vm[g.bus_type == gridgen.BUS_PV] = g.vset[g.bus_type == gridgen.BUS_PV]
+    J = oracle.dense_jacobian(Y, g.bus_type, Vm, Va)
+    ns = np.flatnonzero(g.bus_type != gridgen.BUS_SLACK)
+    pq = np.flatnonzero(g.bus_type == gridgen.BUS_PQ)
+    h = 1e-7
+    cols = []
+    for i in ns:
+        a, b = Va.copy(), Va.copy()
+        a[i] += h
+        b[i] -= h
+        cols.append((reduced_residual(oracle, Y, g, Vm, a, g.Psp, g.Qsp) -
+                     reduced_residual(oracle, Y, g, Vm, b, g.Psp, g.Qsp)) / (2 * h))
+    for i in pq:
+        a, b = Vm.copy(), Vm.copy()
+        a[i] += h
+        b[i] -= h
+        cols.append((reduced_residual(oracle, Y, g, a, Va, g.Psp, g.Qsp) -
+                     reduced_residual(oracle, Y, g, b, Va, g.Psp, g.Qsp)) / (2 * h))
+    Jfd = np.array(cols).T
+    np.testing.assert_allclose(J, Jfd, rtol=1e-6, atol=1e-6 * np.abs(J).max())
+
+
+def block_fd(oracle, sym, Y, g, Vm, Va):
+    """FD Jacobian over all 2 unknowns per non-slack bus, permuted order, with the
+    PV reading applied: |V| rows replaced by the identity, |V| columns dropped."""
+    nn = sym.nn
+    bus_of_pos = sym.perm
+    h = 1e-7
+
+    def F(Vm_, Va_):
+        P, Q = oracle.injections(Y, Vm_, Va_)
+        out = np.zeros(2 * nn)
+        for p in range(nn):
+            i = bus_of_pos[p]
+            out[2 * p] = P[i]
+            out[2 * p + 1] = Q[i] if g.bus_type[i] == gridgen.BUS_PQ else Vm_[i]
+        return out
+
+    A = np.zeros((2 * nn, 2 * nn))
+    for p in range(nn):
+        i = bus_of_pos[p]
+        for comp in range(2):
+            a_m, a_a, b_m, b_a = Vm.copy(), Va.copy(), Vm.copy(), Va.copy()
+            if comp == 0:
+                a_a[i] += h
+                b_a[i] -= h
+            else:
+                a_m[i] += h
+                b_m[i] -= h
+            A[:, 2 * p + comp] = (F(a_m, a_a) - F(b_m, b_a)) / (2 * h)
+    for p in range(nn):
+        if g.bus_type[bus_of_pos[p]] == gridgen.BUS_PV:
+            col = A[:, 2 * p + 1].copy()
+            A[:, 2 * p + 1] = 0
+            A[2 * p + 1, 2 * p + 1] = col[2 * p + 1]
+    return A
+
+
+def test_block_jacobian_fd_and_pattern(oracle):
+    g = gridgen.make_grid(35, 12)
+    Y = oracle.grid_ybus(g)
+    sym = oracle.Sym(g.n, g.f, g.t)
+    Vm, Va = random_state(g, np.random.default_rng(5))
+    pv = g.bus_type == gridgen.BUS_PV
+    Vm[pv] = g.vset[pv]
+    D, Lb, Ub = sym.block_jacobian(Y, g.bus_type, Vm, Va)
+    A = sym.dense_matrix(D, Lb, Ub)
+    Afd = block_fd(oracle, sym, Y, g, Vm, Va)
+    np.testing.assert_allclose(A, Afd, rtol=1e-6, atol=1e-6 * np.abs(A).max())
+
+
+# --------------------------------------------------------------------------
+# linear algebra: dense GE vs LAPACK, sparse LDU vs dense
+# --------------------------------------------------------------------------
+def test_dense_solve_matches_lapack(oracle):
+    rng = np.random.default_rng(0)
+    for N in (1, 5, 40):
+        A = rng.standard_normal((N, N)) + N * np.eye(N)
+        b = rng.standard_normal(N)
+        np.testing.assert_allclose(oracle.dense_solve(A, b), np.linalg.solve(A, b),
+                                   rtol=1e-12, atol=1e-12)
+    with pytest.raises(np.linalg.LinAlgError):
+        oracle.dense_solve(np.zeros((3, 3)), np.ones(3))
+
+
+def test_dense_solve_needs_pivoting(oracle):
+    A = np.array([[0.0, 1.0], [1.0, 1.0]])
+    np.testing.assert_allclose(oracle.dense_solve(A, [2.0, 3.0]), [1.0, 2.0])
+
+
+@pytest.mark.parametrize("n,seed,ordering", [(30, 1, 0), (120, 2, 0), (120, 2, 1), (400, 5, 0)])
+def test_sparse_ldu_reconstructs_and_solves(oracle, n, seed, ordering):
+    g = gridgen.make_grid(n, seed)
+    Y = oracle.grid_ybus(g)
+    sym = oracle.Sym(g.n, g.f, g.t, 0, ordering)
+    Vm, Va = g.flat_start()
+    D, Lb, Ub = sym.block_jacobian(Y, g.bus_type, Vm, Va)
+    A = sym.dense_matrix(D, Lb, Ub)
+    Df, L, U, bad = sym.factor(D, Lb, Ub)
+    assert bad == -1
+    nn = sym.nn
+    Lm = np.eye(2 * nn)
+    Um = np.eye(2 * nn)
+    Dm = np.zeros((2 * nn, 2 * nn))
+    for p in range(nn):
+        Dm[2 * p:2 * p + 2, 2 * p:2 * p + 2] = Df[p]
+        for q in range(sym.Lp[p], sym.Lp[p + 1]):
+            k = sym.Li[q]
+            Lm[2 * k:2 * k + 2, 2 * p:2 * p + 2] = L[q]
+            Um[2 * p:2 * p + 2, 2 * k:2 * k + 2] = U[q]
+    assert np.abs(Lm @ Dm @ Um - A).max() <= 1e-13 * np.abs(A).max()
+    rhs = np.random.default_rng(seed).standard_normal(2 * nn)
+    x = sym.solve(Df, L, U, rhs).reshape(-1)
+    np.testing.assert_allclose(x, np.linalg.solve(A, rhs), rtol=1e-9, atol=1e-10)
+
+
+def test_zero_pivot_reported(oracle):
+    # bus 2 hangs off bus 1 with a zero-impedance-free but purely resistive
+    # branch and zero injection derivative: construct a singular D directly.
+    sym = oracle.Sym(3, np.array([0, 1], np.int32), np.array([1, 2], np.int32))
+    D = np.zeros((2, 2, 2))
+    D[:] = np.eye(2)
+    D[sym.level_nodes[0]] = 0.0
+    Lb = np.zeros((max(sym.nnzL, 1), 2, 2))
+    _, _, _, bad = sym.factor(D, Lb, Lb)
+    assert bad == sym.level_nodes[0]
+
+
+# --------------------------------------------------------------------------
+# symbolic analysis: brute force and definitions
+# --------------------------------------------------------------------------
+def pattern_sets(sym):
+    return [set(sym.Li[sym.Lp[p]:sym.Lp[p + 1]].tolist()) for p in range(sym.nn)]
+
+
+def permuted_adjacency(g, sym):
+    nn = sym.nn
+    pos = np.full(g.n, -1)
+    pos[sym.perm] = np.arange(nn)
+    A = np.zeros((nn, nn), bool)
+    for a, b in zip(g.f, g.t):
+        pa, pb = pos[a], pos[b]
+        if pa >= 0 and pb >= 0:
+            A[pa, pb] = A[pb, pa] = True
+    return A
+
+
+def brute_elimination(A):
+    """Dense boolean Gaussian elimination: higher-neighbour sets in G+."""
+    A = A.copy()
+    nn = A.shape[0]
+    out = []
+    for i in range(nn):
+        hi = np.flatnonzero(A[i, i + 1:]) + i + 1
+        for a in hi:
+            A[a, hi] = True
+        out.append(set(hi.tolist()))
+    return out
+
+
+@pytest.mark.parametrize("n,seed,ordering", [(60, 1, 0), (150, 2, 0), (150, 3, 1), (300, 4, 0)])
+def test_fill_equals_brute_force_elimination(oracle, n, seed, ordering):
+    g = gridgen.make_grid(n, seed)
+    sym = oracle.Sym(g.n, g.f, g.t, 0, ordering)
+    assert pattern_sets(sym) == brute_elimination(permuted_adjacency(g, sym))
+
+
+def test_fill_equals_generic_numeric_lu(oracle):
+    g = gridgen.make_grid(40, 6)
+    sym = oracle.Sym(g.n, g.f, g.t)
+    A = permuted_adjacency(g, sym).astype(float)
+    rng = np.random.default_rng(1)
+    M = np.where(A, rng.uniform(0.1, 1.0, A.shape), 0.0)
+    M = M + M.T + np.diag(rng.uniform(5, 10, A.shape[0]) + A.sum(1) * 2)
+    nn = M.shape[0]
+    for i in range(nn):  # no-pivot LU, right-looking
+        M[i + 1:, i] /= M[i, i]
+        M[i + 1:, i + 1:] -= np.outer(M[i + 1:, i], M[i, i + 1:])
+    pat = [set((np.flatnonzero(np.abs(M[i + 1:, i]) > 1e-300) + i + 1).tolist())
+           for i in range(nn)]
+    assert pat == pattern_sets(sym)
+
+
+def liu_etree(A):
+    """Liu's elimination tree from the pattern of A alone (path compression)."""
+    nn = A.shape[0]
+    parent = np.full(nn, -1)
+    anc = np.full(nn, -1)
+    for i in range(nn):
+        for k in np.flatnonzero(A[i, :i]):
+            r = k
+            while anc[r] != -1 and anc[r] != i:
+                nxt = anc[r]
+                anc[r] = i
+                r = nxt
+            if anc[r] == -1:
+                anc[r] = i
+                parent[r] = i
+    return parent
+
+
+@pytest.mark.parametrize("n,seed", [(80, 1), (250, 9)])
+def test_etree_and_levels_by_definition(oracle, n, seed):
+    g = gridgen.make_grid(n, seed)
+    sym = oracle.Sym(g.n, g.f, g.t)
+    np.testing.assert_array_equal(sym.parent, liu_etree(permuted_adjacency(g, sym)))
+    # level = 1 + max child level, leaves 1 (height in the tree)
+    lev = np.ones(sym.nn, int)
+    for i in range(sym.nn):
+        if sym.parent[i] >= 0:
+            lev[sym.parent[i]] = max(lev[sym.parent[i]], lev[i] + 1)
+    np.testing.assert_array_equal(sym.level, lev)
+    # level lists: grouped by level, ascending inside each level
+    for l in range(sym.nlev):
+        nodes = sym.level_nodes[sym.level_ptr[l]:sym.level_ptr[l + 1]]
+        assert np.all(np.diff(nodes) > 0)
+        assert np.all(sym.level[nodes] == l + 1)
+        anc = set()
+        for v in nodes:
+            p = sym.parent[v]
+            while p >= 0:
+                anc.add(p)
+                p = sym.parent[p]
+        assert not anc & set(nodes.tolist())
+
+
+def test_minimum_degree_property(oracle):
+    g = gridgen.make_grid(120, 3)
+    sym = oracle.Sym(g.n, g.f, g.t)
+    # replay elimination on the bus graph without the slack
+    nbr = {v: set() for v in range(1, g.n)}
+    for a, b in zip(g.f, g.t):
+        if a and b:
+            nbr[a].add(b)
+            nbr[b].add(a)
+    for p in range(sym.nn):
+        alive = sorted(nbr)
+        degs = {v: len(nbr[v]) for v in alive}
+        dmin = min(degs.values())
+        expect = min(v for v in alive if degs[v] == dmin)
+        v = sym.perm[p]
+        assert v == expect
+        nb = nbr.pop(v)
+        for a in nb:
+            nbr[a].discard(v)
+            nbr[a] |= nb - {a}
+
+
+def test_table1_level_partition(oracle):
+    """Table I of the paper from an elimination tree consistent with it."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "table1_levels.txt")
+    rows = [l.split("\t") for l in open(path) if l.strip() and not l.startswith("#")]
+    expect = {int(a): sorted(int(x) for x in b.strip().split(",")) for a, b in rows}
+    parent = {1: 3, 2: 3, 4: 5, 3: 7, 5: 7, 6: 7, 7: 8, 8: 9, 9: 10}
+    f = np.array(list(parent.keys()), np.int32)
+    t = np.array(list(parent.values()), np.int32)
+    # bus 0 is an isolated slack; natural order keeps node k = bus k.
+    sym = oracle.Sym(11, f, t, 0, 1)
+    assert sym.nnzL == len(parent)  # a tree ordered leaves-first has no fill
+    got = {}
+    for l in range(sym.nlev):
+        got[l + 1] = sorted(int(sym.perm[v]) for v in
+                            sym.level_nodes[sym.level_ptr[l]:sym.level_ptr[l + 1]])
+    assert got == expect
+
+
+def test_slack_articulation_forest(oracle):
+    # slack joins two otherwise separate parts: the tree becomes a forest
+    f = np.array([0, 1, 0, 3], np.int32)
+    t = np.array([1, 2, 3, 4], np.int32)
+    sym = oracle.Sym(5, f, t)
+    assert int(np.sum(sym.parent == -1)) == 2
+
+
+# --------------------------------------------------------------------------
+# adjoint
+# --------------------------------------------------------------------------
+def solve_tight(oracle, g, Psp, Qsp, x):
+    Y = oracle.ybus(g.n, g.f, g.t, g.r, x, g.b)
+    Vm0, Va0 = g.flat_start()
+    r = oracle.newton_dense(Y, g.bus_type, Psp, Qsp, Vm0, Va0, tol=1e-13, max_iter=40)
+    assert r.status in (0, 6) and r.norm < 1e-11
+    return r
+
+
+def loss_grad(g, Vm, w):
+    gVm = 2 * w * (Vm - 1)
+    gVm[g.bus_type != gridgen.BUS_PQ] = 0
+    return gVm
+
+
+def test_adjoint_matches_central_fd(oracle):
+    g = gridgen.make_grid(40, 21)
+    rng = np.random.default_rng(6)
+    w = rng.uniform(0, 1, g.n)
+    Y = oracle.grid_ybus(g)
+    base = solve_tight(oracle, g, g.Psp, g.Qsp, g.x)
+    gVm = loss_grad(g, base.Vm, w)
+    gVa = np.zeros(g.n)
+    gP, gQ, gx = oracle.adjoint_dense(g, Y, base.Vm, base.Va, gVm, gVa)
+
+    def loss(Psp, Qsp, x):
+        r = solve_tight(oracle, g, Psp, Qsp, x)
+        pq = g.bus_type == gridgen.BUS_PQ
+        return np.sum((w * (r.Vm - 1) ** 2)[pq])
+
+    h = 1e-6
+    for i in [1, 5, 17, 33]:
+        e = np.zeros(g.n)
+        e[i] = h
+        fdP = (loss(g.Psp + e, g.Qsp, g.x) - loss(g.Psp - e, g.Qsp, g.x)) / (2 * h)
+        fdQ = (loss(g.Psp, g.Qsp + e, g.x) - loss(g.Psp, g.Qsp - e, g.x)) / (2 * h)
+        assert gP[i] == pytest.approx(fdP, rel=1e-5, abs=1e-9)
+        assert gQ[i] == pytest.approx(fdQ, rel=1e-5, abs=1e-9)
+    for ei in [0, 7, 30, 45]:
+        e = np.zeros(g.m)
+        e[ei] = h
+        fdx = (loss(g.Psp, g.Qsp, g.x + e) - loss(g.Psp, g.Qsp, g.x - e)) / (2 * h)
+        assert gx[ei] == pytest.approx(fdx, rel=1e-5, abs=1e-9)
+    assert np.all(gQ[g.bus_type != gridgen.BUS_PQ] == 0)
+    assert gP[0] == 0
+
+
+def test_adjoint_two_bus_closed_form(oracle):
+    """d|V1|/dP and dtheta1/dQ of the closed form vs the adjoint with unit seeds."""
+    r, x, b, P, Q = 0.02, 0.08, 0.04, 0.9, 0.3
+    g = two_bus(r, x, b, P, Q)
+    Y = oracle.grid_ybus(g)
+    res = oracle.solve_grid(g, sparse=False, tol=1e-13, max_iter=30)
+    h = 1e-6
+    # load P is -Psp: d/dPsp = -d/dP
+    dvm_dP = (closed_form_pq(r, x, b, P + h, Q)[0] - closed_form_pq(r, x, b, P - h, Q)[0]) / (2 * h)
+    dth_dQ = (closed_form_pq(r, x, b, P, Q + h)[1] - closed_form_pq(r, x, b, P, Q - h)[1]) / (2 * h)
+    dvm_dx = (closed_form_pq(r, x + h, b, P, Q)[0] - closed_form_pq(r, x - h, b, P, Q)[0]) / (2 * h)
+    gP, gQ, gx = oracle.adjoint_dense(g, Y, res.Vm, res.Va, np.array([0.0, 1.0]), np.zeros(2))
+    assert gP[1] == pytest.approx(-dvm_dP, rel=1e-7)
+    assert gx[0] == pytest.approx(dvm_dx, rel=1e-7)
+    gP, gQ, gx = oracle.adjoint_dense(g, Y, res.Vm, res.Va, np.zeros(2), np.array([0.0, 1.0]))
+    assert gQ[1] == pytest.approx(-dth_dQ, rel=1e-7)
