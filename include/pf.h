@@ -1,0 +1,241 @@
+/*
+ * libpf: Newton-Raphson AC power flow on AMD Instinct MI355X (gfx950).
+ *
+ * The calls follow the paper's statement of the problem (Shi et al.,
+ * "Graph Based Power Flow Calculation for Energy Management System",
+ * arXiv 1811.02512): a grid graph with admittances on edges and shunts on
+ * nodes (Sec. III-A) -> form the admittance matrix (FormMatrixA) -> analyse
+ * the sparsity (FormFilledGraph, FormEliminationTree,
+ * FormHierarchicalPartition; Sec. II-B) -> factorise A = LDU level by level
+ * (FactorizeGraphA, Sec. III-B) -> forward substitution, normalisation and
+ * backward substitution (Sec. III-C), all inside Newton-Raphson (Sec. III).
+ *
+ * Conventions shared by every call
+ *   - Buses are numbered 0..n-1; one bus is the slack (reference) bus.
+ *   - Per-unit quantities, angles in radians, fp64 everywhere.
+ *   - Bus types: PF_BUS_PQ, PF_BUS_PV, PF_BUS_SLACK (int8).  Any type other
+ *     than PF_BUS_PV at a non-slack bus is treated as PQ; the slack is the
+ *     one named to pf_analyze.
+ *   - "Position" p = 0..nn-1 (nn = n-1) is the elimination position of a
+ *     non-slack bus; perm[p] is its bus.
+ *   - A 2x2 block is 4 doubles row-major [r0c0 r0c1 r1c0 r1c1]; row 0 is the
+ *     active-power equation, row 1 the reactive-power equation (PQ bus) or
+ *     the |V| equation (PV bus); column 0 is the angle unknown, column 1 the
+ *     magnitude unknown.  A PV bus keeps |V| fixed: its row-1 block entries
+ *     are (0,1) on the diagonal and (0,0) elsewhere, and its column-1 entries
+ *     off its own row are zero.
+ *   - Filled layout ("vals"), per case, 4*nn + 8*nnzL doubles:
+ *       D section  [nn][4]        diagonal block of position p
+ *       LU section [nnzL][2][4]   for slot s of S(p) (the s-th higher
+ *                                 neighbour k of p in the filled graph):
+ *                                 [0] = block (k, p) below the diagonal,
+ *                                 [1] = block (p, k) above it.
+ *     After pf_factor the same layout holds the factors: D section = D^-1,
+ *     LU[s][0] = L_kp * D_p (lower factor times pivot), LU[s][1] = U_pk (unit
+ *     upper factor), so that A = L D U with L, U unit block-triangular.
+ *   - Device pointers are caller-owned (e.g. torch tensors) and must stay
+ *     valid until the stream work completes.  libpf allocates no device
+ *     memory; pf_symbolic_upload / pf_multi_upload copy into caller buffers.
+ *   - "stride" arguments are in elements between consecutive cases; 0 means
+ *     the array is shared by all cases (inputs only).
+ *   - Every stream argument is a hipStream_t (0 = legacy default stream);
+ *     work is enqueued asynchronously, so per-case numerical outcomes are
+ *     reported in device status arrays, never by the return code.
+ *   - Return codes (pf_status) report argument, analysis and launch errors
+ *     synchronously; pf_last_error() gives a thread-local message.
+ *   - No C++ exception crosses this interface.
+ */
+#ifndef PF_H
+#define PF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pf_symbolic_s* pf_symbolic;
+typedef struct pf_multi_s* pf_multi;
+
+typedef enum {
+    PF_OK = 0,
+    PF_E_INVALID = 1,       /* bad argument, bad branch list, self loop       */
+    PF_E_HIP = 2,           /* a HIP runtime call failed                     */
+    PF_E_WORKSPACE = 3,     /* caller buffer too small / misaligned          */
+    PF_E_DISCONNECTED = 4,  /* some bus is not connected to the slack        */
+    PF_E_ZERO_PIVOT = 5,    /* per case: singular or non-finite pivot block  */
+    PF_E_NOT_CONVERGED = 6, /* per case: max_iter reached                    */
+    PF_E_NONFINITE = 7      /* per case: NaN/Inf mismatch                    */
+} pf_status;
+
+enum { PF_ORDER_MINDEG = 0, PF_ORDER_NATURAL = 1 };
+enum { PF_BUS_PQ = 1, PF_BUS_PV = 2, PF_BUS_SLACK = 3 };
+/* pf_newton flags */
+enum {
+    PF_NEWTON_KEEP_FACTORS = 1 /* after convergence, factor J at the returned
+                                  state into the workspace's vals region */
+};
+
+typedef struct {
+    int32_t n;            /* buses                                          */
+    int32_t m;            /* branches                                       */
+    int32_t nn;           /* positions (non-slack buses) = n - 1            */
+    int32_t slack;
+    int64_t nnz_y;        /* admittance entries (diagonal always present)   */
+    int64_t nnz_l;        /* off-diagonal blocks of L (= of U)              */
+    int64_t n_upd;        /* off-diagonal block updates per factorisation   */
+    int32_t nlevels;      /* hierarchical levels                            */
+    int32_t max_level_width;
+    int64_t vals_doubles;    /* 4*nn + 8*nnz_l: filled layout, one case     */
+    int64_t ws_doubles;      /* pf_newton workspace per case (vals first)   */
+    size_t dev_bytes;        /* device buffer for pf_symbolic_upload        */
+} pf_info;
+
+/* ---- status ------------------------------------------------------------ */
+const char* pf_status_string(int status);
+/* Last error message of the calling thread ("" if none). */
+const char* pf_last_error(void);
+const char* pf_version(void);
+
+/* ---- symbolic analysis (host, synchronous, no GPU needed) ---------------
+ * Paper: FormFilledGraph, FormEliminationTree and FormHierarchicalPartition
+ * (Sec. II-B) on the bus graph without the slack.  The paper eliminates in
+ * the given numbering; ordering PF_ORDER_MINDEG (default) first applies an
+ * exact minimum-degree order (degree = distinct uneliminated neighbours with
+ * fill; ties to the lowest bus number), PF_ORDER_NATURAL keeps bus order.
+ * Levels: synchronous leaf peeling of the elimination tree (Table I); nodes
+ * of a level are listed in ascending position.
+ * from/to: host int32[m]; parallel branches allowed; self loops rejected.
+ * Errors: PF_E_INVALID (n < 2, index out of range, self loop, bad slack),
+ * PF_E_DISCONNECTED (a bus unreachable from the slack).  On success *out
+ * owns a host object; release it with pf_symbolic_destroy.               */
+int pf_analyze(int n, int m, const int32_t* from, const int32_t* to, int slack,
+               int ordering, pf_symbolic* out);
+int pf_symbolic_info(const pf_symbolic sym, pf_info* info);
+/* Copies the analysis into caller host arrays: perm[nn] (bus at position p),
+ * parent[nn] (elimination-tree parent position, -1 for roots), level[nn]
+ * (1-based), level_ptr[nlevels+1], level_nodes[nn], Lp[nn+1], Li[nnz_l]
+ * (S(p) = Li[Lp[p]..Lp[p+1]), ascending).  Any pointer may be NULL.       */
+int pf_symbolic_export(const pf_symbolic sym, int32_t* perm, int32_t* parent,
+                       int32_t* level, int32_t* level_ptr, int32_t* level_nodes,
+                       int32_t* Lp, int32_t* Li);
+/* Thread mapping: lanes per node (1,2,4,...,64) for each level, used by the
+ * level-scheduled kernels.  Defaults come from a work model; an autotuner may
+ * replace them.  Takes effect at the next pf_symbolic_upload.             */
+int pf_symbolic_set_mapping(pf_symbolic sym, const int32_t* lanes_per_level);
+int pf_symbolic_get_mapping(const pf_symbolic sym, int32_t* lanes_per_level);
+/* Copies the integer structure into the caller's device buffer d_buf
+ * (>= info.dev_bytes, 256-byte aligned) on stream s.  The buffer must stay
+ * alive while any call uses this symbolic.  Re-uploading is allowed.    */
+int pf_symbolic_upload(pf_symbolic sym, void* d_buf, size_t bytes, void* stream);
+void pf_symbolic_destroy(pf_symbolic sym);
+
+/* ---- FormMatrixA (Sec. III-A), nodal parallel ---------------------------
+ * One thread per (case, bus) gathers its row from incident branches:
+ * Y_ii = sum (y_e + j b_e/2), Y_ik = -sum y_e, y_e = 1/(r_e + j x_e).
+ * d_r, d_x, d_b: double[B][m] with branch_stride (0 = shared).
+ * d_yval: out, complex as (G, B) pairs, double[B][nnz_y][2] with y_stride
+ * (in doubles, >= 2*nnz_y), entries in the symbolic's CSR order.          */
+int pf_build_ybus(const pf_symbolic sym, int B, const double* d_r, const double* d_x,
+                  const double* d_b, int64_t branch_stride, double* d_yval,
+                  int64_t y_stride, void* stream);
+/* Copies the admittance CSR structure to host arrays yptr[n+1], ycol[nnz_y]. */
+int pf_symbolic_ybus_pattern(const pf_symbolic sym, int32_t* yptr, int32_t* ycol);
+
+/* ---- nodal mismatch (Sec. II-A) -------------------------------------------
+ * P_i + jQ_i = V_i conj(sum_k Y_ik V_k); F = calculated - scheduled.
+ * d_rhs: out double[B][nn][2] (rhs_stride), position order, (F_P, F_Q) with
+ * F_Q = 0 at PV buses.  d_norm: out double[B], max |F| (NaN if any NaN).
+ * d_PQ: optional out double[B][n][2] (P_i, Q_i per bus, stride 2n).       */
+int pf_mismatch(const pf_symbolic sym, int B, const double* d_yval, int64_t y_stride,
+                const int8_t* d_type, int64_t type_stride, const double* d_Psp,
+                const double* d_Qsp, int64_t inj_stride, const double* d_Vm,
+                const double* d_Va, int64_t v_stride, double* d_rhs, int64_t rhs_stride,
+                double* d_norm, double* d_PQ, void* stream);
+
+/* ---- Jacobian ("A matrix formation", Sec. III) ----------------------------
+ * Assembles J = dF/d(theta, |V|) of the non-slack buses into the filled
+ * layout d_vals (vals_stride >= info.vals_doubles); fill slots are zero.  */
+int pf_jacobian(const pf_symbolic sym, int B, const double* d_yval, int64_t y_stride,
+                const int8_t* d_type, int64_t type_stride, const double* d_Vm,
+                const double* d_Va, int64_t v_stride, double* d_vals, int64_t vals_stride,
+                void* stream);
+
+/* ---- FactorizeGraphA (Sec. III-B, eqs. 1-3) --------------------------------
+ * In-place block LDU of B matrices in the filled layout, level by level
+ * (hierarchical parallel), nodes of a level in parallel (nodal parallel).
+ * Each node pulls the updates of its descendants (no atomics, results are
+ * bitwise reproducible).  No pivoting: d_status[b] (int32, may be NULL) is
+ * set to PF_OK or PF_E_ZERO_PIVOT when a pivot block is singular or
+ * non-finite.                                                             */
+int pf_factor(const pf_symbolic sym, int B, double* d_vals, int64_t vals_stride,
+              int32_t* d_status, void* stream);
+
+/* ---- forward substitution, normalisation, backward substitution ---------
+ * (Sec. III-C, eq. 4.)  transpose = 0 solves A x = rhs; transpose = 1 solves
+ * A^T x = rhs with the same factors (U^T forward over levels 1..p, D^-T,
+ * L^T backward over levels p..1).  d_vals: factored filled layout.  d_rhs:
+ * double[B][nn][2] (position order), overwritten with the solution.       */
+int pf_solve(const pf_symbolic sym, int B, const double* d_vals, int64_t vals_stride,
+             double* d_rhs, int64_t rhs_stride, int transpose, void* stream);
+
+/* ---- Newton-Raphson (Sec. III) ---------------------------------------------
+ * One launch runs the whole iteration for B cases sharing this symbolic;
+ * workgroup b owns case b: mismatch, then one sweep over levels 1..p that
+ * assembles J, factorises and forward-substitutes, then one sweep p..1 that
+ * back-substitutes and applies the step (theta -= dtheta, |V| -= d|V| at PQ
+ * buses).  Stops when max|F| < tol at the top of an iteration, or after
+ * max_iter steps.  d_Vm/d_Va: in = start state (flat start is the caller's),
+ * out = solution, double[B][n] (v_stride).  d_ws: workspace double[B][..]
+ * (ws_stride >= info.ws_doubles); its first info.vals_doubles hold the last
+ * factors (at the solution with PF_NEWTON_KEEP_FACTORS).  Outputs:
+ * d_iters[B] (steps applied), d_norm[B] (last max|F|), d_status[B]
+ * (PF_OK, PF_E_ZERO_PIVOT, PF_E_NOT_CONVERGED, PF_E_NONFINITE); any may be
+ * NULL.  The launch never fails because of one case.                      */
+int pf_newton(const pf_symbolic sym, int B, const double* d_yval, int64_t y_stride,
+              const int8_t* d_type, int64_t type_stride, const double* d_Psp,
+              const double* d_Qsp, int64_t inj_stride, double* d_Vm, double* d_Va,
+              int64_t v_stride, double tol, int max_iter, int flags, double* d_ws,
+              int64_t ws_stride, int32_t* d_iters, double* d_norm, int32_t* d_status,
+              void* stream);
+
+/* ---- adjoint parameter gradients (beyond the paper) ------------------------
+ * Given lam = J^-T g at the solution (pf_solve with transpose = 1 on the
+ * factors kept by pf_newton), writes dL/dPsp = lam_P at non-slack buses,
+ * dL/dQsp = lam_Q at PQ buses (0 elsewhere), and
+ * dL/dx_e = -sum_{i in {f,t}} lam_i . d(P_i, Q_i)/dx_e, with
+ * dy_e/dx_e = -j y_e^2 (r_e held fixed).  d_lam: double[B][nn][2].
+ * d_gP, d_gQ: out double[B][n] (g_stride).  d_gx: out; gx_mode 0 writes
+ * double[B][m] (stride m), gx_mode 1 writes the sum over cases, double[m].
+ * One thread per branch: no atomics.                                      */
+int pf_adjoint_params(const pf_symbolic sym, int B, const double* d_lam, int64_t lam_stride,
+                      const int8_t* d_type, int64_t type_stride, const double* d_Vm,
+                      const double* d_Va, int64_t v_stride, const double* d_r,
+                      const double* d_x, int64_t branch_stride, double* d_gP, double* d_gQ,
+                      int64_t g_stride, double* d_gx, int gx_mode, void* stream);
+
+/* ---- batches of cases with their own sparsity (N-1 outages, mixed grids) --
+ * A plan binds G cases to uploaded symbolics (several cases may share one).
+ * Per-case arrays are concatenated; pf_multi_info gives each case's element
+ * offsets: bus arrays (type, Psp, Qsp, Vm, Va: n of its grid), branch
+ * arrays (r, x, b: m of its grid), admittance values (2*nnz_y doubles) and
+ * workspace (ws_doubles).  Cases run largest first, one workgroup each, in
+ * one launch.                                                              */
+int pf_multi_create(int G, const pf_symbolic* syms, pf_multi* out);
+/* offsets: each int64[G+1] (prefix sums), any may be NULL.               */
+int pf_multi_info(const pf_multi plan, size_t* dev_bytes, int64_t* bus_off,
+                  int64_t* branch_off, int64_t* y_off, int64_t* ws_off);
+int pf_multi_upload(pf_multi plan, void* d_buf, size_t bytes, void* stream);
+int pf_build_ybus_multi(const pf_multi plan, const double* d_r, const double* d_x,
+                        const double* d_b, double* d_yval, void* stream);
+int pf_newton_multi(const pf_multi plan, const double* d_yval, const int8_t* d_type,
+                    const double* d_Psp, const double* d_Qsp, double* d_Vm, double* d_Va,
+                    double tol, int max_iter, int flags, double* d_ws, int32_t* d_iters,
+                    double* d_norm, int32_t* d_status, void* stream);
+void pf_multi_destroy(pf_multi plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PF_H */

@@ -1,0 +1,131 @@
+"""Convenience layer over the C ABI: owns handles and torch device buffers.
+
+Nothing here computes power-flow quantities; every numeric step runs in the
+HIP kernels behind :mod:`paper_1811_02512_amd.binding`.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+
+def _dev(device):
+    return torch.device(device if device is not None else "cuda")
+
+
+class Symbolic:
+    """Host analysis of one grid topology plus its device copy."""
+
+    def __init__(self, n, f, t, slack=0, ordering=B.PF_ORDER_MINDEG):
+        self.h = B.pf_analyze(n, f, t, slack, ordering)
+        self.n = int(n)
+        self.f = np.ascontiguousarray(f, np.int32)
+        self.t = np.ascontiguousarray(t, np.int32)
+        self.buf = None
+        self.device = None
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and B is not None and getattr(B, "lib", None) is not None:
+            try:
+                B.pf_symbolic_destroy(h)
+            except Exception:  # interpreter shutdown
+                pass
+            self.h = None
+
+    @property
+    def info(self):
+        return B.pf_symbolic_info(self.h)
+
+    def export(self):
+        return B.pf_symbolic_export(self.h)
+
+    def ybus_pattern(self):
+        return B.pf_symbolic_ybus_pattern(self.h)
+
+    def get_mapping(self):
+        return B.pf_symbolic_get_mapping(self.h)
+
+    def set_mapping(self, lanes):
+        B.pf_symbolic_set_mapping(self.h, lanes)
+        if self.buf is not None:
+            B.pf_symbolic_upload(self.h, self.buf)
+
+    def upload(self, device=None):
+        dev = _dev(device)
+        nbytes = self.info.dev_bytes
+        if self.buf is None or self.buf.numel() < nbytes or self.buf.device != dev:
+            self.buf = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        B.pf_symbolic_upload(self.h, self.buf)
+        self.device = dev
+        return self
+
+    # -- helpers allocating outputs ------------------------------------------------
+    def build_ybus(self, r, x, b):
+        """r, x, b: [m] or [B, m] fp64 device tensors -> yval [B, 2*nnz_y]."""
+        info = self.info
+        Bn = r.shape[0] if r.dim() == 2 else 1
+        bstride = r.shape[-1] if r.dim() == 2 else 0
+        y = torch.empty(Bn, 2 * info.nnz_y, dtype=torch.float64, device=r.device)
+        B.pf_build_ybus(self.h, Bn, r, x, b, bstride, y, 2 * info.nnz_y)
+        return y
+
+    def workspace(self, Bn, device=None):
+        return torch.empty(Bn, self.info.ws_doubles, dtype=torch.float64,
+                           device=_dev(device or self.device))
+
+    def newton(self, yval, bus_type, Psp, Qsp, Vm, Va, tol=1e-8, max_iter=20,
+               keep_factors=False, ws=None):
+        """Batched NR in place on Vm, Va ([B, n]).  Returns (iters, norm, status, ws)."""
+        Bn = Vm.shape[0]
+        info = self.info
+        if ws is None:
+            ws = self.workspace(Bn, Vm.device)
+        iters = torch.empty(Bn, dtype=torch.int32, device=Vm.device)
+        norm = torch.empty(Bn, dtype=torch.float64, device=Vm.device)
+        status = torch.empty(Bn, dtype=torch.int32, device=Vm.device)
+        B.pf_newton(self.h, Bn, yval, _stride(yval), bus_type, _stride(bus_type), Psp, Qsp,
+                    _stride(Psp), Vm, Va, Vm.shape[-1], tol, max_iter,
+                    B.PF_NEWTON_KEEP_FACTORS if keep_factors else 0, ws, info.ws_doubles,
+                    iters, norm, status)
+        return iters, norm, status, ws
+
+
+def _stride(t):
+    """0 for a shared [k] array, row length for a [B, k] array."""
+    return 0 if t.dim() == 1 else t.shape[-1]
+
+
+class MultiPlan:
+    """Batch of cases with their own symbolic analyses (N-1, mixed grids)."""
+
+    def __init__(self, syms, device=None):
+        self.syms = list(syms)
+        self.p = B.pf_multi_create([s.h for s in self.syms])
+        nbytes, self.offs = B.pf_multi_info(self.p, len(self.syms))
+        self.buf = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=_dev(device))
+        B.pf_multi_upload(self.p, self.buf)
+
+    def __del__(self):
+        p = getattr(self, "p", None)
+        if p is not None and B is not None and getattr(B, "lib", None) is not None:
+            try:
+                B.pf_multi_destroy(p)
+            except Exception:  # interpreter shutdown
+                pass
+            self.p = None
+
+    def concat(self, arrays, key, dtype, device=None):
+        """Concatenate per-case host arrays into one device tensor."""
+        tot = int(self.offs[key][-1])
+        out = np.zeros(max(tot, 1), dtype)
+        for g, a in enumerate(arrays):
+            out[self.offs[key][g]:self.offs[key][g + 1]] = a
+        return torch.from_numpy(out).to(_dev(device))
+
+    def split(self, t, key):
+        t = t.cpu().numpy()
+        o = self.offs[key]
+        return [t[o[g]:o[g + 1]] for g in range(len(self.syms))]

@@ -1,0 +1,343 @@
+// Host symbolic analysis for the level-scheduled block LDU.
+//
+// Steps (paper, Sec. II-B): fill-reducing elimination order (our reading:
+// exact minimum degree, the paper itself eliminates in the given numbering),
+// FormFilledGraph, FormEliminationTree, FormHierarchicalPartition.  The
+// filled pattern falls out of the symbolic elimination itself: the neighbours
+// a node still has when it is eliminated are exactly its higher neighbours in
+// the filled graph.  On top of the paper's structures this builds the index
+// maps the kernels need: admittance CSR with its contributing branches,
+// position <-> bus maps, Y entry of every filled block, lower-neighbour lists
+// and the per-destination update pairs of the left-looking factorisation.
+#include <algorithm>
+#include <cstring>
+#include <queue>
+#include <utility>
+
+#include "pf.h"
+#include "pf_internal.h"
+
+namespace pf {
+
+namespace {
+
+// Sorted-vector union of a and b without the values x and y.
+void merge_without(const std::vector<int32_t>& a, const std::vector<int32_t>& b, int32_t x,
+                   int32_t y, std::vector<int32_t>& out)
+{
+    out.clear();
+    out.reserve(a.size() + b.size());
+    size_t i = 0, j = 0;
+    while (i < a.size() || j < b.size()) {
+        int32_t v;
+        if (j >= b.size() || (i < a.size() && a[i] < b[j])) {
+            v = a[i++];
+        } else if (i >= a.size() || b[j] < a[i]) {
+            v = b[j++];
+        } else {
+            v = a[i++];
+            ++j;
+        }
+        if (v != x && v != y) out.push_back(v);
+    }
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace
+
+size_t HostSym::dev_bytes() const
+{
+    const std::vector<int32_t>* arrs[] = {&yptr, &ycol, &ybr_ptr, &ybr, &perm, &pos, &Lp,
+                                          &Li, &ylo, &yup, &ydiag, &Rp, &Ri, &Rs, &Up, &Ua,
+                                          &Ub, &level_ptr, &level_nodes, &level_g};
+    size_t total = 0;
+    for (auto* a : arrs) total += align256(std::max<size_t>(a->size(), 1) * sizeof(int32_t));
+    return total;
+}
+
+int analyze(int n, int m, const int32_t* from, const int32_t* to, int slack, int ordering,
+            HostSym& s, std::string& msg)
+{
+    if (n < 2 || m < 0 || slack < 0 || slack >= n || (m > 0 && (!from || !to))) {
+        msg = "pf_analyze: need n >= 2, m >= 0, 0 <= slack < n and branch arrays";
+        return PF_E_INVALID;
+    }
+    if (ordering != PF_ORDER_MINDEG && ordering != PF_ORDER_NATURAL) {
+        msg = "pf_analyze: unknown ordering";
+        return PF_E_INVALID;
+    }
+    for (int e = 0; e < m; ++e) {
+        if (from[e] < 0 || from[e] >= n || to[e] < 0 || to[e] >= n) {
+            msg = "pf_analyze: branch " + std::to_string(e) + " has a bus index out of range";
+            return PF_E_INVALID;
+        }
+        if (from[e] == to[e]) {
+            msg = "pf_analyze: branch " + std::to_string(e) + " is a self loop";
+            return PF_E_INVALID;
+        }
+    }
+    s = HostSym();
+    s.n = n;
+    s.m = m;
+    s.nn = n - 1;
+    s.slack = slack;
+    s.ordering = ordering;
+    s.from.assign(from, from + m);
+    s.to.assign(to, to + m);
+
+    // incidence: (other bus, branch) per bus, sorted
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> inc(n);
+    for (int e = 0; e < m; ++e) {
+        inc[from[e]].push_back({to[e], e});
+        inc[to[e]].push_back({from[e], e});
+    }
+    for (auto& v : inc) std::sort(v.begin(), v.end());
+
+    // every bus must reach the slack
+    {
+        std::vector<char> seen(n, 0);
+        std::vector<int32_t> stack{slack};
+        seen[slack] = 1;
+        int cnt = 1;
+        while (!stack.empty()) {
+            int v = stack.back();
+            stack.pop_back();
+            for (auto& pe : inc[v])
+                if (!seen[pe.first]) {
+                    seen[pe.first] = 1;
+                    ++cnt;
+                    stack.push_back(pe.first);
+                }
+        }
+        if (cnt != n) {
+            msg = "pf_analyze: " + std::to_string(n - cnt) + " bus(es) not connected to the slack";
+            return PF_E_DISCONNECTED;
+        }
+    }
+
+    // admittance CSR (diagonal always present) and contributing branches
+    s.yptr.assign(n + 1, 0);
+    s.ybr_ptr.push_back(0);
+    for (int i = 0; i < n; ++i) {
+        std::vector<int32_t> cols;
+        cols.push_back(i);
+        for (auto& pe : inc[i]) cols.push_back(pe.first);
+        std::sort(cols.begin(), cols.end());
+        cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+        for (int32_t c : cols) {
+            s.ycol.push_back(c);
+            if (c == i) {
+                std::vector<int32_t> br;
+                for (auto& pe : inc[i]) br.push_back(pe.second);
+                std::sort(br.begin(), br.end());
+                s.ybr.insert(s.ybr.end(), br.begin(), br.end());
+            } else {
+                for (auto& pe : inc[i])
+                    if (pe.first == c) s.ybr.push_back(pe.second);  // ascending branch id
+            }
+            s.ybr_ptr.push_back((int32_t)s.ybr.size());
+        }
+        s.yptr[i + 1] = (int32_t)s.ycol.size();
+    }
+    auto yfind = [&](int32_t row, int32_t col) -> int32_t {
+        auto b = s.ycol.begin() + s.yptr[row], e = s.ycol.begin() + s.yptr[row + 1];
+        auto it = std::lower_bound(b, e, col);
+        return (it != e && *it == col) ? (int32_t)(it - s.ycol.begin()) : -1;
+    };
+
+    // reduced graph: node v <-> bus, ascending bus order without the slack
+    const int nn = s.nn;
+    std::vector<int32_t> bus_of(nn), node_of(n, -1);
+    for (int i = 0, v = 0; i < n; ++i)
+        if (i != slack) {
+            node_of[i] = v;
+            bus_of[v++] = i;
+        }
+    std::vector<std::vector<int32_t>> adj(nn);
+    for (int v = 0; v < nn; ++v) {
+        int i = bus_of[v];
+        for (auto& pe : inc[i]) {
+            int w = node_of[pe.first];
+            if (w >= 0) adj[v].push_back(w);
+        }
+        std::sort(adj[v].begin(), adj[v].end());
+        adj[v].erase(std::unique(adj[v].begin(), adj[v].end()), adj[v].end());
+    }
+
+    // symbolic elimination: minimum degree (ties to the lowest node, i.e.
+    // lowest bus) or the natural order; hi[v] = neighbours left at elimination
+    std::vector<std::vector<int32_t>> hi(nn);
+    std::vector<int32_t> order(nn);
+    {
+        std::vector<char> gone(nn, 0);
+        using Item = std::pair<int32_t, int32_t>;  // (degree, node)
+        std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
+        if (ordering == PF_ORDER_MINDEG)
+            for (int v = 0; v < nn; ++v) heap.push({(int32_t)adj[v].size(), v});
+        std::vector<int32_t> tmp;
+        for (int step = 0; step < nn; ++step) {
+            int p;
+            if (ordering == PF_ORDER_NATURAL) {
+                p = step;
+            } else {
+                for (;;) {
+                    Item it = heap.top();
+                    heap.pop();
+                    if (!gone[it.second] && it.first == (int32_t)adj[it.second].size()) {
+                        p = it.second;
+                        break;
+                    }
+                }
+            }
+            order[step] = p;
+            gone[p] = 1;
+            hi[p] = adj[p];
+            for (int32_t a : hi[p]) {
+                merge_without(adj[a], hi[p], a, p, tmp);
+                adj[a].swap(tmp);
+                if (ordering == PF_ORDER_MINDEG) heap.push({(int32_t)adj[a].size(), a});
+            }
+            adj[p].clear();
+            adj[p].shrink_to_fit();
+        }
+    }
+
+    // positions and the filled pattern S(p)
+    std::vector<int32_t> pos_of_node(nn);
+    for (int p = 0; p < nn; ++p) pos_of_node[order[p]] = p;
+    s.perm.resize(nn);
+    s.pos.assign(n, -1);
+    for (int p = 0; p < nn; ++p) {
+        s.perm[p] = bus_of[order[p]];
+        s.pos[s.perm[p]] = p;
+    }
+    s.Lp.assign(nn + 1, 0);
+    for (int p = 0; p < nn; ++p) {
+        std::vector<int32_t> sp;
+        for (int32_t v : hi[order[p]]) sp.push_back(pos_of_node[v]);
+        std::sort(sp.begin(), sp.end());
+        s.Li.insert(s.Li.end(), sp.begin(), sp.end());
+        s.Lp[p + 1] = (int32_t)s.Li.size();
+    }
+    hi.clear();
+    const int64_t nnzl = (int64_t)s.Li.size();
+
+    // elimination tree and levels (level = 1 + highest child level)
+    s.parent.assign(nn, -1);
+    s.level.assign(nn, 1);
+    for (int p = 0; p < nn; ++p) {
+        if (s.Lp[p + 1] > s.Lp[p]) s.parent[p] = s.Li[s.Lp[p]];
+        if (s.parent[p] >= 0)
+            s.level[s.parent[p]] = std::max(s.level[s.parent[p]], s.level[p] + 1);
+    }
+    int nlev = 0;
+    for (int p = 0; p < nn; ++p) nlev = std::max(nlev, s.level[p]);
+    s.level_ptr.assign(nlev + 1, 0);
+    for (int p = 0; p < nn; ++p) s.level_ptr[s.level[p]]++;
+    for (int l = 0; l < nlev; ++l) s.level_ptr[l + 1] += s.level_ptr[l];
+    s.level_nodes.assign(nn, 0);
+    {
+        std::vector<int32_t> cur(s.level_ptr.begin(), s.level_ptr.end() - 1);
+        for (int p = 0; p < nn; ++p) s.level_nodes[cur[s.level[p] - 1]++] = p;
+    }
+    s.max_width = 0;
+    for (int l = 0; l < nlev; ++l)
+        s.max_width = std::max(s.max_width, s.level_ptr[l + 1] - s.level_ptr[l]);
+
+    // admittance entries of every block
+    s.ydiag.resize(nn);
+    s.ylo.resize(nnzl);
+    s.yup.resize(nnzl);
+    for (int p = 0; p < nn; ++p) {
+        int bp = s.perm[p];
+        s.ydiag[p] = yfind(bp, bp);
+        for (int q = s.Lp[p]; q < s.Lp[p + 1]; ++q) {
+            int bk = s.perm[s.Li[q]];
+            s.ylo[q] = yfind(bk, bp);
+            s.yup[q] = yfind(bp, bk);
+        }
+    }
+
+    // lower neighbours R(p) with the slot of p inside S(i), ascending i
+    s.Rp.assign(nn + 1, 0);
+    for (int64_t q = 0; q < nnzl; ++q) s.Rp[s.Li[q] + 1]++;
+    for (int p = 0; p < nn; ++p) s.Rp[p + 1] += s.Rp[p];
+    s.Ri.resize(nnzl);
+    s.Rs.resize(nnzl);
+    {
+        std::vector<int32_t> cur(s.Rp.begin(), s.Rp.end() - 1);
+        for (int i = 0; i < nn; ++i)
+            for (int q = s.Lp[i]; q < s.Lp[i + 1]; ++q) {
+                int k = s.Li[q];
+                s.Ri[cur[k]] = i;
+                s.Rs[cur[k]] = q;
+                cur[k]++;
+            }
+    }
+
+    // update pairs per destination slot.  For node j and descendant i with
+    // b = slot(i;j), every k after j in S(i) is also in S(j) (the higher
+    // neighbours of a node form a clique in the filled graph); the block
+    // pair at a = slot(i;k) updates destination slot(j;k).
+    s.Up.assign(nnzl + 1, 0);
+    for (int pass = 0; pass < 2; ++pass) {
+        std::vector<int32_t> cur;
+        if (pass == 1) {
+            for (int64_t q = 0; q < nnzl; ++q) s.Up[q + 1] += s.Up[q];
+            s.Ua.resize(s.Up[nnzl]);
+            s.Ub.resize(s.Up[nnzl]);
+            cur.assign(s.Up.begin(), s.Up.end() - 1);
+        }
+        for (int j = 0; j < nn; ++j) {
+            for (int r = s.Rp[j]; r < s.Rp[j + 1]; ++r) {
+                int i = s.Ri[r], b = s.Rs[r];
+                int d = s.Lp[j];
+                for (int a = b + 1; a < s.Lp[i + 1]; ++a) {
+                    int k = s.Li[a];
+                    while (d < s.Lp[j + 1] && s.Li[d] < k) ++d;
+                    if (d >= s.Lp[j + 1] || s.Li[d] != k) {
+                        msg = "pf_analyze: internal error, filled pattern is not closed";
+                        return PF_E_INVALID;
+                    }
+                    if (pass == 0) {
+                        s.Up[d + 1]++;
+                    } else {
+                        s.Ua[cur[d]] = a;
+                        s.Ub[cur[d]] = b;
+                        cur[d]++;
+                    }
+                }
+            }
+        }
+    }
+    default_mapping(s);
+    return PF_OK;
+}
+
+// Lanes per node: enough lanes for the widest per-node loop of the level
+// (its destinations, a quarter of its descendants), but no more than keeps
+// one pass over the level within a 256-thread workgroup.
+void default_mapping(HostSym& s)
+{
+    const int threads = 256;
+    int nlev = (int)s.level_ptr.size() - 1;
+    s.level_g.assign(std::max(nlev, 1), 1);
+    for (int l = 0; l < nlev; ++l) {
+        int w = s.level_ptr[l + 1] - s.level_ptr[l];
+        int need = 1;
+        for (int x = s.level_ptr[l]; x < s.level_ptr[l + 1]; ++x) {
+            int p = s.level_nodes[x];
+            int ns = s.Lp[p + 1] - s.Lp[p];
+            int nr = (s.Rp[p + 1] - s.Rp[p] + 3) / 4;
+            need = std::max(need, std::max(ns, nr));
+        }
+        int g = 1;
+        while (g < need && g < 64) g <<= 1;
+        int fit = 1;
+        while (fit * 2 * w <= threads && fit < 64) fit <<= 1;
+        s.level_g[l] = std::max(1, std::min(g, fit));
+    }
+}
+
+}  // namespace pf

@@ -1,0 +1,155 @@
+"""CPU tests of libpf: the library loads and exports every symbol of
+include/pf.h; its host analysis is bit-exact with the oracle's; argument and
+topology errors come back as status codes without touching a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import gridgen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1811_02512_amd import binding
+
+    return binding
+
+
+def header_symbols():
+    src = open(os.path.join(ROOT, "include", "pf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pf_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_exports_every_header_symbol(B):
+    syms = header_symbols()
+    assert len(syms) >= 20
+    lib = ctypes.CDLL(B.LIB_PATH)
+    missing = [s for s in syms if not hasattr(lib, s)]
+    assert not missing, missing
+    assert B.lib.pf_version().decode().startswith("libpf")
+    assert B.lib.pf_status_string(5).decode() == "zero pivot"
+
+
+@pytest.mark.parametrize("n,seed,ordering", [(30, 2, 0), (200, 1, 0), (200, 1, 1), (2000, 1, 0),
+                                             (2000, 3, 1), (10000, 1, 0)])
+def test_analysis_bit_exact_with_oracle(B, oracle, n, seed, ordering):
+    g = gridgen.make_grid(n, seed)
+    h = B.pf_analyze(g.n, g.f, g.t, 0, ordering)
+    try:
+        ex = B.pf_symbolic_export(h)
+        s = oracle.Sym(g.n, g.f, g.t, 0, ordering)
+        for k in ("perm", "parent", "level", "level_ptr", "level_nodes", "Lp", "Li"):
+            np.testing.assert_array_equal(ex[k], getattr(s, k), err_msg=k)
+        info = B.pf_symbolic_info(h)
+        assert info.nn == n - 1 and info.nnz_l == s.nnzL and info.nlevels == s.nlev
+        assert info.vals_doubles == 4 * info.nn + 8 * info.nnz_l
+        yptr, ycol = B.pf_symbolic_ybus_pattern(h)
+        Y = oracle.grid_ybus(g)
+        np.testing.assert_array_equal(yptr, Y.rowptr)
+        np.testing.assert_array_equal(ycol, Y.col)
+    finally:
+        B.pf_symbolic_destroy(h)
+
+
+def test_analysis_n1_outages_bit_exact(B, oracle):
+    g = gridgen.make_grid(500, 5)
+    for e in gridgen.n1_outages(g, 6, seed=3):
+        gg = g.without_branch(int(e))
+        h = B.pf_analyze(gg.n, gg.f, gg.t)
+        ex = B.pf_symbolic_export(h)
+        s = oracle.Sym(gg.n, gg.f, gg.t)
+        for k in ("perm", "parent", "level_ptr", "level_nodes", "Lp", "Li"):
+            np.testing.assert_array_equal(ex[k], getattr(s, k))
+        B.pf_symbolic_destroy(h)
+
+
+def test_parallel_branches_and_forest(B, oracle):
+    f = np.array([0, 0, 1, 0, 3, 3], np.int32)
+    t = np.array([1, 1, 2, 3, 4, 4], np.int32)
+    h = B.pf_analyze(5, f, t)
+    ex = B.pf_symbolic_export(h)
+    s = oracle.Sym(5, f, t)
+    np.testing.assert_array_equal(ex["parent"], s.parent)
+    assert int(np.sum(ex["parent"] == -1)) == 2
+    yptr, ycol = B.pf_symbolic_ybus_pattern(h)
+    assert yptr[-1] == 5 + 2 * 4  # diagonal + 4 distinct neighbour pairs
+    B.pf_symbolic_destroy(h)
+
+
+def test_table1_levels_through_libpf(B):
+    parent = {1: 3, 2: 3, 4: 5, 3: 7, 5: 7, 6: 7, 7: 8, 8: 9, 9: 10}
+    f = np.array(list(parent), np.int32)
+    t = np.array(list(parent.values()), np.int32)
+    # the analysis requires every bus to reach the slack: hang bus 10 on it
+    f = np.append(f, 10).astype(np.int32)
+    t = np.append(t, 0).astype(np.int32)
+    h = B.pf_analyze(11, f, t, 0, B.PF_ORDER_NATURAL)
+    ex = B.pf_symbolic_export(h)
+    lp, ln = ex["level_ptr"], ex["level_nodes"]
+    got = [sorted(int(ex["perm"][v]) for v in ln[lp[l]:lp[l + 1]]) for l in range(len(lp) - 1)]
+    assert got == [[1, 2, 4, 6], [3, 5], [7], [8], [9], [10]]
+    B.pf_symbolic_destroy(h)
+
+
+@pytest.mark.parametrize("n,f,t,slack,code", [
+    (1, [], [], 0, 1),
+    (3, [0, 1], [1, 1], 0, 1),
+    (3, [0, 1], [1, 5], 0, 1),
+    (3, [0, -1], [1, 2], 0, 1),
+    (3, [0, 1], [1, 2], 3, 1),
+    (4, [0, 1], [1, 2], 0, 4),
+    (4, [2], [3], 0, 4),
+])
+def test_analysis_errors(B, n, f, t, slack, code):
+    with pytest.raises(B.PfError) as ei:
+        B.pf_analyze(n, np.array(f, np.int32), np.array(t, np.int32), slack)
+    assert ei.value.code == code
+    assert B.last_error()
+
+
+def test_device_calls_need_upload(B):
+    g = gridgen.make_grid(20, 1)
+    h = B.pf_analyze(g.n, g.f, g.t)
+    buf = np.zeros(8)
+    with pytest.raises(B.PfError) as ei:
+        B.check(B.lib.pf_factor(h, 1, buf.ctypes.data, 0, None, None), "pf_factor")
+    assert ei.value.code == B.PF_E_INVALID
+    assert "not uploaded" in B.last_error()
+    with pytest.raises(B.PfError):
+        B.check(B.lib.pf_newton(None, 1, *([None, 0] * 2), None, None, 0, None, None, 0, 1e-8,
+                                20, 0, None, 0, None, None, None, None), "pf_newton")
+    B.pf_symbolic_destroy(h)
+
+
+def test_mapping_roundtrip_and_validation(B):
+    g = gridgen.make_grid(300, 2)
+    h = B.pf_analyze(g.n, g.f, g.t)
+    m = B.pf_symbolic_get_mapping(h)
+    assert set(np.unique(m)) <= {1, 2, 4, 8, 16, 32, 64}
+    B.pf_symbolic_set_mapping(h, np.full_like(m, 8))
+    assert (B.pf_symbolic_get_mapping(h) == 8).all()
+    with pytest.raises(B.PfError):
+        B.pf_symbolic_set_mapping(h, np.full_like(m, 3))
+    B.pf_symbolic_destroy(h)
+
+
+def test_multi_plan_offsets(B):
+    gs = [gridgen.make_grid(n, s) for n, s in [(40, 1), (90, 2), (25, 3)]]
+    hs = [B.pf_analyze(g.n, g.f, g.t) for g in gs]
+    p = B.pf_multi_create(hs)
+    nbytes, offs = B.pf_multi_info(p, 3)
+    assert nbytes > 0
+    assert offs["bus"].tolist() == [0, 40, 130, 155]
+    assert offs["branch"].tolist() == [0, gs[0].m, gs[0].m + gs[1].m, sum(g.m for g in gs)]
+    infos = [B.pf_symbolic_info(h) for h in hs]
+    assert np.diff(offs["ws"]).tolist() == [i.ws_doubles for i in infos]
+    assert np.diff(offs["y"]).tolist() == [2 * i.nnz_y for i in infos]
+    B.pf_multi_destroy(p)
+    for h in hs:
+        B.pf_symbolic_destroy(h)
