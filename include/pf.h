@@ -200,6 +200,15 @@ int pf_newton(const pf_symbolic sym, int B, const double* d_yval, int64_t y_stri
               int64_t ws_stride, int32_t* d_iters, double* d_norm, int32_t* d_status,
               void* stream);
 
+/* ---- adjoint right-hand side (beyond the paper) ----------------------------
+ * Gathers the loss gradient with respect to the state into position order:
+ * d_rhs[b][p] = (dL/dtheta, dL/d|V|) of bus perm[p], with the |V| entry set
+ * to zero at PV buses (|V| is fixed there).  d_gVm, d_gVa: double[B][n]
+ * (v_stride); d_rhs: out double[B][nn][2] (rhs_stride).                    */
+int pf_adjoint_rhs(const pf_symbolic sym, int B, const double* d_gVm, const double* d_gVa,
+                   int64_t v_stride, const int8_t* d_type, int64_t type_stride, double* d_rhs,
+                   int64_t rhs_stride, void* stream);
+
 /* ---- adjoint parameter gradients (beyond the paper) ------------------------
  * Given lam = J^-T g at the solution (pf_solve with transpose = 1 on the
  * factors kept by pf_newton), writes dL/dPsp = lam_P at non-slack buses,

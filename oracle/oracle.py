@@ -86,6 +86,12 @@ def lib():
                                        f64p, f64p, i8p, f64p, f64p, f64p, f64p, f64p, f64p,
                                        f64p]
         L.or_adjoint_dense.restype = C.c_int
+        L.or_solve_transpose.argtypes = [C.c_void_p, f64p, f64p, f64p, f64p]
+        L.or_solve_transpose.restype = C.c_int
+        L.or_adjoint_sparse.argtypes = [C.c_void_p, C.c_int, i32p, i32p, f64p, f64p, i32p, i32p,
+                                        f64p, f64p, i8p, f64p, f64p, f64p, f64p, f64p, f64p,
+                                        f64p]
+        L.or_adjoint_sparse.restype = C.c_int
         _lib = L
     return _lib
 
@@ -254,6 +260,33 @@ class Sym:
         if lib().or_solve(self._h, D, L, U, x) != 0:
             raise np.linalg.LinAlgError("singular pivot")
         return x.reshape(-1, 2)
+
+    def solve_transpose(self, D, L, U, rhs):
+        D = _f64(D).reshape(-1)
+        L = _f64(L).reshape(-1)
+        U = _f64(U).reshape(-1)
+        if L.size == 0:
+            L = np.zeros(4)
+            U = np.zeros(4)
+        x = np.array(rhs, np.float64).reshape(-1).copy()
+        if lib().or_solve_transpose(self._h, D, L, U, x) != 0:
+            raise np.linalg.LinAlgError("singular pivot")
+        return x.reshape(-1, 2)
+
+    def adjoint(self, grid, Y: Ybus, Vm, Va, gVm, gVa, x=None):
+        """Sparse adjoint at a converged state: returns (gP, gQ, gx)."""
+        n, m = grid.n, grid.m
+        xx = grid.x if x is None else x
+        gP = np.zeros(n)
+        gQ = np.zeros(n)
+        gx = np.zeros(max(m, 1))
+        st = lib().or_adjoint_sparse(self._h, m, _i32(grid.f), _i32(grid.t), _f64(grid.r),
+                                     _f64(xx), Y.rowptr, Y.col, Y.G, Y.B,
+                                     np.ascontiguousarray(grid.bus_type, np.int8), _f64(Vm),
+                                     _f64(Va), _f64(gVm), _f64(gVa), gP, gQ, gx)
+        if st != 0:
+            raise np.linalg.LinAlgError("zero pivot")
+        return gP, gQ, gx[:m]
 
     def newton(self, Y: Ybus, bus_type, Psp, Qsp, Vm0, Va0, tol=1e-8, max_iter=20) -> NRResult:
         Vm = _f64(Vm0).copy()

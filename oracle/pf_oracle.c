@@ -842,14 +842,40 @@ int or_newton_sparse(const or_sym* s, const int32_t* rowptr, const int32_t* col,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Dense adjoint of the converged solution (beyond the paper).               */
-/* Loss gradients gVm, gVa (length n; slack entries and PV |V| entries are   */
-/* ignored since those values are fixed).  With J the reduced dense          */
-/* Jacobian at the solution, solve J^T lam = g.  Since F(x, p) = 0 defines   */
-/* x(p):  dL/dPsp_i = lam_P,i (non-slack), dL/dQsp_i = lam_Q,i (PQ), and     */
-/* dL/dx_e = -sum_i lam_i . d(P_i, Q_i)/dx_e with dy_e/dx_e = -j y_e^2.      */
-/* Outputs gP, gQ (n) and gx (m).  Returns 0 or 5 (singular).                */
+/* Adjoint of the converged solution (beyond the paper).                     */
+/* F(x, p) = 0 defines the state x(p), so with J^T lam = g (g = dL/dx):       */
+/*   dL/dPsp_i = lam_P,i (non-slack), dL/dQsp_i = lam_Q,i (PQ),              */
+/*   dL/dx_e   = -sum_i lam_i . d(P_i, Q_i)/dx_e, dy_e/dx_e = -j y_e^2.       */
+/* lamP/lamQ are per bus (zero where absent).                                */
 /* ------------------------------------------------------------------------ */
+static void adjoint_param_grads(int n, int m, const int32_t* f, const int32_t* t,
+                                const double* r, const double* x, const double* Vm,
+                                const double* Va, const double* lamP, const double* lamQ,
+                                double* gP, double* gQ, double* gx)
+{
+    for (int i = 0; i < n; ++i) {
+        gP[i] = lamP[i];
+        gQ[i] = lamQ[i];
+    }
+    for (int e = 0; e < m; ++e) {
+        int a = f[e], b = t[e];
+        double complex z = r[e] + I * x[e];
+        double complex y = 1.0 / z;
+        double complex dy = -I * y * y;
+        double complex Va_ = Vm[a] * cexp(I * Va[a]);
+        double complex Vb_ = Vm[b] * cexp(I * Va[b]);
+        double complex dSa = Va_ * conj(dy * (Va_ - Vb_));
+        double complex dSb = Vb_ * conj(dy * (Vb_ - Va_));
+        double acc = 0.0;
+        acc += lamP[a] * creal(dSa) + lamQ[a] * cimag(dSa);
+        acc += lamP[b] * creal(dSb) + lamQ[b] * cimag(dSb);
+        gx[e] = -acc;
+    }
+}
+
+/* Dense: J^T lam = g by Gaussian elimination on the reduced dense J.        */
+/* gVm, gVa: loss gradients per bus (slack and PV |V| entries ignored).      */
+/* Returns 0 or 5 (singular).                                                */
 int or_adjoint_dense(int n, int m, const int32_t* f, const int32_t* t, const double* r,
                      const double* x, const int32_t* rowptr, const int32_t* col,
                      const double* G, const double* B, const int8_t* type,
@@ -861,8 +887,10 @@ int or_adjoint_dense(int n, int m, const int32_t* f, const int32_t* t, const dou
     int na, nv;
     dense_index(n, type, ia, iv, &na, &nv);
     int N = na + nv;
-    double* P = (double*)malloc(sizeof(double) * 2 * (size_t)n);
+    double* P = (double*)malloc(sizeof(double) * 4 * (size_t)n);
     double* Q = P + n;
+    double* lP = P + 2 * n;
+    double* lQ = P + 3 * n;
     or_injections(n, rowptr, col, G, B, Vm, Va, P, Q);
     double* J = (double*)malloc(sizeof(double) * (size_t)N * (size_t)N + 8);
     double* JT = (double*)malloc(sizeof(double) * (size_t)N * (size_t)N + 8);
@@ -876,28 +904,98 @@ int or_adjoint_dense(int n, int m, const int32_t* f, const int32_t* t, const dou
     }
     int st = or_dense_solve(N, JT, lam) ? 5 : 0;
     for (int i = 0; i < n; ++i) {
-        gP[i] = (st == 0 && ia[i] >= 0) ? lam[ia[i]] : 0.0;
-        gQ[i] = (st == 0 && iv[i] >= 0) ? lam[iv[i]] : 0.0;
+        lP[i] = (st == 0 && ia[i] >= 0) ? lam[ia[i]] : 0.0;
+        lQ[i] = (st == 0 && iv[i] >= 0) ? lam[iv[i]] : 0.0;
     }
-    for (int e = 0; e < m; ++e) {
-        int a = f[e], b = t[e];
-        double complex z = r[e] + I * x[e];
-        double complex y = 1.0 / z;
-        double complex dy = -I * y * y;
-        double complex Va_ = Vm[a] * cexp(I * Va[a]);
-        double complex Vb_ = Vm[b] * cexp(I * Va[b]);
-        double complex dSa = Va_ * conj(dy * (Va_ - Vb_));
-        double complex dSb = Vb_ * conj(dy * (Vb_ - Va_));
-        double acc = 0.0;
-        acc += gP[a] * creal(dSa) + gQ[a] * cimag(dSa);
-        acc += gP[b] * creal(dSb) + gQ[b] * cimag(dSb);
-        gx[e] = (st == 0) ? -acc : 0.0;
-    }
+    adjoint_param_grads(n, m, f, t, r, x, Vm, Va, lP, lQ, gP, gQ, gx);
     free(ia);
     free(iv);
     free(P);
     free(J);
     free(JT);
     free(lam);
+    return st;
+}
+
+/* Transposed solve with the paper-path factors, A^T x = rhs, A = L D U:     */
+/*   U^T p = rhs over partitions 1..p: p_i = rhs_i - sum_{j<i} U_ji^T p_j;   */
+/*   normalisation q_i = D_i^-T p_i;                                         */
+/*   L^T x = q over partitions p..1:   x_i = q_i - sum_{k>i} L_ki^T x_k.     */
+int or_solve_transpose(const or_sym* s, const double* D, const double* Lb, const double* Ub,
+                       double* rhs)
+{
+    double Dinv[4];
+    for (int l = 0; l < s->nlev; ++l)
+        for (int x = s->level_ptr[l]; x < s->level_ptr[l + 1]; ++x) {
+            int i = s->level_nodes[x];
+            for (int r = s->Rp[i]; r < s->Rp[i + 1]; ++r) {
+                const double* U = Ub + 4 * (size_t)s->Rslot[r];
+                const double* pj = rhs + 2 * (size_t)s->Ri[r];
+                rhs[2 * i] -= U[0] * pj[0] + U[2] * pj[1];
+                rhs[2 * i + 1] -= U[1] * pj[0] + U[3] * pj[1];
+            }
+        }
+    for (int i = 0; i < s->nn; ++i) {
+        if (b_inv(D + 4 * (size_t)i, Dinv)) return -1;
+        double p0 = rhs[2 * i], p1 = rhs[2 * i + 1];
+        rhs[2 * i] = Dinv[0] * p0 + Dinv[2] * p1;
+        rhs[2 * i + 1] = Dinv[1] * p0 + Dinv[3] * p1;
+    }
+    for (int l = s->nlev - 1; l >= 0; --l)
+        for (int x = s->level_ptr[l]; x < s->level_ptr[l + 1]; ++x) {
+            int i = s->level_nodes[x];
+            for (int q = s->Lp[i]; q < s->Lp[i + 1]; ++q) {
+                const double* L = Lb + 4 * (size_t)q;
+                const double* xk = rhs + 2 * (size_t)s->Li[q];
+                rhs[2 * i] -= L[0] * xk[0] + L[2] * xk[1];
+                rhs[2 * i + 1] -= L[1] * xk[0] + L[3] * xk[1];
+            }
+        }
+    return 0;
+}
+
+/* Sparse adjoint along the paper's path: block Jacobian at the state in the */
+/* filled layout, FactorizeGraphA, then the transposed solve.  The rhs of    */
+/* position p is (dL/dtheta, dL/d|V|) of its bus, with d|V| zero at PV       */
+/* buses (|V| fixed there).  Returns 0, or 5 on a zero pivot.                */
+int or_adjoint_sparse(const or_sym* s, int m, const int32_t* f, const int32_t* t,
+                      const double* r, const double* x, const int32_t* rowptr,
+                      const int32_t* col, const double* G, const double* B,
+                      const int8_t* type, const double* Vm, const double* Va,
+                      const double* gVm, const double* gVa, double* gP, double* gQ,
+                      double* gx)
+{
+    int n = s->n, nn = s->nn;
+    double* P = (double*)malloc(sizeof(double) * 4 * (size_t)n);
+    double *Q = P + n, *lP = P + 2 * n, *lQ = P + 3 * n;
+    double* D = (double*)malloc(sizeof(double) * 4 * ((size_t)nn + 1));
+    double* Lb = (double*)malloc(sizeof(double) * 4 * ((size_t)s->nnzL + 1));
+    double* Ub = (double*)malloc(sizeof(double) * 4 * ((size_t)s->nnzL + 1));
+    double* rhs = (double*)malloc(sizeof(double) * 2 * ((size_t)nn + 1));
+    or_injections(n, rowptr, col, G, B, Vm, Va, P, Q);
+    or_block_jacobian(s, rowptr, col, G, B, type, Vm, Va, P, Q, D, Lb, Ub);
+    int st = 0;
+    if (or_factor(s, D, Lb, Ub) >= 0) st = 5;
+    for (int ni = 0; ni < nn; ++ni) {
+        int p = s->iperm[ni], bus = s->bus_of[ni];
+        rhs[2 * p] = gVa[bus];
+        rhs[2 * p + 1] = (type[bus] == OR_PV) ? 0.0 : gVm[bus];
+    }
+    if (st == 0 && or_solve_transpose(s, D, Lb, Ub, rhs)) st = 5;
+    for (int i = 0; i < n; ++i) {
+        lP[i] = 0.0;
+        lQ[i] = 0.0;
+    }
+    for (int ni = 0; ni < nn && st == 0; ++ni) {
+        int p = s->iperm[ni], bus = s->bus_of[ni];
+        lP[bus] = rhs[2 * p];
+        lQ[bus] = (type[bus] == OR_PV) ? 0.0 : rhs[2 * p + 1];
+    }
+    adjoint_param_grads(n, m, f, t, r, x, Vm, Va, lP, lQ, gP, gQ, gx);
+    free(P);
+    free(D);
+    free(Lb);
+    free(Ub);
+    free(rhs);
     return st;
 }

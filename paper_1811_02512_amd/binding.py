@@ -64,6 +64,7 @@ _SIGS = {
                    _vp, _i64, _vp, _vp, _vp, _vp], _i),
     "pf_adjoint_params": ([_vp, _i, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _vp,
                            _vp, _i64, _vp, _i, _vp], _i),
+    "pf_adjoint_rhs": ([_vp, _i, _vp, _vp, _i64, _vp, _i64, _vp, _i64, _vp], _i),
     "pf_multi_create": ([_i, _vp, C.POINTER(_vp)], _i),
     "pf_multi_info": ([_vp, C.POINTER(C.c_size_t), _vp, _vp, _vp, _vp], _i),
     "pf_multi_upload": ([_vp, _vp, C.c_size_t, _vp], _i),
@@ -210,6 +211,12 @@ def pf_adjoint_params(h, B, lam, lam_stride, bus_type, type_stride, Vm, Va, v_st
                                 ptr(Vm), ptr(Va), v_stride, ptr(r), ptr(x), branch_stride,
                                 ptr(gP), ptr(gQ), g_stride, ptr(gx), int(gx_mode),
                                 stream_ptr(stream)), "pf_adjoint_params")
+
+
+def pf_adjoint_rhs(h, B, gVm, gVa, v_stride, bus_type, type_stride, rhs, rhs_stride,
+                   stream=None):
+    check(lib.pf_adjoint_rhs(h, B, ptr(gVm), ptr(gVa), v_stride, ptr(bus_type), type_stride,
+                             ptr(rhs), rhs_stride, stream_ptr(stream)), "pf_adjoint_rhs")
 
 
 def pf_multi_create(handles):

@@ -639,6 +639,19 @@ __global__ __launch_bounds__(kMaxThreads) void k_newton(DevSym Sarg,
     }
 }
 
+__global__ void k_adj_rhs(DevSym S, const double* gVm, const double* gVa, int64_t v_stride,
+                          const int8_t* type, int64_t type_stride, double* rhs,
+                          int64_t rhs_stride)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (p >= S.nn) return;
+    const int bus = S.perm[p];
+    const double ga = gVa[c * v_stride + bus];
+    const double gm = (type[c * type_stride + bus] == T_PV) ? 0.0 : gVm[c * v_stride + bus];
+    reinterpret_cast<double2*>(rhs + c * rhs_stride)[p] = make_double2(ga, gm);
+}
+
 __global__ void k_adj_bus(DevSym S, const double* lam, int64_t lam_stride, const int8_t* type,
                           int64_t type_stride, double* gP, double* gQ, int64_t g_stride)
 {
@@ -1077,6 +1090,22 @@ int pf_adjoint_params(const pf_symbolic s, int B, const double* d_lam, int64_t l
         return launch_check("pf_adjoint_params");
     }
     return PF_OK;
+}
+
+int pf_adjoint_rhs(const pf_symbolic s, int B, const double* d_gVm, const double* d_gVa,
+                   int64_t v_stride, const int8_t* d_type, int64_t type_stride, double* d_rhs,
+                   int64_t rhs_stride, void* stream)
+{
+    if (!ready(s, "pf_adjoint_rhs")) return PF_E_INVALID;
+    if (B < 0 || B > 65535 || !d_gVm || !d_gVa || !d_type || !d_rhs)
+        return fail(PF_E_INVALID, "pf_adjoint_rhs: bad arguments");
+    if (B > 1 && rhs_stride < 2 * (int64_t)s->h.nn)
+        return fail(PF_E_WORKSPACE, "pf_adjoint_rhs: rhs_stride < 2*nn");
+    if (B == 0) return PF_OK;
+    dim3 grid((s->h.nn + 255) / 256, B);
+    hipLaunchKernelGGL(k_adj_rhs, grid, dim3(256), 0, as_stream(stream), s->h.dev, d_gVm,
+                       d_gVa, v_stride, d_type, type_stride, d_rhs, rhs_stride);
+    return launch_check("pf_adjoint_rhs");
 }
 
 // ---- multi-pattern batches -----------------------------------------------

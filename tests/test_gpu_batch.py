@@ -1,0 +1,107 @@
+"""Batches whose cases carry their own sparsity (N-1 outages, mixed grid sizes),
+solved in one launch, against the oracle case by case."""
+import numpy as np
+import pytest
+
+import gridgen
+from gpu_helpers import Staged, dev, grid, log
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _needs_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def solve_multi(grids, tol=1e-8, max_iter=20):
+    from paper_1811_02512_amd import api
+    from paper_1811_02512_amd import binding as B
+
+    syms = [api.Symbolic(g.n, g.f, g.t).upload() for g in grids]
+    plan = api.MultiPlan(syms)
+    f64 = np.float64
+    r = plan.concat([g.r for g in grids], "branch", f64)
+    x = plan.concat([g.x for g in grids], "branch", f64)
+    b = plan.concat([g.b for g in grids], "branch", f64)
+    yv = torch.empty(int(plan.offs["y"][-1]) + 2, dtype=torch.float64, device="cuda")
+    B.pf_build_ybus_multi(plan.p, r, x, b, yv)
+    ty = plan.concat([g.bus_type for g in grids], "bus", np.int8)
+    P = plan.concat([g.Psp for g in grids], "bus", f64)
+    Q = plan.concat([g.Qsp for g in grids], "bus", f64)
+    Vm = plan.concat([g.flat_start()[0] for g in grids], "bus", f64)
+    Va = plan.concat([g.flat_start()[1] for g in grids], "bus", f64)
+    ws = torch.empty(int(plan.offs["ws"][-1]) + 32, dtype=torch.float64, device="cuda")
+    G = len(grids)
+    it = torch.full((G,), -1, dtype=torch.int32, device="cuda")
+    nrm = torch.empty(G, dtype=torch.float64, device="cuda")
+    st = torch.full((G,), -1, dtype=torch.int32, device="cuda")
+    B.pf_newton_multi(plan.p, yv, ty, P, Q, Vm, Va, tol, max_iter, 0, ws, it, nrm, st)
+    torch.cuda.synchronize()
+    return (plan.split(Vm, "bus"), plan.split(Va, "bus"), it.cpu().numpy(), st.cpu().numpy(),
+            plan)
+
+
+def check_against_oracle(grids, Vms, Vas, it, st):
+    from oracle import oracle as O
+
+    for c, g in enumerate(grids):
+        ref = O.solve_grid(g)
+        assert ref.status == 0
+        assert st[c] == 0, (c, st[c])
+        assert it[c] == ref.iters, (c, it[c], ref.iters)
+        np.testing.assert_allclose(Vms[c], ref.Vm, atol=1e-9)
+        np.testing.assert_allclose(Vas[c], ref.Va, atol=1e-9)
+
+
+def test_n1_outages_reanalysed():
+    g = grid(2000, 1)
+    outs = gridgen.n1_outages(g, 10, seed=3)
+    log(f"[n1] outages {outs.tolist()}")
+    grids = [g.without_branch(int(e)) for e in outs]
+    Vms, Vas, it, st, _ = solve_multi(grids)
+    check_against_oracle(grids, Vms, Vas, it, st)
+
+
+def test_n1_equals_superset_pattern_with_zero_admittance():
+    """An outage solved on its own pattern equals the base pattern with the
+    branch's admittance driven to ~0 (x = 1e150) and no charging."""
+    g = grid(500, 2)
+    e = int(gridgen.n1_outages(g, 1, seed=7)[0])
+    gg = g.without_branch(e)
+    Vms, Vas, it, st, _ = solve_multi([gg])
+    open_ = g.without_branch(e)  # same physics, different pattern source
+    assert open_.m == g.m - 1
+    x = g.x.copy()
+    x[e] = 1e150
+    bb = g.b.copy()
+    bb[e] = 0.0
+    import dataclasses
+
+    s = Staged(dataclasses.replace(g, x=x, b=bb))
+    Vm, Va, it2, _, st2, _ = s.newton()
+    assert st[0] == 0 and st2.item() == 0
+    np.testing.assert_allclose(Vm[0].cpu().numpy(), Vms[0], atol=1e-9)
+    np.testing.assert_allclose(Va[0].cpu().numpy(), Vas[0], atol=1e-9)
+
+
+def test_mixed_grid_sizes_one_launch():
+    sizes = [int(n) for n in gridgen.mixed_sizes(64, 4)[:7]]
+    sizes = [min(n, 6000) for n in sizes]
+    log(f"[mixed] sizes {sizes}")
+    grids = [gridgen.make_grid(n, 1000 + i, load_scale=0.05) for i, n in enumerate(sizes)]
+    Vms, Vas, it, st, plan = solve_multi(grids)
+    check_against_oracle(grids, Vms, Vas, it, st)
+
+
+def test_multi_matches_shared_pattern_path():
+    """The per-case-pattern kernel and the shared-pattern kernel agree bitwise."""
+    g = grid(800, 3)
+    Vms, Vas, it, st, _ = solve_multi([g, g])
+    s = Staged(g)
+    Vm, Va, it2, _, _, _ = s.newton()
+    np.testing.assert_array_equal(Vms[0], Vm[0].cpu().numpy())
+    np.testing.assert_array_equal(Vms[1], Vm[0].cpu().numpy())
+    np.testing.assert_array_equal(Vas[0], Va[0].cpu().numpy())

@@ -591,3 +591,31 @@ def test_adjoint_two_bus_closed_form(oracle):
     assert gx[0] == pytest.approx(dvm_dx, rel=1e-7)
     gP, gQ, gx = oracle.adjoint_dense(g, Y, res.Vm, res.Va, np.zeros(2), np.array([0.0, 1.0]))
     assert gQ[1] == pytest.approx(-dth_dQ, rel=1e-7)
+
+
+def test_sparse_adjoint_equals_dense_adjoint(oracle):
+    for n, seed in [(60, 2), (250, 8)]:
+        g = gridgen.make_grid(n, seed)
+        Y = oracle.grid_ybus(g)
+        res = oracle.solve_grid(g)
+        rng = np.random.default_rng(seed)
+        gVm = rng.standard_normal(n)
+        gVa = rng.standard_normal(n)
+        d = oracle.adjoint_dense(g, Y, res.Vm, res.Va, gVm, gVa)
+        s = oracle.Sym(g.n, g.f, g.t).adjoint(g, Y, res.Vm, res.Va, gVm, gVa)
+        for a, b in zip(d, s):
+            np.testing.assert_allclose(b, a, rtol=0, atol=1e-11 * np.abs(a).max())
+
+
+def test_transpose_solve_matches_lapack(oracle):
+    g = gridgen.make_grid(150, 6)
+    Y = oracle.grid_ybus(g)
+    sym = oracle.Sym(g.n, g.f, g.t)
+    Vm, Va = random_state(g, np.random.default_rng(4))
+    D, Lb, Ub = sym.block_jacobian(Y, g.bus_type, Vm, Va)
+    A = sym.dense_matrix(D, Lb, Ub)
+    fD, fL, fU, bad = sym.factor(D, Lb, Ub)
+    assert bad == -1
+    rhs = np.random.default_rng(1).standard_normal(2 * sym.nn)
+    x = sym.solve_transpose(fD, fL, fU, rhs).reshape(-1)
+    np.testing.assert_allclose(x, np.linalg.solve(A.T, rhs), rtol=1e-9, atol=1e-10)
