@@ -51,7 +51,8 @@ class Workload:
         self.P, self.Q = gridgen.scenario_injections(g, scen, scen_seed)
         self.w = np.random.default_rng(6).uniform(0, 1, g.n)
         t1 = time.time()
-        self.sym = api.Symbolic(g.n, g.f, g.t).upload()
+        self.sym = api.Symbolic(g.n, g.f, g.t).upload()   # tuned for the batch
+        self.sym1 = api.Symbolic(g.n, g.f, g.t).upload()  # tuned for one case per launch
         t2 = time.time()
         log(f"[bench] grid n={n} m={g.m} generated in {t1 - t0:.1f}s, analysed+uploaded in "
             f"{t2 - t1:.3f}s")
@@ -75,7 +76,7 @@ class Workload:
         self.yval = torch.empty(1, 2 * info.nnz_y, dtype=torch.float64, device=dev)
         self.Vm = torch.empty(Bn, g.n, dtype=torch.float64, device=dev)
         self.Va = torch.empty_like(self.Vm)
-        self.ws = torch.empty(Bn, info.ws_doubles, dtype=torch.float64, device=dev)
+        self.ws = self.sym.workspace(Bn)
         self.it = torch.empty(Bn, dtype=torch.int32, device=dev)
         self.nrm = torch.empty(Bn, dtype=torch.float64, device=dev)
         self.st = torch.empty(Bn, dtype=torch.int32, device=dev)
@@ -85,19 +86,37 @@ class Workload:
         self.gx = torch.empty(g.m, dtype=torch.float64, device=dev)
         self.gVa = torch.zeros_like(self.Vm)
 
+    def autotune(self, Bn, sym):
+        from paper_1811_02512_amd import autotune
+
+        g = self.g
+        V0 = self.Vm0.expand(Bn, g.n).contiguous()
+        A0 = self.Va0.expand(Bn, g.n).contiguous()
+        res = autotune.tune(sym, self.yval[0], self.type, self.Pt[:Bn].contiguous(),
+                            self.Qt[:Bn].contiguous(), V0, A0)
+        log(f"[bench] autotune B={Bn}: T={res['threads']} tail={res['tail_budget']} "
+            f"C={res['interleave']} best {res['ms']:.3f} ms, {res['launches']} launches in "
+            f"{res['seconds']:.1f}s")
+        self.info = self.sym.info
+        if sym is self.sym:
+            self.ws = self.sym.workspace(self.B)
+        return res
+
     def step(self, ev=None, adjoint=True, Bn=None):
         """One pass of the hot path.  ev: optional (start, end) events around
         the Newton kernel."""
         from paper_1811_02512_amd import binding as B
 
-        g, info = self.g, self.info
+        g = self.g
         Bn = self.B if Bn is None else Bn
-        B.pf_build_ybus(self.sym.h, 1, self.r, self.x, self.b, 0, self.yval, 2 * info.nnz_y)
+        sym = self.sym if Bn > 1 else self.sym1
+        info = sym.info
+        B.pf_build_ybus(sym.h, 1, self.r, self.x, self.b, 0, self.yval, 2 * info.nnz_y)
         self.Vm[:Bn].copy_(self.Vm0.expand(Bn, g.n))
         self.Va[:Bn].copy_(self.Va0.expand(Bn, g.n))
         if ev is not None:
             ev[0].record()
-        B.pf_newton(self.sym.h, Bn, self.yval, 0, self.type, 0, self.Pt, self.Qt, g.n, self.Vm,
+        B.pf_newton(sym.h, Bn, self.yval, 0, self.type, 0, self.Pt, self.Qt, g.n, self.Vm,
                     self.Va, g.n, 1e-8, 20, B.PF_NEWTON_KEEP_FACTORS if adjoint else 0,
                     self.ws, info.ws_doubles, self.it, self.nrm, self.st)
         if ev is not None:
@@ -105,11 +124,11 @@ class Workload:
         if not adjoint:
             return
         gVm = 2.0 * self.wt * self.pq * (self.Vm[:Bn] - 1.0)  # dLoss/d|V| of the user's loss
-        B.pf_adjoint_rhs(self.sym.h, Bn, gVm, self.gVa, g.n, self.type, 0, self.lam,
-                         2 * info.nn)
-        B.pf_solve(self.sym.h, Bn, self.ws, info.ws_doubles, self.lam, 2 * info.nn, 1)
-        B.pf_adjoint_params(self.sym.h, Bn, self.lam, 2 * info.nn, self.type, 0, self.Vm,
-                            self.Va, g.n, self.r, self.x, 0, self.gP, self.gQ, g.n, self.gx, 1)
+        B.pf_adjoint_rhs(sym.h, Bn, gVm, self.gVa, g.n, self.type, 0, self.lam, 2 * info.nn)
+        B.pf_solve(sym.h, Bn, self.ws, info.ws_doubles, self.lam, 2 * info.nn, 1,
+                   B.pf_newton_interleave(sym.h, Bn))
+        B.pf_adjoint_params(sym.h, Bn, self.lam, 2 * info.nn, self.type, 0, self.Vm, self.Va,
+                            g.n, self.r, self.x, 0, self.gP, self.gQ, g.n, self.gx, 1)
 
 
 def timed(fn, steps, warmup):
@@ -188,7 +207,7 @@ def bench_multi(grids, label, steps=3):
     A0 = plan.concat([g.flat_start()[1] for g in grids], "bus", f64)
     Vm, Va = V0.clone(), A0.clone()
     ws = torch.empty(int(plan.offs["ws"][-1]) + 32, dtype=torch.float64, device="cuda")
-    G = len(grids)
+    G = len(grids)  # per-case patterns: plain (non-interleaved) workspace regions
     it = torch.empty(G, dtype=torch.int32, device="cuda")
     st = torch.empty(G, dtype=torch.int32, device="cuda")
 
@@ -215,6 +234,7 @@ def main():
     ap.add_argument("--scenarios", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--full", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -226,6 +246,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     W = Workload(args.n, 1, args.scenarios, 5)
+    W.step(adjoint=False)  # builds the admittance values the tuner needs
+    tuned = W.autotune(W.B, W.sym) if not args.no_tune else None
+    tuned1 = W.autotune(1, W.sym1) if not args.no_tune else None
     info = W.info
 
     # --- timed steps: whole hot path ---------------------------------------------
@@ -279,6 +302,10 @@ def main():
         "plain_ms_per_solve": plain_ms,
         "adjoint_grads_per_s": W.B / ms_step * 1e3,
         "newton_kernel_ms": newton_ms,
+        "autotune": None if tuned is None else {
+            "batched": {k: tuned[k] for k in ("threads", "tail_budget", "interleave", "ms")},
+            "plain": {k: tuned1[k] for k in ("threads", "tail_budget", "interleave", "ms")},
+            "seconds": tuned["seconds"] + tuned1["seconds"]},
         "roofline": {
             "bound": "hbm",
             "achieved": achieved,

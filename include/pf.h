@@ -38,6 +38,16 @@
  *     memory; pf_symbolic_upload / pf_multi_upload copy into caller buffers.
  *   - "stride" arguments are in elements between consecutive cases; 0 means
  *     the array is shared by all cases (inputs only).
+ *   - Interleaved case groups ("interleave" C in 1, 2, 4, 8): an array of
+ *     per-case doubles with stride S (a multiple of 4) is cut into groups of
+ *     C cases; element d of case c lives at
+ *       (c / C) * C * S + (d / 4) * 4 C + 4 (c % C) + d % 4,
+ *     i.e. every 32-byte chunk (one 2x2 block) of the C cases of a group is
+ *     adjacent, so one 128-byte line carries the same block of four cases.
+ *     The buffer holds ceil(B / C) * C * S doubles.  C = 1 is the plain
+ *     [B][S] layout.  Kernels launch the C workgroups of a group 8 blocks
+ *     apart, which puts them on the same XCD of the MI355X at the same time,
+ *     so the cases of a group share each fetched line through that L2.
  *   - Every stream argument is a hipStream_t (0 = legacy default stream);
  *     work is enqueued asynchronously, so per-case numerical outcomes are
  *     reported in device status arrays, never by the return code.
@@ -90,6 +100,14 @@ typedef struct {
     int64_t vals_doubles;    /* 4*nn + 8*nnz_l: filled layout, one case     */
     int64_t ws_doubles;      /* pf_newton workspace per case (vals first)   */
     size_t dev_bytes;        /* device buffer for pf_symbolic_upload        */
+    int32_t tail_levels;     /* top levels factorised and solved in LDS     */
+    int32_t tail_nodes;
+    int32_t tail_lds_bytes;  /* dynamic LDS per workgroup for the tail      */
+    int32_t threads;         /* workgroup size, 0 = chosen per launch       */
+    int32_t tail_clique;     /* top nodes of the tail handled as a dense     */
+                             /* clique (right-looking, one barrier a pivot) */
+    int32_t ws_interleave;   /* cases per interleaved group in pf_newton's   */
+                             /* workspace (1, 2, 4 or 8)                   */
 } pf_info;
 
 /* ---- status ------------------------------------------------------------ */
@@ -124,6 +142,16 @@ int pf_symbolic_export(const pf_symbolic sym, int32_t* perm, int32_t* parent,
  * level-scheduled kernels.  Defaults come from a work model; an autotuner may
  * replace them.  Takes effect at the next pf_symbolic_upload.             */
 int pf_symbolic_set_mapping(pf_symbolic sym, const int32_t* lanes_per_level);
+/* Launch shape of the level-scheduled kernels: threads per workgroup (0 =
+ * by batch size: 1024 up to 256 cases, 512 up to 512, else 256) and the LDS
+ * budget in bytes of the tail, the largest run of top levels whose values
+ * (64 bytes per filled slot, 48 per node) are factorised and solved in LDS
+ * (0 = none, at most 161792 so that 2 KB of LDS stay for reductions;
+ * default 65536).  A new budget rebuilds the
+ * tail and requires pf_symbolic_upload again.  interleave (1, 2, 4, 8;
+ * default 4) is the case grouping of pf_newton's workspace.               */
+int pf_symbolic_set_launch(pf_symbolic sym, int threads, int64_t tail_lds_budget,
+                           int interleave);
 int pf_symbolic_get_mapping(const pf_symbolic sym, int32_t* lanes_per_level);
 /* Copies the integer structure into the caller's device buffer d_buf
  * (>= info.dev_bytes, 256-byte aligned) on stream s.  The buffer must stay
@@ -160,7 +188,7 @@ int pf_mismatch(const pf_symbolic sym, int B, const double* d_yval, int64_t y_st
 int pf_jacobian(const pf_symbolic sym, int B, const double* d_yval, int64_t y_stride,
                 const int8_t* d_type, int64_t type_stride, const double* d_Vm,
                 const double* d_Va, int64_t v_stride, double* d_vals, int64_t vals_stride,
-                void* stream);
+                int vals_interleave, void* stream);
 
 /* ---- FactorizeGraphA (Sec. III-B, eqs. 1-3) --------------------------------
  * In-place block LDU of B matrices in the filled layout, level by level
@@ -170,7 +198,7 @@ int pf_jacobian(const pf_symbolic sym, int B, const double* d_yval, int64_t y_st
  * set to PF_OK or PF_E_ZERO_PIVOT when a pivot block is singular or
  * non-finite.                                                             */
 int pf_factor(const pf_symbolic sym, int B, double* d_vals, int64_t vals_stride,
-              int32_t* d_status, void* stream);
+              int vals_interleave, int32_t* d_status, void* stream);
 
 /* ---- forward substitution, normalisation, backward substitution ---------
  * (Sec. III-C, eq. 4.)  transpose = 0 solves A x = rhs; transpose = 1 solves
@@ -178,7 +206,8 @@ int pf_factor(const pf_symbolic sym, int B, double* d_vals, int64_t vals_stride,
  * L^T backward over levels p..1).  d_vals: factored filled layout.  d_rhs:
  * double[B][nn][2] (position order), overwritten with the solution.       */
 int pf_solve(const pf_symbolic sym, int B, const double* d_vals, int64_t vals_stride,
-             double* d_rhs, int64_t rhs_stride, int transpose, void* stream);
+             int vals_interleave, double* d_rhs, int64_t rhs_stride, int transpose,
+             void* stream);
 
 /* ---- Newton-Raphson (Sec. III) ---------------------------------------------
  * One launch runs the whole iteration for B cases sharing this symbolic;
@@ -187,9 +216,12 @@ int pf_solve(const pf_symbolic sym, int B, const double* d_vals, int64_t vals_st
  * back-substitutes and applies the step (theta -= dtheta, |V| -= d|V| at PQ
  * buses).  Stops when max|F| < tol at the top of an iteration, or after
  * max_iter steps.  d_Vm/d_Va: in = start state (flat start is the caller's),
- * out = solution, double[B][n] (v_stride).  d_ws: workspace double[B][..]
- * (ws_stride >= info.ws_doubles); its first info.vals_doubles hold the last
- * factors (at the solution with PF_NEWTON_KEEP_FACTORS).  Outputs:
+ * out = solution, double[B][n] (v_stride).  d_ws: workspace in groups of
+ * C = pf_newton_interleave(sym, B) cases (see "Interleaved case groups"), ws_stride
+ * >= info.ws_doubles and a multiple of 4, 16-byte aligned; each case's first
+ * info.vals_doubles hold its last factors in the filled layout (at the
+ * solution with PF_NEWTON_KEEP_FACTORS), so pf_solve can take d_ws with
+ * vals_stride = ws_stride and vals_interleave = C.  Outputs:
  * d_iters[B] (steps applied), d_norm[B] (last max|F|), d_status[B]
  * (PF_OK, PF_E_ZERO_PIVOT, PF_E_NOT_CONVERGED, PF_E_NONFINITE); any may be
  * NULL.  The launch never fails because of one case.                      */
@@ -199,6 +231,10 @@ int pf_newton(const pf_symbolic sym, int B, const double* d_yval, int64_t y_stri
               int64_t v_stride, double tol, int max_iter, int flags, double* d_ws,
               int64_t ws_stride, int32_t* d_iters, double* d_norm, int32_t* d_status,
               void* stream);
+
+/* Case grouping pf_newton uses for a batch of B: info.ws_interleave halved
+ * until it does not exceed B (1 for a single case).  Returns -1 on error.  */
+int pf_newton_interleave(const pf_symbolic sym, int B);
 
 /* ---- adjoint right-hand side (beyond the paper) ----------------------------
  * Gathers the loss gradient with respect to the state into position order:

@@ -53,6 +53,11 @@ class Symbolic:
         if self.buf is not None:
             B.pf_symbolic_upload(self.h, self.buf)
 
+    def set_launch(self, threads=0, tail_lds_budget=65536, interleave=4):
+        B.pf_symbolic_set_launch(self.h, threads, tail_lds_budget, interleave)
+        if self.buf is not None:
+            self.upload(self.device)
+
     def upload(self, device=None):
         dev = _dev(device)
         nbytes = self.info.dev_bytes
@@ -73,7 +78,12 @@ class Symbolic:
         return y
 
     def workspace(self, Bn, device=None):
-        return torch.empty(Bn, self.info.ws_doubles, dtype=torch.float64,
+        """pf_newton workspace for Bn cases: whole interleaved groups of
+        info.ws_interleave cases, one row of ws_doubles per case."""
+        info = self.info
+        C = B.pf_newton_interleave(self.h, Bn)
+        rows = -(-Bn // C) * C
+        return torch.empty(rows, info.ws_doubles, dtype=torch.float64,
                            device=_dev(device or self.device))
 
     def newton(self, yval, bus_type, Psp, Qsp, Vm, Va, tol=1e-8, max_iter=20,

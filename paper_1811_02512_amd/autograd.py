@@ -45,7 +45,8 @@ class PowerFlowFunction(torch.autograd.Function):
         tstride = 0 if bus_type.dim() == 1 else n
         lam = torch.empty(Bn, 2 * info.nn, dtype=torch.float64, device=dev)
         B.pf_adjoint_rhs(sym.h, Bn, gVm, gVa, n, bus_type, tstride, lam, 2 * info.nn)
-        B.pf_solve(sym.h, Bn, ws, info.ws_doubles, lam, 2 * info.nn, 1)
+        B.pf_solve(sym.h, Bn, ws, info.ws_doubles, lam, 2 * info.nn, 1,
+                   B.pf_newton_interleave(sym.h, Bn))
         gP = torch.empty(Bn, n, dtype=torch.float64, device=dev)
         gQ = torch.empty(Bn, n, dtype=torch.float64, device=dev)
         m = x.shape[-1]

@@ -33,11 +33,20 @@ class pf_info(C.Structure):
                 ("nnz_y", C.c_int64), ("nnz_l", C.c_int64), ("n_upd", C.c_int64),
                 ("nlevels", C.c_int32), ("max_level_width", C.c_int32),
                 ("vals_doubles", C.c_int64), ("ws_doubles", C.c_int64),
-                ("dev_bytes", C.c_size_t)]
+                ("dev_bytes", C.c_size_t), ("tail_levels", C.c_int32),
+                ("tail_nodes", C.c_int32), ("tail_lds_bytes", C.c_int32),
+                ("threads", C.c_int32), ("tail_clique", C.c_int32),
+                ("ws_interleave", C.c_int32)]
 
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libpf.so not built ({LIB_PATH}); run __graft_entry__.build()")
+
+# torch bundles its own HIP runtime under the same soname as the system one.
+# Loading torch first makes libpf bind to that already-loaded runtime, so
+# the process holds one HIP runtime and torch's device memory and streams are
+# valid in libpf's calls.
+import torch  # noqa: E402,F401
 
 lib = C.CDLL(LIB_PATH)
 
@@ -51,15 +60,17 @@ _SIGS = {
     "pf_symbolic_export": ([_vp] + [_vp] * 7, _i),
     "pf_symbolic_set_mapping": ([_vp, _vp], _i),
     "pf_symbolic_get_mapping": ([_vp, _vp], _i),
+    "pf_symbolic_set_launch": ([_vp, _i, _i64, _i], _i),
+    "pf_newton_interleave": ([_vp, _i], _i),
     "pf_symbolic_upload": ([_vp, _vp, C.c_size_t, _vp], _i),
     "pf_symbolic_destroy": ([_vp], None),
     "pf_symbolic_ybus_pattern": ([_vp, _vp, _vp], _i),
     "pf_build_ybus": ([_vp, _i, _vp, _vp, _vp, _i64, _vp, _i64, _vp], _i),
     "pf_mismatch": ([_vp, _i, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _i64,
                      _vp, _vp, _vp], _i),
-    "pf_jacobian": ([_vp, _i, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _i64, _vp], _i),
-    "pf_factor": ([_vp, _i, _vp, _i64, _vp, _vp], _i),
-    "pf_solve": ([_vp, _i, _vp, _i64, _vp, _i64, _i, _vp], _i),
+    "pf_jacobian": ([_vp, _i, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _i64, _i, _vp], _i),
+    "pf_factor": ([_vp, _i, _vp, _i64, _i, _vp, _vp], _i),
+    "pf_solve": ([_vp, _i, _vp, _i64, _i, _vp, _i64, _i, _vp], _i),
     "pf_newton": ([_vp, _i, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _d, _i, _i,
                    _vp, _i64, _vp, _vp, _vp, _vp], _i),
     "pf_adjoint_params": ([_vp, _i, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _vp,
@@ -151,6 +162,18 @@ def pf_symbolic_set_mapping(h, lanes):
     check(lib.pf_symbolic_set_mapping(h, ptr(lanes)), "pf_symbolic_set_mapping")
 
 
+def pf_symbolic_set_launch(h, threads=0, tail_lds_budget=65536, interleave=4):
+    check(lib.pf_symbolic_set_launch(h, int(threads), int(tail_lds_budget), int(interleave)),
+          "pf_symbolic_set_launch")
+
+
+def pf_newton_interleave(h, B):
+    C = lib.pf_newton_interleave(h, int(B))
+    if C < 0:
+        raise PfError(PF_E_INVALID, "pf_newton_interleave", last_error())
+    return C
+
+
 def pf_symbolic_get_mapping(h):
     info = pf_symbolic_info(h)
     lanes = np.zeros(max(info.nlevels, 1), np.int32)
@@ -180,20 +203,21 @@ def pf_mismatch(h, B, yval, y_stride, bus_type, type_stride, Psp, Qsp, inj_strid
 
 
 def pf_jacobian(h, B, yval, y_stride, bus_type, type_stride, Vm, Va, v_stride, vals,
-                vals_stride, stream=None):
+                vals_stride, vals_interleave=1, stream=None):
     check(lib.pf_jacobian(h, B, ptr(yval), y_stride, ptr(bus_type), type_stride, ptr(Vm),
-                          ptr(Va), v_stride, ptr(vals), vals_stride, stream_ptr(stream)),
-          "pf_jacobian")
+                          ptr(Va), v_stride, ptr(vals), vals_stride, int(vals_interleave),
+                          stream_ptr(stream)), "pf_jacobian")
 
 
-def pf_factor(h, B, vals, vals_stride, status=None, stream=None):
-    check(lib.pf_factor(h, B, ptr(vals), vals_stride, ptr(status), stream_ptr(stream)),
-          "pf_factor")
+def pf_factor(h, B, vals, vals_stride, status=None, vals_interleave=1, stream=None):
+    check(lib.pf_factor(h, B, ptr(vals), vals_stride, int(vals_interleave), ptr(status),
+                        stream_ptr(stream)), "pf_factor")
 
 
-def pf_solve(h, B, vals, vals_stride, rhs, rhs_stride, transpose=0, stream=None):
-    check(lib.pf_solve(h, B, ptr(vals), vals_stride, ptr(rhs), rhs_stride, int(transpose),
-                       stream_ptr(stream)), "pf_solve")
+def pf_solve(h, B, vals, vals_stride, rhs, rhs_stride, transpose=0, vals_interleave=1,
+             stream=None):
+    check(lib.pf_solve(h, B, ptr(vals), vals_stride, int(vals_interleave), ptr(rhs),
+                       rhs_stride, int(transpose), stream_ptr(stream)), "pf_solve")
 
 
 def pf_newton(h, B, yval, y_stride, bus_type, type_stride, Psp, Qsp, inj_stride, Vm, Va,

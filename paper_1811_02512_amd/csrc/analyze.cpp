@@ -48,9 +48,12 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 size_t HostSym::dev_bytes() const
 {
-    const std::vector<int32_t>* arrs[] = {&yptr, &ycol, &ybr_ptr, &ybr, &perm, &pos, &Lp,
-                                          &Li, &ylo, &yup, &ydiag, &Rp, &Ri, &Rs, &Up, &Ua,
-                                          &Ub, &level_ptr, &level_nodes, &level_g};
+    const std::vector<int32_t>* arrs[] = {&yptr,      &ycol,      &ybr_ptr, &ybr,    &perm,
+                                          &pos,       &Lp,        &Li,      &ylo,    &yup,
+                                          &ydiag,     &Rp,        &Ri,      &Rs,     &level_ptr,
+                                          &level_nodes, &level_g, &node_info, &slot_info, &rl,
+                                          &upd,       &t_node,    &t_slot,  &t_rl,   &t_upd,
+                                          &t_lptr,    &from,      &to};
     size_t total = 0;
     for (auto* a : arrs) total += align256(std::max<size_t>(a->size(), 1) * sizeof(int32_t));
     return total;
@@ -311,8 +314,177 @@ int analyze(int n, int m, const int32_t* from, const int32_t* to, int slack, int
             }
         }
     }
+
+    // packed records (layouts documented with DevSym)
+    s.node_info.assign(12 * (size_t)nn, 0);
+    for (int x = 0; x < nn; ++x) {
+        const int j = s.level_nodes[x];
+        int32_t* r = &s.node_info[12 * (size_t)x];
+        r[0] = j;
+        r[1] = s.perm[j];
+        r[2] = s.Rp[j];
+        r[3] = s.Rp[j + 1];
+        r[4] = s.Lp[j];
+        r[5] = s.Lp[j + 1];
+        r[6] = s.ydiag[j];
+        r[8] = s.yptr[s.perm[j]];
+        r[9] = s.yptr[s.perm[j] + 1];
+    }
+    s.slot_info.assign(8 * (size_t)nnzl, 0);
+    for (int64_t q = 0; q < nnzl; ++q) {
+        int32_t* r = &s.slot_info[8 * (size_t)q];
+        r[0] = s.Li[q];
+        r[1] = s.perm[s.Li[q]];
+        r[2] = s.ylo[q];
+        r[3] = s.yup[q];
+        r[4] = s.Up[q];
+        r[5] = s.Up[q + 1];
+    }
+    s.rl.resize(2 * (size_t)nnzl);
+    for (int64_t q = 0; q < nnzl; ++q) {
+        s.rl[2 * q] = s.Ri[q];
+        s.rl[2 * q + 1] = s.Rs[q];
+    }
+    s.upd.resize(2 * s.Ua.size());
+    for (size_t u = 0; u < s.Ua.size(); ++u) {
+        s.upd[2 * u] = s.Ua[u];
+        s.upd[2 * u + 1] = s.Ub[u];
+    }
     default_mapping(s);
+    build_tail(s, s.tail_budget);
     return PF_OK;
+}
+
+// The LDS tail: the largest run of top levels whose values fit the budget.
+// Its top may be a clique chain: single-node levels where every node is
+// adjacent to all nodes above it in the filled graph.  That part is
+// factorised and solved densely (right-looking, one barrier per pivot).
+void build_tail(HostSym& s, int64_t budget)
+{
+    const int nlev = (int)s.level_ptr.size() - 1;
+    const int nn = s.nn;
+    int L = nlev;
+    int64_t K = 0, TS = 0;
+    if (budget > 0) {
+        while (L > 0) {
+            const int l = L - 1;
+            int64_t k2 = K, t2 = TS;
+            for (int x = s.level_ptr[l]; x < s.level_ptr[l + 1]; ++x) {
+                const int j = s.level_nodes[x];
+                ++k2;
+                t2 += s.Lp[j + 1] - s.Lp[j];
+            }
+            if (tail_bytes(k2, t2) > budget) break;
+            K = k2;
+            TS = t2;
+            L = l;
+        }
+    }
+    s.tail_level = L;
+    s.tail_nodes = (int32_t)K;
+    s.tail_slots = (int32_t)TS;
+    s.tail_lds = K ? (int32_t)tail_bytes(K, TS) : 0;
+    s.tail_clique = 0;
+    s.t_node.clear();
+    s.t_slot.clear();
+    s.t_rl.clear();
+    s.t_upd.clear();
+    s.t_lptr.assign(1, 0);
+    if (K == 0) return;
+
+    // clique chain at the top of the tail: level nlev-1-d holds one node
+    // whose higher neighbours are exactly the d chain nodes above it
+    {
+        std::vector<int32_t> chain;  // from the root down
+        for (int l = nlev - 1; l >= L; --l) {
+            if (s.level_ptr[l + 1] - s.level_ptr[l] != 1) break;
+            const int j = s.level_nodes[s.level_ptr[l]];
+            const int d = (int)chain.size();
+            if (s.Lp[j + 1] - s.Lp[j] != d) break;
+            bool ok = true;
+            for (int q = 0; q < d && ok; ++q) ok = s.Li[s.Lp[j] + q] == chain[d - 1 - q];
+            if (!ok) break;
+            chain.push_back(j);
+        }
+        s.tail_clique = chain.size() >= 3 ? (int32_t)chain.size() : 0;
+    }
+
+    const int64_t nnzl = (int64_t)s.Li.size();
+    std::vector<int32_t> loc(nn, -1), sloc(nnzl, -1), owner(nnzl, -1);
+    for (int p = 0; p < nn; ++p)
+        for (int q = s.Lp[p]; q < s.Lp[p + 1]; ++q) owner[q] = p;
+    std::vector<int32_t> tnodes;
+    for (int l = L; l < nlev; ++l) {
+        for (int x = s.level_ptr[l]; x < s.level_ptr[l + 1]; ++x) {
+            loc[s.level_nodes[x]] = (int32_t)tnodes.size();
+            tnodes.push_back(s.level_nodes[x]);
+        }
+        s.t_lptr.push_back((int32_t)tnodes.size());
+    }
+    const int32_t kfirst = (int32_t)K - s.tail_clique;  // first local node of the clique
+    auto in_clique = [&](int p) { return loc[p] >= kfirst; };
+    int32_t ts = 0;
+    for (int j : tnodes)
+        for (int q = s.Lp[j]; q < s.Lp[j + 1]; ++q) sloc[q] = ts++;
+    s.t_node.assign(12 * (size_t)K, 0);
+    s.t_slot.assign(12 * (size_t)TS, 0);
+    int32_t run = 0;
+    for (size_t jl = 0; jl < tnodes.size(); ++jl) {
+        const int j = tnodes[jl];
+        int32_t* r = &s.t_node[12 * jl];
+        r[0] = j;
+        r[1] = s.perm[j];
+        r[2] = s.ydiag[j];
+        r[3] = run;  // local slots were numbered in this same node order
+        run += s.Lp[j + 1] - s.Lp[j];
+        r[4] = run;
+        r[5] = (int32_t)(s.t_rl.size() / 2);
+        for (int q = s.Rp[j]; q < s.Rp[j + 1]; ++q)
+            if (loc[s.Ri[q]] < 0) {
+                s.t_rl.push_back(s.Ri[q]);
+                s.t_rl.push_back(s.Rs[q]);
+            }
+        r[6] = (int32_t)(s.t_rl.size() / 2);
+        for (int pass = 0; pass < 2; ++pass) {  // tail descendants below the clique first
+            for (int q = s.Rp[j]; q < s.Rp[j + 1]; ++q) {
+                const int i = s.Ri[q];
+                if (loc[i] >= 0 && in_clique(i) == (pass == 1)) {
+                    s.t_rl.push_back(loc[i]);
+                    s.t_rl.push_back(sloc[s.Rs[q]]);
+                }
+            }
+            if (pass == 0) r[8] = (int32_t)(s.t_rl.size() / 2);
+        }
+        r[7] = (int32_t)(s.t_rl.size() / 2);
+        for (int q = s.Lp[j]; q < s.Lp[j + 1]; ++q) {
+            int32_t* t = &s.t_slot[12 * (size_t)sloc[q]];
+            t[0] = q;
+            t[1] = loc[s.Li[q]];
+            t[2] = s.perm[s.Li[q]];
+            t[3] = s.ylo[q];
+            t[4] = s.yup[q];
+            t[5] = (int32_t)(s.t_upd.size() / 2);
+            for (int u = s.Up[q]; u < s.Up[q + 1]; ++u)
+                if (loc[owner[s.Ub[u]]] < 0) {
+                    s.t_upd.push_back(s.Ua[u]);
+                    s.t_upd.push_back(s.Ub[u]);
+                }
+            t[6] = (int32_t)(s.t_upd.size() / 2);
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int u = s.Up[q]; u < s.Up[q + 1]; ++u) {
+                    const int i = owner[s.Ub[u]];
+                    if (loc[i] >= 0 && in_clique(i) == (pass == 1)) {
+                        s.t_upd.push_back(sloc[s.Ua[u]]);
+                        s.t_upd.push_back(sloc[s.Ub[u]]);
+                    }
+                }
+                if (pass == 0) t[10] = (int32_t)(s.t_upd.size() / 2);
+            }
+            t[7] = (int32_t)(s.t_upd.size() / 2);
+            t[8] = s.perm[j];
+            t[9] = (int32_t)jl;
+        }
+    }
 }
 
 // Lanes per node: enough lanes for the widest per-node loop of the level

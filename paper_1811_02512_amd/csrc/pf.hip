@@ -13,7 +13,16 @@
 // the other with a workgroup barrier between them; inside a level, each
 // node gets a group of g lanes (g from the symbolic's per-level mapping);
 // the lanes of a group split the node's destinations and its descendant
-// list, and combine partial sums with a butterfly over the group.
+// list, and combine partial sums with a butterfly over the group.  The top
+// levels whose values fit (the "tail") run in LDS, the top clique of the
+// elimination tree as a dense block.
+//
+// Memory layout across cases: a batch is cut into groups of C cases whose
+// per-case arrays are interleaved every 32 bytes (one 2x2 block), so one
+// 128-byte line holds the same block of four cases.  The C workgroups of a
+// group are launched 8 blocks apart, which places them on the same XCD at
+// the same time: they walk the same pattern in near lockstep and share
+// every line they fetch through that XCD's L2.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,18 +40,85 @@ using namespace pf;
 // ===========================================================================
 // device helpers
 // ===========================================================================
+extern __shared__ double pf_smem[];  // LDS tail (dynamic size: DevSym::tail_lds)
+
 namespace {
 
 constexpr int kMaxThreads = 1024;
+constexpr int kXcds = 8;
+
+// One case's doubles inside an interleaved group of C cases: element d
+// lives at base + (d / 4) * 4C + 4 (case % C) + d % 4.  C = 1 is the plain
+// contiguous layout.
+struct View {
+    double* base;
+    int lane4;  // 4 * (case % C)
+    int sh;     // log2(4 C)
+    __device__ __forceinline__ double* at(int64_t d) const
+    {
+        return base + ((d >> 2) << sh) + lane4 + (d & 3);
+    }
+    __device__ __forceinline__ Blk blk(int64_t d) const { return bload(at(d)); }
+    __device__ __forceinline__ void put(int64_t d, const Blk& v) const { bstore(at(d), v); }
+    __device__ __forceinline__ double2 v2(int64_t d) const
+    {
+        return *reinterpret_cast<const double2*>(at(d));
+    }
+    __device__ __forceinline__ void put2(int64_t d, double2 v) const
+    {
+        *reinterpret_cast<double2*>(at(d)) = v;
+    }
+};
+
+__device__ __forceinline__ int ilog2(int c) { return 31 - __clz(c); }
+
+// Case of block b when groups of C cases are placed 8 blocks apart (same
+// XCD under the round-robin workgroup dispatch); -1 for padding blocks.
+__device__ __forceinline__ int case_of_block(int b, int C, int B)
+{
+    int c = b;
+    if (C > 1) {
+        const int span = kXcds * C;
+        const int hi = b / span, rem = b - hi * span;
+        c = (hi * kXcds + (rem & (kXcds - 1))) * C + rem / kXcds;
+    }
+    return c < B ? c : -1;
+}
+
+__device__ __forceinline__ View case_view(double* buf, int64_t stride, int C, int c)
+{
+    View v;
+    v.base = buf + (int64_t)(c / C) * C * stride;
+    v.lane4 = 4 * (c % C);
+    v.sh = 2 + ilog2(C);
+    return v;
+}
+
+// Offsets of the Newton workspace of one case (doubles):
+//   D [nn][4] | LU [nnz_l][8] | bus records [n][8] | rhs [nn][2]
+// bus record: e, f, |V|, theta | P, Q, P_sp, Q_sp  (e + jf = V, P + jQ = S).
+struct Off {
+    int64_t D, LU, BUS, RHS;
+};
+__device__ __forceinline__ Off ws_off(const DevSym& S)
+{
+    Off o;
+    o.D = 0;
+    o.LU = 4 * (int64_t)S.nn;
+    o.BUS = S.vals_doubles;
+    o.RHS = o.BUS + 8 * (int64_t)S.n;
+    return o;
+}
 
 // Voltage accessors: stored rectangular voltages, or computed from polar.
-struct EFArr {
-    const double* e;
-    const double* f;
+struct EFView {
+    View v;
+    int64_t bus_off;
     __device__ __forceinline__ void get(int k, double& ek, double& fk) const
     {
-        ek = e[k];
-        fk = f[k];
+        const double2 t = v.v2(bus_off + 8 * (int64_t)k);
+        ek = t.x;
+        fk = t.y;
     }
 };
 struct EFPolar {
@@ -57,20 +133,34 @@ struct EFPolar {
     }
 };
 
-// P_i + jQ_i = V_i conj(sum_k Y_ik V_k)  (nodal: one row of Y).
+// P_i + jQ_i = V_i conj(sum_k Y_ik V_k)  (nodal: one row of Y, entries
+// [q0, q1)).  Two entries per step so that their gathers overlap.
 template <class EF>
-__device__ __forceinline__ void injection(const DevSym& S, const double* __restrict__ yv,
-                                          const EF& ef, int i, double& P, double& Q)
+__device__ __forceinline__ void injection_row(const DevSym& S, const double* __restrict__ yv,
+                                              const EF& ef, int i, int q0, int q1, double& P,
+                                              double& Q)
 {
     double ir = 0.0, ii = 0.0;
-    const int q1 = S.yptr[i + 1];
-    for (int q = S.yptr[i]; q < q1; ++q) {
-        const int k = S.ycol[q];
-        const double2 y = reinterpret_cast<const double2*>(yv)[q];
-        double ek, fk;
-        ef.get(k, ek, fk);
-        ir = fma(y.x, ek, fma(-y.y, fk, ir));
-        ii = fma(y.x, fk, fma(y.y, ek, ii));
+    const double2* y2 = reinterpret_cast<const double2*>(yv);
+    int q = q0;
+    for (; q + 1 < q1; q += 2) {
+        const int k0 = S.ycol[q], k1 = S.ycol[q + 1];
+        const double2 y0 = y2[q], y1 = y2[q + 1];
+        double e0, f0, e1, f1;
+        ef.get(k0, e0, f0);
+        ef.get(k1, e1, f1);
+        ir = fma(y0.x, e0, fma(-y0.y, f0, ir));
+        ii = fma(y0.x, f0, fma(y0.y, e0, ii));
+        ir = fma(y1.x, e1, fma(-y1.y, f1, ir));
+        ii = fma(y1.x, f1, fma(y1.y, e1, ii));
+    }
+    if (q < q1) {
+        const int k0 = S.ycol[q];
+        const double2 y0 = y2[q];
+        double e0, f0;
+        ef.get(k0, e0, f0);
+        ir = fma(y0.x, e0, fma(-y0.y, f0, ir));
+        ii = fma(y0.x, f0, fma(y0.y, e0, ii));
     }
     double ei, fi;
     ef.get(i, ei, fi);
@@ -78,70 +168,64 @@ __device__ __forceinline__ void injection(const DevSym& S, const double* __restr
     Q = fi * ir - ei * ii;
 }
 
-// Jacobian source reading the Newton state of one case.
 template <class EF>
-struct AsmState {
-    const DevSym* S;
+__device__ __forceinline__ void injection(const DevSym& S, const double* __restrict__ yv,
+                                          const EF& ef, int i, double& P, double& Q)
+{
+    injection_row(S, yv, ef, i, S.yptr[i], S.yptr[i + 1], P, Q);
+}
+
+// Jacobian source: the Newton state of one case (bus records in the view).
+struct SrcState {
     const double* yv;
     const int8_t* type;
-    const double* Vm;
-    EF ef;
-    const double* P;  // may be null: then computed on the fly
-    const double* Q;
-
-    __device__ __forceinline__ Blk diag(int j) const
+    View w;
+    int64_t bus_off;
+    __device__ __forceinline__ Blk diag(int, int bus, int yd) const
     {
-        const int bus = S->perm[j];
-        const double2 y = reinterpret_cast<const double2*>(yv)[S->ydiag[j]];
-        double p, q;
-        if (P) {
-            p = P[bus];
-            q = Q[bus];
-        } else {
-            injection(*S, yv, ef, bus, p, q);
-        }
-        return jac_diag(y.x, y.y, p, q, Vm[bus], type[bus] == T_PV);
+        const double2 y = reinterpret_cast<const double2*>(yv)[yd];
+        const double vm = *w.at(bus_off + 8 * (int64_t)bus + 2);
+        const double2 s = w.v2(bus_off + 8 * (int64_t)bus + 4);
+        return jac_diag(y.x, y.y, s.x, s.y, vm, type[bus] == T_PV);
     }
-    __device__ __forceinline__ void off(int j, int s, Blk& lo, Blk& up) const
+    // block (k, j) below the diagonal and (j, k) above it; zero at fill
+    __device__ __forceinline__ void off(int, int bj, int bk, int ylo, int yup, Blk& lo,
+                                        Blk& up) const
     {
-        const int ql = S->ylo[s];
-        if (ql < 0) {  // fill-in: structurally present, numerically zero
+        if (ylo < 0) {
             lo = bzero();
             up = bzero();
             return;
         }
-        const int qu = S->yup[s];
-        const int bj = S->perm[j], bk = S->perm[S->Li[s]];
-        double ej, fj, ek, fk;
-        ef.get(bj, ej, fj);
-        ef.get(bk, ek, fk);
+        const Blk rj = w.blk(bus_off + 8 * (int64_t)bj);  // e, f, |V|, theta
+        const Blk rk = w.blk(bus_off + 8 * (int64_t)bk);
         const bool pj = type[bj] == T_PV, pk = type[bk] == T_PV;
-        const double2 yl = reinterpret_cast<const double2*>(yv)[ql];
-        const double2 yu = reinterpret_cast<const double2*>(yv)[qu];
-        lo = jac_off(yl.x, yl.y, ek, fk, ej, fj, Vm[bj], pk, pj);  // block (k, j)
-        up = jac_off(yu.x, yu.y, ej, fj, ek, fk, Vm[bk], pj, pk);  // block (j, k)
+        const double2 yl = reinterpret_cast<const double2*>(yv)[ylo];
+        const double2 yu = reinterpret_cast<const double2*>(yv)[yup];
+        lo = jac_off(yl.x, yl.y, rk.a, rk.b, rj.a, rj.b, rj.c, pk, pj);
+        up = jac_off(yu.x, yu.y, rj.a, rj.b, rk.a, rk.b, rk.c, pj, pk);
     }
 };
 
-// Jacobian source reading an assembled matrix in the filled layout.
-struct AsmLoad {
-    const double* D;
-    const double* LU;
-    __device__ __forceinline__ Blk diag(int j) const { return bload(D + 4 * (int64_t)j); }
-    __device__ __forceinline__ void off(int, int s, Blk& lo, Blk& up) const
+// Jacobian source: an assembled matrix in the filled layout.
+struct SrcLoad {
+    View w;
+    int64_t lu_off;
+    __device__ __forceinline__ Blk diag(int j, int, int) const { return w.blk(4 * (int64_t)j); }
+    __device__ __forceinline__ void off(int s, int, int, int, int, Blk& lo, Blk& up) const
     {
-        lo = bload(LU + 8 * (int64_t)s);
-        up = bload(LU + 8 * (int64_t)s + 4);
+        lo = w.blk(lu_off + 8 * (int64_t)s);
+        up = w.blk(lu_off + 8 * (int64_t)s + 4);
     }
 };
 
-// Runs fn(node, lane, g) over the levels, up (1..p) or down (p..1), with a
-// workgroup barrier after every level.
+// Runs fn(x, lane, g) for the nodes of levels [l0, l1), x indexing the
+// level-ordered node records, up or down, with a barrier after every level.
 template <class F>
-__device__ __forceinline__ void for_levels(const DevSym& S, bool up, F&& fn)
+__device__ __forceinline__ void for_levels(const DevSym& S, int l0, int l1, bool up, F&& fn)
 {
-    for (int li = 0; li < S.nlev; ++li) {
-        const int l = up ? li : S.nlev - 1 - li;
+    for (int li = l0; li < l1; ++li) {
+        const int l = up ? li : l1 - 1 - (li - l0);
         const int g = S.level_g[l];
         const int beg = S.level_ptr[l];
         const int cnt = S.level_ptr[l + 1] - beg;
@@ -150,95 +234,447 @@ __device__ __forceinline__ void for_levels(const DevSym& S, bool up, F&& fn)
         const int lane = threadIdx.x & (g - 1);
         for (int base = 0; base < cnt; base += gpb) {
             const int idx = base + grp;
-            if (idx < cnt) fn(S.level_nodes[beg + idx], lane, g);
+            if (idx < cnt) fn(beg + idx, lane, g);
         }
         __syncthreads();
     }
 }
 
-// Left-looking block LDU of node j (FactorizeGraphA, pull form).
+// Runs fn(jl, lane, g) over tail levels [t0, t1) (tail-local numbering).
+template <class F>
+__device__ __forceinline__ void for_tail_range(const DevSym& S, int t0, int t1, bool up, F&& fn)
+{
+    for (int ti = t0; ti < t1; ++ti) {
+        const int tl = up ? ti : t1 - 1 - (ti - t0);
+        const int g = S.level_g[S.tail_level + tl];
+        const int beg = S.t_lptr[tl];
+        const int cnt = S.t_lptr[tl + 1] - beg;
+        const int gpb = blockDim.x / g;
+        const int grp = threadIdx.x / g;
+        const int lane = threadIdx.x & (g - 1);
+        for (int base = 0; base < cnt; base += gpb) {
+            const int idx = base + grp;
+            if (idx < cnt) fn(beg + idx, lane, g);
+        }
+        __syncthreads();
+    }
+}
+
+// Block updates of one destination slot from pairs (a, b) = (slot(i;k), slot(i;j)):
+//   W_kj -= W_ki U_ij,  V_jk -= W_ji U_ik.
+// Two pairs per step; the next step's indices are fetched before this
+// step's blocks so that index and value loads overlap.
+__device__ __forceinline__ void apply_updates(const int2* __restrict__ upd, int u0, int u1,
+                                              const View& w, int64_t lu, Blk& Wk, Blk& Vk)
+{
+    if (u0 >= u1) return;
+    int2 p = upd[u0];
+    int2 q = (u0 + 1 < u1) ? upd[u0 + 1] : make_int2(0, 0);
+    for (int u = u0; u < u1; u += 2) {
+        const bool has_q = u + 1 < u1;
+        const int2 pn = (u + 2 < u1) ? upd[u + 2] : make_int2(0, 0);
+        const int2 qn = (u + 3 < u1) ? upd[u + 3] : make_int2(0, 0);
+        const Blk Wa = w.blk(lu + 8 * (int64_t)p.x), Ua = w.blk(lu + 8 * (int64_t)p.x + 4);
+        const Blk Wb = w.blk(lu + 8 * (int64_t)p.y), Ub = w.blk(lu + 8 * (int64_t)p.y + 4);
+        if (has_q) {
+            const Blk Wc = w.blk(lu + 8 * (int64_t)q.x), Uc = w.blk(lu + 8 * (int64_t)q.x + 4);
+            const Blk Wd = w.blk(lu + 8 * (int64_t)q.y), Ud = w.blk(lu + 8 * (int64_t)q.y + 4);
+            bmsub(Wk, Wa, Ub);
+            bmsub(Vk, Wb, Ua);
+            bmsub(Wk, Wc, Ud);
+            bmsub(Vk, Wd, Uc);
+        } else {
+            bmsub(Wk, Wa, Ub);
+            bmsub(Vk, Wb, Ua);
+        }
+        p = pn;
+        q = qn;
+    }
+}
+
+// Same with the blocks in LDS (tail-local slot numbering).
+__device__ __forceinline__ void apply_updates_lds(const int2* __restrict__ upd, int u0, int u1,
+                                                  const double* sLU, Blk& Wk, Blk& Vk)
+{
+    if (u0 >= u1) return;
+    int2 p = upd[u0];
+    int2 q = (u0 + 1 < u1) ? upd[u0 + 1] : make_int2(0, 0);
+    for (int u = u0; u < u1; u += 2) {
+        const bool has_q = u + 1 < u1;
+        const int2 pn = (u + 2 < u1) ? upd[u + 2] : make_int2(0, 0);
+        const int2 qn = (u + 3 < u1) ? upd[u + 3] : make_int2(0, 0);
+        bmsub(Wk, bload(sLU + 8 * p.x), bload(sLU + 8 * p.y + 4));
+        bmsub(Vk, bload(sLU + 8 * p.y), bload(sLU + 8 * p.x + 4));
+        if (has_q) {
+            bmsub(Wk, bload(sLU + 8 * q.x), bload(sLU + 8 * q.y + 4));
+            bmsub(Vk, bload(sLU + 8 * q.y), bload(sLU + 8 * q.x + 4));
+        }
+        p = pn;
+        q = qn;
+    }
+}
+
+__device__ __forceinline__ void gsum_blk(Blk& v, int g)
+{
+    v.a = gsum(v.a, g);
+    v.b = gsum(v.b, g);
+    v.c = gsum(v.c, g);
+    v.d = gsum(v.d, g);
+}
+
+// Left-looking block LDU of node record x (FactorizeGraphA, pull form):
 //   D_j  = A_jj - sum_{i in R(j)} W_ji U_ij
 //   W_kj = A_kj - sum_i W_ki U_ij,  V_jk = A_jk - sum_i W_ji U_ik  (k in S(j))
 //   stored: D section <- D_j^-1, LU[s] <- (W_kj, U_jk = D_j^-1 V_jk)
 // With FWD, also the forward substitution and normalisation of the rhs:
 //   y_j = D_j^-1 (b_j - sum_{i in R(j)} W_ji y_i).
-template <class ASM, bool FWD>
-__device__ __forceinline__ void factor_node(const DevSym& S, const ASM& A, int j, int lane,
-                                            int g, double* __restrict__ D,
-                                            double* __restrict__ LU, double* __restrict__ rhs,
+template <class SRC, bool FWD>
+__device__ __forceinline__ void factor_node(const DevSym& S, const SRC& src, int x, int lane,
+                                            int g, const View& w, int64_t lu, int64_t rhs,
                                             int* s_bad)
 {
+    const int4 n0 = S.node_info[3 * x];
+    const int4 n1 = S.node_info[3 * x + 1];
+    const int j = n0.x, bus = n0.y;
     Blk ds = bzero();
     double z0 = 0.0, z1 = 0.0;
-    const int r1 = S.Rp[j + 1];
-    for (int r = S.Rp[j] + lane; r < r1; r += g) {
-        const int b = S.Rs[r];
-        const Blk w = bload(LU + 8 * (int64_t)b);
-        const Blk u = bload(LU + 8 * (int64_t)b + 4);
-        bmadd(ds, w, u);
+    for (int r = n0.z + lane; r < n0.w; r += g) {
+        const int2 e = S.rl[r];
+        const Blk wv = w.blk(lu + 8 * (int64_t)e.y);
+        const Blk uv = w.blk(lu + 8 * (int64_t)e.y + 4);
+        bmadd(ds, wv, uv);
         if (FWD) {
-            const double2 yi = reinterpret_cast<const double2*>(rhs)[S.Ri[r]];
-            mvadd(z0, z1, w, yi.x, yi.y);
+            const double2 yi = w.v2(rhs + 2 * (int64_t)e.x);
+            mvadd(z0, z1, wv, yi.x, yi.y);
         }
     }
     if (g > 1) {
-        ds.a = gsum(ds.a, g);
-        ds.b = gsum(ds.b, g);
-        ds.c = gsum(ds.c, g);
-        ds.d = gsum(ds.d, g);
+        gsum_blk(ds, g);
         if (FWD) {
             z0 = gsum(z0, g);
             z1 = gsum(z1, g);
         }
     }
-    const Blk Ajj = A.diag(j);
+    const Blk Ajj = src.diag(j, bus, n1.z);
     const Blk Dj = {Ajj.a - ds.a, Ajj.b - ds.b, Ajj.c - ds.c, Ajj.d - ds.d};
     bool ok;
     const Blk Di = binv(Dj, ok);
-    const int s1 = S.Lp[j + 1];
-    for (int s = S.Lp[j] + lane; s < s1; s += g) {
+    for (int s = n1.x + lane; s < n1.y; s += g) {
+        const int4 a = S.slot_info[2 * s];
+        const int4 b = S.slot_info[2 * s + 1];
         Blk Wk, Vk;
-        A.off(j, s, Wk, Vk);
-        const int u1 = S.Up[s + 1];
-        for (int u = S.Up[s]; u < u1; ++u) {
-            const int a = S.Ua[u], b = S.Ub[u];
-            const Blk Wa = bload(LU + 8 * (int64_t)a);
-            const Blk Uak = bload(LU + 8 * (int64_t)a + 4);
-            const Blk Wb = bload(LU + 8 * (int64_t)b);
-            const Blk Ubj = bload(LU + 8 * (int64_t)b + 4);
-            bmsub(Wk, Wa, Ubj);
-            bmsub(Vk, Wb, Uak);
-        }
-        bstore(LU + 8 * (int64_t)s, Wk);
-        bstore(LU + 8 * (int64_t)s + 4, bmul(Di, Vk));
+        src.off(s, bus, a.y, a.z, a.w, Wk, Vk);
+        apply_updates(S.upd, b.x, b.y, w, lu, Wk, Vk);
+        w.put(lu + 8 * (int64_t)s, Wk);
+        w.put(lu + 8 * (int64_t)s + 4, bmul(Di, Vk));
     }
     if (lane == 0) {
         if (!ok) *s_bad = 1;
-        bstore(D + 4 * (int64_t)j, Di);
+        w.put(4 * (int64_t)j, Di);
         if (FWD) {
-            const double2 bj = reinterpret_cast<const double2*>(rhs)[j];
-            const double x0 = bj.x - z0, x1 = bj.y - z1;
+            const double2 bj = w.v2(rhs + 2 * (int64_t)j);
             double y0 = 0.0, y1 = 0.0;
-            mvadd(y0, y1, Di, x0, x1);
-            reinterpret_cast<double2*>(rhs)[j] = make_double2(y0, y1);
+            mvadd(y0, y1, Di, bj.x - z0, bj.y - z1);
+            w.put2(rhs + 2 * (int64_t)j, make_double2(y0, y1));
         }
     }
 }
 
-// Backward substitution of node j: x_j = y_j - sum_{k in S(j)} U_jk x_k.
-// With the Newton update, also theta -= dtheta, |V| -= d|V| (PQ) and the
-// rectangular voltage of the bus.
-template <bool UPDATE>
-__device__ __forceinline__ void back_node(const DevSym& S, int j, int lane, int g,
-                                          const double* __restrict__ LU,
-                                          double* __restrict__ rhs, const int8_t* type,
-                                          double* Vm, double* Va, double* e, double* f)
+// Local slot of clique pair (a, b), a < b: the clique's slots are numbered
+// node by node, node a owning KC - a - 1 of them.
+__device__ __forceinline__ int clique_slot(int c0, int KC, int a, int b)
 {
+    return c0 + a * (KC - 1) - (a * (a - 1)) / 2 + (b - a - 1);
+}
+
+// The LDS tail of the factorisation.
+// Phase A (all threads, no ordering): every tail diagonal, rhs entry and
+//   slot takes the updates of descendants outside the tail (global memory).
+// Phase B: the tail levels below the clique, in order, in LDS.
+// Phase C: clique entries take the updates of tail nodes below the clique.
+// Phase D: the clique as a dense block, right-looking: at pivot a every
+//   thread forms D_a^-1 and y_a itself, then the trailing blocks (k, l) are
+//   updated in parallel, A_kl -= W_ka D_a^-1 V_al, with one barrier per
+//   pivot; row a is normalised (U_al = D_a^-1 V_al) during pivot a + 1,
+//   when nobody reads it any more.
+// WRITE stores the tail's factors to global memory.
+template <class SRC, bool FWD, bool WRITE>
+__device__ void tail_factor(const DevSym& S, const SRC& src, const View& w, int64_t lu,
+                            int64_t rhs, int* s_bad)
+{
+    const int K = S.tail_nodes, TS = S.tail_slots, KC = S.tail_clique;
+    const int nT = S.nlev - S.tail_level;
+    double* sLU = pf_smem;             // TS x 8: W, then V -> U
+    double* sD = pf_smem + 8 * TS;     // K x 4: accumulated pivot, then D^-1
+    double* sy = sD + 4 * K;           // K x 2: accumulated rhs, then y
+    for (int it = threadIdx.x; it < K + TS; it += blockDim.x) {
+        if (it < K) {
+            const int4 t0 = S.t_node[3 * it];
+            const int4 t1 = S.t_node[3 * it + 1];
+            Blk acc = src.diag(t0.x, t0.y, t0.z);
+            double z0 = 0.0, z1 = 0.0;
+            if (FWD) {
+                const double2 b = w.v2(rhs + 2 * (int64_t)t0.x);
+                z0 = b.x;
+                z1 = b.y;
+            }
+            for (int r = t1.y; r < t1.z; ++r) {
+                const int2 e = S.t_rl[r];
+                const Blk wv = w.blk(lu + 8 * (int64_t)e.y);
+                bmsub(acc, wv, w.blk(lu + 8 * (int64_t)e.y + 4));
+                if (FWD) {
+                    const double2 yi = w.v2(rhs + 2 * (int64_t)e.x);
+                    z0 = fma(-wv.a, yi.x, fma(-wv.b, yi.y, z0));
+                    z1 = fma(-wv.c, yi.x, fma(-wv.d, yi.y, z1));
+                }
+            }
+            bstore(sD + 4 * it, acc);
+            sy[2 * it] = z0;
+            sy[2 * it + 1] = z1;
+        } else {
+            const int t = it - K;
+            const int4 a = S.t_slot[3 * t];
+            const int4 b = S.t_slot[3 * t + 1];
+            const int4 c = S.t_slot[3 * t + 2];
+            Blk Wk, Vk;
+            src.off(a.x, c.x, a.z, a.w, b.x, Wk, Vk);
+            apply_updates(S.t_upd, b.y, b.z, w, lu, Wk, Vk);
+            bstore(sLU + 8 * t, Wk);
+            bstore(sLU + 8 * t + 4, Vk);
+        }
+    }
+    __syncthreads();
+    for_tail_range(S, 0, nT - KC, true, [&](int jl, int lane, int g) {
+        const int4 t0 = S.t_node[3 * jl];
+        const int4 t1 = S.t_node[3 * jl + 1];
+        Blk ds = bzero();
+        double z0 = 0.0, z1 = 0.0;
+        for (int r = t1.z + lane; r < t1.w; r += g) {
+            const int2 e = S.t_rl[r];
+            const Blk wv = bload(sLU + 8 * e.y);
+            bmadd(ds, wv, bload(sLU + 8 * e.y + 4));
+            if (FWD) mvadd(z0, z1, wv, sy[2 * e.x], sy[2 * e.x + 1]);
+        }
+        if (g > 1) {
+            gsum_blk(ds, g);
+            if (FWD) {
+                z0 = gsum(z0, g);
+                z1 = gsum(z1, g);
+            }
+        }
+        const Blk A = bload(sD + 4 * jl);
+        bool ok;
+        const Blk Di = binv({A.a - ds.a, A.b - ds.b, A.c - ds.c, A.d - ds.d}, ok);
+        for (int t = t0.w + lane; t < t1.x; t += g) {
+            const int4 b = S.t_slot[3 * t + 1];
+            Blk Wk = bload(sLU + 8 * t), Vk = bload(sLU + 8 * t + 4);
+            apply_updates_lds(S.t_upd, b.z, b.w, sLU, Wk, Vk);
+            bstore(sLU + 8 * t, Wk);
+            bstore(sLU + 8 * t + 4, bmul(Di, Vk));
+        }
+        if (lane == 0) {
+            if (!ok) *s_bad = 1;
+            bstore(sD + 4 * jl, Di);
+            if (FWD) {
+                double y0 = 0.0, y1 = 0.0;
+                mvadd(y0, y1, Di, sy[2 * jl] - z0, sy[2 * jl + 1] - z1);
+                sy[2 * jl] = y0;
+                sy[2 * jl + 1] = y1;
+            }
+        }
+    });
+    if (KC > 0) {
+        const int kf = K - KC;
+        const int c0 = S.t_node[3 * kf].w;  // first local slot of the clique
+        // phase C: clique diagonals, rhs and slots take the tail updates from below
+        for (int it = threadIdx.x; it < KC + (TS - c0); it += blockDim.x) {
+            if (it < KC) {
+                const int jl = kf + it;
+                const int4 t1 = S.t_node[3 * jl + 1];
+                const int rmid = S.t_node[3 * jl + 2].x;
+                Blk acc = bload(sD + 4 * jl);
+                double z0 = sy[2 * jl], z1 = sy[2 * jl + 1];
+                for (int r = t1.z; r < rmid; ++r) {
+                    const int2 e = S.t_rl[r];
+                    const Blk wv = bload(sLU + 8 * e.y);
+                    bmsub(acc, wv, bload(sLU + 8 * e.y + 4));
+                    if (FWD) {
+                        z0 = fma(-wv.a, sy[2 * e.x], fma(-wv.b, sy[2 * e.x + 1], z0));
+                        z1 = fma(-wv.c, sy[2 * e.x], fma(-wv.d, sy[2 * e.x + 1], z1));
+                    }
+                }
+                bstore(sD + 4 * jl, acc);
+                sy[2 * jl] = z0;
+                sy[2 * jl + 1] = z1;
+            } else {
+                const int t = c0 + (it - KC);
+                const int4 b = S.t_slot[3 * t + 1];
+                const int umid = S.t_slot[3 * t + 2].z;
+                Blk Wk = bload(sLU + 8 * t), Vk = bload(sLU + 8 * t + 4);
+                apply_updates_lds(S.t_upd, b.z, umid, sLU, Wk, Vk);
+                bstore(sLU + 8 * t, Wk);
+                bstore(sLU + 8 * t + 4, Vk);
+            }
+        }
+        __syncthreads();
+        // phase D: dense right-looking over the clique's pivots
+        Blk Dprev = bzero();
+        double yp0 = 0.0, yp1 = 0.0;
+        for (int a = 0; a <= KC; ++a) {
+            const int m = KC - 1 - a;  // trailing size
+            Blk Di = bzero();
+            double ya0 = 0.0, ya1 = 0.0;
+            if (a < KC) {
+                const int ja = kf + a;
+                bool ok;
+                Di = binv(bload(sD + 4 * ja), ok);
+                if (!ok && threadIdx.x == 0) *s_bad = 1;
+                if (FWD) mvadd(ya0, ya1, Di, sy[2 * ja], sy[2 * ja + 1]);
+            }
+            const int nupd = (a < KC) ? m * m : 0;
+            const int nnorm = (a > 0) ? (KC - a) + 1 : 0;  // row a-1 slots + its pivot
+            for (int it = threadIdx.x; it < nupd + nnorm; it += blockDim.x) {
+                if (it < nupd) {
+                    const int k = a + 1 + it / m, l = a + 1 + it % m;
+                    const Blk Wka = bload(sLU + 8 * clique_slot(c0, KC, a, k));
+                    const Blk Ual = bmul(Di, bload(sLU + 8 * clique_slot(c0, KC, a, l) + 4));
+                    const int jk = kf + k;
+                    if (k == l) {
+                        Blk d = bload(sD + 4 * jk);
+                        bmsub(d, Wka, Ual);
+                        bstore(sD + 4 * jk, d);
+                        if (FWD) {
+                            sy[2 * jk] = fma(-Wka.a, ya0, fma(-Wka.b, ya1, sy[2 * jk]));
+                            sy[2 * jk + 1] = fma(-Wka.c, ya0, fma(-Wka.d, ya1, sy[2 * jk + 1]));
+                        }
+                    } else if (k > l) {
+                        double* p = sLU + 8 * clique_slot(c0, KC, l, k);
+                        Blk v = bload(p);
+                        bmsub(v, Wka, Ual);
+                        bstore(p, v);
+                    } else {
+                        double* p = sLU + 8 * clique_slot(c0, KC, k, l) + 4;
+                        Blk v = bload(p);
+                        bmsub(v, Wka, Ual);
+                        bstore(p, v);
+                    }
+                } else {
+                    const int r = it - nupd;  // normalise row a-1
+                    const int jp = kf + a - 1;
+                    if (r < KC - a) {
+                        double* p = sLU + 8 * clique_slot(c0, KC, a - 1, a + r) + 4;
+                        bstore(p, bmul(Dprev, bload(p)));
+                    } else {
+                        bstore(sD + 4 * jp, Dprev);
+                        if (FWD) {
+                            sy[2 * jp] = yp0;
+                            sy[2 * jp + 1] = yp1;
+                        }
+                    }
+                }
+            }
+            Dprev = Di;
+            yp0 = ya0;
+            yp1 = ya1;
+            __syncthreads();
+        }
+    }
+    if (WRITE) {
+        for (int t = threadIdx.x; t < TS; t += blockDim.x) {
+            const int s = S.t_slot[3 * t].x;
+            w.put(lu + 8 * (int64_t)s, bload(sLU + 8 * t));
+            w.put(lu + 8 * (int64_t)s + 4, bload(sLU + 8 * t + 4));
+        }
+        for (int jl = threadIdx.x; jl < K; jl += blockDim.x) {
+            const int j = S.t_node[3 * jl].x;
+            w.put(4 * (int64_t)j, bload(sD + 4 * jl));
+            if (FWD) w.put2(rhs + 2 * (int64_t)j, make_double2(sy[2 * jl], sy[2 * jl + 1]));
+        }
+        __syncthreads();
+    }
+}
+
+// Newton step of one bus: theta -= dtheta, |V| -= d|V| (PQ), new e + jf;
+// the record's first 32 bytes (e, f, |V|, theta) are rewritten in one store.
+__device__ __forceinline__ void apply_step(const View& w, int64_t rec, bool pv, double x0,
+                                           double x1)
+{
+    const Blk r = w.blk(rec);
+    const double va = r.d - x0;
+    const double vm = pv ? r.c : r.c - x1;
+    double sn, cs;
+    sincos(va, &sn, &cs);
+    w.put(rec, {vm * cs, vm * sn, vm, va});
+}
+
+// Backward substitution of the tail from LDS: x_j = y_j - sum U_jk x_k, the
+// x of tail nodes also written to the rhs for the levels below.  The clique
+// goes first, column-oriented: once x_a is final, y_k -= U_ka x_a for all
+// clique nodes k below a in parallel, one barrier per pivot.
+template <bool UPDATE>
+__device__ void tail_backward(const DevSym& S, const View& w, int64_t rhs, int64_t bus_off,
+                              const int8_t* type)
+{
+    const int K = S.tail_nodes, TS = S.tail_slots, KC = S.tail_clique;
+    const int nT = S.nlev - S.tail_level;
+    const double* sLU = pf_smem;
+    double* sy = pf_smem + 8 * TS + 4 * K;
+    if (KC > 0) {
+        const int kf = K - KC;
+        const int c0 = S.t_node[3 * kf].w;
+        for (int a = KC - 1; a >= 0; --a) {
+            const int ja = kf + a;
+            const double x0 = sy[2 * ja], x1 = sy[2 * ja + 1];
+            for (int k = threadIdx.x; k <= a; k += blockDim.x) {
+                if (k < a) {
+                    const int jk = kf + k;
+                    const Blk U = bload(sLU + 8 * clique_slot(c0, KC, k, a) + 4);
+                    sy[2 * jk] = fma(-U.a, x0, fma(-U.b, x1, sy[2 * jk]));
+                    sy[2 * jk + 1] = fma(-U.c, x0, fma(-U.d, x1, sy[2 * jk + 1]));
+                } else {
+                    const int4 t0 = S.t_node[3 * ja];
+                    w.put2(rhs + 2 * (int64_t)t0.x, make_double2(x0, x1));
+                    if (UPDATE)
+                        apply_step(w, bus_off + 8 * (int64_t)t0.y, type[t0.y] == T_PV, x0, x1);
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for_tail_range(S, 0, nT - KC, false, [&](int jl, int lane, int g) {
+        const int4 t0 = S.t_node[3 * jl];
+        const int4 t1 = S.t_node[3 * jl + 1];
+        double a0 = 0.0, a1 = 0.0;
+        for (int t = t0.w + lane; t < t1.x; t += g) {
+            const int kl = S.t_slot[3 * t].y;
+            mvadd(a0, a1, bload(sLU + 8 * t + 4), sy[2 * kl], sy[2 * kl + 1]);
+        }
+        if (g > 1) {
+            a0 = gsum(a0, g);
+            a1 = gsum(a1, g);
+        }
+        if (lane == 0) {
+            const double x0 = sy[2 * jl] - a0, x1 = sy[2 * jl + 1] - a1;
+            sy[2 * jl] = x0;
+            sy[2 * jl + 1] = x1;
+            w.put2(rhs + 2 * (int64_t)t0.x, make_double2(x0, x1));
+            if (UPDATE) apply_step(w, bus_off + 8 * (int64_t)t0.y, type[t0.y] == T_PV, x0, x1);
+        }
+    });
+}
+
+// Backward substitution of node record x: x_j = y_j - sum_{k in S(j)} U_jk x_k.
+template <bool UPDATE>
+__device__ __forceinline__ void back_node(const DevSym& S, int x, int lane, int g,
+                                          const View& w, int64_t lu, int64_t rhs,
+                                          int64_t bus_off, const int8_t* type)
+{
+    const int4 n0 = S.node_info[3 * x];
+    const int4 n1 = S.node_info[3 * x + 1];
     double a0 = 0.0, a1 = 0.0;
-    const int s1 = S.Lp[j + 1];
-    for (int s = S.Lp[j] + lane; s < s1; s += g) {
-        const Blk u = bload(LU + 8 * (int64_t)s + 4);
-        const double2 xk = reinterpret_cast<const double2*>(rhs)[S.Li[s]];
+    for (int s = n1.x + lane; s < n1.y; s += g) {
+        const Blk u = w.blk(lu + 8 * (int64_t)s + 4);
+        const double2 xk = w.v2(rhs + 2 * (int64_t)S.Li[s]);
         mvadd(a0, a1, u, xk.x, xk.y);
     }
     if (g > 1) {
@@ -246,21 +682,10 @@ __device__ __forceinline__ void back_node(const DevSym& S, int j, int lane, int 
         a1 = gsum(a1, g);
     }
     if (lane == 0) {
-        const double2 y = reinterpret_cast<const double2*>(rhs)[j];
+        const double2 y = w.v2(rhs + 2 * (int64_t)n0.x);
         const double x0 = y.x - a0, x1 = y.y - a1;
-        reinterpret_cast<double2*>(rhs)[j] = make_double2(x0, x1);
-        if (UPDATE) {
-            const int bus = S.perm[j];
-            const double va = Va[bus] - x0;
-            double vm = Vm[bus];
-            if (type[bus] != T_PV) vm -= x1;
-            Va[bus] = va;
-            Vm[bus] = vm;
-            double sn, cs;
-            sincos(va, &sn, &cs);
-            e[bus] = vm * cs;
-            f[bus] = vm * sn;
-        }
+        w.put2(rhs + 2 * (int64_t)n0.x, make_double2(x0, x1));
+        if (UPDATE) apply_step(w, bus_off + 8 * (int64_t)n0.y, type[n0.y] == T_PV, x0, x1);
     }
 }
 
@@ -271,10 +696,10 @@ __device__ double block_max(double v, int nan, int& any_nan)
     __shared__ int s_n[kMaxThreads / 64 + 1];
     for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
     nan = __any(nan);
-    const int w = threadIdx.x >> 6;
+    const int wv = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
-        s_v[w] = v;
-        s_n[w] = nan;
+        s_v[wv] = v;
+        s_n[wv] = nan;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -294,34 +719,6 @@ __device__ double block_max(double v, int nan, int& any_nan)
     return r;
 }
 
-// Mismatch of one case (all threads of the workgroup): P, Q per bus and the
-// position-ordered rhs (F_P, F_Q), F_Q = 0 at PV buses.  Returns max |F|.
-template <class EF>
-__device__ double mismatch_case(const DevSym& S, const double* yv, const EF& ef,
-                                const int8_t* type, const double* Psp, const double* Qsp,
-                                double* P, double* Q, double* rhs, int& any_nan)
-{
-    double m = 0.0;
-    int nan = 0;
-    for (int i = threadIdx.x; i < S.n; i += blockDim.x) {
-        double p, q;
-        injection(S, yv, ef, i, p, q);
-        if (P) {
-            P[i] = p;
-            Q[i] = q;
-        }
-        const int ps = S.pos[i];
-        if (ps >= 0) {
-            const double fp = p - Psp[i];
-            const double fq = (type[i] == T_PV) ? 0.0 : q - Qsp[i];
-            reinterpret_cast<double2*>(rhs)[ps] = make_double2(fp, fq);
-            nan |= (fp != fp) | (fq != fq);
-            m = fmax(m, fmax(fabs(fp), fabs(fq)));
-        }
-    }
-    return block_max(m, nan, any_nan);
-}
-
 struct NewtonArgs {
     const double* yval;
     int64_t y_stride;
@@ -338,6 +735,8 @@ struct NewtonArgs {
     double tol;
     int max_iter;
     int flags;
+    int interleave;
+    int B;
     int32_t* iters;
     double* norm;
     int32_t* status;
@@ -348,29 +747,50 @@ struct CaseDesc {
     int64_t bus_off, br_off, y_off, ws_off;
 };
 
-// The whole Newton-Raphson loop of one case, run by one workgroup.
+// The whole Newton-Raphson loop of one case, run by one workgroup.  The
+// case's voltages and injections are copied into its bus records first and
+// the solution copied back at the end.
 __device__ void newton_case(const DevSym& S, const double* yv, const int8_t* type,
                             const double* Psp, const double* Qsp, double* Vm, double* Va,
-                            double* ws, double tol, int max_iter, int flags, int32_t* o_iters,
-                            double* o_norm, int32_t* o_status)
+                            const View& w, double tol, int max_iter, int flags,
+                            int32_t* o_iters, double* o_norm, int32_t* o_status)
 {
     __shared__ int s_bad;
-    CaseState c = case_state(S, ws);
+    const Off o = ws_off(S);
     for (int i = threadIdx.x; i < S.n; i += blockDim.x) {
         double sn, cs;
-        sincos(Va[i], &sn, &cs);
-        c.e[i] = Vm[i] * cs;
-        c.f[i] = Vm[i] * sn;
+        const double vm = Vm[i], va = Va[i];
+        sincos(va, &sn, &cs);
+        w.put(o.BUS + 8 * (int64_t)i, {vm * cs, vm * sn, vm, va});
+        w.put2(o.BUS + 8 * (int64_t)i + 6, make_double2(Psp[i], Qsp[i]));
     }
     if (threadIdx.x == 0) s_bad = 0;
     __syncthreads();
-    const EFArr ef{c.e, c.f};
-    const AsmState<EFArr> A{&S, yv, type, Vm, ef, c.P, c.Q};
+    const SrcState src{yv, type, w, o.BUS};
+    const EFView ef{w, o.BUS};
+    const bool tail = S.tail_nodes > 0;
     int it = 0, st = ST_NOT_CONVERGED;
     double nrm = 0.0;
     for (;;) {
+        double mx = 0.0;
+        int nan = 0;
+        for (int x = threadIdx.x; x < S.nn; x += blockDim.x) {
+            const int4 n0 = S.node_info[3 * x];
+            const int4 n2 = S.node_info[3 * x + 2];
+            const int bus = n0.y;
+            double p, q;
+            injection_row(S, yv, ef, bus, n2.x, n2.y, p, q);
+            const int64_t rec = o.BUS + 8 * (int64_t)bus;
+            const double2 sp = w.v2(rec + 6);
+            w.put2(rec + 4, make_double2(p, q));
+            const double fp = p - sp.x;
+            const double fq = (type[bus] == T_PV) ? 0.0 : q - sp.y;
+            w.put2(o.RHS + 2 * (int64_t)n0.x, make_double2(fp, fq));
+            nan |= (fp != fp) | (fq != fq);
+            mx = fmax(mx, fmax(fabs(fp), fabs(fq)));
+        }
         int any_nan = 0;
-        nrm = mismatch_case(S, yv, ef, type, Psp, Qsp, c.P, c.Q, c.rhs, any_nan);
+        nrm = block_max(mx, nan, any_nan);
         if (any_nan || !isfinite(nrm)) {
             st = ST_NONFINITE;
             break;
@@ -383,23 +803,31 @@ __device__ void newton_case(const DevSym& S, const double* yv, const int8_t* typ
             st = ST_NOT_CONVERGED;
             break;
         }
-        for_levels(S, true, [&](int j, int lane, int g) {
-            factor_node<AsmState<EFArr>, true>(S, A, j, lane, g, c.D, c.LU, c.rhs, &s_bad);
+        for_levels(S, 0, S.tail_level, true, [&](int x, int lane, int g) {
+            factor_node<SrcState, true>(S, src, x, lane, g, w, o.LU, o.RHS, &s_bad);
         });
+        if (tail) tail_factor<SrcState, true, false>(S, src, w, o.LU, o.RHS, &s_bad);
         if (s_bad) {
             st = ST_ZERO_PIVOT;
             break;
         }
-        for_levels(S, false, [&](int j, int lane, int g) {
-            back_node<true>(S, j, lane, g, c.LU, c.rhs, type, Vm, Va, c.e, c.f);
+        if (tail) tail_backward<true>(S, w, o.RHS, o.BUS, type);
+        for_levels(S, 0, S.tail_level, false, [&](int x, int lane, int g) {
+            back_node<true>(S, x, lane, g, w, o.LU, o.RHS, o.BUS, type);
         });
         ++it;
     }
     if ((flags & PF_NEWTON_KEEP_FACTORS) && st == ST_OK) {
-        for_levels(S, true, [&](int j, int lane, int g) {
-            factor_node<AsmState<EFArr>, false>(S, A, j, lane, g, c.D, c.LU, c.rhs, &s_bad);
+        for_levels(S, 0, S.tail_level, true, [&](int x, int lane, int g) {
+            factor_node<SrcState, false>(S, src, x, lane, g, w, o.LU, o.RHS, &s_bad);
         });
+        if (tail) tail_factor<SrcState, false, true>(S, src, w, o.LU, o.RHS, &s_bad);
         if (s_bad) st = ST_ZERO_PIVOT;
+    }
+    for (int i = threadIdx.x; i < S.n; i += blockDim.x) {
+        const Blk r = w.blk(o.BUS + 8 * (int64_t)i);
+        Vm[i] = r.c;
+        Va[i] = r.d;
     }
     if (threadIdx.x == 0) {
         if (o_iters) *o_iters = it;
@@ -407,6 +835,41 @@ __device__ void newton_case(const DevSym& S, const double* yv, const int8_t* typ
         if (o_status) *o_status = st;
     }
 }
+
+// Jacobian assembly straight from polar voltages (standalone kernel).
+struct AsmPolar {
+    const DevSym* S;
+    const double* yv;
+    const int8_t* type;
+    const double* Vm;
+    EFPolar ef;
+    __device__ __forceinline__ Blk diag(int j) const
+    {
+        const int bus = S->perm[j];
+        const double2 y = reinterpret_cast<const double2*>(yv)[S->ydiag[j]];
+        double p, q;
+        injection(*S, yv, ef, bus, p, q);
+        return jac_diag(y.x, y.y, p, q, Vm[bus], type[bus] == T_PV);
+    }
+    __device__ __forceinline__ void off(int j, int s, Blk& lo, Blk& up) const
+    {
+        const int ylo = S->ylo[s];
+        if (ylo < 0) {
+            lo = bzero();
+            up = bzero();
+            return;
+        }
+        const int bj = S->perm[j], bk = S->perm[S->Li[s]];
+        double ej, fj, ek, fk;
+        ef.get(bj, ej, fj);
+        ef.get(bk, ek, fk);
+        const bool pj = type[bj] == T_PV, pk = type[bk] == T_PV;
+        const double2 yl = reinterpret_cast<const double2*>(yv)[ylo];
+        const double2 yu = reinterpret_cast<const double2*>(yv)[S->yup[s]];
+        lo = jac_off(yl.x, yl.y, ek, fk, ej, fj, Vm[bj], pk, pj);
+        up = jac_off(yu.x, yu.y, ej, fj, ek, fk, Vm[bk], pj, pk);
+    }
+};
 
 }  // namespace
 
@@ -512,38 +975,41 @@ __global__ __launch_bounds__(kMaxThreads) void k_mismatch(
 
 __global__ void k_jacobian(DevSym S, const double* yval, int64_t y_stride, const int8_t* type,
                            int64_t type_stride, const double* Vm, const double* Va,
-                           int64_t v_stride, double* vals, int64_t vals_stride)
+                           int64_t v_stride, double* vals, int64_t vals_stride, int C)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
     if (j >= S.nn) return;
     const EFPolar ef{Vm + c * v_stride, Va + c * v_stride};
-    const AsmState<EFPolar> A{&S, yval + c * y_stride, type + c * type_stride,
-                              Vm + c * v_stride, ef, nullptr, nullptr};
-    double* D = vals + c * vals_stride;
-    double* LU = D + 4 * (int64_t)S.nn;
-    bstore(D + 4 * (int64_t)j, A.diag(j));
+    const AsmPolar A{&S, yval + c * y_stride, type + c * type_stride, Vm + c * v_stride, ef};
+    const View w = case_view(vals, vals_stride, C, c);
+    const int64_t lu = 4 * (int64_t)S.nn;
+    w.put(4 * (int64_t)j, A.diag(j));
     for (int s = S.Lp[j]; s < S.Lp[j + 1]; ++s) {
         Blk lo, up;
         A.off(j, s, lo, up);
-        bstore(LU + 8 * (int64_t)s, lo);
-        bstore(LU + 8 * (int64_t)s + 4, up);
+        w.put(lu + 8 * (int64_t)s, lo);
+        w.put(lu + 8 * (int64_t)s + 4, up);
     }
 }
 
 __global__ __launch_bounds__(kMaxThreads) void k_factor(DevSym S, double* vals,
-                                                        int64_t vals_stride, int32_t* status)
+                                                        int64_t vals_stride, int C, int B,
+                                                        int32_t* status)
 {
     __shared__ int s_bad;
-    const int c = blockIdx.x;
-    double* D = vals + c * vals_stride;
-    double* LU = D + 4 * (int64_t)S.nn;
+    const int c = case_of_block(blockIdx.x, C, B);
+    if (c < 0) return;
+    const View w = case_view(vals, vals_stride, C, c);
+    const int64_t lu = 4 * (int64_t)S.nn;
     if (threadIdx.x == 0) s_bad = 0;
     __syncthreads();
-    const AsmLoad A{D, LU};
-    for_levels(S, true, [&](int j, int lane, int g) {
-        factor_node<AsmLoad, false>(S, A, j, lane, g, D, LU, nullptr, &s_bad);
+    const SrcLoad src{w, lu};
+    for_levels(S, 0, S.tail_level, true, [&](int x, int lane, int g) {
+        factor_node<SrcLoad, false>(S, src, x, lane, g, w, lu, 0, &s_bad);
     });
+    if (S.tail_nodes > 0) tail_factor<SrcLoad, false, true>(S, src, w, lu, 0, &s_bad);
+    __syncthreads();
     if (threadIdx.x == 0 && status) status[c] = s_bad ? ST_ZERO_PIVOT : ST_OK;
 }
 
@@ -553,21 +1019,22 @@ __global__ __launch_bounds__(kMaxThreads) void k_factor(DevSym S, double* vals,
 //                l_j = D_j^-T (p_j - sum_{k in S(j)} W_kj^T l_k)  (levels down).
 template <bool TRANS>
 __global__ __launch_bounds__(kMaxThreads) void k_solve(DevSym S, const double* vals,
-                                                       int64_t vals_stride, double* rhs,
-                                                       int64_t rhs_stride)
+                                                       int64_t vals_stride, int C, int B,
+                                                       double* rhs, int64_t rhs_stride)
 {
-    const int c = blockIdx.x;
-    const double* D = vals + c * vals_stride;
-    const double* LU = D + 4 * (int64_t)S.nn;
-    double* x = rhs + c * rhs_stride;
-    double2* x2 = reinterpret_cast<double2*>(x);
-    for_levels(S, true, [&](int j, int lane, int g) {
+    const int c = case_of_block(blockIdx.x, C, B);
+    if (c < 0) return;
+    const View w = case_view(const_cast<double*>(vals), vals_stride, C, c);
+    const int64_t lu = 4 * (int64_t)S.nn;
+    double2* x2 = reinterpret_cast<double2*>(rhs + c * rhs_stride);
+    for_levels(S, 0, S.nlev, true, [&](int xi, int lane, int g) {
+        const int j = S.level_nodes[xi];
         double z0 = 0.0, z1 = 0.0;
         for (int r = S.Rp[j] + lane; r < S.Rp[j + 1]; r += g) {
-            const double2 xi = x2[S.Ri[r]];
-            const Blk M = bload(LU + 8 * (int64_t)S.Rs[r] + (TRANS ? 4 : 0));
-            if (TRANS) mtvadd(z0, z1, M, xi.x, xi.y);
-            else mvadd(z0, z1, M, xi.x, xi.y);
+            const double2 xv = x2[S.Ri[r]];
+            const Blk M = w.blk(lu + 8 * (int64_t)S.Rs[r] + (TRANS ? 4 : 0));
+            if (TRANS) mtvadd(z0, z1, M, xv.x, xv.y);
+            else mvadd(z0, z1, M, xv.x, xv.y);
         }
         if (g > 1) {
             z0 = gsum(z0, g);
@@ -577,7 +1044,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_solve(DevSym S, const double* v
             const double2 b = x2[j];
             double u0 = b.x - z0, u1 = b.y - z1;
             if (!TRANS) {
-                const Blk Di = bload(D + 4 * (int64_t)j);
+                const Blk Di = w.blk(4 * (int64_t)j);
                 double y0 = 0.0, y1 = 0.0;
                 mvadd(y0, y1, Di, u0, u1);
                 u0 = y0;
@@ -586,11 +1053,12 @@ __global__ __launch_bounds__(kMaxThreads) void k_solve(DevSym S, const double* v
             x2[j] = make_double2(u0, u1);
         }
     });
-    for_levels(S, false, [&](int j, int lane, int g) {
+    for_levels(S, 0, S.nlev, false, [&](int xi, int lane, int g) {
+        const int j = S.level_nodes[xi];
         double a0 = 0.0, a1 = 0.0;
         for (int s = S.Lp[j] + lane; s < S.Lp[j + 1]; s += g) {
             const double2 xk = x2[S.Li[s]];
-            const Blk M = bload(LU + 8 * (int64_t)s + (TRANS ? 0 : 4));
+            const Blk M = w.blk(lu + 8 * (int64_t)s + (TRANS ? 0 : 4));
             if (TRANS) mtvadd(a0, a1, M, xk.x, xk.y);
             else mvadd(a0, a1, M, xk.x, xk.y);
         }
@@ -602,7 +1070,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_solve(DevSym S, const double* v
             const double2 y = x2[j];
             double u0 = y.x - a0, u1 = y.y - a1;
             if (TRANS) {
-                const Blk Di = bload(D + 4 * (int64_t)j);
+                const Blk Di = w.blk(4 * (int64_t)j);
                 double l0 = 0.0, l1 = 0.0;
                 mtvadd(l0, l1, Di, u0, u1);
                 u0 = l0;
@@ -619,22 +1087,23 @@ __global__ __launch_bounds__(kMaxThreads) void k_newton(DevSym Sarg,
                                                         const int32_t* __restrict__ order,
                                                         NewtonArgs a)
 {
-    int c;
     if (MULTI) {
-        c = order[blockIdx.x];
+        const int c = order[blockIdx.x];
         const CaseDesc& cd = descs[c];
         const DevSym S = cd.sym;
+        const View w = case_view(a.ws + cd.ws_off, 0, 1, 0);
         newton_case(S, a.yval + cd.y_off, a.type + cd.bus_off, a.Psp + cd.bus_off,
-                    a.Qsp + cd.bus_off, a.Vm + cd.bus_off, a.Va + cd.bus_off,
-                    a.ws + cd.ws_off, a.tol, a.max_iter, a.flags,
-                    a.iters ? a.iters + c : nullptr, a.norm ? a.norm + c : nullptr,
-                    a.status ? a.status + c : nullptr);
+                    a.Qsp + cd.bus_off, a.Vm + cd.bus_off, a.Va + cd.bus_off, w, a.tol,
+                    a.max_iter, a.flags, a.iters ? a.iters + c : nullptr,
+                    a.norm ? a.norm + c : nullptr, a.status ? a.status + c : nullptr);
     } else {
-        c = blockIdx.x;
+        const int c = case_of_block(blockIdx.x, a.interleave, a.B);
+        if (c < 0) return;
+        const View w = case_view(a.ws, a.ws_stride, a.interleave, c);
         newton_case(Sarg, a.yval + c * a.y_stride, a.type + c * a.type_stride,
                     a.Psp + c * a.inj_stride, a.Qsp + c * a.inj_stride, a.Vm + c * a.v_stride,
-                    a.Va + c * a.v_stride, a.ws + c * a.ws_stride, a.tol, a.max_iter,
-                    a.flags, a.iters ? a.iters + c : nullptr, a.norm ? a.norm + c : nullptr,
+                    a.Va + c * a.v_stride, w, a.tol, a.max_iter, a.flags,
+                    a.iters ? a.iters + c : nullptr, a.norm ? a.norm + c : nullptr,
                     a.status ? a.status + c : nullptr);
     }
 }
@@ -671,7 +1140,7 @@ __global__ void k_adj_bus(DevSym S, const double* lam, int64_t lam_stride, const
 
 // dL/dx_e for one case: dS_f = V_f conj(dy (V_f - V_t)), dS_t = V_t conj(dy (V_t - V_f)),
 // dy = -j y^2, gx = -(lamP_f Re dS_f + lamQ_f Im dS_f + same at t).
-__device__ __forceinline__ double adj_branch(const DevSym& S, int e, int fb, int tb,
+__device__ __forceinline__ double adj_branch(const DevSym& S, int fb, int tb,
                                              const double* lam, const int8_t* type,
                                              const double* Vm, const double* Va, double r,
                                              double x)
@@ -699,10 +1168,12 @@ __device__ __forceinline__ double adj_branch(const DevSym& S, int e, int fb, int
         const double lq = (type[tb] == T_PV) ? 0.0 : l.y;
         acc += l.x * (-(et * cr + ft * ci)) + lq * (-(ft * cr - et * ci));
     }
-    (void)e;
     return -acc;
 }
 
+// mode 1 (x shared by the cases): one workgroup per 64 branches, its waves
+// split the cases and combine them in a fixed order, so no atomics are
+// needed and the sum is reproducible.  mode 0: one thread per (case, branch).
 __global__ void k_adj_branch(DevSym S, const int32_t* __restrict__ from,
                              const int32_t* __restrict__ to, int B, const double* lam,
                              int64_t lam_stride, const int8_t* type, int64_t type_stride,
@@ -710,20 +1181,31 @@ __global__ void k_adj_branch(DevSym S, const int32_t* __restrict__ from,
                              const double* r, const double* x, int64_t branch_stride,
                              double* gx, int mode)
 {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= S.m) return;
-    const int fb = from[e], tb = to[e];
     if (mode == 1) {
+        __shared__ double part[16][64];
+        const int e = blockIdx.x * 64 + (threadIdx.x & 63);
+        const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
         double acc = 0.0;
-        for (int c = 0; c < B; ++c)
-            acc += adj_branch(S, e, fb, tb, lam + c * lam_stride, type + c * type_stride,
-                              Vm + c * v_stride, Va + c * v_stride, r[c * branch_stride + e],
-                              x[c * branch_stride + e]);
-        gx[e] = acc;
+        if (e < S.m) {
+            const int fb = from[e], tb = to[e];
+            for (int c = wv; c < B; c += nw)
+                acc += adj_branch(S, fb, tb, lam + c * lam_stride, type + c * type_stride,
+                                  Vm + c * v_stride, Va + c * v_stride,
+                                  r[c * branch_stride + e], x[c * branch_stride + e]);
+        }
+        part[wv][threadIdx.x & 63] = acc;
+        __syncthreads();
+        if (wv == 0 && e < S.m) {
+            double s = 0.0;
+            for (int k = 0; k < nw; ++k) s += part[k][threadIdx.x];
+            gx[e] = s;
+        }
     } else {
+        const int e = blockIdx.x * blockDim.x + threadIdx.x;
         const int c = blockIdx.y;
+        if (e >= S.m) return;
         gx[(int64_t)c * S.m + e] =
-            adj_branch(S, e, fb, tb, lam + c * lam_stride, type + c * type_stride,
+            adj_branch(S, from[e], to[e], lam + c * lam_stride, type + c * type_stride,
                        Vm + c * v_stride, Va + c * v_stride, r[c * branch_stride + e],
                        x[c * branch_stride + e]);
     }
@@ -734,7 +1216,6 @@ __global__ void k_adj_branch(DevSym S, const int32_t* __restrict__ from,
 // ===========================================================================
 struct pf_symbolic_s {
     HostSym h;
-    int threads = 256;
     const int32_t* d_from = nullptr;  // device copies of the branch ends
     const int32_t* d_to = nullptr;
 };
@@ -743,7 +1224,6 @@ struct pf_multi_s {
     std::vector<pf_symbolic> syms;
     std::vector<int64_t> bus_off, br_off, y_off, ws_off;
     std::vector<int32_t> order;
-    int threads = 256;
     const CaseDesc* d_desc = nullptr;
     const int32_t* d_order = nullptr;
     bool uploaded = false;
@@ -767,6 +1247,65 @@ int hip_check(hipError_t e, const char* what)
 }
 
 int launch_check(const char* what) { return hip_check(hipGetLastError(), what); }
+
+// Workgroup size of the level-scheduled kernels: the symbolic's setting, or
+// by batch size so that a small batch still brings 16 waves to its CUs.
+int launch_threads(const HostSym& h, int B)
+{
+    if (h.threads > 0) return h.threads;
+    if (B <= 256) return 1024;
+    if (B <= 512) return 512;
+    return 256;
+}
+
+// Blocks for B cases in groups of C placed one XCD round apart.
+int grid_blocks(int B, int C)
+{
+    if (C <= 1) return B;
+    const int span = 8 * C;
+    return ((B + span - 1) / span) * span;
+}
+
+bool valid_interleave(int C) { return C == 1 || C == 2 || C == 4 || C == 8; }
+
+// Interleave pf_newton uses for B cases: the symbolic's setting, reduced so
+// that a group never outnumbers the batch (a lone case stays contiguous).
+int newton_interleave(const HostSym& h, int B)
+{
+    int C = h.interleave;
+    while (C > 1 && C > B) C >>= 1;
+    return C;
+}
+
+// Raises the dynamic-LDS limit of the level-scheduled kernels to what the
+// device allows (160 KB per workgroup on gfx950) minus their static LDS.
+// Failures only keep the default limit; the sticky error is cleared so that
+// it is not reported by the next launch check.
+void allow_big_lds()
+{
+    static bool done = false;
+    if (done) return;
+    done = true;
+    int dev = 0, lds_max = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+            hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    const void* kernels[] = {reinterpret_cast<const void*>(&k_newton<false>),
+                             reinterpret_cast<const void*>(&k_newton<true>),
+                             reinterpret_cast<const void*>(&k_factor)};
+    for (const void* k : kernels) {
+        hipFuncAttributes fa{};
+        if (hipFuncGetAttributes(&fa, k) == hipSuccess) {
+            const int dyn = lds_max - (int)fa.sharedSizeBytes;
+            if (dyn > 0)
+                (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+        }
+    }
+    (void)hipGetLastError();
+}
 
 bool ready(const pf_symbolic s, const char* fn)
 {
@@ -842,7 +1381,13 @@ int pf_symbolic_info(const pf_symbolic s, pf_info* info)
     info->max_level_width = h.max_width;
     info->vals_doubles = h.vals_doubles();
     info->ws_doubles = h.ws_doubles();
-    info->dev_bytes = h.dev_bytes() + 2 * ((std::max<size_t>(h.m, 1) * 4 + 255) & ~(size_t)255);
+    info->dev_bytes = h.dev_bytes();
+    info->tail_levels = (int32_t)h.level_ptr.size() - 1 - h.tail_level;
+    info->tail_nodes = h.tail_nodes;
+    info->tail_lds_bytes = h.tail_lds;
+    info->tail_clique = h.tail_clique;
+    info->ws_interleave = h.interleave;
+    info->threads = h.threads;
     return PF_OK;
 }
 
@@ -884,6 +1429,32 @@ int pf_symbolic_set_mapping(pf_symbolic s, const int32_t* lanes)
     }
     for (int l = 0; l < nlev; ++l) s->h.level_g[l] = lanes[l];
     return PF_OK;
+}
+
+int pf_symbolic_set_launch(pf_symbolic s, int threads, int64_t tail_lds_budget, int interleave)
+{
+    if (!s) return fail(PF_E_INVALID, "pf_symbolic_set_launch: NULL symbolic");
+    if (!valid_interleave(interleave))
+        return fail(PF_E_INVALID, "pf_symbolic_set_launch: interleave must be 1, 2, 4 or 8");
+    s->h.interleave = interleave;
+    if (threads != 0 && threads != 64 && threads != 128 && threads != 256 && threads != 512 &&
+        threads != 1024)
+        return fail(PF_E_INVALID, "pf_symbolic_set_launch: threads must be 0 or 64..1024 (pow2)");
+    if (tail_lds_budget < 0 || tail_lds_budget > 158 * 1024)
+        return fail(PF_E_INVALID, "pf_symbolic_set_launch: tail budget must be 0..161792 bytes");
+    s->h.threads = threads;
+    if (tail_lds_budget != s->h.tail_budget) {
+        s->h.tail_budget = tail_lds_budget;
+        pf::build_tail(s->h, tail_lds_budget);
+        s->h.uploaded = false;  // device copy is stale: upload again
+    }
+    return PF_OK;
+}
+
+int pf_newton_interleave(const pf_symbolic s, int B)
+{
+    if (!s || B < 0) return fail(PF_E_INVALID, "pf_newton_interleave: bad arguments"), -1;
+    return newton_interleave(s->h, B);
 }
 
 int pf_symbolic_get_mapping(const pf_symbolic s, int32_t* lanes)
@@ -939,15 +1510,35 @@ int pf_symbolic_upload(pf_symbolic s, void* d_buf, size_t bytes, void* stream)
     d.Rp = put(h.Rp);
     d.Ri = put(h.Ri);
     d.Rs = put(h.Rs);
-    d.Up = put(h.Up);
-    d.Ua = put(h.Ua);
-    d.Ub = put(h.Ub);
     d.level_ptr = put(h.level_ptr);
     d.level_nodes = put(h.level_nodes);
     d.level_g = put(h.level_g);
+    d.node_info = reinterpret_cast<const int4*>(put(h.node_info));
+    d.slot_info = reinterpret_cast<const int4*>(put(h.slot_info));
+    d.rl = reinterpret_cast<const int2*>(put(h.rl));
+    d.upd = reinterpret_cast<const int2*>(put(h.upd));
+    d.tail_level = h.tail_level;
+    d.tail_nodes = h.tail_nodes;
+    d.tail_slots = h.tail_slots;
+    d.tail_lds = h.tail_lds;
+    d.tail_clique = h.tail_clique;
+    d.t_node = reinterpret_cast<const int4*>(put(h.t_node));
+    d.t_slot = reinterpret_cast<const int4*>(put(h.t_slot));
+    d.t_rl = reinterpret_cast<const int2*>(put(h.t_rl));
+    d.t_upd = reinterpret_cast<const int2*>(put(h.t_upd));
+    d.t_lptr = put(h.t_lptr);
     s->d_from = put(h.from);
     s->d_to = put(h.to);
     if (off > info.dev_bytes) return fail(PF_E_WORKSPACE, "pf_symbolic_upload: size mismatch");
+    {
+        int dev = 0, lds_max = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) ==
+                hipSuccess &&
+            h.tail_lds + 2048 > lds_max)
+            return fail(PF_E_WORKSPACE, "pf_symbolic_upload: LDS tail larger than the device's "
+                                        "LDS; lower it with pf_symbolic_set_launch");
+    }
     int rc = hip_check(hipMemcpyAsync(d_buf, stage.data(), off, hipMemcpyHostToDevice,
                                       as_stream(stream)),
                        "pf_symbolic_upload: hipMemcpyAsync");
@@ -995,48 +1586,56 @@ int pf_mismatch(const pf_symbolic s, int B, const double* d_yval, int64_t y_stri
 
 int pf_jacobian(const pf_symbolic s, int B, const double* d_yval, int64_t y_stride,
                 const int8_t* d_type, int64_t type_stride, const double* d_Vm, const double* d_Va,
-                int64_t v_stride, double* d_vals, int64_t vals_stride, void* stream)
+                int64_t v_stride, double* d_vals, int64_t vals_stride, int vals_interleave,
+                void* stream)
 {
     if (!ready(s, "pf_jacobian")) return PF_E_INVALID;
-    if (B < 0 || B > 65535 || !d_yval || !d_type || !d_Vm || !d_Va || !d_vals)
+    if (B < 0 || B > 65535 || !d_yval || !d_type || !d_Vm || !d_Va || !d_vals ||
+        !valid_interleave(vals_interleave) || (vals_stride & 3))
         return fail(PF_E_INVALID, "pf_jacobian: bad arguments");
     if (B > 1 && vals_stride < s->h.vals_doubles())
         return fail(PF_E_WORKSPACE, "pf_jacobian: vals_stride < vals_doubles");
     if (B == 0 || s->h.nn == 0) return PF_OK;
     dim3 grid((s->h.nn + 255) / 256, B);
     hipLaunchKernelGGL(k_jacobian, grid, dim3(256), 0, as_stream(stream), s->h.dev, d_yval,
-                       y_stride, d_type, type_stride, d_Vm, d_Va, v_stride, d_vals, vals_stride);
+                       y_stride, d_type, type_stride, d_Vm, d_Va, v_stride, d_vals, vals_stride,
+                       vals_interleave);
     return launch_check("pf_jacobian");
 }
 
 int pf_factor(const pf_symbolic s, int B, double* d_vals, int64_t vals_stride,
-              int32_t* d_status, void* stream)
+              int vals_interleave, int32_t* d_status, void* stream)
 {
     if (!ready(s, "pf_factor")) return PF_E_INVALID;
-    if (B < 0 || !d_vals) return fail(PF_E_INVALID, "pf_factor: bad arguments");
+    if (B < 0 || !d_vals || !valid_interleave(vals_interleave) || (vals_stride & 3))
+        return fail(PF_E_INVALID, "pf_factor: bad arguments");
     if (B > 1 && vals_stride < s->h.vals_doubles())
         return fail(PF_E_WORKSPACE, "pf_factor: vals_stride < vals_doubles");
     if (B == 0) return PF_OK;
-    hipLaunchKernelGGL(k_factor, dim3(B), dim3(s->threads), 0, as_stream(stream), s->h.dev,
-                       d_vals, vals_stride, d_status);
+    allow_big_lds();
+    hipLaunchKernelGGL(k_factor, dim3(grid_blocks(B, vals_interleave)),
+                       dim3(launch_threads(s->h, B)), s->h.tail_lds, as_stream(stream), s->h.dev,
+                       d_vals, vals_stride, vals_interleave, B, d_status);
     return launch_check("pf_factor");
 }
 
 int pf_solve(const pf_symbolic s, int B, const double* d_vals, int64_t vals_stride,
-             double* d_rhs, int64_t rhs_stride, int transpose, void* stream)
+             int vals_interleave, double* d_rhs, int64_t rhs_stride, int transpose, void* stream)
 {
     if (!ready(s, "pf_solve")) return PF_E_INVALID;
-    if (B < 0 || !d_vals || !d_rhs || (transpose != 0 && transpose != 1))
+    if (B < 0 || !d_vals || !d_rhs || (transpose != 0 && transpose != 1) ||
+        !valid_interleave(vals_interleave) || (vals_stride & 3))
         return fail(PF_E_INVALID, "pf_solve: bad arguments");
     if (B > 1 && rhs_stride < 2 * (int64_t)s->h.nn)
         return fail(PF_E_WORKSPACE, "pf_solve: rhs_stride < 2*nn");
     if (B == 0) return PF_OK;
+    const dim3 grid(grid_blocks(B, vals_interleave)), block(launch_threads(s->h, B));
     if (transpose)
-        hipLaunchKernelGGL(k_solve<true>, dim3(B), dim3(s->threads), 0, as_stream(stream),
-                           s->h.dev, d_vals, vals_stride, d_rhs, rhs_stride);
+        hipLaunchKernelGGL(k_solve<true>, grid, block, 0, as_stream(stream), s->h.dev, d_vals,
+                           vals_stride, vals_interleave, B, d_rhs, rhs_stride);
     else
-        hipLaunchKernelGGL(k_solve<false>, dim3(B), dim3(s->threads), 0, as_stream(stream),
-                           s->h.dev, d_vals, vals_stride, d_rhs, rhs_stride);
+        hipLaunchKernelGGL(k_solve<false>, grid, block, 0, as_stream(stream), s->h.dev, d_vals,
+                           vals_stride, vals_interleave, B, d_rhs, rhs_stride);
     return launch_check("pf_solve");
 }
 
@@ -1051,15 +1650,21 @@ int pf_newton(const pf_symbolic s, int B, const double* d_yval, int64_t y_stride
     if (B < 0 || max_iter < 0 || !(tol >= 0.0) || !d_yval || !d_type || !d_Psp || !d_Qsp ||
         !d_Vm || !d_Va || !d_ws)
         return fail(PF_E_INVALID, "pf_newton: bad arguments");
-    if (B > 1 && (ws_stride < s->h.ws_doubles() || v_stride < s->h.n))
-        return fail(PF_E_WORKSPACE, "pf_newton: ws_stride or v_stride too small");
+    if (B > 1 && v_stride < s->h.n)
+        return fail(PF_E_WORKSPACE, "pf_newton: v_stride too small");
+    if (ws_stride < s->h.ws_doubles() || (ws_stride & 3))
+        return fail(PF_E_WORKSPACE, "pf_newton: ws_stride must be >= ws_doubles, a multiple of 4");
     if (reinterpret_cast<uintptr_t>(d_ws) & 15)
         return fail(PF_E_WORKSPACE, "pf_newton: workspace must be 16-byte aligned");
     if (B == 0) return PF_OK;
+    const int C = newton_interleave(s->h, B);
     NewtonArgs a{d_yval, y_stride, d_type, type_stride, d_Psp, d_Qsp, inj_stride, d_Vm, d_Va,
-                 v_stride, d_ws, ws_stride, tol, max_iter, flags, d_iters, d_norm, d_status};
-    hipLaunchKernelGGL(k_newton<false>, dim3(B), dim3(s->threads), 0, as_stream(stream),
-                       s->h.dev, (const CaseDesc*)nullptr, (const int32_t*)nullptr, a);
+                 v_stride, d_ws, ws_stride, tol, max_iter, flags, C, B, d_iters, d_norm,
+                 d_status};
+    allow_big_lds();
+    hipLaunchKernelGGL(k_newton<false>, dim3(grid_blocks(B, C)), dim3(launch_threads(s->h, B)),
+                       s->h.tail_lds, as_stream(stream), s->h.dev, (const CaseDesc*)nullptr,
+                       (const int32_t*)nullptr, a);
     return launch_check("pf_newton");
 }
 
@@ -1083,8 +1688,10 @@ int pf_adjoint_params(const pf_symbolic s, int B, const double* d_lam, int64_t l
     }
     if (d_gx && s->h.m > 0) {
         if (!d_r || !d_x) return fail(PF_E_INVALID, "pf_adjoint_params: need r and x");
-        dim3 grid((s->h.m + 255) / 256, gx_mode == 1 ? 1 : B);
-        hipLaunchKernelGGL(k_adj_branch, grid, dim3(256), 0, as_stream(stream), s->h.dev,
+        const dim3 grid(gx_mode == 1 ? (s->h.m + 63) / 64 : (s->h.m + 255) / 256,
+                        gx_mode == 1 ? 1 : B);
+        const dim3 block(gx_mode == 1 ? 1024 : 256);
+        hipLaunchKernelGGL(k_adj_branch, grid, block, 0, as_stream(stream), s->h.dev,
                            s->d_from, s->d_to, B, d_lam, lam_stride, d_type, type_stride, d_Vm,
                            d_Va, v_stride, d_r, d_x, branch_stride, d_gx, gx_mode);
         return launch_check("pf_adjoint_params");
@@ -1217,9 +1824,16 @@ int pf_newton_multi(const pf_multi p, const double* d_yval, const int8_t* d_type
         return fail(PF_E_WORKSPACE, "pf_newton_multi: workspace must be 16-byte aligned");
     if (p->syms.empty()) return PF_OK;
     NewtonArgs a{d_yval, 0, d_type, 0, d_Psp, d_Qsp, 0, d_Vm, d_Va, 0, d_ws, 0, tol, max_iter,
-                 flags, d_iters, d_norm, d_status};
+                 flags, 1, (int)p->syms.size(), d_iters, d_norm, d_status};
     DevSym none{};
-    hipLaunchKernelGGL(k_newton<true>, dim3(p->syms.size()), dim3(p->threads), 0,
+    int lds = 0, threads = 0;
+    for (auto* sy : p->syms) {
+        lds = std::max(lds, sy->h.tail_lds);
+        threads = std::max(threads, sy->h.threads);
+    }
+    if (threads == 0) threads = (p->syms.size() <= 256) ? 1024 : 256;
+    allow_big_lds();
+    hipLaunchKernelGGL(k_newton<true>, dim3(p->syms.size()), dim3(threads), lds,
                        as_stream(stream), none, p->d_desc, p->d_order, a);
     return launch_check("pf_newton_multi");
 }

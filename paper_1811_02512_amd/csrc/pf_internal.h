@@ -1,6 +1,8 @@
 // Internal structures shared by the host analysis and the HIP kernels.
 #pragma once
 
+#include <hip/hip_vector_types.h>
+
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -10,6 +12,39 @@ namespace pf {
 // Device view of one symbolic analysis.  Every pointer is a device address
 // inside the caller's upload buffer.  Passed to kernels by value, or stored
 // in a per-case table for batches with several sparsity patterns.
+//
+// Packed records (int4 = 4 x int32) let a lane fetch everything it needs
+// about a node or a slot with one or two wide loads instead of a chain of
+// dependent scalar loads:
+//   node_info[x] (level order, 3 x int4): {j, bus, r0, r1}, {s0, s1, ydiag, 0},
+//                                          {q0, q1, 0, 0}
+//     j = position, [r0, r1) = its lower-neighbour range in rl,
+//     [s0, s1) = its slots (higher neighbours), ydiag = Y entry (bus, bus),
+//     [q0, q1) = the bus's admittance row
+//   slot_info[s] (2 x int4): {k, bus_k, ylo, yup}, {u0, u1, 0, 0}
+//     k = higher neighbour, ylo/yup = Y entries (bus_k, bus_j) / (bus_j,
+//     bus_k) or -1 for fill, [u0, u1) = its update pairs in upd
+//   rl[r] = (i, slot(i;j))      upd[u] = (slot(i;k), slot(i;j))
+//
+// Tail: the top levels [tail_level, nlev) of the elimination tree, whose
+// values fit in LDS, are factorised and solved in LDS.  Every higher
+// neighbour of a tail node is itself in the tail.  Local numbering: tail
+// nodes 0..K-1 in level order, tail slots 0..TS-1 in node order.
+//   t_node[jl] (3 x int4): {j, bus, ydiag, sl0}, {sl1, rn0, rn1, rt1}, {rmid, 0, 0, 0}
+//     [sl0, sl1) local slots, [rn0, rn1) lower neighbours outside the tail
+//     as (i, slot) global pairs in t_rl, [rn1, rt1) lower neighbours inside
+//     the tail as (local i, local slot) pairs in t_rl, those below the
+//     clique first: [rn1, rmid) below, [rmid, rt1) in the clique
+//   t_slot[t] (3 x int4): {s, kl, bus_k, ylo}, {yup, un0, un1, ut1},
+//                         {bus_j, jl, umid, 0}
+//     s = global slot, kl = local node of k, [un0, un1) update pairs from
+//     outside the tail (global slots) and [un1, ut1) from inside (local),
+//     [un1, umid) from below the clique, [umid, ut1) from the clique;
+//     jl = local node owning the slot
+//   The clique is the last tail_clique local nodes: a chain of single-node
+//   levels, each adjacent to every node above it (local slot of clique pair
+//   (a, b), a < b, is t_node[a].sl0 + b - a - 1).
+//   t_lptr[l - tail_level .. ]: local node range of each tail level
 struct DevSym {
     int32_t n, m, nn, slack;
     int32_t nnz_y, nnz_l, nlev, pad0;
@@ -33,15 +68,23 @@ struct DevSym {
     const int32_t* Rp;       // nn+1
     const int32_t* Ri;       // nnz_l: i
     const int32_t* Rs;       // nnz_l: slot of p in S(i)
-    // per destination slot s = (p;k): pairs (slot(i;k), slot(i;p)) of the
-    // descendants i that update block (k,p) and (p,k)
-    const int32_t* Up;       // nnz_l+1
-    const int32_t* Ua;       // n_upd
-    const int32_t* Ub;       // n_upd
     // hierarchical partition
     const int32_t* level_ptr;    // nlev+1
     const int32_t* level_nodes;  // nn
     const int32_t* level_g;      // nlev: lanes per node
+    // packed records
+    const int4* node_info;   // 3 nn
+    const int4* slot_info;   // 2 nnz_l
+    const int2* rl;          // nnz_l
+    const int2* upd;         // n_upd
+    // LDS tail
+    int32_t tail_level, tail_nodes, tail_slots, tail_lds;
+    int32_t tail_clique, pad1;
+    const int4* t_node;      // 3 K
+    const int4* t_slot;      // 3 TS
+    const int2* t_rl;
+    const int2* t_upd;
+    const int32_t* t_lptr;   // nlev - tail_level + 1
 };
 
 struct HostSym {
@@ -53,24 +96,37 @@ struct HostSym {
     std::vector<int32_t> Rp, Ri, Rs;
     std::vector<int32_t> Up, Ua, Ub;
     std::vector<int32_t> level_ptr, level_nodes, level_g;
+    std::vector<int32_t> node_info, slot_info, rl, upd;  // packed (int32 view)
+    // tail
+    int32_t tail_level = 0, tail_nodes = 0, tail_slots = 0, tail_lds = 0, tail_clique = 0;
+    int64_t tail_budget = 64 * 1024;
+    std::vector<int32_t> t_node, t_slot, t_rl, t_upd, t_lptr;
     int32_t max_width = 0;
+    int32_t threads = 0;  // 0: chosen per launch from the batch size
+    int32_t interleave = 4;  // cases per interleaved workspace group
     // device copy
     DevSym dev{};
     bool uploaded = false;
 
     int64_t vals_doubles() const { return 4 * (int64_t)nn + 8 * (int64_t)Li.size(); }
     int64_t ws_doubles() const {
-        // vals | e f P Q (n each) | rhs (2 nn)
-        int64_t w = vals_doubles() + 4 * (int64_t)n + 2 * (int64_t)nn;
+        // vals | bus records (8 n) | rhs (2 nn)
+        int64_t w = vals_doubles() + 8 * (int64_t)n + 2 * (int64_t)nn;
         return (w + 31) & ~(int64_t)31;
     }
     size_t dev_bytes() const;
 };
+
+// LDS bytes of a tail with K nodes and TS slots: W and U (or V) blocks per
+// slot, D^-1 and the forward vector per node.
+inline int64_t tail_bytes(int64_t K, int64_t TS) { return TS * 64 + K * 48; }
 
 // Host analysis; returns a pf_status code and sets msg on failure.
 int analyze(int n, int m, const int32_t* from, const int32_t* to, int slack, int ordering,
             HostSym& out, std::string& msg);
 // Default lanes-per-node for every level from a simple work model.
 void default_mapping(HostSym& s);
+// (Re)builds the LDS tail for an LDS budget in bytes (0 disables it).
+void build_tail(HostSym& s, int64_t budget);
 
 }  // namespace pf

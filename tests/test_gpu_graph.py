@@ -28,7 +28,7 @@ def test_graph_replays_match_eager():
     Vm_in = s.Vm0.repeat(Bn, 1).contiguous()
     Va_in = s.Va0.repeat(Bn, 1).contiguous()
     Vm, Va = Vm_in.clone(), Va_in.clone()
-    ws = torch.empty(Bn, info.ws_doubles, dtype=torch.float64, device="cuda")
+    ws = s.sym.workspace(Bn)
     it = torch.empty(Bn, dtype=torch.int32, device="cuda")
     nrm = torch.empty(Bn, dtype=torch.float64, device="cuda")
     st = torch.empty(Bn, dtype=torch.int32, device="cuda")

@@ -261,3 +261,83 @@ def test_two_bus_closed_form():
     assert status.item() == 0
     assert Vm[0, 1].item() == pytest.approx(vm, abs=1e-12)
     assert Va[0, 1].item() == pytest.approx(th, abs=1e-12)
+
+
+@pytest.mark.parametrize("threads,budget", [(64, 0), (256, 4096), (1024, 65536), (512, 161792),
+                                            (128, 20000)])
+def test_launch_shapes_and_lds_tail(O, threads, budget):
+    """Every workgroup size and LDS-tail size gives the oracle's solution, and
+    the standalone factorisation (which writes the tail back) matches too."""
+    B = _B()
+    s = staged(2000, 2)
+    g = s.g
+    s.sym.set_launch(threads, budget)
+    info = s.info
+    log(f"[launch] threads={threads} budget={budget} tail_levels={info.tail_levels} "
+        f"tail_nodes={info.tail_nodes} lds={info.tail_lds_bytes}")
+    ref = O.solve_grid(g)
+    Vm, Va, iters, _, status, _ = s.newton(2)
+    assert (status.cpu().numpy() == 0).all()
+    assert (iters.cpu().numpy() == ref.iters).all()
+    np.testing.assert_allclose(Vm[1].cpu().numpy(), ref.Vm, atol=1e-9)
+    np.testing.assert_allclose(Va[1].cpu().numpy(), ref.Va, atol=1e-9)
+    Vm_, Va_ = rand_state(g, 5)
+    _, _, _, vals = jac_gpu(s, Vm_, Va_)
+    sym = O.Sym(g.n, g.f, g.t)
+    oD, oL, oU = sym.block_jacobian(O.grid_ybus(g), g.bus_type, Vm_, Va_)
+    fD, fL, fU, _ = sym.factor(oD, oL, oU)
+    B.pf_factor(s.sym.h, 1, vals, info.vals_doubles, None)
+    v = vals[0].cpu().numpy()
+    nn = info.nn
+    np.testing.assert_allclose(v[4 * nn:].reshape(-1, 2, 2, 2)[:, 1], fU, rtol=0,
+                               atol=1e-10 * max(1.0, np.abs(fU).max()))
+    np.testing.assert_allclose(np.linalg.inv(v[:4 * nn].reshape(-1, 2, 2)), fD, rtol=0,
+                               atol=1e-10 * np.abs(fD).max())
+
+
+@pytest.mark.parametrize("C", [1, 2, 8])
+def test_interleaved_case_groups_bitwise_equal(C):
+    """The workspace grouping (1, 2, 4 or 8 cases per 32-byte-interleaved
+    group, groups spread over the XCDs) changes addresses only: results are
+    bitwise those of the default grouping, for a batch that is not a
+    multiple of the group size."""
+    s = staged(2000, 3)
+    g = s.g
+    Bn = 7
+    P, Q = gridgen.scenario_injections(g, Bn, seed=11)
+    ref = s.newton(Bn, dev(P), dev(Q))
+    s.sym.set_launch(0, 65536, C)
+    assert s.sym.info.ws_interleave == C
+    got = s.newton(Bn, dev(P), dev(Q))
+    s.sym.set_launch(0, 65536, 4)
+    for a, b in zip(ref[:5], got[:5]):
+        assert torch.equal(a, b)
+
+
+def test_factor_solve_interleaved_vals():
+    B = _B()
+    s = staged(300, 5)
+    g = s.g
+    nn = s.info.nn
+    vd = s.info.vals_doubles
+    Bn, C = 5, 4
+    rows = -(-Bn // C) * C
+    rng = np.random.default_rng(3)
+    plain = torch.zeros(Bn, vd, dtype=torch.float64, device="cuda")
+    inter = torch.zeros(rows, vd, dtype=torch.float64, device="cuda")
+    states = [rand_state(g, 20 + c) for c in range(Bn)]
+    Vm = dev(np.stack([v for v, _ in states]))
+    Va = dev(np.stack([a for _, a in states]))
+    B.pf_jacobian(s.sym.h, Bn, s.yval, 0, s.type, 0, Vm, Va, g.n, plain, vd, 1)
+    B.pf_jacobian(s.sym.h, Bn, s.yval, 0, s.type, 0, Vm, Va, g.n, inter, vd, C)
+    B.pf_factor(s.sym.h, Bn, plain, vd, None, 1)
+    B.pf_factor(s.sym.h, Bn, inter, vd, None, C)
+    rhs = rng.standard_normal((Bn, 2 * nn))
+    r1 = dev(rhs.copy())
+    r2 = dev(rhs.copy())
+    B.pf_solve(s.sym.h, Bn, plain, vd, r1, 2 * nn, 1, 1)
+    B.pf_solve(s.sym.h, Bn, inter, vd, r2, 2 * nn, 1, C)
+    assert torch.equal(r1, r2)
+    # the interleaved buffer holds the same numbers, just regrouped
+    v = inter.view(rows // C, vd // 4, C, 4).permute(0, 2, 1, 3).reshape(rows, vd)[:Bn]
+    assert torch.equal(v, plain)

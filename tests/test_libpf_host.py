@@ -118,7 +118,7 @@ def test_device_calls_need_upload(B):
     h = B.pf_analyze(g.n, g.f, g.t)
     buf = np.zeros(8)
     with pytest.raises(B.PfError) as ei:
-        B.check(B.lib.pf_factor(h, 1, buf.ctypes.data, 0, None, None), "pf_factor")
+        B.check(B.lib.pf_factor(h, 1, buf.ctypes.data, 0, 1, None, None), "pf_factor")
     assert ei.value.code == B.PF_E_INVALID
     assert "not uploaded" in B.last_error()
     with pytest.raises(B.PfError):
@@ -153,3 +153,18 @@ def test_multi_plan_offsets(B):
     B.pf_multi_destroy(p)
     for h in hs:
         B.pf_symbolic_destroy(h)
+
+
+def test_single_hip_runtime_whatever_the_import_order():
+    """Importing the package before torch must not load a second HIP runtime."""
+    import subprocess
+    import sys
+
+    code = ("import paper_1811_02512_amd, torch\n"
+            "maps = [l.split()[-1] for l in open('/proc/self/maps') "
+            "if 'libamdhip64' in l and 'r-xp' in l]\n"
+            "print(len(set(maps)))\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                         timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
