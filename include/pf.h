@@ -142,8 +142,8 @@ int pf_symbolic_export(const pf_symbolic sym, int32_t* perm, int32_t* parent,
  * level-scheduled kernels.  Defaults come from a work model; an autotuner may
  * replace them.  Takes effect at the next pf_symbolic_upload.             */
 int pf_symbolic_set_mapping(pf_symbolic sym, const int32_t* lanes_per_level);
-/* Launch shape of the level-scheduled kernels: threads per workgroup (0 =
- * by batch size: 1024 up to 256 cases, 512 up to 512, else 256) and the LDS
+/* Launch shape of the level-scheduled kernels: threads per workgroup (64,
+ * 128, 256 or 512; 0 = by batch size: 512 up to 512 cases, else 256) and the LDS
  * budget in bytes of the tail, the largest run of top levels whose values
  * (64 bytes per filled slot, 48 per node) are factorised and solved in LDS
  * (0 = none, at most 161792 so that 2 KB of LDS stay for reductions;

@@ -2,7 +2,7 @@
 
 The search times the real batched Newton launch (pf_newton on the caller's
 batch) with HIP events and keeps the fastest setting of:
-  * threads per workgroup (256, 512, 1024),
+  * threads per workgroup (256, 512),
   * LDS-tail budget (how many top levels run in LDS),
   * case interleave of the workspace (1, 2, 4, 8),
   * lanes per node for each level class (levels grouped by width), by
@@ -81,7 +81,7 @@ class _Timer:
 
 
 def tune(sym, yval, bus_type, Psp, Qsp, Vm0, Va0, tol=1e-8, max_iter=20, reps=2,
-         threads=(256, 512, 1024), budgets=(32768, 65536, 114688, 161792),
+         threads=(256, 512), budgets=(32768, 65536, 114688, 161792),
          interleaves=(1, 2, 4, 8), passes=2, verbose=False):
     """Tunes `sym` (an uploaded api.Symbolic) for this batch in place.
 

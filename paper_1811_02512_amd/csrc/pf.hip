@@ -45,6 +45,11 @@ extern __shared__ double pf_smem[];  // LDS tail (dynamic size: DevSym::tail_lds
 namespace {
 
 constexpr int kMaxThreads = 1024;
+// The level-scheduled kernels are bounded at 512 threads per workgroup, which
+// leaves them 256 VGPRs per lane: their per-node working set (two 2x2
+// destination pairs, prefetched records, reduction partials) then fits in
+// registers without spilling.
+constexpr int kLevelThreads = 512;
 constexpr int kXcds = 8;
 
 // One case's doubles inside an interleaved group of C cases: element d
@@ -240,6 +245,43 @@ __device__ __forceinline__ void for_levels(const DevSym& S, int l0, int l1, bool
     }
 }
 
+// Level-ordered node record (see DevSym::node_info).
+struct NodeRec {
+    int4 a, b, c;
+};
+
+__device__ __forceinline__ NodeRec load_rec(const DevSym& S, int x)
+{
+    return {S.node_info[3 * x], S.node_info[3 * x + 1], S.node_info[3 * x + 2]};
+}
+
+// As for_levels, passing fn(x, rec, lane, g) the node's record; the record
+// of the group's next node in the level is fetched before fn runs so that
+// its latency overlaps the current node's work.
+template <class F>
+__device__ __forceinline__ void for_nodes(const DevSym& S, int l0, int l1, bool up, F&& fn)
+{
+    for (int li = l0; li < l1; ++li) {
+        const int l = up ? li : l1 - 1 - (li - l0);
+        const int g = S.level_g[l];
+        const int beg = S.level_ptr[l];
+        const int cnt = S.level_ptr[l + 1] - beg;
+        const int gpb = blockDim.x / g;
+        const int grp = threadIdx.x / g;
+        const int lane = threadIdx.x & (g - 1);
+        int idx = grp;
+        NodeRec cur = idx < cnt ? load_rec(S, beg + idx) : NodeRec{};
+        while (idx < cnt) {
+            const int nxt = idx + gpb;
+            const NodeRec pre = nxt < cnt ? load_rec(S, beg + nxt) : NodeRec{};
+            fn(beg + idx, cur, lane, g);
+            cur = pre;
+            idx = nxt;
+        }
+        __syncthreads();
+    }
+}
+
 // Runs fn(jl, lane, g) over tail levels [t0, t1) (tail-local numbering).
 template <class F>
 __device__ __forceinline__ void for_tail_range(const DevSym& S, int t0, int t1, bool up, F&& fn)
@@ -329,12 +371,12 @@ __device__ __forceinline__ void gsum_blk(Blk& v, int g)
 // With FWD, also the forward substitution and normalisation of the rhs:
 //   y_j = D_j^-1 (b_j - sum_{i in R(j)} W_ji y_i).
 template <class SRC, bool FWD>
-__device__ __forceinline__ void factor_node(const DevSym& S, const SRC& src, int x, int lane,
-                                            int g, const View& w, int64_t lu, int64_t rhs,
-                                            int* s_bad)
+__device__ __forceinline__ void factor_node(const DevSym& S, const SRC& src, const NodeRec& rec,
+                                            int lane, int g, const View& w, int64_t lu,
+                                            int64_t rhs, int* s_bad)
 {
-    const int4 n0 = S.node_info[3 * x];
-    const int4 n1 = S.node_info[3 * x + 1];
+    const int4 n0 = rec.a;
+    const int4 n1 = rec.b;
     const int j = n0.x, bus = n0.y;
     Blk ds = bzero();
     double z0 = 0.0, z1 = 0.0;
@@ -359,14 +401,26 @@ __device__ __forceinline__ void factor_node(const DevSym& S, const SRC& src, int
     const Blk Dj = {Ajj.a - ds.a, Ajj.b - ds.b, Ajj.c - ds.c, Ajj.d - ds.d};
     bool ok;
     const Blk Di = binv(Dj, ok);
-    for (int s = n1.x + lane; s < n1.y; s += g) {
+    // destinations two at a time: both slot records, both Jacobian pairs and
+    // both update lists are in flight together
+    for (int s = n1.x + lane; s < n1.y; s += 2 * g) {
+        const int s2 = s + g;
+        const bool two = s2 < n1.y;
         const int4 a = S.slot_info[2 * s];
         const int4 b = S.slot_info[2 * s + 1];
-        Blk Wk, Vk;
+        const int4 a2 = two ? S.slot_info[2 * s2] : make_int4(0, 0, -1, 0);
+        const int4 b2 = two ? S.slot_info[2 * s2 + 1] : make_int4(0, 0, 0, 0);
+        Blk Wk, Vk, Wk2 = bzero(), Vk2 = bzero();
         src.off(s, bus, a.y, a.z, a.w, Wk, Vk);
+        if (two) src.off(s2, bus, a2.y, a2.z, a2.w, Wk2, Vk2);
         apply_updates(S.upd, b.x, b.y, w, lu, Wk, Vk);
+        apply_updates(S.upd, b2.x, b2.y, w, lu, Wk2, Vk2);
         w.put(lu + 8 * (int64_t)s, Wk);
         w.put(lu + 8 * (int64_t)s + 4, bmul(Di, Vk));
+        if (two) {
+            w.put(lu + 8 * (int64_t)s2, Wk2);
+            w.put(lu + 8 * (int64_t)s2 + 4, bmul(Di, Vk2));
+        }
     }
     if (lane == 0) {
         if (!ok) *s_bad = 1;
@@ -665,12 +719,12 @@ __device__ void tail_backward(const DevSym& S, const View& w, int64_t rhs, int64
 
 // Backward substitution of node record x: x_j = y_j - sum_{k in S(j)} U_jk x_k.
 template <bool UPDATE>
-__device__ __forceinline__ void back_node(const DevSym& S, int x, int lane, int g,
+__device__ __forceinline__ void back_node(const DevSym& S, const NodeRec& rec, int lane, int g,
                                           const View& w, int64_t lu, int64_t rhs,
                                           int64_t bus_off, const int8_t* type)
 {
-    const int4 n0 = S.node_info[3 * x];
-    const int4 n1 = S.node_info[3 * x + 1];
+    const int4 n0 = rec.a;
+    const int4 n1 = rec.b;
     double a0 = 0.0, a1 = 0.0;
     for (int s = n1.x + lane; s < n1.y; s += g) {
         const Blk u = w.blk(lu + 8 * (int64_t)s + 4);
@@ -774,9 +828,13 @@ __device__ void newton_case(const DevSym& S, const double* yv, const int8_t* typ
     for (;;) {
         double mx = 0.0;
         int nan = 0;
-        for (int x = threadIdx.x; x < S.nn; x += blockDim.x) {
-            const int4 n0 = S.node_info[3 * x];
-            const int4 n2 = S.node_info[3 * x + 2];
+        int x = threadIdx.x;
+        int4 n0 = x < S.nn ? S.node_info[3 * x] : make_int4(0, 0, 0, 0);
+        int4 n2 = x < S.nn ? S.node_info[3 * x + 2] : make_int4(0, 0, 0, 0);
+        for (; x < S.nn; x += blockDim.x) {
+            const int xn = x + blockDim.x;
+            const int4 p0 = xn < S.nn ? S.node_info[3 * xn] : make_int4(0, 0, 0, 0);
+            const int4 p2 = xn < S.nn ? S.node_info[3 * xn + 2] : make_int4(0, 0, 0, 0);
             const int bus = n0.y;
             double p, q;
             injection_row(S, yv, ef, bus, n2.x, n2.y, p, q);
@@ -788,6 +846,8 @@ __device__ void newton_case(const DevSym& S, const double* yv, const int8_t* typ
             w.put2(o.RHS + 2 * (int64_t)n0.x, make_double2(fp, fq));
             nan |= (fp != fp) | (fq != fq);
             mx = fmax(mx, fmax(fabs(fp), fabs(fq)));
+            n0 = p0;
+            n2 = p2;
         }
         int any_nan = 0;
         nrm = block_max(mx, nan, any_nan);
@@ -803,8 +863,8 @@ __device__ void newton_case(const DevSym& S, const double* yv, const int8_t* typ
             st = ST_NOT_CONVERGED;
             break;
         }
-        for_levels(S, 0, S.tail_level, true, [&](int x, int lane, int g) {
-            factor_node<SrcState, true>(S, src, x, lane, g, w, o.LU, o.RHS, &s_bad);
+        for_nodes(S, 0, S.tail_level, true, [&](int, const NodeRec& r, int lane, int g) {
+            factor_node<SrcState, true>(S, src, r, lane, g, w, o.LU, o.RHS, &s_bad);
         });
         if (tail) tail_factor<SrcState, true, false>(S, src, w, o.LU, o.RHS, &s_bad);
         if (s_bad) {
@@ -812,14 +872,14 @@ __device__ void newton_case(const DevSym& S, const double* yv, const int8_t* typ
             break;
         }
         if (tail) tail_backward<true>(S, w, o.RHS, o.BUS, type);
-        for_levels(S, 0, S.tail_level, false, [&](int x, int lane, int g) {
-            back_node<true>(S, x, lane, g, w, o.LU, o.RHS, o.BUS, type);
+        for_nodes(S, 0, S.tail_level, false, [&](int, const NodeRec& r, int lane, int g) {
+            back_node<true>(S, r, lane, g, w, o.LU, o.RHS, o.BUS, type);
         });
         ++it;
     }
     if ((flags & PF_NEWTON_KEEP_FACTORS) && st == ST_OK) {
-        for_levels(S, 0, S.tail_level, true, [&](int x, int lane, int g) {
-            factor_node<SrcState, false>(S, src, x, lane, g, w, o.LU, o.RHS, &s_bad);
+        for_nodes(S, 0, S.tail_level, true, [&](int, const NodeRec& r, int lane, int g) {
+            factor_node<SrcState, false>(S, src, r, lane, g, w, o.LU, o.RHS, &s_bad);
         });
         if (tail) tail_factor<SrcState, false, true>(S, src, w, o.LU, o.RHS, &s_bad);
         if (s_bad) st = ST_ZERO_PIVOT;
@@ -993,7 +1053,7 @@ __global__ void k_jacobian(DevSym S, const double* yval, int64_t y_stride, const
     }
 }
 
-__global__ __launch_bounds__(kMaxThreads) void k_factor(DevSym S, double* vals,
+__global__ __launch_bounds__(kLevelThreads) void k_factor(DevSym S, double* vals,
                                                         int64_t vals_stride, int C, int B,
                                                         int32_t* status)
 {
@@ -1005,8 +1065,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_factor(DevSym S, double* vals,
     if (threadIdx.x == 0) s_bad = 0;
     __syncthreads();
     const SrcLoad src{w, lu};
-    for_levels(S, 0, S.tail_level, true, [&](int x, int lane, int g) {
-        factor_node<SrcLoad, false>(S, src, x, lane, g, w, lu, 0, &s_bad);
+    for_nodes(S, 0, S.tail_level, true, [&](int, const NodeRec& r, int lane, int g) {
+        factor_node<SrcLoad, false>(S, src, r, lane, g, w, lu, 0, &s_bad);
     });
     if (S.tail_nodes > 0) tail_factor<SrcLoad, false, true>(S, src, w, lu, 0, &s_bad);
     __syncthreads();
@@ -1082,7 +1142,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_solve(DevSym S, const double* v
 }
 
 template <bool MULTI>
-__global__ __launch_bounds__(kMaxThreads) void k_newton(DevSym Sarg,
+__global__ __launch_bounds__(kLevelThreads) void k_newton(DevSym Sarg,
                                                         const CaseDesc* __restrict__ descs,
                                                         const int32_t* __restrict__ order,
                                                         NewtonArgs a)
@@ -1253,9 +1313,7 @@ int launch_check(const char* what) { return hip_check(hipGetLastError(), what); 
 int launch_threads(const HostSym& h, int B)
 {
     if (h.threads > 0) return h.threads;
-    if (B <= 256) return 1024;
-    if (B <= 512) return 512;
-    return 256;
+    return B <= 512 ? 512 : 256;
 }
 
 // Blocks for B cases in groups of C placed one XCD round apart.
@@ -1437,9 +1495,8 @@ int pf_symbolic_set_launch(pf_symbolic s, int threads, int64_t tail_lds_budget, 
     if (!valid_interleave(interleave))
         return fail(PF_E_INVALID, "pf_symbolic_set_launch: interleave must be 1, 2, 4 or 8");
     s->h.interleave = interleave;
-    if (threads != 0 && threads != 64 && threads != 128 && threads != 256 && threads != 512 &&
-        threads != 1024)
-        return fail(PF_E_INVALID, "pf_symbolic_set_launch: threads must be 0 or 64..1024 (pow2)");
+    if (threads != 0 && threads != 64 && threads != 128 && threads != 256 && threads != 512)
+        return fail(PF_E_INVALID, "pf_symbolic_set_launch: threads must be 0, 64, 128, 256 or 512");
     if (tail_lds_budget < 0 || tail_lds_budget > 158 * 1024)
         return fail(PF_E_INVALID, "pf_symbolic_set_launch: tail budget must be 0..161792 bytes");
     s->h.threads = threads;
@@ -1831,7 +1888,7 @@ int pf_newton_multi(const pf_multi p, const double* d_yval, const int8_t* d_type
         lds = std::max(lds, sy->h.tail_lds);
         threads = std::max(threads, sy->h.threads);
     }
-    if (threads == 0) threads = (p->syms.size() <= 256) ? 1024 : 256;
+    if (threads == 0) threads = (p->syms.size() <= 512) ? 512 : 256;
     allow_big_lds();
     hipLaunchKernelGGL(k_newton<true>, dim3(p->syms.size()), dim3(threads), lds,
                        as_stream(stream), none, p->d_desc, p->d_order, a);

@@ -29,7 +29,7 @@ def test_autotune_keeps_results_bitwise():
     ref = s.newton(Bn, P, Q)
     V0 = s.Vm0.repeat(Bn, 1).contiguous()
     A0 = s.Va0.repeat(Bn, 1).contiguous()
-    res = autotune.tune(s.sym, s.yval[0], s.type, P, Q, V0, A0, reps=1, threads=(256, 1024),
+    res = autotune.tune(s.sym, s.yval[0], s.type, P, Q, V0, A0, reps=1, threads=(256, 512),
                         budgets=(16384, 65536), interleaves=(1, 4), passes=1)
     assert res["ms"] > 0 and res["launches"] > 8
     got = s.newton(Bn, P, Q)

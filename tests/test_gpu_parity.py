@@ -263,7 +263,7 @@ def test_two_bus_closed_form():
     assert Va[0, 1].item() == pytest.approx(th, abs=1e-12)
 
 
-@pytest.mark.parametrize("threads,budget", [(64, 0), (256, 4096), (1024, 65536), (512, 161792),
+@pytest.mark.parametrize("threads,budget", [(64, 0), (256, 4096), (512, 65536), (512, 161792),
                                             (128, 20000)])
 def test_launch_shapes_and_lds_tail(O, threads, budget):
     """Every workgroup size and LDS-tail size gives the oracle's solution, and
