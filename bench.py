@@ -26,6 +26,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("paper_1811_02512_amd/csrc/pf.hip", "paper_1811_02512_amd/csrc/pf_kernels.h",
+                  "paper_1811_02512_amd/csrc/pf_internal.h", "paper_1811_02512_amd/csrc/analyze.cpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_newton_10k_x256_hbm_traffic.md")
 
 
 def log(*a):
@@ -131,6 +134,52 @@ class Workload:
                             g.n, self.r, self.x, 0, self.gP, self.gQ, g.n, self.gx, 1)
 
 
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(settings):
+    """HBM bytes per launch of the batched Newton kernel from the committed
+    PMC summary, or None when the kernel sources or the launch settings have
+    changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = {}
+    for line in open(TRAFFIC_FILE):
+        if line.startswith("traffic:"):
+            for kv in line.split()[1:]:
+                k, v = kv.split("=")
+                rec[k] = v
+    if rec.get("sources") != kernel_source_hash():
+        return None
+    if settings is None or rec.get("launch") != launch_tag(settings):
+        return None
+    return float(rec["bytes_per_launch"])
+
+
+def launch_tag(s):
+    return f"T{s['threads']}-tail{s['tail_budget']}-C{s['interleave']}"
+
+
+def copy_calibration():
+    """One plain 1 GiB device copy (1 GiB read, 1 GiB written): the reference
+    for scaling the FETCH_SIZE / WRITE_SIZE counters of a PMC pass."""
+    import torch
+
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    log("[bench] copy calibration: 1 GiB copied")
+
+
 def timed(fn, steps, warmup):
     import torch
 
@@ -147,9 +196,10 @@ def timed(fn, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
-def cpu_baseline(W, max_cases, budget_s=20.0):
-    """The oracle (paper-path sparse NR + sparse adjoint) over scenarios on a
-    thread pool of the host's cores; ctypes releases the GIL."""
+def cpu_baseline(W, wall_s=15.0):
+    """The oracle (paper-path sparse NR + sparse adjoint) over the load
+    scenarios on a thread pool of the host's cores (ctypes releases the GIL),
+    cycling through the scenarios until about `wall_s` seconds of wall time."""
     from concurrent.futures import ThreadPoolExecutor
 
     from oracle import oracle as O
@@ -161,23 +211,29 @@ def cpu_baseline(W, max_cases, budget_s=20.0):
     cores = min(os.cpu_count() or 1, 16)
 
     def one(c):
+        c %= W.B
         r = osym.newton(Y, g.bus_type, W.P[c], W.Q[c], Vm0, Va0)
         gVm = 2 * W.w * (r.Vm - 1) * (g.bus_type == 1)
         osym.adjoint(g, Y, r.Vm, r.Va, gVm, np.zeros(g.n))
         return r.status
 
-    t0 = time.time()
     one(0)
-    per_case = time.time() - t0
-    count = int(max(cores, min(max_cases, budget_s / max(per_case, 1e-6))))
+    t0 = time.time()
+    for c in range(1, 4):
+        one(c)
+    per_case = (time.time() - t0) / 3
+    count = max(cores, int(wall_s * cores / max(per_case, 1e-6)))
+    log(f"[bench] cpu baseline: {per_case * 1e3:.1f} ms per case on one thread, "
+        f"{count} cases on {cores} threads")
     t0 = time.time()
     with ThreadPoolExecutor(cores) as ex:
         sts = list(ex.map(one, range(count)))
     wall = time.time() - t0
     return dict(value=count / wall, unit="solves/s", cores=cores, kind="oracle",
-                sample=f"{count} of the {W.B} load scenarios on the {g.n}-bus grid, forward NR "
-                       f"(sparse paper path, tol 1e-8) + sparse adjoint, {cores} threads, "
-                       f"{wall:.1f}s wall, converged {sum(s == 0 for s in sts)}/{count}")
+                sample=f"{count} solves cycling over the {W.B} load scenarios of the {g.n}-bus "
+                       f"grid: forward NR (sparse paper path, tol 1e-8) + sparse adjoint each, "
+                       f"{cores} threads, {wall:.1f}s wall, converged "
+                       f"{sum(s == 0 for s in sts)}/{count}")
 
 
 def bench_multi(grids, label, steps=3):
@@ -221,8 +277,10 @@ def bench_multi(grids, label, steps=3):
     ok = int((st == 0).sum().item())
     log(f"[bench] {label}: {G} cases, {ms:.2f} ms/launch, converged {ok}/{G}, host analysis "
         f"{t_an:.2f}s")
-    return dict(solves_per_s=G / ms * 1e3, ms=ms, cases=G, converged=ok,
-                host_analysis_s=t_an, buses=int(sum(g.n for g in grids)))
+    # only converged cases count as solves
+    return dict(solves_per_s=ok / ms * 1e3, ms=ms, cases=G, converged=ok,
+                host_analysis_s=t_an, buses=int(sum(g.n for g in grids)),
+                bus_solves_per_s=sum(g.n for g, s in zip(grids, st.tolist()) if s == 0) / ms * 1e3)
 
 
 def main():
@@ -235,6 +293,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--full", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
+    ap.add_argument("--settings", help="JSON of launch settings saved by --save-settings "
+                    "(applied instead of tuning)")
+    ap.add_argument("--save-settings", help="write the tuned launch settings to this JSON file")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain 1 GiB copy first (PMC byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -245,10 +308,27 @@ def main():
     import torch
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        copy_calibration()
     W = Workload(args.n, 1, args.scenarios, 5)
     W.step(adjoint=False)  # builds the admittance values the tuner needs
-    tuned = W.autotune(W.B, W.sym) if not args.no_tune else None
-    tuned1 = W.autotune(1, W.sym1) if not args.no_tune else None
+    tuned = tuned1 = None
+    if args.settings:
+        from paper_1811_02512_amd import autotune
+
+        saved = json.load(open(args.settings))
+        tuned, tuned1 = saved["batched"], saved["plain"]
+        autotune.apply(W.sym, tuned)
+        autotune.apply(W.sym1, tuned1)
+        W.info = W.sym.info
+        W.ws = W.sym.workspace(W.B)
+        log(f"[bench] launch settings from {args.settings}: batched {launch_tag(tuned)}, "
+            f"plain {launch_tag(tuned1)}")
+    elif not args.no_tune:
+        tuned = W.autotune(W.B, W.sym)
+        tuned1 = W.autotune(1, W.sym1)
+    if args.save_settings and tuned is not None:
+        json.dump({"batched": tuned, "plain": tuned1}, open(args.save_settings, "w"))
     info = W.info
 
     # --- timed steps: whole hot path ---------------------------------------------
@@ -276,7 +356,9 @@ def main():
 
     b_it = survey_bytes_per_iter(info)
     units = float(iters.sum())
-    achieved = b_it * units / (newton_ms * 1e-3) / 1e9
+    alg_bytes = b_it * units  # per launch: bytes per case-iteration x case-iterations
+    achieved = alg_bytes / (newton_ms * 1e-3) / 1e9
+    traffic = measured_traffic(tuned)
     out = {
         "metric": "NR power-flow solves/s to 1e-8 p.u. at 10k buses; batched & adjoint vs plain",
         "value": W.B / ms_step * 1e3,
@@ -305,14 +387,21 @@ def main():
         "autotune": None if tuned is None else {
             "batched": {k: tuned[k] for k in ("threads", "tail_budget", "interleave", "ms")},
             "plain": {k: tuned1[k] for k in ("threads", "tail_budget", "interleave", "ms")},
-            "seconds": tuned["seconds"] + tuned1["seconds"]},
+            "seconds": tuned["seconds"] + tuned1["seconds"],
+            "from_file": bool(args.settings)},
+        "kernel_sources": kernel_source_hash(),
         "roofline": {
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
+            "kernel": "k_newton (batched launch)",
+            "algorithmic_bytes_per_launch": alg_bytes,
+            "bytes_per_case_iteration": b_it,
+            "case_iterations_per_launch": units,
+            "launch": None if tuned is None else launch_tag(tuned),
         },
         "paper_context": "Table III: graph-based NR 119.22 ms per solve on a 10790-bus system, "
                          "TigerGraph on 2x6-core x2-thread 2.10 GHz CPUs",
@@ -321,18 +410,25 @@ def main():
         import gridgen
 
         W2 = Workload(2000, 1, 1024, 2)
+        W2.step(adjoint=False)
+        if not args.no_tune:
+            W2.autotune(W2.B, W2.sym)
+            W2.autotune(1, W2.sym1)
         ms2 = timed(lambda: W2.step(adjoint=False), 5, 1)
         out["batch_2k_x1024_solves_per_s"] = 1024 / ms2 * 1e3
         out["plain_2k_solves_per_s"] = 1e3 / timed(lambda: W2.step(adjoint=False, Bn=1), 5, 1)
         outs = gridgen.n1_outages(W.g, 512, 3)
         n1 = [W.g.without_branch(int(e)) for e in outs]
         out["n1_10k_x512"] = bench_multi(n1, "N-1 10k x 512")
-        sizes = gridgen.mixed_sizes(64, 4)
-        mixed = [gridgen.make_grid(int(s), 1000 + i, load_scale=0.05)
-                 for i, s in enumerate(sizes)]
+        spec = json.load(open(os.path.join(ROOT, "tests", "golden", "mixed_batch.json")))
+        mixed = []
+        for i, gs in enumerate(spec["grids"]):
+            mixed.append(gridgen.make_grid(gs["n"], gs["seed"], load_scale=spec["load_scale"]))
+            if i % 8 == 7:
+                log(f"[bench] generated {i + 1}/64 mixed grids")
         out["mixed_64_grids"] = bench_multi(mixed, "mixed 64 grids 500-20k buses")
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(W, W.B)
+        out["cpu_baseline"] = cpu_baseline(W)
     print(json.dumps(out))
 
 

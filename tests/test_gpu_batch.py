@@ -88,10 +88,16 @@ def test_n1_equals_superset_pattern_with_zero_admittance():
 
 
 def test_mixed_grid_sizes_one_launch():
-    sizes = [int(n) for n in gridgen.mixed_sizes(64, 4)[:7]]
-    sizes = [min(n, 6000) for n in sizes]
-    log(f"[mixed] sizes {sizes}")
-    grids = [gridgen.make_grid(n, 1000 + i, load_scale=0.05) for i, n in enumerate(sizes)]
+    """The first mixed-batch grids of up to 6,000 buses (sizes and seeds from
+    tests/golden/mixed_batch.json) in one launch, each against the oracle."""
+    import json
+    import os
+
+    spec = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "mixed_batch.json")))
+    chosen = [gs for gs in spec["grids"] if gs["n"] <= 6000][:7]
+    log(f"[mixed] sizes {[gs['n'] for gs in chosen]}")
+    grids = [gridgen.make_grid(gs["n"], gs["seed"], load_scale=spec["load_scale"])
+             for gs in chosen]
     Vms, Vas, it, st, plan = solve_multi(grids)
     check_against_oracle(grids, Vms, Vas, it, st)
 
