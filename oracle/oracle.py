@@ -92,6 +92,20 @@ def lib():
                                         f64p, f64p, i8p, f64p, f64p, f64p, f64p, f64p, f64p,
                                         f64p]
         L.or_adjoint_sparse.restype = C.c_int
+        L.or_fdpf_matrices.argtypes = [C.c_void_p, C.c_int, i32p, i32p, f64p, f64p, f64p, i8p,
+                                       f64p, f64p, f64p, f64p]
+        L.or_fdpf_matrices.restype = None
+        L.or_factor1.argtypes = [C.c_void_p, f64p, f64p, f64p]
+        L.or_factor1.restype = C.c_int
+        L.or_solve1.argtypes = [C.c_void_p, f64p, f64p, f64p, f64p]
+        L.or_solve1.restype = None
+        L.or_fdpf.argtypes = [C.c_void_p, i32p, i32p, f64p, f64p, i8p, f64p, f64p, f64p, f64p,
+                              f64p, f64p, f64p, f64p, f64p, f64p, C.c_double, C.c_int,
+                              C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+        L.or_fdpf.restype = C.c_int
+        L.or_branch_flows.argtypes = [C.c_int, i32p, i32p, f64p, f64p, f64p, f64p, f64p, f64p,
+                                      f64p, f64p, f64p]
+        L.or_branch_flows.restype = None
         _lib = L
     return _lib
 
@@ -300,6 +314,67 @@ class Sym:
                                     C.byref(nrm), C.byref(bad))
         return NRResult(Vm, Va, it.value, nrm.value, st, bad.value)
 
+    # -- fast decoupled power flow (scalar elements) --------------------------
+    def fdpf_matrices(self, grid, r=None, x=None, b=None):
+        """XB matrices in the scalar filled layout: (d1, a1, d2, a2), d per
+        position, a per slot (entry (p, Li[q]) = entry (Li[q], p))."""
+        nn, nz = self.nn, max(self.nnzL, 1)
+        d1, d2 = np.zeros(max(nn, 1)), np.zeros(max(nn, 1))
+        a1, a2 = np.zeros(nz), np.zeros(nz)
+        lib().or_fdpf_matrices(self._h, grid.m, _i32(grid.f), _i32(grid.t),
+                               _f64(grid.r if r is None else r), _f64(grid.x if x is None else x),
+                               _f64(grid.b if b is None else b),
+                               np.ascontiguousarray(grid.bus_type, np.int8), d1, a1, d2, a2)
+        return d1[:nn], a1[: self.nnzL], d2[:nn], a2[: self.nnzL]
+
+    def factor1(self, d, a_lo, a_up=None):
+        """Scalar FactorizeGraphA on a full copy: returns (d, L, U, bad)."""
+        d = np.array(d, np.float64).copy()
+        lo = np.array(a_lo, np.float64).copy()
+        up = np.array(a_lo if a_up is None else a_up, np.float64).copy()
+        if lo.size == 0:
+            lo, up = np.zeros(1), np.zeros(1)
+        bad = lib().or_factor1(self._h, d, lo, up)
+        return d, lo[: self.nnzL], up[: self.nnzL], bad
+
+    def solve1(self, d, L, U, rhs):
+        L = _f64(L) if len(L) else np.zeros(1)
+        U = _f64(U) if len(U) else np.zeros(1)
+        x = np.array(rhs, np.float64).copy()
+        lib().or_solve1(self._h, _f64(d), L, U, x)
+        return x
+
+    def fdpf(self, Y: Ybus, grid, Psp, Qsp, Vm0, Va0, tol=1e-8, max_iter=40,
+             factors=None) -> NRResult:
+        """Fast decoupled iteration (XB) from (Vm0, Va0); factors may be given
+        as ((d1, L1, U1), (d2, L2, U2))."""
+        if factors is None:
+            d1, a1, d2, a2 = self.fdpf_matrices(grid)
+            f1 = self.factor1(d1, a1)
+            f2 = self.factor1(d2, a2)
+            if f1[3] >= 0 or f2[3] >= 0:
+                raise np.linalg.LinAlgError("zero pivot in B' or B''")
+            factors = (f1[:3], f2[:3])
+        (d1, L1, U1), (d2, L2, U2) = factors
+        pad = (lambda a: _f64(a) if len(a) else np.zeros(1))
+        Vm = _f64(Vm0).copy()
+        Va = _f64(Va0).copy()
+        it = C.c_int32()
+        nrm = C.c_double()
+        st = lib().or_fdpf(self._h, Y.rowptr, Y.col, Y.G, Y.B,
+                           np.ascontiguousarray(grid.bus_type, np.int8), _f64(Psp), _f64(Qsp),
+                           _f64(d1), pad(L1), pad(U1), _f64(d2), pad(L2), pad(U2), Vm, Va, tol,
+                           max_iter, C.byref(it), C.byref(nrm))
+        return NRResult(Vm, Va, it.value, nrm.value, st)
+
+    def scalar_matrix(self, d, a):
+        """Dense symmetric matrix (position order) from scalar filled values."""
+        A = np.diag(np.asarray(d, np.float64))
+        for p in range(self.nn):
+            for q in range(self.Lp[p], self.Lp[p + 1]):
+                A[p, self.Li[q]] = A[self.Li[q], p] = a[q]
+        return A
+
     def dense_matrix(self, D, Lb, Ub):
         """Assemble the permuted block matrix from filled-layout blocks."""
         nn = self.nn
@@ -340,3 +415,22 @@ def solve_grid(grid, sparse=True, tol=1e-8, max_iter=20, Psp=None, Qsp=None, ord
         s = sym if sym is not None else Sym(grid.n, grid.f, grid.t, 0, ordering)
         return s.newton(Y, grid.bus_type, Psp, Qsp, Vm0, Va0, tol, max_iter)
     return newton_dense(Y, grid.bus_type, Psp, Qsp, Vm0, Va0, tol, max_iter)
+
+
+def branch_flows(grid, Vm, Va, r=None, x=None, b=None):
+    """Complex power at both ends of every branch: (Pft, Qft, Ptf, Qtf)."""
+    m = grid.m
+    out = [np.zeros(max(m, 1)) for _ in range(4)]
+    lib().or_branch_flows(m, _i32(grid.f), _i32(grid.t), _f64(grid.r if r is None else r),
+                          _f64(grid.x if x is None else x), _f64(grid.b if b is None else b),
+                          _f64(Vm), _f64(Va), *out)
+    return tuple(o[:m] for o in out)
+
+
+def solve_grid_fdpf(grid, tol=1e-8, max_iter=40, Psp=None, Qsp=None, sym=None):
+    """Convenience: flat-start fast decoupled power flow on a gridgen.Grid."""
+    Y = grid_ybus(grid)
+    Vm0, Va0 = grid.flat_start()
+    s = sym if sym is not None else Sym(grid.n, grid.f, grid.t)
+    return s.fdpf(Y, grid, grid.Psp if Psp is None else Psp, grid.Qsp if Qsp is None else Qsp,
+                  Vm0, Va0, tol, max_iter)

@@ -21,7 +21,10 @@
  *     FactorizeGraphA right-looking LDU over the partition (Sec. III-B,
  *     eqs. 1-3), forward substitution, normalisation (eq. 4) and backward
  *     substitution (Sec. III-C);
- *   - a dense adjoint of the converged solution (beyond the paper).
+ *   - a dense adjoint of the converged solution (beyond the paper);
+ *   - fast decoupled power flow (Sec. III, Table III; XB matrices, our
+ *     reading) on the symmetric factorisation of eqs. 1-3 with scalar
+ *     elements, and branch flows of a solved state.
  *
  * Parity pins live in the CPU tests: a 2-bus closed form, power balance
  * (Tellegen) at arbitrary voltages, finite-difference Jacobians, brute-force
@@ -998,4 +1001,192 @@ int or_adjoint_sparse(const or_sym* s, int m, const int32_t* f, const int32_t* t
     free(Ub);
     free(rhs);
     return st;
+}
+
+/* ======================================================================== */
+/* Fast decoupled power flow (Sec. III: the second method the paper runs;   */
+/* Table III).  The paper fixes no variant; this follows the XB scheme of   */
+/* Stott and Alsac with van Amerongen's choice of matrices (our reading):   */
+/*   B'  : branch reactances only, b'_ik = -sum_e 1/x_e over branches (i,k), */
+/*         b'_ii = sum_e 1/x_e over branches at i (slack branches included); */
+/*   B'' : -Im(Y) of the full pi-model (r, x and charging).                  */
+/* Both are symmetric, so the paper's symmetric factorisation applies       */
+/* (Sec. III-B, eqs. 1-3).  Positions and slots are those of or_analyze:     */
+/* d[p] diagonal, a[q] = entry (p, Li[q]) = entry (Li[q], p).  B'' keeps    */
+/* the non-slack pattern: a PV position gets diagonal 1 and zero off-        */
+/* diagonals, which leaves the reduced system over PQ buses unchanged.       */
+/* ======================================================================== */
+void or_fdpf_matrices(const or_sym* s, int m, const int32_t* f, const int32_t* t,
+                      const double* r, const double* x, const double* b, const int8_t* type,
+                      double* d1, double* a1, double* d2, double* a2)
+{
+    int nn = s->nn;
+    memset(d1, 0, sizeof(double) * (size_t)nn);
+    memset(d2, 0, sizeof(double) * (size_t)nn);
+    memset(a1, 0, sizeof(double) * (size_t)s->nnzL);
+    memset(a2, 0, sizeof(double) * (size_t)s->nnzL);
+    for (int e = 0; e < m; ++e) {
+        int nf = s->node_of[f[e]], nt = s->node_of[t[e]];
+        int pf = nf >= 0 ? s->iperm[nf] : -1, pt = nt >= 0 ? s->iperm[nt] : -1;
+        double bx = 1.0 / x[e];
+        double bs = x[e] / (r[e] * r[e] + x[e] * x[e]); /* -Im(1/(r+jx)) */
+        double sh = b[e] / 2.0;
+        if (pf >= 0) {
+            d1[pf] += bx;
+            d2[pf] += bs - sh;
+        }
+        if (pt >= 0) {
+            d1[pt] += bx;
+            d2[pt] += bs - sh;
+        }
+        if (pf >= 0 && pt >= 0) {
+            int lo = pf < pt ? pf : pt, hi = pf < pt ? pt : pf;
+            int64_t q = slot_of(s, lo, hi);
+            a1[q] -= bx;
+            a2[q] -= bs;
+        }
+    }
+    for (int ni = 0; ni < nn; ++ni) {
+        if (type[s->bus_of[ni]] != OR_PV) continue;
+        int p = s->iperm[ni];
+        d2[p] = 1.0;
+        for (int q = s->Lp[p]; q < s->Lp[p + 1]; ++q) a2[q] = 0.0;
+        for (int rr = s->Rp[p]; rr < s->Rp[p + 1]; ++rr) a2[s->Rslot[rr]] = 0.0;
+    }
+}
+
+/* FactorizeGraphA with scalar elements (Sec. III-B), right-looking over the */
+/* partition like or_factor, on a full (non-symmetric) copy so that eq. 2   */
+/* can be checked on the result: for i in partition order, the row is      */
+/* normalised u_ij = a_ij / a_ii, every intersection of the column and row  */
+/* structure is updated a_kj -= a_ki u_ij, then the column is normalised    */
+/* l_ki = a_ki / a_ii.  In place: d keeps d_i, lo becomes L, up becomes U.  */
+/* Returns -1, or the first position with a zero or non-finite pivot.       */
+int or_factor1(const or_sym* s, double* d, double* lo, double* up)
+{
+    for (int l = 0; l < s->nlev; ++l)
+        for (int xx = s->level_ptr[l]; xx < s->level_ptr[l + 1]; ++xx) {
+            int i = s->level_nodes[xx];
+            double di = d[i];
+            if (di == 0.0 || !isfinite(di)) return i;
+            for (int q = s->Lp[i]; q < s->Lp[i + 1]; ++q) up[q] /= di;
+            for (int qk = s->Lp[i]; qk < s->Lp[i + 1]; ++qk) {
+                int k = s->Li[qk];
+                for (int qj = s->Lp[i]; qj < s->Lp[i + 1]; ++qj) {
+                    int j = s->Li[qj];
+                    double v = lo[qk] * up[qj];
+                    if (k == j) d[k] -= v;
+                    else if (k > j) lo[slot_of(s, j, k)] -= v;
+                    else up[slot_of(s, k, j)] -= v;
+                }
+            }
+            for (int q = s->Lp[i]; q < s->Lp[i + 1]; ++q) lo[q] /= di;
+        }
+    return -1;
+}
+
+/* Forward substitution, normalisation (eq. 4) and backward substitution    */
+/* (Sec. III-C) with scalar factors; rhs (one per position) is overwritten. */
+void or_solve1(const or_sym* s, const double* d, const double* lo, const double* up,
+               double* rhs)
+{
+    for (int l = 0; l < s->nlev; ++l)
+        for (int xx = s->level_ptr[l]; xx < s->level_ptr[l + 1]; ++xx) {
+            int i = s->level_nodes[xx];
+            for (int rr = s->Rp[i]; rr < s->Rp[i + 1]; ++rr)
+                rhs[i] -= lo[s->Rslot[rr]] * rhs[s->Ri[rr]];
+        }
+    for (int i = 0; i < s->nn; ++i) rhs[i] /= d[i];
+    for (int l = s->nlev - 1; l >= 0; --l)
+        for (int xx = s->level_ptr[l]; xx < s->level_ptr[l + 1]; ++xx) {
+            int i = s->level_nodes[xx];
+            for (int q = s->Lp[i]; q < s->Lp[i + 1]; ++q) rhs[i] -= up[q] * rhs[s->Li[q]];
+        }
+}
+
+/* The fast decoupled iteration on factored B' (d1, l1, u1) and B''         */
+/* (d2, l2, u2).  F = calculated - scheduled as for NR.  Each iteration:     */
+/* stop if max|F| < tol (status 0), else theta -= B'^-1 (F_P / |V|); stop    */
+/* if max|F| < tol; else |V| -= B''^-1 (F_Q / |V|) at PQ buses.  iters       */
+/* counts the angle half-steps, max_iter bounds them.  Returns 0, 6 (not     */
+/* converged) or 7 (non-finite).                                             */
+int or_fdpf(const or_sym* s, const int32_t* rowptr, const int32_t* col, const double* G,
+            const double* B, const int8_t* type, const double* Psp, const double* Qsp,
+            const double* d1, const double* l1, const double* u1, const double* d2,
+            const double* l2, const double* u2, double* Vm, double* Va, double tol,
+            int max_iter, int32_t* iters, double* norm)
+{
+    int n = s->n, nn = s->nn;
+    double* P = (double*)malloc(sizeof(double) * (size_t)n * 4);
+    double *Q = P + n, *FP = P + 2 * n, *FQ = P + 3 * n;
+    double* rhs = (double*)malloc(sizeof(double) * ((size_t)nn + 1));
+    int status = 6, it = 0, half = 0;
+    double nrm = 0.0;
+    for (;;) {
+        or_injections(n, rowptr, col, G, B, Vm, Va, P, Q);
+        nrm = or_mismatch(n, type, P, Q, Psp, Qsp, FP, FQ);
+        if (!(nrm == nrm) || isinf(nrm)) {
+            status = 7;
+            break;
+        }
+        if (nrm < tol) {
+            status = 0;
+            break;
+        }
+        if (half == 0) {
+            if (it >= max_iter) {
+                status = 6;
+                break;
+            }
+            for (int ni = 0; ni < nn; ++ni) {
+                int bus = s->bus_of[ni];
+                rhs[s->iperm[ni]] = FP[bus] / Vm[bus];
+            }
+            or_solve1(s, d1, l1, u1, rhs);
+            for (int ni = 0; ni < nn; ++ni) Va[s->bus_of[ni]] -= rhs[s->iperm[ni]];
+            ++it;
+            half = 1;
+        } else {
+            for (int ni = 0; ni < nn; ++ni) {
+                int bus = s->bus_of[ni];
+                rhs[s->iperm[ni]] = type[bus] == OR_PQ ? FQ[bus] / Vm[bus] : 0.0;
+            }
+            or_solve1(s, d2, l2, u2, rhs);
+            for (int ni = 0; ni < nn; ++ni) {
+                int bus = s->bus_of[ni];
+                if (type[bus] == OR_PQ) Vm[bus] -= rhs[s->iperm[ni]];
+            }
+            half = 0;
+        }
+    }
+    *iters = it;
+    *norm = nrm;
+    free(P);
+    free(rhs);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Branch flows after convergence (Sec. II-A lists this post-convergence    */
+/* step among the nodal-parallel ones).  Branch e from f to t,              */
+/* pi-model with series y = 1/(r + jx) and charging b:                      */
+/*   I_ft = (y + jb/2) V_f - y V_t,  S_ft = V_f conj(I_ft), and the same    */
+/*   with f and t swapped; losses = S_ft + S_tf.                            */
+/* ------------------------------------------------------------------------ */
+void or_branch_flows(int m, const int32_t* f, const int32_t* t, const double* r,
+                     const double* x, const double* b, const double* Vm, const double* Va,
+                     double* Pft, double* Qft, double* Ptf, double* Qtf)
+{
+    for (int e = 0; e < m; ++e) {
+        double complex y = 1.0 / (r[e] + I * x[e]);
+        double complex ysh = I * (b[e] / 2.0);
+        double complex vf = Vm[f[e]] * cexp(I * Va[f[e]]);
+        double complex vt = Vm[t[e]] * cexp(I * Va[t[e]]);
+        double complex sft = vf * conj((y + ysh) * vf - y * vt);
+        double complex stf = vt * conj((y + ysh) * vt - y * vf);
+        Pft[e] = creal(sft);
+        Qft[e] = cimag(sft);
+        Ptf[e] = creal(stf);
+        Qtf[e] = cimag(stf);
+    }
 }

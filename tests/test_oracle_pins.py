@@ -619,3 +619,173 @@ def test_transpose_solve_matches_lapack(oracle):
     rhs = np.random.default_rng(1).standard_normal(2 * sym.nn)
     x = sym.solve_transpose(fD, fL, fU, rhs).reshape(-1)
     np.testing.assert_allclose(x, np.linalg.solve(A.T, rhs), rtol=1e-9, atol=1e-10)
+
+
+# --------------------------------------------------------------------------
+# fast decoupled power flow and branch flows
+# --------------------------------------------------------------------------
+def dense_xb(g):
+    """B' and B'' over non-slack buses in bus order, written branch by branch
+    from their definitions (independent of the oracle's sparse assembly)."""
+    keep = [i for i in range(g.n) if g.bus_type[i] != gridgen.BUS_SLACK]
+    idx = {bus: k for k, bus in enumerate(keep)}
+    N = len(keep)
+    B1 = np.zeros((N, N))
+    B2 = np.zeros((N, N))
+    for e in range(g.m):
+        a, c = int(g.f[e]), int(g.t[e])
+        y = 1.0 / complex(g.r[e], g.x[e])
+        for u, v in ((a, c), (c, a)):
+            if u in idx:
+                B1[idx[u], idx[u]] += 1.0 / g.x[e]
+                B2[idx[u], idx[u]] += -(y.imag + g.b[e] / 2.0)
+                if v in idx:
+                    B1[idx[u], idx[v]] -= 1.0 / g.x[e]
+                    B2[idx[u], idx[v]] -= -y.imag
+    for bus in keep:
+        if g.bus_type[bus] == gridgen.BUS_PV:
+            k = idx[bus]
+            B2[k, :] = 0.0
+            B2[:, k] = 0.0
+            B2[k, k] = 1.0
+    return keep, B1, B2
+
+
+def to_bus_order(s, A):
+    """Position-order dense matrix -> non-slack bus order."""
+    bus_of_pos = s.perm  # perm[p] = bus at position p
+    order = np.argsort(bus_of_pos)
+    return A[np.ix_(order, order)]
+
+
+@pytest.mark.parametrize("n,seed", [(60, 1), (200, 2)])
+def test_fdpf_matrices_match_definition(oracle, n, seed):
+    g = gridgen.make_grid(n, seed)
+    s = oracle.Sym(g.n, g.f, g.t)
+    d1, a1, d2, a2 = s.fdpf_matrices(g)
+    keep, B1, B2 = dense_xb(g)
+    np.testing.assert_allclose(to_bus_order(s, s.scalar_matrix(d1, a1)), B1, rtol=0, atol=1e-10)
+    np.testing.assert_allclose(to_bus_order(s, s.scalar_matrix(d2, a2)), B2, rtol=0, atol=1e-10)
+    # lossless, charging-free branches make the two matrices agree away from PV buses
+    g0 = gridgen.make_grid(n, seed)
+    g0.r[:] = 0.0
+    g0.b[:] = 0.0
+    e1, b1, e2, b2 = s.fdpf_matrices(g0)
+    pq = np.array([g0.bus_type[s.perm[p]] == gridgen.BUS_PQ for p in range(s.nn)])
+    np.testing.assert_allclose(e1[pq], e2[pq], rtol=1e-14)
+
+
+@pytest.mark.parametrize("n,seed,ordering", [(80, 1, 0), (200, 3, 0), (150, 2, 1)])
+def test_symmetric_factor_eq2_and_reconstruction(oracle, n, seed, ordering):
+    """Eq. 2 (u_ij = l_ji) holds on the factors of a symmetric matrix, and
+    L D L^T rebuilds it; solves agree with LAPACK."""
+    g = gridgen.make_grid(n, seed)
+    s = oracle.Sym(g.n, g.f, g.t, 0, ordering)
+    for d, a in (s.fdpf_matrices(g)[:2], s.fdpf_matrices(g)[2:]):
+        fd, L, U, bad = s.factor1(d, a)
+        assert bad == -1
+        np.testing.assert_allclose(L, U, rtol=1e-12, atol=1e-15)
+        nn = s.nn
+        Lm = np.eye(nn)
+        for p in range(nn):
+            for q in range(s.Lp[p], s.Lp[p + 1]):
+                Lm[s.Li[q], p] = L[q]
+        A = s.scalar_matrix(d, a)
+        np.testing.assert_allclose(Lm @ np.diag(fd) @ Lm.T, A, rtol=0,
+                                   atol=1e-12 * np.abs(A).max())
+        rhs = np.random.default_rng(seed).standard_normal(nn)
+        np.testing.assert_allclose(s.solve1(fd, L, U, rhs), np.linalg.solve(A, rhs), rtol=0,
+                                   atol=1e-10 * np.abs(np.linalg.solve(A, rhs)).max())
+
+
+def test_symmetric_factor_zero_pivot(oracle):
+    g = gridgen.make_grid(60, 1)
+    s = oracle.Sym(g.n, g.f, g.t)
+    d, a, _, _ = s.fdpf_matrices(g)
+    d = d.copy()
+    leaf = int(s.level_nodes[0])
+    d[leaf] = 0.0
+    assert s.factor1(d, a)[3] == leaf
+
+
+def fdpf_dense(g, Psp, Qsp, tol=1e-8, max_iter=40):
+    """The XB iteration with dense matrices and LAPACK solves."""
+    O = __import__("oracle.oracle", fromlist=["oracle"])
+    keep, B1, B2 = dense_xb(g)
+    keep = np.array(keep)
+    Y = O.grid_ybus(g)
+    Vm, Va = g.flat_start()
+    pq = g.bus_type[keep] == gridgen.BUS_PQ
+    it, half = 0, 0
+    while True:
+        P, Q = O.injections(Y, Vm, Va)
+        FP, FQ, nrm = O.mismatch(g.bus_type, P, Q, Psp, Qsp)
+        if nrm < tol:
+            return Vm, Va, it, 0
+        if half == 0:
+            if it >= max_iter:
+                return Vm, Va, it, 6
+            Va = Va.copy()
+            Va[keep] -= np.linalg.solve(B1, FP[keep] / Vm[keep])
+            it += 1
+        else:
+            Vm = Vm.copy()
+            rhs = np.where(pq, FQ[keep] / Vm[keep], 0.0)
+            Vm[keep] -= np.where(pq, np.linalg.solve(B2, rhs), 0.0)
+        half ^= 1
+
+
+@pytest.mark.parametrize("n,seed", [(100, 1), (300, 4)])
+def test_fdpf_sparse_equals_dense_definition(oracle, n, seed):
+    g = gridgen.make_grid(n, seed)
+    Vm, Va, it, st = fdpf_dense(g, g.Psp, g.Qsp)
+    r = oracle.solve_grid_fdpf(g)
+    assert st == 0 and r.status == 0
+    assert r.iters == it
+    np.testing.assert_allclose(r.Vm, Vm, rtol=0, atol=1e-11)
+    np.testing.assert_allclose(r.Va, Va, rtol=0, atol=1e-11)
+
+
+@pytest.mark.parametrize("n,seed", [(200, 1), (2000, 2)])
+def test_fdpf_reaches_the_newton_solution(oracle, n, seed):
+    """Both methods stop at max|F| < 1e-8 on the same equations, so they
+    reach the same state up to that tolerance."""
+    g = gridgen.make_grid(n, seed)
+    a = oracle.solve_grid_fdpf(g)
+    b = oracle.solve_grid(g)
+    assert a.status == 0 and b.status == 0
+    assert a.iters > b.iters  # decoupled steps are cheaper but more
+    np.testing.assert_allclose(a.Vm, b.Vm, rtol=0, atol=1e-8)
+    np.testing.assert_allclose(a.Va, b.Va, rtol=0, atol=1e-8)
+
+
+def test_fdpf_not_converged_and_nonfinite(oracle):
+    g = gridgen.make_grid(200, 1)
+    assert oracle.solve_grid_fdpf(g, max_iter=2).status == 6
+    P = g.Psp.copy()
+    P[5] = np.nan
+    assert oracle.solve_grid_fdpf(g, Psp=P).status == 7
+
+
+@pytest.mark.parametrize("n,seed", [(200, 1), (1000, 3)])
+def test_branch_flows_kcl_and_series_losses(oracle, n, seed):
+    """Flows leaving each bus sum to its injection (Kirchhoff), and each
+    branch's losses equal the series-element loss minus the charging."""
+    g = gridgen.make_grid(n, seed)
+    r = oracle.solve_grid(g)
+    Pft, Qft, Ptf, Qtf = oracle.branch_flows(g, r.Vm, r.Va)
+    P, Q = oracle.injections(oracle.grid_ybus(g), r.Vm, r.Va)
+    sp = np.zeros(g.n)
+    sq = np.zeros(g.n)
+    np.add.at(sp, g.f, Pft)
+    np.add.at(sp, g.t, Ptf)
+    np.add.at(sq, g.f, Qft)
+    np.add.at(sq, g.t, Qtf)
+    np.testing.assert_allclose(sp, P, rtol=0, atol=1e-11)
+    np.testing.assert_allclose(sq, Q, rtol=0, atol=1e-11)
+    V = r.Vm * np.exp(1j * r.Va)
+    i_series = (V[g.f] - V[g.t]) / (g.r + 1j * g.x)
+    np.testing.assert_allclose(Pft + Ptf, g.r * np.abs(i_series) ** 2, rtol=1e-9, atol=1e-13)
+    np.testing.assert_allclose(
+        Qft + Qtf, g.x * np.abs(i_series) ** 2 - g.b / 2 * (r.Vm[g.f] ** 2 + r.Vm[g.t] ** 2),
+        rtol=1e-9, atol=1e-13)
