@@ -236,6 +236,50 @@ def cpu_baseline(W, wall_s=15.0):
                        f"{sum(s == 0 for s in sts)}/{count}")
 
 
+def bench_fdpf(W, steps):
+    """Fast decoupled power flow on the workload's grid and scenarios: one
+    step = B' and B'' built and factored once for the batch (shared
+    impedances) + the batched decoupled iteration to 1e-8 + branch flows of
+    every case.  Also the one-case-per-launch rate."""
+    import torch
+
+    from paper_1811_02512_amd import binding as B
+
+    g, sym, info = W.g, W.sym1, W.sym1.info
+    Bn = W.B
+    dev = W.Vm.device
+    mat = torch.empty(1, info.fd_mat_doubles, dtype=torch.float64, device=dev)
+    fst = torch.empty(1, dtype=torch.int32, device=dev)
+    ws = torch.empty(Bn, info.fd_ws_doubles, dtype=torch.float64, device=dev)
+    it = torch.empty(Bn, dtype=torch.int32, device=dev)
+    st = torch.empty(Bn, dtype=torch.int32, device=dev)
+    flows = [torch.empty(Bn, g.m, dtype=torch.float64, device=dev) for _ in range(4)]
+
+    def step(b=Bn, with_flows=True):
+        B.pf_build_ybus(sym.h, 1, W.r, W.x, W.b, 0, W.yval, 2 * info.nnz_y)
+        B.pf_fdpf_matrices(sym.h, 1, W.r, W.x, W.b, 0, W.type, 0, mat, info.fd_mat_doubles)
+        B.pf_fdpf_factor(sym.h, 1, mat, info.fd_mat_doubles, fst)
+        W.Vm[:b].copy_(W.Vm0.expand(b, g.n))
+        W.Va[:b].copy_(W.Va0.expand(b, g.n))
+        B.pf_fdpf(sym.h, b, W.yval, 0, W.type, 0, W.Pt, W.Qt, g.n, W.Vm, W.Va, g.n, mat, 0,
+                  1e-8, 40, ws, info.fd_ws_doubles, it, None, st)
+        if with_flows:
+            B.pf_branch_flows(sym.h, b, W.r, W.x, W.b, 0, W.Vm, W.Va, g.n, *flows, g.m)
+
+    ms = timed(step, steps, 1)
+    status = st.cpu().numpy()
+    ok = int((status == 0).sum())
+    iters = it.cpu().numpy()
+    plain = timed(lambda: step(1, False), max(3, steps // 2), 1)
+    log(f"[bench] fdpf {Bn} cases: {ms:.2f} ms/step, converged {ok}/{Bn}, mean iterations "
+        f"{iters.mean():.2f}; one case {plain:.2f} ms")
+    return dict(solves_per_s=ok / ms * 1e3, ms_per_step=ms, converged=ok, cases=Bn,
+                mean_iterations=float(iters.mean()), plain_solves_per_s=1e3 / plain,
+                plain_ms_per_solve=plain,
+                step="Ybus + B', B'' built and factored once + batched decoupled iteration "
+                     "to 1e-8 + branch flows")
+
+
 def bench_multi(grids, label, steps=3):
     """One launch over cases with their own analyses; returns (solves/s, info)."""
     import torch
@@ -354,6 +398,8 @@ def main():
     fwd_ms = timed(lambda: W.step(adjoint=False), max(3, args.steps // 2), 1)
     plain_ms = timed(lambda: W.step(adjoint=False, Bn=1), max(3, args.steps // 2), 1)
 
+    fdpf = bench_fdpf(W, max(3, args.steps // 2))
+
     b_it = survey_bytes_per_iter(info)
     units = float(iters.sum())
     alg_bytes = b_it * units  # per launch: bytes per case-iteration x case-iterations
@@ -390,6 +436,7 @@ def main():
             "seconds": tuned["seconds"] + tuned1["seconds"],
             "from_file": bool(args.settings)},
         "kernel_sources": kernel_source_hash(),
+        "fdpf_10k_x256": fdpf,
         "roofline": {
             "bound": "hbm",
             "achieved": achieved,

@@ -24,9 +24,12 @@
  *     magnitude unknown.  A PV bus keeps |V| fixed: its row-1 block entries
  *     are (0,1) on the diagonal and (0,0) elsewhere, and its column-1 entries
  *     off its own row are zero.
- *   - Filled layout ("vals"), per case, 4*nn + 8*nnzL doubles:
- *       D section  [nn][4]        diagonal block of position p
- *       LU section [nnzL][2][4]   for slot s of S(p) (the s-th higher
+ *   - Filled layout ("vals"), per case, lu_offset + 8*nnzL doubles with
+ *     lu_offset = 8*ceil(nn/2) (info.lu_offset):
+ *       D section  [nn][4]        diagonal block of position p, then zero
+ *                                 padding up to lu_offset (so that every
+ *                                 slot record starts on a 64-byte boundary)
+ *       LU section [nnzL][2][4]   at lu_offset: for slot s of S(p) (the s-th higher
  *                                 neighbour k of p in the filled graph):
  *                                 [0] = block (k, p) below the diagonal,
  *                                 [1] = block (p, k) above it.
@@ -39,11 +42,12 @@
  *   - "stride" arguments are in elements between consecutive cases; 0 means
  *     the array is shared by all cases (inputs only).
  *   - Interleaved case groups ("interleave" C in 1, 2, 4, 8): an array of
- *     per-case doubles with stride S (a multiple of 4) is cut into groups of
+ *     per-case doubles with stride S (a multiple of 8) is cut into groups of
  *     C cases; element d of case c lives at
- *       (c / C) * C * S + (d / 4) * 4 C + 4 (c % C) + d % 4,
- *     i.e. every 32-byte chunk (one 2x2 block) of the C cases of a group is
- *     adjacent, so one 128-byte line carries the same block of four cases.
+ *       (c / C) * C * S + (d / 8) * 8 C + 8 (c % C) + d % 8,
+ *     i.e. the 64-byte chunks (one slot record, two D blocks, one Newton bus
+ *     record) of the C cases of a group alternate: a case's record stays in
+ *     one 128-byte line, and a line carries the same record of two cases.
  *     The buffer holds ceil(B / C) * C * S doubles.  C = 1 is the plain
  *     [B][S] layout.  Kernels launch the C workgroups of a group 8 blocks
  *     apart, which puts them on the same XCD of the MI355X at the same time,
@@ -97,7 +101,7 @@ typedef struct {
     int64_t n_upd;        /* off-diagonal block updates per factorisation   */
     int32_t nlevels;      /* hierarchical levels                            */
     int32_t max_level_width;
-    int64_t vals_doubles;    /* 4*nn + 8*nnz_l: filled layout, one case     */
+    int64_t vals_doubles;    /* lu_offset + 8*nnz_l: filled layout, one case */
     int64_t ws_doubles;      /* pf_newton workspace per case (vals first)   */
     size_t dev_bytes;        /* device buffer for pf_symbolic_upload        */
     int32_t tail_levels;     /* top levels factorised and solved in LDS     */
@@ -108,6 +112,9 @@ typedef struct {
                              /* clique (right-looking, one barrier a pivot) */
     int32_t ws_interleave;   /* cases per interleaved group in pf_newton's   */
                              /* workspace (1, 2, 4 or 8)                   */
+    int64_t lu_offset;       /* doubles before the LU section (8*ceil(nn/2)) */
+    int64_t fd_mat_doubles;  /* fast decoupled B' and B'' of one case        */
+    int64_t fd_ws_doubles;   /* pf_fdpf workspace per case                   */
 } pf_info;
 
 /* ---- status ------------------------------------------------------------ */
@@ -184,7 +191,8 @@ int pf_mismatch(const pf_symbolic sym, int B, const double* d_yval, int64_t y_st
 
 /* ---- Jacobian ("A matrix formation", Sec. III) ----------------------------
  * Assembles J = dF/d(theta, |V|) of the non-slack buses into the filled
- * layout d_vals (vals_stride >= info.vals_doubles); fill slots are zero.  */
+ * layout d_vals (vals_stride >= info.vals_doubles, a multiple of 8); fill
+ * slots and the D padding are zero.                                       */
 int pf_jacobian(const pf_symbolic sym, int B, const double* d_yval, int64_t y_stride,
                 const int8_t* d_type, int64_t type_stride, const double* d_Vm,
                 const double* d_Va, int64_t v_stride, double* d_vals, int64_t vals_stride,
@@ -218,7 +226,7 @@ int pf_solve(const pf_symbolic sym, int B, const double* d_vals, int64_t vals_st
  * max_iter steps.  d_Vm/d_Va: in = start state (flat start is the caller's),
  * out = solution, double[B][n] (v_stride).  d_ws: workspace in groups of
  * C = pf_newton_interleave(sym, B) cases (see "Interleaved case groups"), ws_stride
- * >= info.ws_doubles and a multiple of 4, 16-byte aligned; each case's first
+ * >= info.ws_doubles and a multiple of 8, 16-byte aligned; each case's first
  * info.vals_doubles hold its last factors in the filled layout (at the
  * solution with PF_NEWTON_KEEP_FACTORS), so pf_solve can take d_ws with
  * vals_stride = ws_stride and vals_interleave = C.  Outputs:
@@ -235,6 +243,54 @@ int pf_newton(const pf_symbolic sym, int B, const double* d_yval, int64_t y_stri
 /* Case grouping pf_newton uses for a batch of B: info.ws_interleave halved
  * until it does not exceed B (1 for a single case).  Returns -1 on error.  */
 int pf_newton_interleave(const pf_symbolic sym, int B);
+
+/* ---- fast decoupled power flow (Sec. III; Table III) -----------------------
+ * XB scheme (our reading; the paper fixes none): B' from branch reactances
+ * only (b'_ik = -sum 1/x over branches i-k, b'_ii = sum 1/x over branches at
+ * i), B'' = -Im(Y) of the pi-model with r, x and charging.  Both symmetric,
+ * so the factorisation is the paper's LDL^T (eqs. 1-3) with scalar elements
+ * on the same filled graph, elimination tree and levels as NR.
+ * Matrix layout per case (info.fd_mat_doubles = 2 * M): B' at 0, B'' at M,
+ * each d [round8(nn)] (diagonal by position, zero padded) then (lo, up) per
+ * slot of S(p) (the symmetric pair of entries).  A PV bus's B'' row and
+ * column are the identity.  After pf_fdpf_factor: d = 1/d_j, lo = l_kj d_j,
+ * up = l_kj (unit upper factor u_jk = l_kj, eq. 2).
+ * pf_fdpf_matrices: branch arrays as pf_build_ybus; d_type int8[B][n];
+ * d_mat 16-byte aligned, mat_stride a multiple of 8 (>= fd_mat_doubles if
+ * B > 1).  pf_fdpf_factor: in place; d_status[B] (may be NULL) PF_OK or
+ * PF_E_ZERO_PIVOT.  Matrices and factors depend on r, x, b and the bus
+ * types only, so a batch of scenarios shares one (mat_stride = 0).        */
+int pf_fdpf_matrices(const pf_symbolic sym, int B, const double* d_r, const double* d_x,
+                     const double* d_b, int64_t branch_stride, const int8_t* d_type,
+                     int64_t type_stride, double* d_mat, int64_t mat_stride, void* stream);
+int pf_fdpf_factor(const pf_symbolic sym, int B, double* d_mat, int64_t mat_stride,
+                   int32_t* d_status, void* stream);
+
+/* One launch runs the decoupled iteration for B cases, one workgroup per
+ * case, with the factors of pf_fdpf_factor (mat_stride = 0: shared): with
+ * F = calculated - scheduled as for pf_newton, repeat { stop if max|F| < tol;
+ * theta -= B'^-1 (F_P / |V|); stop if max|F| < tol; |V| -= B''^-1 (F_Q / |V|)
+ * at PQ buses }.  d_iters counts angle half steps, max_iter bounds them.
+ * d_ws: ws_stride >= info.fd_ws_doubles (a multiple of 8), 16-byte aligned.
+ * d_Vm/d_Va in/out and the outputs as pf_newton (status PF_OK,
+ * PF_E_NOT_CONVERGED or PF_E_NONFINITE).                                   */
+int pf_fdpf(const pf_symbolic sym, int B, const double* d_yval, int64_t y_stride,
+            const int8_t* d_type, int64_t type_stride, const double* d_Psp, const double* d_Qsp,
+            int64_t inj_stride, double* d_Vm, double* d_Va, int64_t v_stride,
+            const double* d_mat, int64_t mat_stride, double tol, int max_iter, double* d_ws,
+            int64_t ws_stride, int32_t* d_iters, double* d_norm, int32_t* d_status,
+            void* stream);
+
+/* ---- branch flows (Sec. II-A: post-convergence, nodal/edge parallel) -------
+ * For every branch e (from f to t, the analysis' order) of B cases: with
+ * y = 1/(r + jx) and charging b, I_ft = (y + jb/2) V_f - y V_t and
+ * S_ft = V_f conj(I_ft) = Pft + j Qft, and the same from the to end.  Branch
+ * arrays as pf_build_ybus; d_Vm/d_Va double[B][n] (v_stride); outputs
+ * double[B][m] (out_stride).                                              */
+int pf_branch_flows(const pf_symbolic sym, int B, const double* d_r, const double* d_x,
+                    const double* d_b, int64_t branch_stride, const double* d_Vm,
+                    const double* d_Va, int64_t v_stride, double* d_Pft, double* d_Qft,
+                    double* d_Ptf, double* d_Qtf, int64_t out_stride, void* stream);
 
 /* ---- adjoint right-hand side (beyond the paper) ----------------------------
  * Gathers the loss gradient with respect to the state into position order:

@@ -102,6 +102,44 @@ class Symbolic:
                     iters, norm, status)
         return iters, norm, status, ws
 
+    # -- fast decoupled power flow and branch flows ---------------------------
+    def fdpf_factors(self, r, x, b, bus_type):
+        """B' and B'' built and factored on the device.  r, x, b: [m] (shared)
+        or [B, m]; bus_type: [n] or [B, n].  Returns (mat, status) with mat
+        [1 or B, fd_mat_doubles]."""
+        info = self.info
+        Bn = 1 if r.dim() == 1 else r.shape[0]
+        mat = torch.empty(Bn, info.fd_mat_doubles, dtype=torch.float64, device=r.device)
+        status = torch.empty(Bn, dtype=torch.int32, device=r.device)
+        B.pf_fdpf_matrices(self.h, Bn, r, x, b, _stride(r), bus_type, _stride(bus_type), mat,
+                           info.fd_mat_doubles)
+        B.pf_fdpf_factor(self.h, Bn, mat, info.fd_mat_doubles, status)
+        return mat, status
+
+    def fdpf(self, yval, bus_type, Psp, Qsp, Vm, Va, mat, tol=1e-8, max_iter=40, ws=None):
+        """Batched fast decoupled power flow in place on Vm, Va ([B, n]) with
+        factors from fdpf_factors (one row shared, or one per case).
+        Returns (iters, norm, status, ws)."""
+        Bn = Vm.shape[0]
+        info = self.info
+        if ws is None:
+            ws = torch.empty(Bn, info.fd_ws_doubles, dtype=torch.float64, device=Vm.device)
+        iters = torch.empty(Bn, dtype=torch.int32, device=Vm.device)
+        norm = torch.empty(Bn, dtype=torch.float64, device=Vm.device)
+        status = torch.empty(Bn, dtype=torch.int32, device=Vm.device)
+        mstride = 0 if mat.shape[0] == 1 else info.fd_mat_doubles
+        B.pf_fdpf(self.h, Bn, yval, _stride(yval), bus_type, _stride(bus_type), Psp, Qsp,
+                  _stride(Psp), Vm, Va, Vm.shape[-1], mat, mstride, tol, max_iter, ws,
+                  info.fd_ws_doubles, iters, norm, status)
+        return iters, norm, status, ws
+
+    def branch_flows(self, r, x, b, Vm, Va):
+        """(Pft, Qft, Ptf, Qtf), each [B, m], of the states Vm, Va ([B, n])."""
+        Bn, m = Vm.shape[0], self.info.m
+        out = [torch.empty(Bn, m, dtype=torch.float64, device=Vm.device) for _ in range(4)]
+        B.pf_branch_flows(self.h, Bn, r, x, b, _stride(r), Vm, Va, Vm.shape[-1], *out, m)
+        return tuple(out)
+
 
 def _stride(t):
     """0 for a shared [k] array, row length for a [B, k] array."""

@@ -36,7 +36,8 @@ class pf_info(C.Structure):
                 ("dev_bytes", C.c_size_t), ("tail_levels", C.c_int32),
                 ("tail_nodes", C.c_int32), ("tail_lds_bytes", C.c_int32),
                 ("threads", C.c_int32), ("tail_clique", C.c_int32),
-                ("ws_interleave", C.c_int32)]
+                ("ws_interleave", C.c_int32), ("lu_offset", C.c_int64),
+                ("fd_mat_doubles", C.c_int64), ("fd_ws_doubles", C.c_int64)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -83,6 +84,12 @@ _SIGS = {
     "pf_newton_multi": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _d, _i, _i, _vp, _vp, _vp, _vp,
                          _vp], _i),
     "pf_multi_destroy": ([_vp], None),
+    "pf_fdpf_matrices": ([_vp, _i, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _i64, _vp], _i),
+    "pf_fdpf_factor": ([_vp, _i, _vp, _i64, _vp, _vp], _i),
+    "pf_fdpf": ([_vp, _i, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _i64, _d,
+                 _i, _vp, _i64, _vp, _vp, _vp, _vp], _i),
+    "pf_branch_flows": ([_vp, _i, _vp, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp,
+                         _i64, _vp], _i),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(lib, _name)
@@ -278,3 +285,31 @@ def pf_newton_multi(p, yval, bus_type, Psp, Qsp, Vm, Va, tol, max_iter, flags, w
 
 def pf_multi_destroy(p):
     lib.pf_multi_destroy(p)
+
+
+def pf_fdpf_matrices(h, B, r, x, b, branch_stride, bus_type, type_stride, mat, mat_stride,
+                     stream=None):
+    check(lib.pf_fdpf_matrices(h, B, ptr(r), ptr(x), ptr(b), branch_stride, ptr(bus_type),
+                               type_stride, ptr(mat), mat_stride, stream_ptr(stream)),
+          "pf_fdpf_matrices")
+
+
+def pf_fdpf_factor(h, B, mat, mat_stride, status=None, stream=None):
+    check(lib.pf_fdpf_factor(h, B, ptr(mat), mat_stride, ptr(status), stream_ptr(stream)),
+          "pf_fdpf_factor")
+
+
+def pf_fdpf(h, B, yval, y_stride, bus_type, type_stride, Psp, Qsp, inj_stride, Vm, Va,
+            v_stride, mat, mat_stride, tol, max_iter, ws, ws_stride, iters=None, norm=None,
+            status=None, stream=None):
+    check(lib.pf_fdpf(h, B, ptr(yval), y_stride, ptr(bus_type), type_stride, ptr(Psp), ptr(Qsp),
+                      inj_stride, ptr(Vm), ptr(Va), v_stride, ptr(mat), mat_stride, tol,
+                      max_iter, ptr(ws), ws_stride, ptr(iters), ptr(norm), ptr(status),
+                      stream_ptr(stream)), "pf_fdpf")
+
+
+def pf_branch_flows(h, B, r, x, b, branch_stride, Vm, Va, v_stride, Pft, Qft, Ptf, Qtf,
+                    out_stride, stream=None):
+    check(lib.pf_branch_flows(h, B, ptr(r), ptr(x), ptr(b), branch_stride, ptr(Vm), ptr(Va),
+                              v_stride, ptr(Pft), ptr(Qft), ptr(Ptf), ptr(Qtf), out_stride,
+                              stream_ptr(stream)), "pf_branch_flows")

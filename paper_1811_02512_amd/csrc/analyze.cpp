@@ -355,7 +355,8 @@ int analyze(int n, int m, const int32_t* from, const int32_t* to, int slack, int
     return PF_OK;
 }
 
-// The LDS tail: the largest run of top levels whose values fit the budget.
+// The LDS tail: the largest run of top levels whose values, with the
+// Newton kernel's PV bitmask, fit the budget.
 // Its top may be a clique chain: single-node levels where every node is
 // adjacent to all nodes above it in the filled graph.  That part is
 // factorised and solved densely (right-looking, one barrier per pivot).
@@ -374,7 +375,7 @@ void build_tail(HostSym& s, int64_t budget)
                 ++k2;
                 t2 += s.Lp[j + 1] - s.Lp[j];
             }
-            if (tail_bytes(k2, t2) > budget) break;
+            if (tail_bytes(k2, t2) + pv_mask_bytes(s.n) > budget) break;
             K = k2;
             TS = t2;
             L = l;

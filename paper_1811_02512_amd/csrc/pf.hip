@@ -53,15 +53,20 @@ constexpr int kLevelThreads = 512;
 constexpr int kXcds = 8;
 
 // One case's doubles inside an interleaved group of C cases: element d
-// lives at base + (d / 4) * 4C + 4 (case % C) + d % 4.  C = 1 is the plain
-// contiguous layout.
+// lives at base + (d / K) * K C + K (case % C) + d % K, i.e. chunks of K
+// doubles of the C cases alternate.  The filled values use K = 8 (a slot
+// record W, U is one 64-byte chunk, in a single cache line); the Newton
+// bus records and rhs use K = 4 (the 32-byte voltage part of a bus record,
+// which is what neighbours gather, shares its line with three other
+// cases' only).  C = 1 is the plain contiguous layout.
 struct View {
     double* base;
-    int lane4;  // 4 * (case % C)
-    int sh;     // log2(4 C)
+    int lane;  // K * (case % C)
+    int sh;    // log2(K C)
+    int cs;    // log2(K)
     __device__ __forceinline__ double* at(int64_t d) const
     {
-        return base + ((d >> 2) << sh) + lane4 + (d & 3);
+        return base + ((d >> cs) << sh) + lane + (d & ((1 << cs) - 1));
     }
     __device__ __forceinline__ Blk blk(int64_t d) const { return bload(at(d)); }
     __device__ __forceinline__ void put(int64_t d, const Blk& v) const { bstore(at(d), v); }
@@ -90,17 +95,33 @@ __device__ __forceinline__ int case_of_block(int b, int C, int B)
     return c < B ? c : -1;
 }
 
+// Filled values of case c (64-byte chunks).
 __device__ __forceinline__ View case_view(double* buf, int64_t stride, int C, int c)
 {
     View v;
     v.base = buf + (int64_t)(c / C) * C * stride;
-    v.lane4 = 4 * (c % C);
+    v.lane = 8 * (c % C);
+    v.sh = 3 + ilog2(C);
+    v.cs = 3;
+    return v;
+}
+
+// The Newton workspace's part after the filled values (bus records, rhs) of
+// case c, offsets relative to its start (32-byte chunks).
+__device__ __forceinline__ View case_bus_view(double* buf, int64_t stride, int C, int c,
+                                              int64_t vals)
+{
+    View v;
+    v.base = buf + (int64_t)(c / C) * C * stride + vals * C;
+    v.lane = 4 * (c % C);
     v.sh = 2 + ilog2(C);
+    v.cs = 2;
     return v;
 }
 
 // Offsets of the Newton workspace of one case (doubles):
-//   D [nn][4] | LU [nnz_l][8] | bus records [n][8] | rhs [nn][2]
+//   D [nn][4] (padded) | LU [nnz_l][8] | bus records [n][8] | rhs [nn][2]
+// D and LU through the values view; BUS and RHS relative to the bus view.
 // bus record: e, f, |V|, theta | P, Q, P_sp, Q_sp  (e + jf = V, P + jQ = S).
 struct Off {
     int64_t D, LU, BUS, RHS;
@@ -109,9 +130,9 @@ __device__ __forceinline__ Off ws_off(const DevSym& S)
 {
     Off o;
     o.D = 0;
-    o.LU = 4 * (int64_t)S.nn;
-    o.BUS = S.vals_doubles;
-    o.RHS = o.BUS + 8 * (int64_t)S.n;
+    o.LU = S.lu_off;
+    o.BUS = 0;
+    o.RHS = 8 * (int64_t)S.n;
     return o;
 }
 
@@ -139,15 +160,37 @@ struct EFPolar {
 };
 
 // P_i + jQ_i = V_i conj(sum_k Y_ik V_k)  (nodal: one row of Y, entries
-// [q0, q1)).  Two entries per step so that their gathers overlap.
+// [q0, q1), summed in order).  The first four entries' indices, admittances
+// and voltages are requested together (in-bounds loads of entry q0 stand in
+// for absent ones), the rest two at a time.
 template <class EF>
 __device__ __forceinline__ void injection_row(const DevSym& S, const double* __restrict__ yv,
                                               const EF& ef, int i, int q0, int q1, double& P,
                                               double& Q)
 {
-    double ir = 0.0, ii = 0.0;
     const double2* y2 = reinterpret_cast<const double2*>(yv);
-    int q = q0;
+    double ei, fi;
+    ef.get(i, ei, fi);
+    int kq[4];
+    double2 yq[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int q = q0 + k < q1 ? q0 + k : q0;
+        kq[k] = S.ycol[q];
+        yq[k] = y2[q];
+    }
+    double ek[4], fk[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ef.get(kq[k], ek[k], fk[k]);
+    double ir = 0.0, ii = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (q0 + k < q1) {
+            ir = fma(yq[k].x, ek[k], fma(-yq[k].y, fk[k], ir));
+            ii = fma(yq[k].x, fk[k], fma(yq[k].y, ek[k], ii));
+        }
+    }
+    int q = q0 + 4;
     for (; q + 1 < q1; q += 2) {
         const int k0 = S.ycol[q], k1 = S.ycol[q + 1];
         const double2 y0 = y2[q], y1 = y2[q + 1];
@@ -167,8 +210,6 @@ __device__ __forceinline__ void injection_row(const DevSym& S, const double* __r
         ir = fma(y0.x, e0, fma(-y0.y, f0, ir));
         ii = fma(y0.x, f0, fma(y0.y, e0, ii));
     }
-    double ei, fi;
-    ef.get(i, ei, fi);
     P = ei * ir + fi * ii;
     Q = fi * ir - ei * ii;
 }
@@ -180,18 +221,158 @@ __device__ __forceinline__ void injection(const DevSym& S, const double* __restr
     injection_row(S, yv, ef, i, S.yptr[i], S.yptr[i + 1], P, Q);
 }
 
+// PV flags of one case's buses, one bit per bus, in LDS after the tail.
+struct PvMask {
+    const uint32_t* m;
+    __device__ __forceinline__ bool operator()(int k) const { return (m[k >> 5] >> (k & 31)) & 1u; }
+};
+
+__device__ __forceinline__ uint32_t* pv_words(const DevSym& S)
+{
+    return reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(pf_smem) + S.tail_lds);
+}
+
+// Fills the mask m from the case's bus types (a ballot per wavefront); the
+// caller synchronises before use.
+__device__ __forceinline__ void pv_fill_at(uint32_t* m, const DevSym& S, const int8_t* type)
+{
+    for (int base = 0; base < S.n; base += blockDim.x) {
+        const int i = base + threadIdx.x;
+        const unsigned long long bits = __ballot(i < S.n && type[i] == T_PV);
+        if ((threadIdx.x & 63) == 0 && i < S.n) {
+            m[i >> 5] = (uint32_t)bits;
+            m[(i >> 5) + 1] = (uint32_t)(bits >> 32);
+        }
+    }
+}
+
+__device__ __forceinline__ void pv_fill(const DevSym& S, const int8_t* type)
+{
+    pv_fill_at(pv_words(S), S, type);
+}
+
+// First four admittance entries of one row: indices and values, then the
+// voltages they multiply (two dependent batches of loads, no stores).
+struct RowHead {
+    double2 y[4];
+    double e[4], f[4];
+};
+
+template <class EF>
+__device__ __forceinline__ void row_head_idx(const DevSym& S, const double* __restrict__ yv,
+                                             int q0, int q1, int (&k)[4], RowHead& h)
+{
+    const double2* y2 = reinterpret_cast<const double2*>(yv);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int q = q0 + t < q1 ? q0 + t : q0;
+        k[t] = S.ycol[q];
+        h.y[t] = y2[q];
+    }
+}
+
+template <class EF>
+__device__ __forceinline__ void row_head_v(const EF& ef, const int (&k)[4], RowHead& h)
+{
+#pragma unroll
+    for (int t = 0; t < 4; ++t) ef.get(k[t], h.e[t], h.f[t]);
+}
+
+// Sum of the row (head from registers, the rest loaded two at a time), in
+// entry order, and the injection at bus voltage (ei, fi).
+template <class EF>
+__device__ __forceinline__ void row_finish(const DevSym& S, const double* __restrict__ yv,
+                                           const EF& ef, int q0, int q1, const RowHead& h,
+                                           double ei, double fi, double& P, double& Q)
+{
+    const double2* y2 = reinterpret_cast<const double2*>(yv);
+    double ir = 0.0, ii = 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        if (q0 + t < q1) {
+            ir = fma(h.y[t].x, h.e[t], fma(-h.y[t].y, h.f[t], ir));
+            ii = fma(h.y[t].x, h.f[t], fma(h.y[t].y, h.e[t], ii));
+        }
+    }
+    int q = q0 + 4;
+    for (; q + 1 < q1; q += 2) {
+        const int k0 = S.ycol[q], k1 = S.ycol[q + 1];
+        const double2 y0 = y2[q], y1 = y2[q + 1];
+        double e0, f0, e1, f1;
+        ef.get(k0, e0, f0);
+        ef.get(k1, e1, f1);
+        ir = fma(y0.x, e0, fma(-y0.y, f0, ir));
+        ii = fma(y0.x, f0, fma(y0.y, e0, ii));
+        ir = fma(y1.x, e1, fma(-y1.y, f1, ir));
+        ii = fma(y1.x, f1, fma(y1.y, e1, ii));
+    }
+    if (q < q1) {
+        const int k0 = S.ycol[q];
+        const double2 y0 = y2[q];
+        double e0, f0;
+        ef.get(k0, e0, f0);
+        ir = fma(y0.x, e0, fma(-y0.y, f0, ir));
+        ii = fma(y0.x, f0, fma(y0.y, e0, ii));
+    }
+    P = ei * ir + fi * ii;
+    Q = fi * ir - ei * ii;
+}
+
 // Jacobian source: the Newton state of one case (bus records in the view).
+// diag_in / off_in only issue loads, diag_of / off_of only compute, so that a
+// caller can have all of a node's loads in flight before it waits for any.
+// Invalid indices are never dereferenced: a fill slot (no admittance entry)
+// reads entry 0 and is then zeroed.
 struct SrcState {
     const double* yv;
-    const int8_t* type;
+    PvMask type;
     View w;
     int64_t bus_off;
+    struct DiagIn {
+        double2 y;
+        Blk r;  // e, f, |V|, theta of the node's bus
+        double2 s;
+        bool pv;
+    };
+    struct OffIn {
+        Blk rk;
+        double2 yl, yu;
+        bool pk, fill;
+    };
+    __device__ __forceinline__ DiagIn diag_in(int, int bus, int yd) const
+    {
+        const double2* y2 = reinterpret_cast<const double2*>(yv);
+        const int64_t rec = bus_off + 8 * (int64_t)bus;
+        return {y2[yd], w.blk(rec), w.v2(rec + 4), type(bus)};
+    }
+    __device__ __forceinline__ Blk diag_of(const DiagIn& d) const
+    {
+        return jac_diag(d.y.x, d.y.y, d.s.x, d.s.y, d.r.c, d.pv);
+    }
+    __device__ __forceinline__ OffIn off_in(int, int bk, int ylo, int yup) const
+    {
+        const double2* y2 = reinterpret_cast<const double2*>(yv);
+        const bool fill = ylo < 0;
+        return {w.blk(bus_off + 8 * (int64_t)bk), y2[fill ? 0 : ylo], y2[fill ? 0 : yup],
+                type(bk), fill};
+    }
+    __device__ __forceinline__ void off_of(const DiagIn& dj, const OffIn& o, Blk& lo,
+                                           Blk& up) const
+    {
+        if (o.fill) {
+            lo = bzero();
+            up = bzero();
+            return;
+        }
+        lo = jac_off(o.yl.x, o.yl.y, o.rk.a, o.rk.b, dj.r.a, dj.r.b, dj.r.c, o.pk, dj.pv);
+        up = jac_off(o.yu.x, o.yu.y, dj.r.a, dj.r.b, o.rk.a, o.rk.b, o.rk.c, dj.pv, o.pk);
+    }
     __device__ __forceinline__ Blk diag(int, int bus, int yd) const
     {
         const double2 y = reinterpret_cast<const double2*>(yv)[yd];
         const double vm = *w.at(bus_off + 8 * (int64_t)bus + 2);
         const double2 s = w.v2(bus_off + 8 * (int64_t)bus + 4);
-        return jac_diag(y.x, y.y, s.x, s.y, vm, type[bus] == T_PV);
+        return jac_diag(y.x, y.y, s.x, s.y, vm, type(bus));
     }
     // block (k, j) below the diagonal and (j, k) above it; zero at fill
     __device__ __forceinline__ void off(int, int bj, int bk, int ylo, int yup, Blk& lo,
@@ -204,7 +385,7 @@ struct SrcState {
         }
         const Blk rj = w.blk(bus_off + 8 * (int64_t)bj);  // e, f, |V|, theta
         const Blk rk = w.blk(bus_off + 8 * (int64_t)bk);
-        const bool pj = type[bj] == T_PV, pk = type[bk] == T_PV;
+        const bool pj = type(bj), pk = type(bk);
         const double2 yl = reinterpret_cast<const double2*>(yv)[ylo];
         const double2 yu = reinterpret_cast<const double2*>(yv)[yup];
         lo = jac_off(yl.x, yl.y, rk.a, rk.b, rj.a, rj.b, rj.c, pk, pj);
@@ -216,6 +397,27 @@ struct SrcState {
 struct SrcLoad {
     View w;
     int64_t lu_off;
+    struct DiagIn {
+        Blk a;
+    };
+    struct OffIn {
+        Blk lo, up;
+    };
+    __device__ __forceinline__ DiagIn diag_in(int j, int, int) const
+    {
+        return {w.blk(4 * (int64_t)j)};
+    }
+    __device__ __forceinline__ Blk diag_of(const DiagIn& d) const { return d.a; }
+    __device__ __forceinline__ OffIn off_in(int s, int, int, int) const
+    {
+        return {w.blk(lu_off + 8 * (int64_t)s), w.blk(lu_off + 8 * (int64_t)s + 4)};
+    }
+    __device__ __forceinline__ void off_of(const DiagIn&, const OffIn& o, Blk& lo,
+                                           Blk& up) const
+    {
+        lo = o.lo;
+        up = o.up;
+    }
     __device__ __forceinline__ Blk diag(int j, int, int) const { return w.blk(4 * (int64_t)j); }
     __device__ __forceinline__ void off(int s, int, int, int, int, Blk& lo, Blk& up) const
     {
@@ -245,14 +447,15 @@ __device__ __forceinline__ void for_levels(const DevSym& S, int l0, int l1, bool
     }
 }
 
-// Level-ordered node record (see DevSym::node_info).
+// Level-ordered node record, the part the sweeps use ({j, bus, r0, r1},
+// {s0, s1, ydiag, 0}); the admittance-row range is read by the mismatch only.
 struct NodeRec {
-    int4 a, b, c;
+    int4 a, b;
 };
 
 __device__ __forceinline__ NodeRec load_rec(const DevSym& S, int x)
 {
-    return {S.node_info[3 * x], S.node_info[3 * x + 1], S.node_info[3 * x + 2]};
+    return {S.node_info[3 * x], S.node_info[3 * x + 1]};
 }
 
 // As for_levels, passing fn(x, rec, lane, g) the node's record; the record
@@ -305,29 +508,60 @@ __device__ __forceinline__ void for_tail_range(const DevSym& S, int t0, int t1, 
 // Block updates of one destination slot from pairs (a, b) = (slot(i;k), slot(i;j)):
 //   W_kj -= W_ki U_ij,  V_jk -= W_ji U_ik.
 // Two pairs per step; the next step's indices are fetched before this
-// step's blocks so that index and value loads overlap.
+// step's blocks so that index and value loads overlap.  Absent pairs read
+// entry 0 (always in bounds) and contribute nothing.
+__device__ __forceinline__ int2 upd_at(const int2* __restrict__ upd, int u, int u1)
+{
+    return upd[u < u1 ? u : 0];
+}
+
 __device__ __forceinline__ void apply_updates(const int2* __restrict__ upd, int u0, int u1,
                                               const View& w, int64_t lu, Blk& Wk, Blk& Vk)
 {
     if (u0 >= u1) return;
     int2 p = upd[u0];
-    int2 q = (u0 + 1 < u1) ? upd[u0 + 1] : make_int2(0, 0);
+    int2 q = upd_at(upd, u0 + 1, u1);
     for (int u = u0; u < u1; u += 2) {
         const bool has_q = u + 1 < u1;
-        const int2 pn = (u + 2 < u1) ? upd[u + 2] : make_int2(0, 0);
-        const int2 qn = (u + 3 < u1) ? upd[u + 3] : make_int2(0, 0);
+        const int2 pn = upd_at(upd, u + 2, u1);
+        const int2 qn = upd_at(upd, u + 3, u1);
         const Blk Wa = w.blk(lu + 8 * (int64_t)p.x), Ua = w.blk(lu + 8 * (int64_t)p.x + 4);
         const Blk Wb = w.blk(lu + 8 * (int64_t)p.y), Ub = w.blk(lu + 8 * (int64_t)p.y + 4);
+        const Blk Wc = w.blk(lu + 8 * (int64_t)q.x), Uc = w.blk(lu + 8 * (int64_t)q.x + 4);
+        const Blk Wd = w.blk(lu + 8 * (int64_t)q.y), Ud = w.blk(lu + 8 * (int64_t)q.y + 4);
+        bmsub(Wk, Wa, Ub);
+        bmsub(Vk, Wb, Ua);
         if (has_q) {
-            const Blk Wc = w.blk(lu + 8 * (int64_t)q.x), Uc = w.blk(lu + 8 * (int64_t)q.x + 4);
-            const Blk Wd = w.blk(lu + 8 * (int64_t)q.y), Ud = w.blk(lu + 8 * (int64_t)q.y + 4);
-            bmsub(Wk, Wa, Ub);
-            bmsub(Vk, Wb, Ua);
             bmsub(Wk, Wc, Ud);
             bmsub(Vk, Wd, Uc);
-        } else {
+        }
+        p = pn;
+        q = qn;
+    }
+}
+
+// The updates of two destinations at once, one pair of each per step, with
+// the first pairs (p, q) already loaded: both chains of loads are in flight
+// together.  The order of the updates of each destination is the list order.
+__device__ __forceinline__ void apply_updates2(const int2* __restrict__ upd, int u0, int u1,
+                                               int v0, int v1, int2 p, int2 q, const View& w,
+                                               int64_t lu, Blk& Wk, Blk& Vk, Blk& Wk2, Blk& Vk2)
+{
+    for (int a = u0, b = v0; a < u1 || b < v1; ++a, ++b) {
+        const bool hp = a < u1, hq = b < v1;
+        const int2 pn = upd_at(upd, a + 1, u1);
+        const int2 qn = upd_at(upd, b + 1, v1);
+        const Blk Wa = w.blk(lu + 8 * (int64_t)p.x), Ua = w.blk(lu + 8 * (int64_t)p.x + 4);
+        const Blk Wb = w.blk(lu + 8 * (int64_t)p.y), Ub = w.blk(lu + 8 * (int64_t)p.y + 4);
+        const Blk Wc = w.blk(lu + 8 * (int64_t)q.x), Uc = w.blk(lu + 8 * (int64_t)q.x + 4);
+        const Blk Wd = w.blk(lu + 8 * (int64_t)q.y), Ud = w.blk(lu + 8 * (int64_t)q.y + 4);
+        if (hp) {
             bmsub(Wk, Wa, Ub);
             bmsub(Vk, Wb, Ua);
+        }
+        if (hq) {
+            bmsub(Wk2, Wc, Ud);
+            bmsub(Vk2, Wd, Uc);
         }
         p = pn;
         q = qn;
@@ -367,27 +601,56 @@ __device__ __forceinline__ void gsum_blk(Blk& v, int g)
 // Left-looking block LDU of node record x (FactorizeGraphA, pull form):
 //   D_j  = A_jj - sum_{i in R(j)} W_ji U_ij
 //   W_kj = A_kj - sum_i W_ki U_ij,  V_jk = A_jk - sum_i W_ji U_ik  (k in S(j))
-//   stored: D section <- D_j^-1, LU[s] <- (W_kj, U_jk = D_j^-1 V_jk)
+//   stored: LU[s] <- (W_kj, U_jk = D_j^-1 V_jk), and with STORE_D the D
+//   section <- D_j^-1 (needed only by later solves with these factors).
 // With FWD, also the forward substitution and normalisation of the rhs:
 //   y_j = D_j^-1 (b_j - sum_{i in R(j)} W_ji y_i).
-template <class SRC, bool FWD>
+// Loads are issued in batches so that the chain of dependent requests per
+// node stays short: the record's dependants first (diagonal inputs, rhs,
+// the first two destinations' slot records, the first R indices), then R(j)
+// four entries per lane at a time, then two destinations per step with both
+// update chains in flight together.  Every load is in bounds: absent items
+// read entry 0 and are masked out.
+template <class SRC, bool FWD, bool STORE_D>
 __device__ __forceinline__ void factor_node(const DevSym& S, const SRC& src, const NodeRec& rec,
                                             int lane, int g, const View& w, int64_t lu,
-                                            int64_t rhs, int* s_bad)
+                                            const View& wr, int64_t rhs, int* s_bad)
 {
     const int4 n0 = rec.a;
     const int4 n1 = rec.b;
     const int j = n0.x, bus = n0.y;
+    const int r1 = n0.w, s1 = n1.y;
+    const typename SRC::DiagIn din = src.diag_in(j, bus, n1.z);
+    double2 bj = make_double2(0.0, 0.0);
+    if (FWD) bj = wr.v2(rhs + 2 * (int64_t)j);
+    int s = n1.x + lane;
+    int sc = s < s1 ? s : 0, sc2 = s + g < s1 ? s + g : 0;
+    int4 sa = S.slot_info[2 * sc], sb = S.slot_info[2 * sc + 1];
+    int4 sa2 = S.slot_info[2 * sc2], sb2 = S.slot_info[2 * sc2 + 1];
+    int2 e[4];
+    int r = n0.z + lane;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) e[k] = S.rl[r + k * g < r1 ? r + k * g : 0];
     Blk ds = bzero();
     double z0 = 0.0, z1 = 0.0;
-    for (int r = n0.z + lane; r < n0.w; r += g) {
-        const int2 e = S.rl[r];
-        const Blk wv = w.blk(lu + 8 * (int64_t)e.y);
-        const Blk uv = w.blk(lu + 8 * (int64_t)e.y + 4);
-        bmadd(ds, wv, uv);
-        if (FWD) {
-            const double2 yi = w.v2(rhs + 2 * (int64_t)e.x);
-            mvadd(z0, z1, wv, yi.x, yi.y);
+    for (; r < r1; r += 4 * g) {
+        Blk wv[4], uv[4];
+        double2 yi[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            wv[k] = w.blk(lu + 8 * (int64_t)e[k].y);
+            uv[k] = w.blk(lu + 8 * (int64_t)e[k].y + 4);
+            if (FWD) yi[k] = wr.v2(rhs + 2 * (int64_t)e[k].x);
+        }
+        const int rn = r + 4 * g;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) e[k] = S.rl[rn + k * g < r1 ? rn + k * g : 0];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (r + k * g < r1) {
+                bmadd(ds, wv[k], uv[k]);
+                if (FWD) mvadd(z0, z1, wv[k], yi[k].x, yi[k].y);
+            }
         }
     }
     if (g > 1) {
@@ -397,24 +660,27 @@ __device__ __forceinline__ void factor_node(const DevSym& S, const SRC& src, con
             z1 = gsum(z1, g);
         }
     }
-    const Blk Ajj = src.diag(j, bus, n1.z);
-    const Blk Dj = {Ajj.a - ds.a, Ajj.b - ds.b, Ajj.c - ds.c, Ajj.d - ds.d};
+    const Blk Ajj = src.diag_of(din);
     bool ok;
-    const Blk Di = binv(Dj, ok);
-    // destinations two at a time: both slot records, both Jacobian pairs and
-    // both update lists are in flight together
-    for (int s = n1.x + lane; s < n1.y; s += 2 * g) {
+    const Blk Di = binv({Ajj.a - ds.a, Ajj.b - ds.b, Ajj.c - ds.c, Ajj.d - ds.d}, ok);
+    for (; s < s1; s += 2 * g) {
         const int s2 = s + g;
-        const bool two = s2 < n1.y;
-        const int4 a = S.slot_info[2 * s];
-        const int4 b = S.slot_info[2 * s + 1];
-        const int4 a2 = two ? S.slot_info[2 * s2] : make_int4(0, 0, -1, 0);
-        const int4 b2 = two ? S.slot_info[2 * s2 + 1] : make_int4(0, 0, 0, 0);
-        Blk Wk, Vk, Wk2 = bzero(), Vk2 = bzero();
-        src.off(s, bus, a.y, a.z, a.w, Wk, Vk);
-        if (two) src.off(s2, bus, a2.y, a2.z, a2.w, Wk2, Vk2);
-        apply_updates(S.upd, b.x, b.y, w, lu, Wk, Vk);
-        apply_updates(S.upd, b2.x, b2.y, w, lu, Wk2, Vk2);
+        const bool two = s2 < s1;
+        const typename SRC::OffIn o1 = src.off_in(s, sa.y, sa.z, sa.w);
+        const typename SRC::OffIn o2 = src.off_in(two ? s2 : s, sa2.y, sa2.z, sa2.w);
+        const int u0 = sb.x, u1 = sb.y, v0 = two ? sb2.x : 0, v1 = two ? sb2.y : 0;
+        const int2 p = upd_at(S.upd, u0, u1), q = upd_at(S.upd, v0, v1);
+        const int sn = s + 2 * g;
+        sc = sn < s1 ? sn : 0;
+        sc2 = sn + g < s1 ? sn + g : 0;
+        sa = S.slot_info[2 * sc];
+        sb = S.slot_info[2 * sc + 1];
+        sa2 = S.slot_info[2 * sc2];
+        sb2 = S.slot_info[2 * sc2 + 1];
+        Blk Wk, Vk, Wk2, Vk2;
+        src.off_of(din, o1, Wk, Vk);
+        src.off_of(din, o2, Wk2, Vk2);
+        apply_updates2(S.upd, u0, u1, v0, v1, p, q, w, lu, Wk, Vk, Wk2, Vk2);
         w.put(lu + 8 * (int64_t)s, Wk);
         w.put(lu + 8 * (int64_t)s + 4, bmul(Di, Vk));
         if (two) {
@@ -424,12 +690,11 @@ __device__ __forceinline__ void factor_node(const DevSym& S, const SRC& src, con
     }
     if (lane == 0) {
         if (!ok) *s_bad = 1;
-        w.put(4 * (int64_t)j, Di);
+        if (STORE_D) w.put(4 * (int64_t)j, Di);
         if (FWD) {
-            const double2 bj = w.v2(rhs + 2 * (int64_t)j);
             double y0 = 0.0, y1 = 0.0;
             mvadd(y0, y1, Di, bj.x - z0, bj.y - z1);
-            w.put2(rhs + 2 * (int64_t)j, make_double2(y0, y1));
+            wr.put2(rhs + 2 * (int64_t)j, make_double2(y0, y1));
         }
     }
 }
@@ -454,7 +719,7 @@ __device__ __forceinline__ int clique_slot(int c0, int KC, int a, int b)
 // WRITE stores the tail's factors to global memory.
 template <class SRC, bool FWD, bool WRITE>
 __device__ void tail_factor(const DevSym& S, const SRC& src, const View& w, int64_t lu,
-                            int64_t rhs, int* s_bad)
+                            const View& wr, int64_t rhs, int* s_bad)
 {
     const int K = S.tail_nodes, TS = S.tail_slots, KC = S.tail_clique;
     const int nT = S.nlev - S.tail_level;
@@ -468,7 +733,7 @@ __device__ void tail_factor(const DevSym& S, const SRC& src, const View& w, int6
             Blk acc = src.diag(t0.x, t0.y, t0.z);
             double z0 = 0.0, z1 = 0.0;
             if (FWD) {
-                const double2 b = w.v2(rhs + 2 * (int64_t)t0.x);
+                const double2 b = wr.v2(rhs + 2 * (int64_t)t0.x);
                 z0 = b.x;
                 z1 = b.y;
             }
@@ -477,7 +742,7 @@ __device__ void tail_factor(const DevSym& S, const SRC& src, const View& w, int6
                 const Blk wv = w.blk(lu + 8 * (int64_t)e.y);
                 bmsub(acc, wv, w.blk(lu + 8 * (int64_t)e.y + 4));
                 if (FWD) {
-                    const double2 yi = w.v2(rhs + 2 * (int64_t)e.x);
+                    const double2 yi = wr.v2(rhs + 2 * (int64_t)e.x);
                     z0 = fma(-wv.a, yi.x, fma(-wv.b, yi.y, z0));
                     z1 = fma(-wv.c, yi.x, fma(-wv.d, yi.y, z1));
                 }
@@ -642,7 +907,7 @@ __device__ void tail_factor(const DevSym& S, const SRC& src, const View& w, int6
         for (int jl = threadIdx.x; jl < K; jl += blockDim.x) {
             const int j = S.t_node[3 * jl].x;
             w.put(4 * (int64_t)j, bload(sD + 4 * jl));
-            if (FWD) w.put2(rhs + 2 * (int64_t)j, make_double2(sy[2 * jl], sy[2 * jl + 1]));
+            if (FWD) wr.put2(rhs + 2 * (int64_t)j, make_double2(sy[2 * jl], sy[2 * jl + 1]));
         }
         __syncthreads();
     }
@@ -650,15 +915,20 @@ __device__ void tail_factor(const DevSym& S, const SRC& src, const View& w, int6
 
 // Newton step of one bus: theta -= dtheta, |V| -= d|V| (PQ), new e + jf;
 // the record's first 32 bytes (e, f, |V|, theta) are rewritten in one store.
-__device__ __forceinline__ void apply_step(const View& w, int64_t rec, bool pv, double x0,
-                                           double x1)
+__device__ __forceinline__ void apply_step_to(const View& w, int64_t rec, const Blk& r, bool pv,
+                                              double x0, double x1)
 {
-    const Blk r = w.blk(rec);
     const double va = r.d - x0;
     const double vm = pv ? r.c : r.c - x1;
     double sn, cs;
     sincos(va, &sn, &cs);
     w.put(rec, {vm * cs, vm * sn, vm, va});
+}
+
+__device__ __forceinline__ void apply_step(const View& w, int64_t rec, bool pv, double x0,
+                                           double x1)
+{
+    apply_step_to(w, rec, w.blk(rec), pv, x0, x1);
 }
 
 // Backward substitution of the tail from LDS: x_j = y_j - sum U_jk x_k, the
@@ -667,7 +937,7 @@ __device__ __forceinline__ void apply_step(const View& w, int64_t rec, bool pv, 
 // clique nodes k below a in parallel, one barrier per pivot.
 template <bool UPDATE>
 __device__ void tail_backward(const DevSym& S, const View& w, int64_t rhs, int64_t bus_off,
-                              const int8_t* type)
+                              PvMask type)
 {
     const int K = S.tail_nodes, TS = S.tail_slots, KC = S.tail_clique;
     const int nT = S.nlev - S.tail_level;
@@ -689,7 +959,7 @@ __device__ void tail_backward(const DevSym& S, const View& w, int64_t rhs, int64
                     const int4 t0 = S.t_node[3 * ja];
                     w.put2(rhs + 2 * (int64_t)t0.x, make_double2(x0, x1));
                     if (UPDATE)
-                        apply_step(w, bus_off + 8 * (int64_t)t0.y, type[t0.y] == T_PV, x0, x1);
+                        apply_step(w, bus_off + 8 * (int64_t)t0.y, type(t0.y), x0, x1);
                 }
             }
             __syncthreads();
@@ -712,34 +982,59 @@ __device__ void tail_backward(const DevSym& S, const View& w, int64_t rhs, int64
             sy[2 * jl] = x0;
             sy[2 * jl + 1] = x1;
             w.put2(rhs + 2 * (int64_t)t0.x, make_double2(x0, x1));
-            if (UPDATE) apply_step(w, bus_off + 8 * (int64_t)t0.y, type[t0.y] == T_PV, x0, x1);
+            if (UPDATE) apply_step(w, bus_off + 8 * (int64_t)t0.y, type(t0.y), x0, x1);
         }
     });
 }
 
-// Backward substitution of node record x: x_j = y_j - sum_{k in S(j)} U_jk x_k.
+// Backward substitution of node record x: x_j = y_j - sum_{k in S(j)} U_jk x_k,
+// four slots per lane at a time (next indices in flight), the node's own
+// rhs entry and bus record requested first.
 template <bool UPDATE>
 __device__ __forceinline__ void back_node(const DevSym& S, const NodeRec& rec, int lane, int g,
-                                          const View& w, int64_t lu, int64_t rhs,
-                                          int64_t bus_off, const int8_t* type)
+                                          const View& w, int64_t lu, const View& wb,
+                                          int64_t rhs, int64_t bus_off, PvMask type)
 {
     const int4 n0 = rec.a;
     const int4 n1 = rec.b;
+    const int s1 = n1.y;
+    const double2 y = wb.v2(rhs + 2 * (int64_t)n0.x);
+    const int64_t brec = bus_off + 8 * (int64_t)n0.y;
+    Blk br = bzero();
+    bool pv = false;
+    if (UPDATE) {
+        br = wb.blk(brec);
+        pv = type(n0.y);
+    }
+    int s = n1.x + lane;
+    int kk[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) kk[k] = S.Li[s + k * g < s1 ? s + k * g : 0];
     double a0 = 0.0, a1 = 0.0;
-    for (int s = n1.x + lane; s < n1.y; s += g) {
-        const Blk u = w.blk(lu + 8 * (int64_t)s + 4);
-        const double2 xk = w.v2(rhs + 2 * (int64_t)S.Li[s]);
-        mvadd(a0, a1, u, xk.x, xk.y);
+    for (; s < s1; s += 4 * g) {
+        Blk u[4];
+        double2 xk[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int sk = s + k * g < s1 ? s + k * g : 0;
+            u[k] = w.blk(lu + 8 * (int64_t)sk + 4);
+            xk[k] = wb.v2(rhs + 2 * (int64_t)kk[k]);
+        }
+        const int sn = s + 4 * g;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) kk[k] = S.Li[sn + k * g < s1 ? sn + k * g : 0];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (s + k * g < s1) mvadd(a0, a1, u[k], xk[k].x, xk[k].y);
     }
     if (g > 1) {
         a0 = gsum(a0, g);
         a1 = gsum(a1, g);
     }
     if (lane == 0) {
-        const double2 y = w.v2(rhs + 2 * (int64_t)n0.x);
         const double x0 = y.x - a0, x1 = y.y - a1;
-        w.put2(rhs + 2 * (int64_t)n0.x, make_double2(x0, x1));
-        if (UPDATE) apply_step(w, bus_off + 8 * (int64_t)n0.y, type[n0.y] == T_PV, x0, x1);
+        wb.put2(rhs + 2 * (int64_t)n0.x, make_double2(x0, x1));
+        if (UPDATE) apply_step_to(wb, brec, br, pv, x0, x1);
     }
 }
 
@@ -801,13 +1096,69 @@ struct CaseDesc {
     int64_t bus_off, br_off, y_off, ws_off;
 };
 
+// Mismatch pass of one case: P + jQ into the bus records and F = calculated
+// - scheduled (F_Q = 0 at PV buses) into the rhs in position order, divided
+// by |V| with SCALE (the fast decoupled right-hand sides); the thread's max
+// |F| and NaN flag accumulate into mx and nan.
+template <bool SCALE>
+__device__ __forceinline__ void mismatch_pass(const DevSym& S, const double* yv, const EFView& ef,
+                                              const View& wb, const Off& o, const PvMask& pvm,
+                                              double& mx, int& nan)
+{
+    // mismatch: two buses per thread per step, all of their loads issued
+    // before either is summed; the next step's records are in flight
+    const int bd = blockDim.x;
+    int x = threadIdx.x;
+    int4 a0 = S.node_info[3 * (x < S.nn ? x : 0)];
+    int4 a2 = S.node_info[3 * (x < S.nn ? x : 0) + 2];
+    int4 b0 = S.node_info[3 * (x + bd < S.nn ? x + bd : 0)];
+    int4 b2 = S.node_info[3 * (x + bd < S.nn ? x + bd : 0) + 2];
+    for (; x < S.nn; x += 2 * bd) {
+        const bool two = x + bd < S.nn;
+        const int4 c0 = a0, c2 = a2, d0 = b0, d2 = b2;
+        const int xa = x + 2 * bd < S.nn ? x + 2 * bd : 0;
+        const int xb = x + 3 * bd < S.nn ? x + 3 * bd : 0;
+        a0 = S.node_info[3 * xa];
+        a2 = S.node_info[3 * xa + 2];
+        b0 = S.node_info[3 * xb];
+        b2 = S.node_info[3 * xb + 2];
+        const int64_t rc = o.BUS + 8 * (int64_t)c0.y, rd = o.BUS + 8 * (int64_t)d0.y;
+        const Blk vc = wb.blk(rc), vd = wb.blk(rd);
+        const double2 spc = wb.v2(rc + 6), spd = wb.v2(rd + 6);
+        const bool pvc = pvm(c0.y), pvd = pvm(d0.y);
+        int kc[4], kd[4];
+        RowHead hc, hd;
+        row_head_idx<EFView>(S, yv, c2.x, c2.y, kc, hc);
+        row_head_idx<EFView>(S, yv, d2.x, d2.y, kd, hd);
+        row_head_v(ef, kc, hc);
+        row_head_v(ef, kd, hd);
+        double p, q, p2, q2;
+        row_finish(S, yv, ef, c2.x, c2.y, hc, vc.a, vc.b, p, q);
+        row_finish(S, yv, ef, d2.x, d2.y, hd, vd.a, vd.b, p2, q2);
+        const double fp = p - spc.x, fq = pvc ? 0.0 : q - spc.y;
+        wb.put2(rc + 4, make_double2(p, q));
+        wb.put2(o.RHS + 2 * (int64_t)c0.x,
+                SCALE ? make_double2(fp / vc.c, fq / vc.c) : make_double2(fp, fq));
+        nan |= (fp != fp) | (fq != fq);
+        mx = fmax(mx, fmax(fabs(fp), fabs(fq)));
+        if (two) {
+            const double fp2 = p2 - spd.x, fq2 = pvd ? 0.0 : q2 - spd.y;
+            wb.put2(rd + 4, make_double2(p2, q2));
+            wb.put2(o.RHS + 2 * (int64_t)d0.x, SCALE ? make_double2(fp2 / vd.c, fq2 / vd.c)
+                                                     : make_double2(fp2, fq2));
+            nan |= (fp2 != fp2) | (fq2 != fq2);
+            mx = fmax(mx, fmax(fabs(fp2), fabs(fq2)));
+        }
+    }
+}
+
 // The whole Newton-Raphson loop of one case, run by one workgroup.  The
 // case's voltages and injections are copied into its bus records first and
 // the solution copied back at the end.
 __device__ void newton_case(const DevSym& S, const double* yv, const int8_t* type,
                             const double* Psp, const double* Qsp, double* Vm, double* Va,
-                            const View& w, double tol, int max_iter, int flags,
-                            int32_t* o_iters, double* o_norm, int32_t* o_status)
+                            const View& w, const View& wb, double tol, int max_iter,
+                            int flags, int32_t* o_iters, double* o_norm, int32_t* o_status)
 {
     __shared__ int s_bad;
     const Off o = ws_off(S);
@@ -815,40 +1166,22 @@ __device__ void newton_case(const DevSym& S, const double* yv, const int8_t* typ
         double sn, cs;
         const double vm = Vm[i], va = Va[i];
         sincos(va, &sn, &cs);
-        w.put(o.BUS + 8 * (int64_t)i, {vm * cs, vm * sn, vm, va});
-        w.put2(o.BUS + 8 * (int64_t)i + 6, make_double2(Psp[i], Qsp[i]));
+        wb.put(o.BUS + 8 * (int64_t)i, {vm * cs, vm * sn, vm, va});
+        wb.put2(o.BUS + 8 * (int64_t)i + 6, make_double2(Psp[i], Qsp[i]));
     }
+    pv_fill(S, type);
     if (threadIdx.x == 0) s_bad = 0;
     __syncthreads();
-    const SrcState src{yv, type, w, o.BUS};
-    const EFView ef{w, o.BUS};
+    const PvMask pvm{pv_words(S)};
+    const SrcState src{yv, pvm, wb, o.BUS};
+    const EFView ef{wb, o.BUS};
     const bool tail = S.tail_nodes > 0;
     int it = 0, st = ST_NOT_CONVERGED;
     double nrm = 0.0;
     for (;;) {
         double mx = 0.0;
         int nan = 0;
-        int x = threadIdx.x;
-        int4 n0 = x < S.nn ? S.node_info[3 * x] : make_int4(0, 0, 0, 0);
-        int4 n2 = x < S.nn ? S.node_info[3 * x + 2] : make_int4(0, 0, 0, 0);
-        for (; x < S.nn; x += blockDim.x) {
-            const int xn = x + blockDim.x;
-            const int4 p0 = xn < S.nn ? S.node_info[3 * xn] : make_int4(0, 0, 0, 0);
-            const int4 p2 = xn < S.nn ? S.node_info[3 * xn + 2] : make_int4(0, 0, 0, 0);
-            const int bus = n0.y;
-            double p, q;
-            injection_row(S, yv, ef, bus, n2.x, n2.y, p, q);
-            const int64_t rec = o.BUS + 8 * (int64_t)bus;
-            const double2 sp = w.v2(rec + 6);
-            w.put2(rec + 4, make_double2(p, q));
-            const double fp = p - sp.x;
-            const double fq = (type[bus] == T_PV) ? 0.0 : q - sp.y;
-            w.put2(o.RHS + 2 * (int64_t)n0.x, make_double2(fp, fq));
-            nan |= (fp != fp) | (fq != fq);
-            mx = fmax(mx, fmax(fabs(fp), fabs(fq)));
-            n0 = p0;
-            n2 = p2;
-        }
+        mismatch_pass<false>(S, yv, ef, wb, o, pvm, mx, nan);
         int any_nan = 0;
         nrm = block_max(mx, nan, any_nan);
         if (any_nan || !isfinite(nrm)) {
@@ -864,28 +1197,28 @@ __device__ void newton_case(const DevSym& S, const double* yv, const int8_t* typ
             break;
         }
         for_nodes(S, 0, S.tail_level, true, [&](int, const NodeRec& r, int lane, int g) {
-            factor_node<SrcState, true>(S, src, r, lane, g, w, o.LU, o.RHS, &s_bad);
+            factor_node<SrcState, true, false>(S, src, r, lane, g, w, o.LU, wb, o.RHS, &s_bad);
         });
-        if (tail) tail_factor<SrcState, true, false>(S, src, w, o.LU, o.RHS, &s_bad);
+        if (tail) tail_factor<SrcState, true, false>(S, src, w, o.LU, wb, o.RHS, &s_bad);
         if (s_bad) {
             st = ST_ZERO_PIVOT;
             break;
         }
-        if (tail) tail_backward<true>(S, w, o.RHS, o.BUS, type);
+        if (tail) tail_backward<true>(S, wb, o.RHS, o.BUS, pvm);
         for_nodes(S, 0, S.tail_level, false, [&](int, const NodeRec& r, int lane, int g) {
-            back_node<true>(S, r, lane, g, w, o.LU, o.RHS, o.BUS, type);
+            back_node<true>(S, r, lane, g, w, o.LU, wb, o.RHS, o.BUS, pvm);
         });
         ++it;
     }
     if ((flags & PF_NEWTON_KEEP_FACTORS) && st == ST_OK) {
         for_nodes(S, 0, S.tail_level, true, [&](int, const NodeRec& r, int lane, int g) {
-            factor_node<SrcState, false>(S, src, r, lane, g, w, o.LU, o.RHS, &s_bad);
+            factor_node<SrcState, false, true>(S, src, r, lane, g, w, o.LU, wb, o.RHS, &s_bad);
         });
-        if (tail) tail_factor<SrcState, false, true>(S, src, w, o.LU, o.RHS, &s_bad);
+        if (tail) tail_factor<SrcState, false, true>(S, src, w, o.LU, wb, o.RHS, &s_bad);
         if (s_bad) st = ST_ZERO_PIVOT;
     }
     for (int i = threadIdx.x; i < S.n; i += blockDim.x) {
-        const Blk r = w.blk(o.BUS + 8 * (int64_t)i);
+        const Blk r = wb.blk(o.BUS + 8 * (int64_t)i);
         Vm[i] = r.c;
         Va[i] = r.d;
     }
@@ -930,6 +1263,185 @@ struct AsmPolar {
         up = jac_off(yu.x, yu.y, ej, fj, ek, fk, Vm[bk], pj, pk);
     }
 };
+
+
+// ---------------------------------------------------------------------------
+// Fast decoupled power flow (Sec. III names it beside NR; Table III times it),
+// XB matrices: B' from branch reactances only, B'' = -Im(Y) of the full
+// pi-model, both symmetric, so the paper's factorisation is LDL^T (eqs. 1-3)
+// with scalar elements.  Per matrix: d section [fd_lu] then (w, u) per slot
+// with w_kj = l_kj d_j and u_jk = l_kj; after factorisation d holds 1/d_j.
+// B'' of a PV bus is the identity row and column, so its |V| never moves.
+// ---------------------------------------------------------------------------
+
+// Entry of B' (XB = false) or B'' from the branches of admittance entry q.
+template <bool XB>
+__device__ __forceinline__ double fd_entry(const DevSym& S, int q, bool diag,
+                                           const double* __restrict__ r,
+                                           const double* __restrict__ x,
+                                           const double* __restrict__ b)
+{
+    double v = 0.0;
+    for (int t = S.ybr_ptr[q]; t < S.ybr_ptr[q + 1]; ++t) {
+        const int e = S.ybr[t];
+        if (!XB) {
+            const double bx = 1.0 / x[e];
+            v += diag ? bx : -bx;
+        } else {
+            const double rr = r[e], xx = x[e];
+            const double bs = xx / (rr * rr + xx * xx);
+            v += diag ? bs - b[e] / 2.0 : -bs;
+        }
+    }
+    return v;
+}
+
+// Left-looking LDL^T of one node (pull form, like factor_node with 1x1
+// blocks and U = L^T):
+//   d_j = a_jj - sum_{i in R(j)} w_ji u_ij,
+//   w_kj = a_kj - sum_i w_ki u_ij (k in S(j)),  u_jk = w_kj / d_j.
+__device__ __forceinline__ void fd_factor_node(const DevSym& S, const NodeRec& rec, int lane,
+                                               int g, double* m, int* s_bad)
+{
+    const int j = rec.a.x;
+    double2* sl = reinterpret_cast<double2*>(m + S.fd_lu);
+    double ds = 0.0;
+    for (int r = rec.a.z + lane; r < rec.a.w; r += g) {
+        const double2 wu = sl[S.rl[r].y];
+        ds = fma(wu.x, wu.y, ds);
+    }
+    if (g > 1) ds = gsum(ds, g);
+    const double D = m[j] - ds;
+    const bool ok = D != 0.0 && isfinite(D);
+    const double Dinv = 1.0 / D;
+    for (int s = rec.b.x + lane; s < rec.b.y; s += g) {
+        const int4 b = S.slot_info[2 * s + 1];
+        double W = sl[s].x;
+        for (int u = b.x; u < b.y; ++u) {
+            const int2 p = S.upd[u];
+            W = fma(-sl[p.x].x, sl[p.y].y, W);
+        }
+        sl[s] = make_double2(W, W * Dinv);
+    }
+    if (lane == 0) {
+        m[j] = Dinv;
+        if (!ok) *s_bad = 1;
+    }
+}
+
+// Forward substitution and normalisation on component comp of the rhs:
+//   y_j = (1/d_j) (b_j - sum_{i in R(j)} w_ji y_i), levels upward.
+__device__ __forceinline__ void fd_forward(const DevSym& S, const double* m, const View& wb,
+                                           int64_t rhs, int comp)
+{
+    const double2* sl = reinterpret_cast<const double2*>(m + S.fd_lu);
+    for_nodes(S, 0, S.nlev, true, [&](int, const NodeRec& rec, int lane, int g) {
+        double z = 0.0;
+        for (int r = rec.a.z + lane; r < rec.a.w; r += g) {
+            const int2 e = S.rl[r];
+            z = fma(sl[e.y].x, *wb.at(rhs + 2 * (int64_t)e.x + comp), z);
+        }
+        if (g > 1) z = gsum(z, g);
+        if (lane == 0) {
+            double* bj = wb.at(rhs + 2 * (int64_t)rec.a.x + comp);
+            *bj = m[rec.a.x] * (*bj - z);
+        }
+    });
+}
+
+// Backward substitution x_j = y_j - sum_{k in S(j)} u_jk x_k, levels
+// downward, and the half step at bus(j): ANGLE: theta -= x_j; else
+// |V| -= x_j at PQ buses.
+template <bool ANGLE>
+__device__ __forceinline__ void fd_backward(const DevSym& S, const double* m, const View& wb,
+                                            int64_t rhs, int64_t bus_off, const PvMask& pv)
+{
+    const double2* sl = reinterpret_cast<const double2*>(m + S.fd_lu);
+    const int comp = ANGLE ? 0 : 1;
+    for_nodes(S, 0, S.nlev, false, [&](int, const NodeRec& rec, int lane, int g) {
+        double a = 0.0;
+        for (int s = rec.b.x + lane; s < rec.b.y; s += g)
+            a = fma(sl[s].y, *wb.at(rhs + 2 * (int64_t)S.Li[s] + comp), a);
+        if (g > 1) a = gsum(a, g);
+        if (lane == 0) {
+            double* yj = wb.at(rhs + 2 * (int64_t)rec.a.x + comp);
+            const double xj = *yj - a;
+            *yj = xj;
+            const int bus = rec.a.y;
+            const int64_t br = bus_off + 8 * (int64_t)bus;
+            const Blk v = wb.blk(br);
+            double vm = v.c, va = v.d;
+            if (ANGLE) va -= xj;
+            else if (!pv(bus)) vm -= xj;
+            double sn, cs;
+            sincos(va, &sn, &cs);
+            wb.put(br, {vm * cs, vm * sn, vm, va});
+        }
+    });
+}
+
+// The fast decoupled iteration of one case (one workgroup): mismatch, angle
+// half step with B', mismatch, magnitude half step with B'', until max|F| <
+// tol; iters counts angle half steps and max_iter bounds them.
+__device__ void fdpf_case(const DevSym& S, const double* yv, const int8_t* type,
+                          const double* Psp, const double* Qsp, double* Vm, double* Va,
+                          const View& wb, const double* m1, const double* m2, double tol,
+                          int max_iter, int32_t* o_iters, double* o_norm, int32_t* o_status)
+{
+    uint32_t* fd_pv = reinterpret_cast<uint32_t*>(pf_smem);
+    const Off o = ws_off(S);
+    for (int i = threadIdx.x; i < S.n; i += blockDim.x) {
+        double sn, cs;
+        const double vm = Vm[i], va = Va[i];
+        sincos(va, &sn, &cs);
+        wb.put(o.BUS + 8 * (int64_t)i, {vm * cs, vm * sn, vm, va});
+        wb.put2(o.BUS + 8 * (int64_t)i + 6, make_double2(Psp[i], Qsp[i]));
+    }
+    pv_fill_at(fd_pv, S, type);
+    __syncthreads();
+    const PvMask pvm{fd_pv};
+    const EFView ef{wb, o.BUS};
+    int it = 0, half = 0, st = ST_NOT_CONVERGED;
+    double nrm = 0.0;
+    for (;;) {
+        double mx = 0.0;
+        int nan = 0;
+        mismatch_pass<true>(S, yv, ef, wb, o, pvm, mx, nan);
+        int any_nan = 0;
+        nrm = block_max(mx, nan, any_nan);
+        if (any_nan || !isfinite(nrm)) {
+            st = ST_NONFINITE;
+            break;
+        }
+        if (nrm < tol) {
+            st = ST_OK;
+            break;
+        }
+        if (half == 0) {
+            if (it >= max_iter) {
+                st = ST_NOT_CONVERGED;
+                break;
+            }
+            fd_forward(S, m1, wb, o.RHS, 0);
+            fd_backward<true>(S, m1, wb, o.RHS, o.BUS, pvm);
+            ++it;
+        } else {
+            fd_forward(S, m2, wb, o.RHS, 1);
+            fd_backward<false>(S, m2, wb, o.RHS, o.BUS, pvm);
+        }
+        half ^= 1;
+    }
+    for (int i = threadIdx.x; i < S.n; i += blockDim.x) {
+        const Blk r = wb.blk(o.BUS + 8 * (int64_t)i);
+        Vm[i] = r.c;
+        Va[i] = r.d;
+    }
+    if (threadIdx.x == 0) {
+        if (o_iters) *o_iters = it;
+        if (o_norm) *o_norm = nrm;
+        if (o_status) *o_status = st;
+    }
+}
 
 }  // namespace
 
@@ -1043,7 +1555,7 @@ __global__ void k_jacobian(DevSym S, const double* yval, int64_t y_stride, const
     const EFPolar ef{Vm + c * v_stride, Va + c * v_stride};
     const AsmPolar A{&S, yval + c * y_stride, type + c * type_stride, Vm + c * v_stride, ef};
     const View w = case_view(vals, vals_stride, C, c);
-    const int64_t lu = 4 * (int64_t)S.nn;
+    const int64_t lu = S.lu_off;
     w.put(4 * (int64_t)j, A.diag(j));
     for (int s = S.Lp[j]; s < S.Lp[j + 1]; ++s) {
         Blk lo, up;
@@ -1061,14 +1573,14 @@ __global__ __launch_bounds__(kLevelThreads) void k_factor(DevSym S, double* vals
     const int c = case_of_block(blockIdx.x, C, B);
     if (c < 0) return;
     const View w = case_view(vals, vals_stride, C, c);
-    const int64_t lu = 4 * (int64_t)S.nn;
+    const int64_t lu = S.lu_off;
     if (threadIdx.x == 0) s_bad = 0;
     __syncthreads();
     const SrcLoad src{w, lu};
     for_nodes(S, 0, S.tail_level, true, [&](int, const NodeRec& r, int lane, int g) {
-        factor_node<SrcLoad, false>(S, src, r, lane, g, w, lu, 0, &s_bad);
+        factor_node<SrcLoad, false, true>(S, src, r, lane, g, w, lu, w, 0, &s_bad);
     });
-    if (S.tail_nodes > 0) tail_factor<SrcLoad, false, true>(S, src, w, lu, 0, &s_bad);
+    if (S.tail_nodes > 0) tail_factor<SrcLoad, false, true>(S, src, w, lu, w, 0, &s_bad);
     __syncthreads();
     if (threadIdx.x == 0 && status) status[c] = s_bad ? ST_ZERO_PIVOT : ST_OK;
 }
@@ -1085,7 +1597,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_solve(DevSym S, const double* v
     const int c = case_of_block(blockIdx.x, C, B);
     if (c < 0) return;
     const View w = case_view(const_cast<double*>(vals), vals_stride, C, c);
-    const int64_t lu = 4 * (int64_t)S.nn;
+    const int64_t lu = S.lu_off;
     double2* x2 = reinterpret_cast<double2*>(rhs + c * rhs_stride);
     for_levels(S, 0, S.nlev, true, [&](int xi, int lane, int g) {
         const int j = S.level_nodes[xi];
@@ -1152,17 +1664,19 @@ __global__ __launch_bounds__(kLevelThreads) void k_newton(DevSym Sarg,
         const CaseDesc& cd = descs[c];
         const DevSym S = cd.sym;
         const View w = case_view(a.ws + cd.ws_off, 0, 1, 0);
+        const View wb = case_bus_view(a.ws + cd.ws_off, 0, 1, 0, S.vals_doubles);
         newton_case(S, a.yval + cd.y_off, a.type + cd.bus_off, a.Psp + cd.bus_off,
-                    a.Qsp + cd.bus_off, a.Vm + cd.bus_off, a.Va + cd.bus_off, w, a.tol,
+                    a.Qsp + cd.bus_off, a.Vm + cd.bus_off, a.Va + cd.bus_off, w, wb, a.tol,
                     a.max_iter, a.flags, a.iters ? a.iters + c : nullptr,
                     a.norm ? a.norm + c : nullptr, a.status ? a.status + c : nullptr);
     } else {
         const int c = case_of_block(blockIdx.x, a.interleave, a.B);
         if (c < 0) return;
         const View w = case_view(a.ws, a.ws_stride, a.interleave, c);
+        const View wb = case_bus_view(a.ws, a.ws_stride, a.interleave, c, Sarg.vals_doubles);
         newton_case(Sarg, a.yval + c * a.y_stride, a.type + c * a.type_stride,
                     a.Psp + c * a.inj_stride, a.Qsp + c * a.inj_stride, a.Vm + c * a.v_stride,
-                    a.Va + c * a.v_stride, w, a.tol, a.max_iter, a.flags,
+                    a.Va + c * a.v_stride, w, wb, a.tol, a.max_iter, a.flags,
                     a.iters ? a.iters + c : nullptr, a.norm ? a.norm + c : nullptr,
                     a.status ? a.status + c : nullptr);
     }
@@ -1269,6 +1783,111 @@ __global__ void k_adj_branch(DevSym S, const int32_t* __restrict__ from,
                        Vm + c * v_stride, Va + c * v_stride, r[c * branch_stride + e],
                        x[c * branch_stride + e]);
     }
+}
+
+
+// Fast decoupled matrices of B cases: B' then B'' (fd_mat doubles each) in
+// the scalar filled layout, lower and upper values equal.
+__global__ void k_fd_matrices(DevSym S, const double* __restrict__ r,
+                              const double* __restrict__ x, const double* __restrict__ b,
+                              int64_t bstride, const int8_t* __restrict__ type,
+                              int64_t type_stride, double* __restrict__ mat, int64_t mstride)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (p >= S.fd_lu) return;
+    const double* rc = r + c * bstride;
+    const double* xc = x + c * bstride;
+    const double* bc = b + c * bstride;
+    const int8_t* tc = type + c * type_stride;
+    double* m1 = mat + c * mstride;
+    double* m2 = m1 + S.fd_mat;
+    if (p >= S.nn) {  // padding of the d sections
+        m1[p] = 0.0;
+        m2[p] = 0.0;
+        return;
+    }
+    const bool pvj = tc[S.perm[p]] == T_PV;
+    m1[p] = fd_entry<false>(S, S.ydiag[p], true, rc, xc, bc);
+    m2[p] = pvj ? 1.0 : fd_entry<true>(S, S.ydiag[p], true, rc, xc, bc);
+    double2* s1 = reinterpret_cast<double2*>(m1 + S.fd_lu);
+    double2* s2 = reinterpret_cast<double2*>(m2 + S.fd_lu);
+    for (int s = S.Lp[p]; s < S.Lp[p + 1]; ++s) {
+        const int q = S.ylo[s];
+        const bool pvk = tc[S.perm[S.Li[s]]] == T_PV;
+        const double v1 = q < 0 ? 0.0 : fd_entry<false>(S, q, false, rc, xc, bc);
+        const double v2 = (q < 0 || pvj || pvk) ? 0.0 : fd_entry<true>(S, q, false, rc, xc, bc);
+        s1[s] = make_double2(v1, v1);
+        s2[s] = make_double2(v2, v2);
+    }
+}
+
+// In-place LDL^T of B' and B'' of case blockIdx.x, level by level.
+__global__ __launch_bounds__(kLevelThreads) void k_fd_factor(DevSym S, double* mat,
+                                                             int64_t mstride, int32_t* status)
+{
+    __shared__ int s_bad;
+    const int c = blockIdx.x;
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
+    for (int which = 0; which < 2; ++which) {
+        double* m = mat + c * mstride + which * S.fd_mat;
+        for_nodes(S, 0, S.nlev, true, [&](int, const NodeRec& rec, int lane, int g) {
+            fd_factor_node(S, rec, lane, g, m, &s_bad);
+        });
+    }
+    if (threadIdx.x == 0 && status) status[c] = s_bad ? ST_ZERO_PIVOT : ST_OK;
+}
+
+__global__ __launch_bounds__(kLevelThreads) void k_fdpf(DevSym S, NewtonArgs a,
+                                                        const double* mat, int64_t mstride)
+{
+    const int c = blockIdx.x;
+    View wb;
+    wb.base = a.ws + c * a.ws_stride;
+    wb.lane = 0;
+    wb.sh = 2;
+    wb.cs = 2;
+    const double* m1 = mat + c * mstride;
+    fdpf_case(S, a.yval + c * a.y_stride, a.type + c * a.type_stride, a.Psp + c * a.inj_stride,
+              a.Qsp + c * a.inj_stride, a.Vm + c * a.v_stride, a.Va + c * a.v_stride, wb, m1,
+              m1 + S.fd_mat, a.tol, a.max_iter, a.iters ? a.iters + c : nullptr,
+              a.norm ? a.norm + c : nullptr, a.status ? a.status + c : nullptr);
+}
+
+// Branch flows (Sec. II-A: post-convergence, edge by edge): pi-model with
+// series y = 1/(r + jx) and charging b, I_ft = (y + jb/2) V_f - y V_t,
+// S_ft = V_f conj(I_ft), and the same from the other end.
+__global__ void k_branch_flows(int m, const int32_t* __restrict__ from,
+                               const int32_t* __restrict__ to, const double* __restrict__ r,
+                               const double* __restrict__ x, const double* __restrict__ b,
+                               int64_t bstride, const double* __restrict__ Vm,
+                               const double* __restrict__ Va, int64_t vstride, double* Pft,
+                               double* Qft, double* Ptf, double* Qtf, int64_t ostride)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (e >= m) return;
+    const int fb = from[e], tb = to[e];
+    const double rr = r[c * bstride + e], xx = x[c * bstride + e], hb = b[c * bstride + e] / 2.0;
+    const double den = rr * rr + xx * xx;
+    const double yg = rr / den, yb = -xx / den;
+    const double* vm = Vm + c * vstride;
+    const double* va = Va + c * vstride;
+    double sf, cf, st, ct;
+    sincos(va[fb], &sf, &cf);
+    sincos(va[tb], &st, &ct);
+    const double ef = vm[fb] * cf, ff = vm[fb] * sf, et = vm[tb] * ct, ft = vm[tb] * st;
+    // I_ft = (yg + j(yb + hb)) V_f - (yg + j yb) V_t, and symmetrically
+    const double ifr = yg * ef - (yb + hb) * ff - (yg * et - yb * ft);
+    const double ifi = yg * ff + (yb + hb) * ef - (yg * ft + yb * et);
+    const double itr = yg * et - (yb + hb) * ft - (yg * ef - yb * ff);
+    const double iti = yg * ft + (yb + hb) * et - (yg * ff + yb * ef);
+    const int64_t o = c * ostride + e;
+    Pft[o] = ef * ifr + ff * ifi;  // V conj(I)
+    Qft[o] = ff * ifr - ef * ifi;
+    Ptf[o] = et * itr + ft * iti;
+    Qtf[o] = ft * itr - et * iti;
 }
 
 // ===========================================================================
@@ -1438,6 +2057,9 @@ int pf_symbolic_info(const pf_symbolic s, pf_info* info)
     info->nlevels = (int32_t)h.level_ptr.size() - 1;
     info->max_level_width = h.max_width;
     info->vals_doubles = h.vals_doubles();
+    info->lu_offset = h.lu_off();
+    info->fd_mat_doubles = 2 * h.fd_mat();
+    info->fd_ws_doubles = h.fd_ws_doubles();
     info->ws_doubles = h.ws_doubles();
     info->dev_bytes = h.dev_bytes();
     info->tail_levels = (int32_t)h.level_ptr.size() - 1 - h.tail_level;
@@ -1552,6 +2174,9 @@ int pf_symbolic_upload(pf_symbolic s, void* d_buf, size_t bytes, void* stream)
     d.nlev = (int32_t)h.level_ptr.size() - 1;
     d.n_upd = (int64_t)h.Ua.size();
     d.vals_doubles = h.vals_doubles();
+    d.lu_off = h.lu_off();
+    d.fd_lu = h.fd_lu();
+    d.fd_mat = h.fd_mat();
     d.ws_doubles = h.ws_doubles();
     d.yptr = put(h.yptr);
     d.ycol = put(h.ycol);
@@ -1592,7 +2217,7 @@ int pf_symbolic_upload(pf_symbolic s, void* d_buf, size_t bytes, void* stream)
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) ==
                 hipSuccess &&
-            h.tail_lds + 2048 > lds_max)
+            h.tail_lds + pv_mask_bytes(h.n) + 2048 > lds_max)
             return fail(PF_E_WORKSPACE, "pf_symbolic_upload: LDS tail larger than the device's "
                                         "LDS; lower it with pf_symbolic_set_launch");
     }
@@ -1648,7 +2273,7 @@ int pf_jacobian(const pf_symbolic s, int B, const double* d_yval, int64_t y_stri
 {
     if (!ready(s, "pf_jacobian")) return PF_E_INVALID;
     if (B < 0 || B > 65535 || !d_yval || !d_type || !d_Vm || !d_Va || !d_vals ||
-        !valid_interleave(vals_interleave) || (vals_stride & 3))
+        !valid_interleave(vals_interleave) || (vals_stride & 7))
         return fail(PF_E_INVALID, "pf_jacobian: bad arguments");
     if (B > 1 && vals_stride < s->h.vals_doubles())
         return fail(PF_E_WORKSPACE, "pf_jacobian: vals_stride < vals_doubles");
@@ -1664,7 +2289,7 @@ int pf_factor(const pf_symbolic s, int B, double* d_vals, int64_t vals_stride,
               int vals_interleave, int32_t* d_status, void* stream)
 {
     if (!ready(s, "pf_factor")) return PF_E_INVALID;
-    if (B < 0 || !d_vals || !valid_interleave(vals_interleave) || (vals_stride & 3))
+    if (B < 0 || !d_vals || !valid_interleave(vals_interleave) || (vals_stride & 7))
         return fail(PF_E_INVALID, "pf_factor: bad arguments");
     if (B > 1 && vals_stride < s->h.vals_doubles())
         return fail(PF_E_WORKSPACE, "pf_factor: vals_stride < vals_doubles");
@@ -1681,7 +2306,7 @@ int pf_solve(const pf_symbolic s, int B, const double* d_vals, int64_t vals_stri
 {
     if (!ready(s, "pf_solve")) return PF_E_INVALID;
     if (B < 0 || !d_vals || !d_rhs || (transpose != 0 && transpose != 1) ||
-        !valid_interleave(vals_interleave) || (vals_stride & 3))
+        !valid_interleave(vals_interleave) || (vals_stride & 7))
         return fail(PF_E_INVALID, "pf_solve: bad arguments");
     if (B > 1 && rhs_stride < 2 * (int64_t)s->h.nn)
         return fail(PF_E_WORKSPACE, "pf_solve: rhs_stride < 2*nn");
@@ -1709,8 +2334,8 @@ int pf_newton(const pf_symbolic s, int B, const double* d_yval, int64_t y_stride
         return fail(PF_E_INVALID, "pf_newton: bad arguments");
     if (B > 1 && v_stride < s->h.n)
         return fail(PF_E_WORKSPACE, "pf_newton: v_stride too small");
-    if (ws_stride < s->h.ws_doubles() || (ws_stride & 3))
-        return fail(PF_E_WORKSPACE, "pf_newton: ws_stride must be >= ws_doubles, a multiple of 4");
+    if (ws_stride < s->h.ws_doubles() || (ws_stride & 7))
+        return fail(PF_E_WORKSPACE, "pf_newton: ws_stride must be >= ws_doubles, a multiple of 8");
     if (reinterpret_cast<uintptr_t>(d_ws) & 15)
         return fail(PF_E_WORKSPACE, "pf_newton: workspace must be 16-byte aligned");
     if (B == 0) return PF_OK;
@@ -1720,9 +2345,87 @@ int pf_newton(const pf_symbolic s, int B, const double* d_yval, int64_t y_stride
                  d_status};
     allow_big_lds();
     hipLaunchKernelGGL(k_newton<false>, dim3(grid_blocks(B, C)), dim3(launch_threads(s->h, B)),
-                       s->h.tail_lds, as_stream(stream), s->h.dev, (const CaseDesc*)nullptr,
+                       s->h.tail_lds + pv_mask_bytes(s->h.n), as_stream(stream), s->h.dev, (const CaseDesc*)nullptr,
                        (const int32_t*)nullptr, a);
     return launch_check("pf_newton");
+}
+
+int pf_fdpf_matrices(const pf_symbolic s, int B, const double* d_r, const double* d_x,
+                     const double* d_b, int64_t branch_stride, const int8_t* d_type,
+                     int64_t type_stride, double* d_mat, int64_t mat_stride, void* stream)
+{
+    if (!ready(s, "pf_fdpf_matrices")) return PF_E_INVALID;
+    if (B < 0 || B > 65535 || !d_r || !d_x || !d_b || !d_type || !d_mat || (mat_stride & 7))
+        return fail(PF_E_INVALID, "pf_fdpf_matrices: bad arguments");
+    if (reinterpret_cast<uintptr_t>(d_mat) & 15)
+        return fail(PF_E_WORKSPACE, "pf_fdpf_matrices: d_mat must be 16-byte aligned");
+    if (B > 1 && mat_stride < 2 * s->h.fd_mat())
+        return fail(PF_E_WORKSPACE, "pf_fdpf_matrices: mat_stride < fd_mat_doubles");
+    if (B == 0) return PF_OK;
+    dim3 grid((unsigned)((s->h.fd_lu() + 255) / 256), B);
+    hipLaunchKernelGGL(k_fd_matrices, grid, dim3(256), 0, as_stream(stream), s->h.dev, d_r, d_x,
+                       d_b, branch_stride, d_type, type_stride, d_mat, mat_stride);
+    return launch_check("pf_fdpf_matrices");
+}
+
+int pf_fdpf_factor(const pf_symbolic s, int B, double* d_mat, int64_t mat_stride,
+                   int32_t* d_status, void* stream)
+{
+    if (!ready(s, "pf_fdpf_factor")) return PF_E_INVALID;
+    if (B < 0 || !d_mat || (mat_stride & 7))
+        return fail(PF_E_INVALID, "pf_fdpf_factor: bad arguments");
+    if (reinterpret_cast<uintptr_t>(d_mat) & 15)
+        return fail(PF_E_WORKSPACE, "pf_fdpf_factor: d_mat must be 16-byte aligned");
+    if (B > 1 && mat_stride < 2 * s->h.fd_mat())
+        return fail(PF_E_WORKSPACE, "pf_fdpf_factor: mat_stride < fd_mat_doubles");
+    if (B == 0) return PF_OK;
+    hipLaunchKernelGGL(k_fd_factor, dim3(B), dim3(launch_threads(s->h, B)), 0,
+                       as_stream(stream), s->h.dev, d_mat, mat_stride, d_status);
+    return launch_check("pf_fdpf_factor");
+}
+
+int pf_fdpf(const pf_symbolic s, int B, const double* d_yval, int64_t y_stride,
+            const int8_t* d_type, int64_t type_stride, const double* d_Psp, const double* d_Qsp,
+            int64_t inj_stride, double* d_Vm, double* d_Va, int64_t v_stride,
+            const double* d_mat, int64_t mat_stride, double tol, int max_iter, double* d_ws,
+            int64_t ws_stride, int32_t* d_iters, double* d_norm, int32_t* d_status,
+            void* stream)
+{
+    if (!ready(s, "pf_fdpf")) return PF_E_INVALID;
+    if (B < 0 || max_iter < 0 || !(tol >= 0.0) || !d_yval || !d_type || !d_Psp || !d_Qsp ||
+        !d_Vm || !d_Va || !d_mat || !d_ws || (mat_stride & 7))
+        return fail(PF_E_INVALID, "pf_fdpf: bad arguments");
+    if (B > 1 && v_stride < s->h.n) return fail(PF_E_WORKSPACE, "pf_fdpf: v_stride too small");
+    if (ws_stride < s->h.fd_ws_doubles() || (ws_stride & 7))
+        return fail(PF_E_WORKSPACE,
+                    "pf_fdpf: ws_stride must be >= fd_ws_doubles, a multiple of 8");
+    if ((reinterpret_cast<uintptr_t>(d_ws) & 15) || (reinterpret_cast<uintptr_t>(d_mat) & 15))
+        return fail(PF_E_WORKSPACE, "pf_fdpf: d_ws and d_mat must be 16-byte aligned");
+    if (B == 0) return PF_OK;
+    NewtonArgs a{d_yval, y_stride, d_type, type_stride, d_Psp, d_Qsp, inj_stride, d_Vm, d_Va,
+                 v_stride, d_ws, ws_stride, tol, max_iter, 0, 1, B, d_iters, d_norm, d_status};
+    hipLaunchKernelGGL(k_fdpf, dim3(B), dim3(launch_threads(s->h, B)),
+                       pv_mask_bytes(s->h.n), as_stream(stream), s->h.dev, a, d_mat, mat_stride);
+    return launch_check("pf_fdpf");
+}
+
+int pf_branch_flows(const pf_symbolic s, int B, const double* d_r, const double* d_x,
+                    const double* d_b, int64_t branch_stride, const double* d_Vm,
+                    const double* d_Va, int64_t v_stride, double* d_Pft, double* d_Qft,
+                    double* d_Ptf, double* d_Qtf, int64_t out_stride, void* stream)
+{
+    if (!ready(s, "pf_branch_flows")) return PF_E_INVALID;
+    if (B < 0 || B > 65535 || !d_r || !d_x || !d_b || !d_Vm || !d_Va || !d_Pft || !d_Qft ||
+        !d_Ptf || !d_Qtf)
+        return fail(PF_E_INVALID, "pf_branch_flows: bad arguments");
+    if (B > 1 && (v_stride < s->h.n || out_stride < s->h.m))
+        return fail(PF_E_WORKSPACE, "pf_branch_flows: stride too small");
+    if (B == 0 || s->h.m == 0) return PF_OK;
+    dim3 grid((s->h.m + 255) / 256, B);
+    hipLaunchKernelGGL(k_branch_flows, grid, dim3(256), 0, as_stream(stream), s->h.m, s->d_from,
+                       s->d_to, d_r, d_x, d_b, branch_stride, d_Vm, d_Va, v_stride, d_Pft, d_Qft,
+                       d_Ptf, d_Qtf, out_stride);
+    return launch_check("pf_branch_flows");
 }
 
 int pf_adjoint_params(const pf_symbolic s, int B, const double* d_lam, int64_t lam_stride,
@@ -1885,7 +2588,7 @@ int pf_newton_multi(const pf_multi p, const double* d_yval, const int8_t* d_type
     DevSym none{};
     int lds = 0, threads = 0;
     for (auto* sy : p->syms) {
-        lds = std::max(lds, sy->h.tail_lds);
+        lds = std::max(lds, (int)(sy->h.tail_lds + pv_mask_bytes(sy->h.n)));
         threads = std::max(threads, sy->h.threads);
     }
     if (threads == 0) threads = (p->syms.size() <= 512) ? 512 : 256;

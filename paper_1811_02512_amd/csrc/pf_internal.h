@@ -50,6 +50,8 @@ struct DevSym {
     int32_t nnz_y, nnz_l, nlev, pad0;
     int64_t n_upd;
     int64_t vals_doubles, ws_doubles;
+    int64_t lu_off;  // doubles before the LU section (D padded to 64 bytes)
+    int64_t fd_lu, fd_mat;  // fast decoupled: d section (padded), one matrix
     // admittance matrix, CSR by bus
     const int32_t* yptr;     // n+1
     const int32_t* ycol;     // nnz_y
@@ -108,7 +110,18 @@ struct HostSym {
     DevSym dev{};
     bool uploaded = false;
 
-    int64_t vals_doubles() const { return 4 * (int64_t)nn + 8 * (int64_t)Li.size(); }
+    // D [nn][4], zero padding to a multiple of 8 doubles, LU [nnz_l][8]: every
+    // slot record (W, U) and bus record starts on a 64-byte boundary.
+    int64_t lu_off() const { return 8 * (((int64_t)nn + 1) / 2); }
+    int64_t vals_doubles() const { return lu_off() + 8 * (int64_t)Li.size(); }
+    // fast decoupled matrices: per matrix d [fd_lu()] | (w, u) per slot; two
+    // matrices (B', B'') per case
+    int64_t fd_lu() const { return ((int64_t)nn + 7) & ~(int64_t)7; }
+    int64_t fd_mat() const { return (fd_lu() + 2 * (int64_t)Li.size() + 7) & ~(int64_t)7; }
+    int64_t fd_ws_doubles() const {
+        int64_t w = 8 * (int64_t)n + 2 * (int64_t)nn;  // bus records | rhs
+        return (w + 31) & ~(int64_t)31;
+    }
     int64_t ws_doubles() const {
         // vals | bus records (8 n) | rhs (2 nn)
         int64_t w = vals_doubles() + 8 * (int64_t)n + 2 * (int64_t)nn;
@@ -120,6 +133,10 @@ struct HostSym {
 // LDS bytes of a tail with K nodes and TS slots: W and U (or V) blocks per
 // slot, D^-1 and the forward vector per node.
 inline int64_t tail_bytes(int64_t K, int64_t TS) { return TS * 64 + K * 48; }
+
+// LDS bytes of the PV bitmask the Newton kernel keeps after the tail (one bit
+// per bus, whole 64-bit ballot words).
+inline int64_t pv_mask_bytes(int64_t n) { return 8 * ((n + 63) / 64); }
 
 // Host analysis; returns a pf_status code and sets msg on failure.
 int analyze(int n, int m, const int32_t* from, const int32_t* to, int slack, int ordering,

@@ -90,34 +90,6 @@ __device__ __forceinline__ double gsum(double v, int g)
     return v;
 }
 
-// ---------------------------------------------------------------------------
-// Newton state of one case inside the workspace:
-//   vals (D | LU) , e[n], f[n], P[n], Q[n] (bus order), rhs[2 nn] (position)
-// e + jf is the rectangular bus voltage, P + jQ the calculated injection.
-// ---------------------------------------------------------------------------
-struct CaseState {
-    double* D;    // nn x 4
-    double* LU;   // nnz_l x 8
-    double* e;
-    double* f;
-    double* P;
-    double* Q;
-    double* rhs;  // nn x 2
-};
-
-__device__ __forceinline__ CaseState case_state(const DevSym& S, double* ws)
-{
-    CaseState c;
-    c.D = ws;
-    c.LU = ws + 4 * (int64_t)S.nn;
-    c.e = ws + S.vals_doubles;
-    c.f = c.e + S.n;
-    c.P = c.f + S.n;
-    c.Q = c.P + S.n;
-    c.rhs = c.Q + S.n;
-    return c;
-}
-
 // Off-diagonal Jacobian block (i, k) = d(P_i, Q_i)/d(theta_k, |V_k|) from
 // Y_ik = G + jB and rectangular voltages.  With a = |V_i||V_k| cos(t_ik) and
 // s = |V_i||V_k| sin(t_ik):

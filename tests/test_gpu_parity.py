@@ -111,7 +111,7 @@ def jac_gpu(s, Vm, Va):
     v = vals[0].cpu().numpy()
     nn = s.info.nn
     D = v[:4 * nn].reshape(-1, 2, 2)
-    LU = v[4 * nn:].reshape(-1, 2, 2, 2)
+    LU = v[s.info.lu_offset:].reshape(-1, 2, 2, 2)
     return D, LU[:, 0], LU[:, 1], vals
 
 
@@ -141,14 +141,15 @@ def test_factor_and_solve(O, n, seed, ordering):
     assert bad == -1
     # factor the oracle's matrix on the GPU
     nn = s.info.nn
-    vals = torch.from_numpy(np.concatenate([oD.reshape(-1), np.stack([oL, oU], 1).reshape(-1)])
+    pad = np.zeros(s.info.lu_offset - 4 * nn)
+    vals = torch.from_numpy(np.concatenate([oD.reshape(-1), pad, np.stack([oL, oU], 1).reshape(-1)])
                             ).to("cuda").reshape(1, -1).contiguous()
     status = torch.full((1,), -1, dtype=torch.int32, device="cuda")
     B.pf_factor(s.sym.h, 1, vals, s.info.vals_doubles, status)
     assert status.item() == 0
     v = vals[0].cpu().numpy()
     Dinv = v[:4 * nn].reshape(-1, 2, 2)
-    LU = v[4 * nn:].reshape(-1, 2, 2, 2)
+    LU = v[s.info.lu_offset:].reshape(-1, 2, 2, 2)
     scale = np.abs(fD).max()
     np.testing.assert_allclose(np.linalg.inv(Dinv), fD, rtol=0, atol=1e-10 * scale)
     # lower factor is stored as L D
@@ -289,7 +290,7 @@ def test_launch_shapes_and_lds_tail(O, threads, budget):
     B.pf_factor(s.sym.h, 1, vals, info.vals_doubles, None)
     v = vals[0].cpu().numpy()
     nn = info.nn
-    np.testing.assert_allclose(v[4 * nn:].reshape(-1, 2, 2, 2)[:, 1], fU, rtol=0,
+    np.testing.assert_allclose(v[info.lu_offset:].reshape(-1, 2, 2, 2)[:, 1], fU, rtol=0,
                                atol=1e-10 * max(1.0, np.abs(fU).max()))
     np.testing.assert_allclose(np.linalg.inv(v[:4 * nn].reshape(-1, 2, 2)), fD, rtol=0,
                                atol=1e-10 * np.abs(fD).max())
@@ -297,7 +298,7 @@ def test_launch_shapes_and_lds_tail(O, threads, budget):
 
 @pytest.mark.parametrize("C", [1, 2, 8])
 def test_interleaved_case_groups_bitwise_equal(C):
-    """The workspace grouping (1, 2, 4 or 8 cases per 32-byte-interleaved
+    """The workspace grouping (1, 2, 4 or 8 cases per 64-byte-interleaved
     group, groups spread over the XCDs) changes addresses only: results are
     bitwise those of the default grouping, for a batch that is not a
     multiple of the group size."""
@@ -339,5 +340,5 @@ def test_factor_solve_interleaved_vals():
     B.pf_solve(s.sym.h, Bn, inter, vd, r2, 2 * nn, 1, C)
     assert torch.equal(r1, r2)
     # the interleaved buffer holds the same numbers, just regrouped
-    v = inter.view(rows // C, vd // 4, C, 4).permute(0, 2, 1, 3).reshape(rows, vd)[:Bn]
+    v = inter.view(rows // C, vd // 8, C, 8).permute(0, 2, 1, 3).reshape(rows, vd)[:Bn]
     assert torch.equal(v, plain)

@@ -48,7 +48,8 @@ def test_analysis_bit_exact_with_oracle(B, oracle, n, seed, ordering):
             np.testing.assert_array_equal(ex[k], getattr(s, k), err_msg=k)
         info = B.pf_symbolic_info(h)
         assert info.nn == n - 1 and info.nnz_l == s.nnzL and info.nlevels == s.nlev
-        assert info.vals_doubles == 4 * info.nn + 8 * info.nnz_l
+        assert info.lu_offset == 8 * ((info.nn + 1) // 2)
+        assert info.vals_doubles == info.lu_offset + 8 * info.nnz_l
         yptr, ycol = B.pf_symbolic_ybus_pattern(h)
         Y = oracle.grid_ybus(g)
         np.testing.assert_array_equal(yptr, Y.rowptr)
