@@ -53,7 +53,7 @@ size_t HostSym::dev_bytes() const
                                           &ydiag,     &Rp,        &Ri,      &Rs,     &level_ptr,
                                           &level_nodes, &level_g, &node_info, &slot_info, &rl,
                                           &upd,       &t_node,    &t_slot,  &t_rl,   &t_upd,
-                                          &t_lptr,    &from,      &to};
+                                          &t_lptr,    &t_pk,      &from,    &to};
     size_t total = 0;
     for (auto* a : arrs) total += align256(std::max<size_t>(a->size(), 1) * sizeof(int32_t));
     return total;
@@ -375,7 +375,7 @@ void build_tail(HostSym& s, int64_t budget)
                 ++k2;
                 t2 += s.Lp[j + 1] - s.Lp[j];
             }
-            if (tail_bytes(k2, t2) + pv_mask_bytes(s.n) > budget) break;
+            if (tail_bytes(k2, t2) + pv_mask_bytes(s.n) > budget || t2 > 65535) break;
             K = k2;
             TS = t2;
             L = l;
@@ -390,6 +390,7 @@ void build_tail(HostSym& s, int64_t budget)
     s.t_slot.clear();
     s.t_rl.clear();
     s.t_upd.clear();
+    s.t_pk.clear();
     s.t_lptr.assign(1, 0);
     if (K == 0) return;
 
@@ -485,6 +486,24 @@ void build_tail(HostSym& s, int64_t budget)
             t[8] = s.perm[j];
             t[9] = (int32_t)jl;
         }
+    }
+    // packed copies of the local lists (local indices are below 2^16: the
+    // tail's slots fit in LDS)
+    auto pack = [&](const std::vector<int32_t>& src, int32_t b, int32_t e) {
+        const int32_t start = (int32_t)(s.t_pk.size() / 4);
+        for (int32_t u = b; u < e; ++u)
+            s.t_pk.push_back((int32_t)((uint32_t)src[2 * (size_t)u] |
+                                       ((uint32_t)src[2 * (size_t)u + 1] << 16)));
+        while (s.t_pk.size() % 4) s.t_pk.push_back(0);
+        return start;
+    };
+    for (int64_t jl = 0; jl < K; ++jl) {
+        int32_t* r = &s.t_node[12 * (size_t)jl];
+        r[9] = pack(s.t_rl, r[6], r[7]);
+    }
+    for (int64_t t = 0; t < TS; ++t) {
+        int32_t* u = &s.t_slot[12 * (size_t)t];
+        u[11] = pack(s.t_upd, u[6], u[7]);
     }
 }
 

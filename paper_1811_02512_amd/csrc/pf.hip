@@ -505,6 +505,43 @@ __device__ __forceinline__ void for_tail_range(const DevSym& S, int t0, int t1, 
     }
 }
 
+// As for_tail_range, passing fn(jl, the three parts of t_node[jl], lane, g);
+// each thread's first record of the next level is requested before the
+// barrier that ends the current one, so it is in registers when that level
+// starts.
+template <class F>
+__device__ __forceinline__ void for_tail_pf(const DevSym& S, int t0, int t1, bool up, F&& fn)
+{
+    if (t0 >= t1) return;
+    int g = 1, beg = 0, cnt = 0;
+    int4 ra = make_int4(0, 0, 0, 0), rb = ra, rc = ra;
+    auto fetch = [&](int tl) {
+        g = S.level_g[S.tail_level + tl];
+        beg = S.t_lptr[tl];
+        cnt = S.t_lptr[tl + 1] - beg;
+        const int idx = threadIdx.x / g;
+        const int jl = beg + (idx < cnt ? idx : 0);
+        ra = S.t_node[3 * jl];
+        rb = S.t_node[3 * jl + 1];
+        rc = S.t_node[3 * jl + 2];
+    };
+    fetch(up ? t0 : t1 - 1);
+    for (int ti = t0; ti < t1; ++ti) {
+        const int gg = g, b0 = beg, c0 = cnt;
+        const int4 a0 = ra, a1 = rb, a2 = rc;
+        if (ti + 1 < t1) fetch(up ? ti + 1 : t1 - 2 - (ti - t0));
+        const int gpb = blockDim.x / gg, grp = threadIdx.x / gg, lane = threadIdx.x & (gg - 1);
+        for (int base = 0; base < c0; base += gpb) {
+            const int idx = base + grp;
+            if (idx >= c0) continue;
+            const int jl = b0 + idx;
+            if (base == 0) fn(jl, a0, a1, a2, lane, gg);
+            else fn(jl, S.t_node[3 * jl], S.t_node[3 * jl + 1], S.t_node[3 * jl + 2], lane, gg);
+        }
+        __syncthreads();
+    }
+}
+
 // Block updates of one destination slot from pairs (a, b) = (slot(i;k), slot(i;j)):
 //   W_kj -= W_ki U_ij,  V_jk -= W_ji U_ik.
 // Two pairs per step; the next step's indices are fetched before this
@@ -584,6 +621,69 @@ __device__ __forceinline__ void apply_updates_lds(const int2* __restrict__ upd, 
         if (has_q) {
             bmsub(Wk, bload(sLU + 8 * q.x), bload(sLU + 8 * q.y + 4));
             bmsub(Vk, bload(sLU + 8 * q.y), bload(sLU + 8 * q.x + 4));
+        }
+        p = pn;
+        q = qn;
+    }
+}
+
+// Word k of a 16-byte load of a packed list.
+__device__ __forceinline__ uint32_t pk_word(const uint4& q, int k)
+{
+    return k == 0 ? q.x : k == 1 ? q.y : k == 2 ? q.z : q.w;
+}
+
+// Updates of two tail destinations from their packed local pair lists
+// (n1, n2 pairs starting at loads l1, l2; words (slot(i;k), slot(i;j))):
+// four pairs of each per step, the next step's loads in flight.  The order
+// of the updates of each destination is the list order.
+__device__ __forceinline__ void apply_packed2_lds(const uint4* __restrict__ pk, int l1, int n1,
+                                                  int l2, int n2, const double* sLU, Blk& Wk,
+                                                  Blk& Vk, Blk& Wk2, Blk& Vk2)
+{
+    uint4 q1 = pk[n1 > 0 ? l1 : 0], q2 = pk[n2 > 0 ? l2 : 0];
+    for (int k = 0; k < n1 || k < n2; k += 4) {
+        const int i = (k >> 2) + 1;
+        const uint4 q1n = pk[k + 4 < n1 ? l1 + i : 0];
+        const uint4 q2n = pk[k + 4 < n2 ? l2 + i : 0];
+        // one pair of each destination in flight at a time (register budget)
+#pragma unroll 1
+        for (int c = 0; c < 4; ++c) {
+            if (k + c < n1) {
+                const uint32_t v = pk_word(q1, c);
+                const int a = v & 0xffff, b = v >> 16;
+                bmsub(Wk, bload(sLU + 8 * a), bload(sLU + 8 * b + 4));
+                bmsub(Vk, bload(sLU + 8 * b), bload(sLU + 8 * a + 4));
+            }
+            if (k + c < n2) {
+                const uint32_t v = pk_word(q2, c);
+                const int a = v & 0xffff, b = v >> 16;
+                bmsub(Wk2, bload(sLU + 8 * a), bload(sLU + 8 * b + 4));
+                bmsub(Vk2, bload(sLU + 8 * b), bload(sLU + 8 * a + 4));
+            }
+        }
+        q1 = q1n;
+        q2 = q2n;
+    }
+}
+
+// apply_updates2 with the blocks in LDS; an absent pair reads no LDS.
+__device__ __forceinline__ void apply_updates2_lds(const int2* __restrict__ upd, int u0, int u1,
+                                                   int v0, int v1, int2 p, int2 q,
+                                                   const double* sLU, Blk& Wk, Blk& Vk, Blk& Wk2,
+                                                   Blk& Vk2)
+{
+    for (int a = u0, b = v0; a < u1 || b < v1; ++a, ++b) {
+        const bool hp = a < u1, hq = b < v1;
+        const int2 pn = upd_at(upd, a + 1, u1);
+        const int2 qn = upd_at(upd, b + 1, v1);
+        if (hp) {
+            bmsub(Wk, bload(sLU + 8 * p.x), bload(sLU + 8 * p.y + 4));
+            bmsub(Vk, bload(sLU + 8 * p.y), bload(sLU + 8 * p.x + 4));
+        }
+        if (hq) {
+            bmsub(Wk2, bload(sLU + 8 * q.x), bload(sLU + 8 * q.y + 4));
+            bmsub(Vk2, bload(sLU + 8 * q.y), bload(sLU + 8 * q.x + 4));
         }
         p = pn;
         q = qn;
@@ -763,16 +863,30 @@ __device__ void tail_factor(const DevSym& S, const SRC& src, const View& w, int6
         }
     }
     __syncthreads();
-    for_tail_range(S, 0, nT - KC, true, [&](int jl, int lane, int g) {
-        const int4 t0 = S.t_node[3 * jl];
-        const int4 t1 = S.t_node[3 * jl + 1];
+    // phase B: per node, its packed local R list (four entries per load, the
+    // loads split over the node's lanes), then its destinations, each taking
+    // its updates from its packed pair list
+    for_tail_pf(S, 0, nT - KC, true, [&](int jl, const int4& t0, const int4& t1,
+                                          const int4& t2, int lane, int g) {
+        const int nR = t1.w - t1.z, s1 = t1.x;
+        const int nq = (nR + 3) >> 2;
         Blk ds = bzero();
         double z0 = 0.0, z1 = 0.0;
-        for (int r = t1.z + lane; r < t1.w; r += g) {
-            const int2 e = S.t_rl[r];
-            const Blk wv = bload(sLU + 8 * e.y);
-            bmadd(ds, wv, bload(sLU + 8 * e.y + 4));
-            if (FWD) mvadd(z0, z1, wv, sy[2 * e.x], sy[2 * e.x + 1]);
+        int qi = lane;
+        uint4 q = S.t_pk[qi < nq ? t2.y + qi : 0];
+        for (; qi < nq; qi += g) {
+            const uint4 qn = S.t_pk[qi + g < nq ? t2.y + qi + g : 0];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if (4 * qi + c < nR) {
+                    const uint32_t v = pk_word(q, c);
+                    const int il = v & 0xffff, sl = v >> 16;
+                    const Blk wv = bload(sLU + 8 * sl);
+                    bmadd(ds, wv, bload(sLU + 8 * sl + 4));
+                    if (FWD) mvadd(z0, z1, wv, sy[2 * il], sy[2 * il + 1]);
+                }
+            }
+            q = qn;
         }
         if (g > 1) {
             gsum_blk(ds, g);
@@ -784,12 +898,47 @@ __device__ void tail_factor(const DevSym& S, const SRC& src, const View& w, int6
         const Blk A = bload(sD + 4 * jl);
         bool ok;
         const Blk Di = binv({A.a - ds.a, A.b - ds.b, A.c - ds.c, A.d - ds.d}, ok);
-        for (int t = t0.w + lane; t < t1.x; t += g) {
-            const int4 b = S.t_slot[3 * t + 1];
-            Blk Wk = bload(sLU + 8 * t), Vk = bload(sLU + 8 * t + 4);
-            apply_updates_lds(S.t_upd, b.z, b.w, sLU, Wk, Vk);
-            bstore(sLU + 8 * t, Wk);
-            bstore(sLU + 8 * t + 4, bmul(Di, Vk));
+        // destinations: h lanes share one destination's pair list (four pairs
+        // per load, loads split over the h lanes), then sum over the h lanes
+        const int nS = s1 - t0.w;
+        int p2 = 1;
+        while (p2 < nS) p2 <<= 1;
+        const int h = g > p2 ? g / p2 : 1;
+        const int nd = g / h, dl = lane / h, ph = lane & (h - 1);
+        for (int base = 0; base < nS; base += nd) {
+            const int tt = t0.w + base + dl;
+            const bool live = tt < s1;
+            const int tq = live ? tt : 0;
+            const int4 b = S.t_slot[3 * tq + 1], c = S.t_slot[3 * tq + 2];
+            const int n = live ? b.w - b.z : 0, nq = (n + 3) >> 2;
+            Blk Wk = bzero(), Vk = bzero();
+            if (live && ph == 0) {
+                Wk = bload(sLU + 8 * tt);
+                Vk = bload(sLU + 8 * tt + 4);
+            }
+            int qi = ph;
+            uint4 q = S.t_pk[qi < nq ? c.w + qi : 0];
+            for (; qi < nq; qi += h) {
+                const uint4 qn = S.t_pk[qi + h < nq ? c.w + qi + h : 0];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (4 * qi + k < n) {
+                        const uint32_t v = pk_word(q, k);
+                        const int a = v & 0xffff, bb = v >> 16;
+                        bmsub(Wk, bload(sLU + 8 * a), bload(sLU + 8 * bb + 4));
+                        bmsub(Vk, bload(sLU + 8 * bb), bload(sLU + 8 * a + 4));
+                    }
+                }
+                q = qn;
+            }
+            if (h > 1) {
+                gsum_blk(Wk, h);
+                gsum_blk(Vk, h);
+            }
+            if (live && ph == 0) {
+                bstore(sLU + 8 * tt, Wk);
+                bstore(sLU + 8 * tt + 4, bmul(Di, Vk));
+            }
         }
         if (lane == 0) {
             if (!ok) *s_bad = 1;
@@ -808,29 +957,42 @@ __device__ void tail_factor(const DevSym& S, const SRC& src, const View& w, int6
         // phase C: clique diagonals, rhs and slots take the tail updates from below
         for (int it = threadIdx.x; it < KC + (TS - c0); it += blockDim.x) {
             if (it < KC) {
+                // the packed local R list, below-clique part (its prefix)
                 const int jl = kf + it;
                 const int4 t1 = S.t_node[3 * jl + 1];
-                const int rmid = S.t_node[3 * jl + 2].x;
+                const int4 t2 = S.t_node[3 * jl + 2];
+                const int nR = t2.x - t1.z;
                 Blk acc = bload(sD + 4 * jl);
                 double z0 = sy[2 * jl], z1 = sy[2 * jl + 1];
-                for (int r = t1.z; r < rmid; ++r) {
-                    const int2 e = S.t_rl[r];
-                    const Blk wv = bload(sLU + 8 * e.y);
-                    bmsub(acc, wv, bload(sLU + 8 * e.y + 4));
-                    if (FWD) {
-                        z0 = fma(-wv.a, sy[2 * e.x], fma(-wv.b, sy[2 * e.x + 1], z0));
-                        z1 = fma(-wv.c, sy[2 * e.x], fma(-wv.d, sy[2 * e.x + 1], z1));
+                uint4 q = S.t_pk[nR > 0 ? t2.y : 0];
+                for (int k = 0; k < nR; k += 4) {
+                    const uint4 qn = S.t_pk[k + 4 < nR ? t2.y + (k >> 2) + 1 : 0];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        if (k + c < nR) {
+                            const uint32_t v = pk_word(q, c);
+                            const int il = v & 0xffff, sl = v >> 16;
+                            const Blk wv = bload(sLU + 8 * sl);
+                            bmsub(acc, wv, bload(sLU + 8 * sl + 4));
+                            if (FWD) {
+                                z0 = fma(-wv.a, sy[2 * il], fma(-wv.b, sy[2 * il + 1], z0));
+                                z1 = fma(-wv.c, sy[2 * il], fma(-wv.d, sy[2 * il + 1], z1));
+                            }
+                        }
                     }
+                    q = qn;
                 }
                 bstore(sD + 4 * jl, acc);
                 sy[2 * jl] = z0;
                 sy[2 * jl + 1] = z1;
             } else {
+                // the packed local pair list, below-clique part (its prefix)
                 const int t = c0 + (it - KC);
                 const int4 b = S.t_slot[3 * t + 1];
-                const int umid = S.t_slot[3 * t + 2].z;
+                const int4 c = S.t_slot[3 * t + 2];
                 Blk Wk = bload(sLU + 8 * t), Vk = bload(sLU + 8 * t + 4);
-                apply_updates_lds(S.t_upd, b.z, umid, sLU, Wk, Vk);
+                Blk W2 = bzero(), V2 = bzero();
+                apply_packed2_lds(S.t_pk, c.w, c.z - b.z, 0, 0, sLU, Wk, Vk, W2, V2);
                 bstore(sLU + 8 * t, Wk);
                 bstore(sLU + 8 * t + 4, Vk);
             }
@@ -965,13 +1127,37 @@ __device__ void tail_backward(const DevSym& S, const View& w, int64_t rhs, int64
             __syncthreads();
         }
     }
-    for_tail_range(S, 0, nT - KC, false, [&](int jl, int lane, int g) {
-        const int4 t0 = S.t_node[3 * jl];
-        const int4 t1 = S.t_node[3 * jl + 1];
+    // sparse part: slot indices four per lane at a time and the bus record
+    // of the step requested before any LDS work
+    for_tail_pf(S, 0, nT - KC, false, [&](int jl, const int4& t0, const int4& t1, const int4&,
+                                           int lane, int g) {
+        const int s1 = t1.x;
+        const int64_t brec = bus_off + 8 * (int64_t)t0.y;
+        Blk br = bzero();
+        bool pv = false;
+        if (UPDATE) {
+            br = w.blk(brec);
+            pv = type(t0.y);
+        }
+        int t = t0.w + lane;
+        int kk[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) kk[k] = S.t_slot[3 * (t + k * g < s1 ? t + k * g : 0)].y;
         double a0 = 0.0, a1 = 0.0;
-        for (int t = t0.w + lane; t < t1.x; t += g) {
-            const int kl = S.t_slot[3 * t].y;
-            mvadd(a0, a1, bload(sLU + 8 * t + 4), sy[2 * kl], sy[2 * kl + 1]);
+        for (; t < s1; t += 4 * g) {
+            const int tn = t + 4 * g;
+            int kn[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) kn[k] = S.t_slot[3 * (tn + k * g < s1 ? tn + k * g : 0)].y;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (t + k * g < s1) {
+                    const int kl = kk[k];
+                    mvadd(a0, a1, bload(sLU + 8 * (t + k * g) + 4), sy[2 * kl], sy[2 * kl + 1]);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) kk[k] = kn[k];
         }
         if (g > 1) {
             a0 = gsum(a0, g);
@@ -982,7 +1168,7 @@ __device__ void tail_backward(const DevSym& S, const View& w, int64_t rhs, int64
             sy[2 * jl] = x0;
             sy[2 * jl + 1] = x1;
             w.put2(rhs + 2 * (int64_t)t0.x, make_double2(x0, x1));
-            if (UPDATE) apply_step(w, bus_off + 8 * (int64_t)t0.y, type(t0.y), x0, x1);
+            if (UPDATE) apply_step_to(w, brec, br, pv, x0, x1);
         }
     });
 }
@@ -1332,10 +1518,10 @@ __device__ __forceinline__ void fd_factor_node(const DevSym& S, const NodeRec& r
 // Forward substitution and normalisation on component comp of the rhs:
 //   y_j = (1/d_j) (b_j - sum_{i in R(j)} w_ji y_i), levels upward.
 __device__ __forceinline__ void fd_forward(const DevSym& S, const double* m, const View& wb,
-                                           int64_t rhs, int comp)
+                                           int64_t rhs, int comp, int l1)
 {
     const double2* sl = reinterpret_cast<const double2*>(m + S.fd_lu);
-    for_nodes(S, 0, S.nlev, true, [&](int, const NodeRec& rec, int lane, int g) {
+    for_nodes(S, 0, l1, true, [&](int, const NodeRec& rec, int lane, int g) {
         double z = 0.0;
         for (int r = rec.a.z + lane; r < rec.a.w; r += g) {
             const int2 e = S.rl[r];
@@ -1349,16 +1535,100 @@ __device__ __forceinline__ void fd_forward(const DevSym& S, const double* m, con
     });
 }
 
+// The half step at a bus: ANGLE: theta -= x; else |V| -= x at PQ buses.
+template <bool ANGLE>
+__device__ __forceinline__ void fd_half_step(const View& wb, int64_t bus_off, int bus,
+                                             const PvMask& pv, double x)
+{
+    const int64_t br = bus_off + 8 * (int64_t)bus;
+    const Blk v = wb.blk(br);
+    double vm = v.c, va = v.d;
+    if (ANGLE) va -= x;
+    else if (!pv(bus)) vm -= x;
+    double sn, cs;
+    sincos(va, &sn, &cs);
+    wb.put(br, {vm * cs, vm * sn, vm, va});
+}
+
+// The top of the tree (the LDS tail's levels) of a factored matrix, copied
+// into LDS once per launch: (w, u) per local slot, 1/d per local node.
+struct FdTail {
+    double2* wu;  // TS
+    double* d;    // K
+};
+
+__device__ __forceinline__ void fd_tail_load(const DevSym& S, const double* m, const FdTail& t)
+{
+    const double2* sl = reinterpret_cast<const double2*>(m + S.fd_lu);
+    for (int i = threadIdx.x; i < S.tail_slots; i += blockDim.x) t.wu[i] = sl[S.t_slot[3 * i].x];
+    for (int i = threadIdx.x; i < S.tail_nodes; i += blockDim.x) t.d[i] = m[S.t_node[3 * i].x];
+}
+
+// Forward substitution of the tail levels in LDS on component comp: each
+// tail node first takes b_j and the terms of its descendants outside the
+// tail (global lists, all nodes at once), then the tail levels go upward
+// with the local lists.  y of the tail stays in sy for the backward sweep.
+__device__ __forceinline__ void fd_forward_tail(const DevSym& S, const double* m, const FdTail& t,
+                                                double* sy, const View& wb, int64_t rhs,
+                                                int comp)
+{
+    const double2* sl = reinterpret_cast<const double2*>(m + S.fd_lu);
+    for (int jl = threadIdx.x; jl < S.tail_nodes; jl += blockDim.x) {
+        const int4 a = S.t_node[3 * jl], b = S.t_node[3 * jl + 1];
+        double z = *wb.at(rhs + 2 * (int64_t)a.x + comp);
+        for (int r = b.y; r < b.z; ++r) {
+            const int2 e = S.t_rl[r];
+            z = fma(-sl[e.y].x, *wb.at(rhs + 2 * (int64_t)e.x + comp), z);
+        }
+        sy[jl] = z;
+    }
+    __syncthreads();
+    const int nT = S.nlev - S.tail_level;
+    for_tail_pf(S, 0, nT, true, [&](int jl, const int4&, const int4& b, const int4&, int lane,
+                                    int g) {
+        double z = 0.0;
+        for (int r = b.z + lane; r < b.w; r += g) {
+            const int2 e = S.t_rl[r];
+            z = fma(t.wu[e.y].x, sy[e.x], z);
+        }
+        if (g > 1) z = gsum(z, g);
+        if (lane == 0) sy[jl] = t.d[jl] * (sy[jl] - z);
+    });
+}
+
+// Backward substitution of the tail levels in LDS, downward; each tail x is
+// written to the rhs for the levels below and its bus takes the half step.
+template <bool ANGLE>
+__device__ __forceinline__ void fd_backward_tail(const DevSym& S, const FdTail& t, double* sy,
+                                                 const View& wb, int64_t rhs, int64_t bus_off,
+                                                 const PvMask& pv)
+{
+    const int comp = ANGLE ? 0 : 1;
+    const int nT = S.nlev - S.tail_level;
+    for_tail_pf(S, 0, nT, false, [&](int jl, const int4& a, const int4& b, const int4&, int lane,
+                                     int g) {
+        double s = 0.0;
+        for (int q = a.w + lane; q < b.x; q += g) s = fma(t.wu[q].y, sy[S.t_slot[3 * q].y], s);
+        if (g > 1) s = gsum(s, g);
+        if (lane == 0) {
+            const double x = sy[jl] - s;
+            sy[jl] = x;
+            *wb.at(rhs + 2 * (int64_t)a.x + comp) = x;
+            fd_half_step<ANGLE>(wb, bus_off, a.y, pv, x);
+        }
+    });
+}
+
 // Backward substitution x_j = y_j - sum_{k in S(j)} u_jk x_k, levels
-// downward, and the half step at bus(j): ANGLE: theta -= x_j; else
-// |V| -= x_j at PQ buses.
+// downward, and the half step at bus(j).
 template <bool ANGLE>
 __device__ __forceinline__ void fd_backward(const DevSym& S, const double* m, const View& wb,
-                                            int64_t rhs, int64_t bus_off, const PvMask& pv)
+                                            int64_t rhs, int64_t bus_off, const PvMask& pv,
+                                            int l1)
 {
     const double2* sl = reinterpret_cast<const double2*>(m + S.fd_lu);
     const int comp = ANGLE ? 0 : 1;
-    for_nodes(S, 0, S.nlev, false, [&](int, const NodeRec& rec, int lane, int g) {
+    for_nodes(S, 0, l1, false, [&](int, const NodeRec& rec, int lane, int g) {
         double a = 0.0;
         for (int s = rec.b.x + lane; s < rec.b.y; s += g)
             a = fma(sl[s].y, *wb.at(rhs + 2 * (int64_t)S.Li[s] + comp), a);
@@ -1367,15 +1637,7 @@ __device__ __forceinline__ void fd_backward(const DevSym& S, const double* m, co
             double* yj = wb.at(rhs + 2 * (int64_t)rec.a.x + comp);
             const double xj = *yj - a;
             *yj = xj;
-            const int bus = rec.a.y;
-            const int64_t br = bus_off + 8 * (int64_t)bus;
-            const Blk v = wb.blk(br);
-            double vm = v.c, va = v.d;
-            if (ANGLE) va -= xj;
-            else if (!pv(bus)) vm -= xj;
-            double sn, cs;
-            sincos(va, &sn, &cs);
-            wb.put(br, {vm * cs, vm * sn, vm, va});
+            fd_half_step<ANGLE>(wb, bus_off, rec.a.y, pv, xj);
         }
     });
 }
@@ -1388,7 +1650,19 @@ __device__ void fdpf_case(const DevSym& S, const double* yv, const int8_t* type,
                           const View& wb, const double* m1, const double* m2, double tol,
                           int max_iter, int32_t* o_iters, double* o_norm, int32_t* o_status)
 {
+    // LDS: PV mask | (w, u) of B' and B'' tails | 1/d of both | tail y
     uint32_t* fd_pv = reinterpret_cast<uint32_t*>(pf_smem);
+    double* lds = pf_smem + ((((S.n + 63) / 64) + 1) & ~1);  // mask: 8 bytes per 64 buses
+    const int K = S.tail_nodes, TS = S.tail_slots;
+    const FdTail t1{reinterpret_cast<double2*>(lds), lds + 4 * TS};
+    const FdTail t2{reinterpret_cast<double2*>(lds + 2 * TS), lds + 4 * TS + K};
+    double* sy = lds + 4 * TS + 2 * K;
+    const bool tail = K > 0;
+    const int lg = tail ? S.tail_level : S.nlev;  // levels swept in global memory
+    if (tail) {
+        fd_tail_load(S, m1, t1);
+        fd_tail_load(S, m2, t2);
+    }
     const Off o = ws_off(S);
     for (int i = threadIdx.x; i < S.n; i += blockDim.x) {
         double sn, cs;
@@ -1422,12 +1696,20 @@ __device__ void fdpf_case(const DevSym& S, const double* yv, const int8_t* type,
                 st = ST_NOT_CONVERGED;
                 break;
             }
-            fd_forward(S, m1, wb, o.RHS, 0);
-            fd_backward<true>(S, m1, wb, o.RHS, o.BUS, pvm);
+            fd_forward(S, m1, wb, o.RHS, 0, lg);
+            if (tail) {
+                fd_forward_tail(S, m1, t1, sy, wb, o.RHS, 0);
+                fd_backward_tail<true>(S, t1, sy, wb, o.RHS, o.BUS, pvm);
+            }
+            fd_backward<true>(S, m1, wb, o.RHS, o.BUS, pvm, lg);
             ++it;
         } else {
-            fd_forward(S, m2, wb, o.RHS, 1);
-            fd_backward<false>(S, m2, wb, o.RHS, o.BUS, pvm);
+            fd_forward(S, m2, wb, o.RHS, 1, lg);
+            if (tail) {
+                fd_forward_tail(S, m2, t2, sy, wb, o.RHS, 1);
+                fd_backward_tail<false>(S, t2, sy, wb, o.RHS, o.BUS, pvm);
+            }
+            fd_backward<false>(S, m2, wb, o.RHS, o.BUS, pvm, lg);
         }
         half ^= 1;
     }
@@ -1929,6 +2211,14 @@ int launch_check(const char* what) { return hip_check(hipGetLastError(), what); 
 
 // Workgroup size of the level-scheduled kernels: the symbolic's setting, or
 // by batch size so that a small batch still brings 16 waves to its CUs.
+// Dynamic LDS of the fast decoupled kernel: PV mask (rounded to 16 bytes),
+// then (w, u) of both matrices' tails, 1/d of both, and the tail's y.
+size_t fd_lds_bytes(const HostSym& h)
+{
+    const size_t mask = ((pv_mask_bytes(h.n) + 15) / 16) * 16;
+    return mask + 8 * (4 * (size_t)h.tail_slots + 3 * (size_t)h.tail_nodes);
+}
+
 int launch_threads(const HostSym& h, int B)
 {
     if (h.threads > 0) return h.threads;
@@ -2209,6 +2499,7 @@ int pf_symbolic_upload(pf_symbolic s, void* d_buf, size_t bytes, void* stream)
     d.t_rl = reinterpret_cast<const int2*>(put(h.t_rl));
     d.t_upd = reinterpret_cast<const int2*>(put(h.t_upd));
     d.t_lptr = put(h.t_lptr);
+    d.t_pk = reinterpret_cast<const uint4*>(put(h.t_pk));
     s->d_from = put(h.from);
     s->d_to = put(h.to);
     if (off > info.dev_bytes) return fail(PF_E_WORKSPACE, "pf_symbolic_upload: size mismatch");
@@ -2404,8 +2695,9 @@ int pf_fdpf(const pf_symbolic s, int B, const double* d_yval, int64_t y_stride,
     if (B == 0) return PF_OK;
     NewtonArgs a{d_yval, y_stride, d_type, type_stride, d_Psp, d_Qsp, inj_stride, d_Vm, d_Va,
                  v_stride, d_ws, ws_stride, tol, max_iter, 0, 1, B, d_iters, d_norm, d_status};
+    allow_big_lds();
     hipLaunchKernelGGL(k_fdpf, dim3(B), dim3(launch_threads(s->h, B)),
-                       pv_mask_bytes(s->h.n), as_stream(stream), s->h.dev, a, d_mat, mat_stride);
+                       fd_lds_bytes(s->h), as_stream(stream), s->h.dev, a, d_mat, mat_stride);
     return launch_check("pf_fdpf");
 }
 

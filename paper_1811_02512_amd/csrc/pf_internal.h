@@ -30,13 +30,13 @@ namespace pf {
 // values fit in LDS, are factorised and solved in LDS.  Every higher
 // neighbour of a tail node is itself in the tail.  Local numbering: tail
 // nodes 0..K-1 in level order, tail slots 0..TS-1 in node order.
-//   t_node[jl] (3 x int4): {j, bus, ydiag, sl0}, {sl1, rn0, rn1, rt1}, {rmid, 0, 0, 0}
+//   t_node[jl] (3 x int4): {j, bus, ydiag, sl0}, {sl1, rn0, rn1, rt1}, {rmid, pk, 0, 0}
 //     [sl0, sl1) local slots, [rn0, rn1) lower neighbours outside the tail
 //     as (i, slot) global pairs in t_rl, [rn1, rt1) lower neighbours inside
 //     the tail as (local i, local slot) pairs in t_rl, those below the
 //     clique first: [rn1, rmid) below, [rmid, rt1) in the clique
 //   t_slot[t] (3 x int4): {s, kl, bus_k, ylo}, {yup, un0, un1, ut1},
-//                         {bus_j, jl, umid, 0}
+//                         {bus_j, jl, umid, pk}
 //     s = global slot, kl = local node of k, [un0, un1) update pairs from
 //     outside the tail (global slots) and [un1, ut1) from inside (local),
 //     [un1, umid) from below the clique, [umid, ut1) from the clique;
@@ -45,6 +45,11 @@ namespace pf {
 //   levels, each adjacent to every node above it (local slot of clique pair
 //   (a, b), a < b, is t_node[a].sl0 + b - a - 1).
 //   t_lptr[l - tail_level .. ]: local node range of each tail level
+//   t_pk: the local lists again, packed: each 32-bit word holds a local pair
+//     (lo 16 bits, hi 16 bits), four words per 16-byte load; a node's local
+//     lower neighbours [rn1, rt1) start at load t_node.pk, a slot's local
+//     update pairs [un1, ut1) at load t_slot.pk; each list is padded to
+//     whole loads
 struct DevSym {
     int32_t n, m, nn, slack;
     int32_t nnz_y, nnz_l, nlev, pad0;
@@ -87,6 +92,7 @@ struct DevSym {
     const int2* t_rl;
     const int2* t_upd;
     const int32_t* t_lptr;   // nlev - tail_level + 1
+    const uint4* t_pk;
 };
 
 struct HostSym {
@@ -102,7 +108,7 @@ struct HostSym {
     // tail
     int32_t tail_level = 0, tail_nodes = 0, tail_slots = 0, tail_lds = 0, tail_clique = 0;
     int64_t tail_budget = 64 * 1024;
-    std::vector<int32_t> t_node, t_slot, t_rl, t_upd, t_lptr;
+    std::vector<int32_t> t_node, t_slot, t_rl, t_upd, t_lptr, t_pk;
     int32_t max_width = 0;
     int32_t threads = 0;  // 0: chosen per launch from the batch size
     int32_t interleave = 4;  // cases per interleaved workspace group
