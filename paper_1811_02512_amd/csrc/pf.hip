@@ -122,7 +122,7 @@ __device__ __forceinline__ View case_bus_view(double* buf, int64_t stride, int C
 // Offsets of the Newton workspace of one case (doubles):
 //   D [nn][4] (padded) | LU [nnz_l][8] | bus records [n][8] | rhs [nn][2]
 // D and LU through the values view; BUS and RHS relative to the bus view.
-// bus record: e, f, |V|, theta | P, Q, P_sp, Q_sp  (e + jf = V, P + jQ = S).
+// bus record: e, f, |V|, theta | P, Q, -, -  (e + jf = V, P + jQ = S).
 struct Off {
     int64_t D, LU, BUS, RHS;
 };
@@ -667,29 +667,6 @@ __device__ __forceinline__ void apply_packed2_lds(const uint4* __restrict__ pk, 
     }
 }
 
-// apply_updates2 with the blocks in LDS; an absent pair reads no LDS.
-__device__ __forceinline__ void apply_updates2_lds(const int2* __restrict__ upd, int u0, int u1,
-                                                   int v0, int v1, int2 p, int2 q,
-                                                   const double* sLU, Blk& Wk, Blk& Vk, Blk& Wk2,
-                                                   Blk& Vk2)
-{
-    for (int a = u0, b = v0; a < u1 || b < v1; ++a, ++b) {
-        const bool hp = a < u1, hq = b < v1;
-        const int2 pn = upd_at(upd, a + 1, u1);
-        const int2 qn = upd_at(upd, b + 1, v1);
-        if (hp) {
-            bmsub(Wk, bload(sLU + 8 * p.x), bload(sLU + 8 * p.y + 4));
-            bmsub(Vk, bload(sLU + 8 * p.y), bload(sLU + 8 * p.x + 4));
-        }
-        if (hq) {
-            bmsub(Wk2, bload(sLU + 8 * q.x), bload(sLU + 8 * q.y + 4));
-            bmsub(Vk2, bload(sLU + 8 * q.y), bload(sLU + 8 * q.x + 4));
-        }
-        p = pn;
-        q = qn;
-    }
-}
-
 __device__ __forceinline__ void gsum_blk(Blk& v, int g)
 {
     v.a = gsum(v.a, g);
@@ -863,30 +840,16 @@ __device__ void tail_factor(const DevSym& S, const SRC& src, const View& w, int6
         }
     }
     __syncthreads();
-    // phase B: per node, its packed local R list (four entries per load, the
-    // loads split over the node's lanes), then its destinations, each taking
-    // its updates from its packed pair list
-    for_tail_pf(S, 0, nT - KC, true, [&](int jl, const int4& t0, const int4& t1,
-                                          const int4& t2, int lane, int g) {
-        const int nR = t1.w - t1.z, s1 = t1.x;
-        const int nq = (nR + 3) >> 2;
+    for_tail_range(S, 0, nT - KC, true, [&](int jl, int lane, int g) {
+        const int4 t0 = S.t_node[3 * jl];
+        const int4 t1 = S.t_node[3 * jl + 1];
         Blk ds = bzero();
         double z0 = 0.0, z1 = 0.0;
-        int qi = lane;
-        uint4 q = S.t_pk[qi < nq ? t2.y + qi : 0];
-        for (; qi < nq; qi += g) {
-            const uint4 qn = S.t_pk[qi + g < nq ? t2.y + qi + g : 0];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                if (4 * qi + c < nR) {
-                    const uint32_t v = pk_word(q, c);
-                    const int il = v & 0xffff, sl = v >> 16;
-                    const Blk wv = bload(sLU + 8 * sl);
-                    bmadd(ds, wv, bload(sLU + 8 * sl + 4));
-                    if (FWD) mvadd(z0, z1, wv, sy[2 * il], sy[2 * il + 1]);
-                }
-            }
-            q = qn;
+        for (int r = t1.z + lane; r < t1.w; r += g) {
+            const int2 e = S.t_rl[r];
+            const Blk wv = bload(sLU + 8 * e.y);
+            bmadd(ds, wv, bload(sLU + 8 * e.y + 4));
+            if (FWD) mvadd(z0, z1, wv, sy[2 * e.x], sy[2 * e.x + 1]);
         }
         if (g > 1) {
             gsum_blk(ds, g);
@@ -898,47 +861,12 @@ __device__ void tail_factor(const DevSym& S, const SRC& src, const View& w, int6
         const Blk A = bload(sD + 4 * jl);
         bool ok;
         const Blk Di = binv({A.a - ds.a, A.b - ds.b, A.c - ds.c, A.d - ds.d}, ok);
-        // destinations: h lanes share one destination's pair list (four pairs
-        // per load, loads split over the h lanes), then sum over the h lanes
-        const int nS = s1 - t0.w;
-        int p2 = 1;
-        while (p2 < nS) p2 <<= 1;
-        const int h = g > p2 ? g / p2 : 1;
-        const int nd = g / h, dl = lane / h, ph = lane & (h - 1);
-        for (int base = 0; base < nS; base += nd) {
-            const int tt = t0.w + base + dl;
-            const bool live = tt < s1;
-            const int tq = live ? tt : 0;
-            const int4 b = S.t_slot[3 * tq + 1], c = S.t_slot[3 * tq + 2];
-            const int n = live ? b.w - b.z : 0, nq = (n + 3) >> 2;
-            Blk Wk = bzero(), Vk = bzero();
-            if (live && ph == 0) {
-                Wk = bload(sLU + 8 * tt);
-                Vk = bload(sLU + 8 * tt + 4);
-            }
-            int qi = ph;
-            uint4 q = S.t_pk[qi < nq ? c.w + qi : 0];
-            for (; qi < nq; qi += h) {
-                const uint4 qn = S.t_pk[qi + h < nq ? c.w + qi + h : 0];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    if (4 * qi + k < n) {
-                        const uint32_t v = pk_word(q, k);
-                        const int a = v & 0xffff, bb = v >> 16;
-                        bmsub(Wk, bload(sLU + 8 * a), bload(sLU + 8 * bb + 4));
-                        bmsub(Vk, bload(sLU + 8 * bb), bload(sLU + 8 * a + 4));
-                    }
-                }
-                q = qn;
-            }
-            if (h > 1) {
-                gsum_blk(Wk, h);
-                gsum_blk(Vk, h);
-            }
-            if (live && ph == 0) {
-                bstore(sLU + 8 * tt, Wk);
-                bstore(sLU + 8 * tt + 4, bmul(Di, Vk));
-            }
+        for (int t = t0.w + lane; t < t1.x; t += g) {
+            const int4 b = S.t_slot[3 * t + 1];
+            Blk Wk = bload(sLU + 8 * t), Vk = bload(sLU + 8 * t + 4);
+            apply_updates_lds(S.t_upd, b.z, b.w, sLU, Wk, Vk);
+            bstore(sLU + 8 * t, Wk);
+            bstore(sLU + 8 * t + 4, bmul(Di, Vk));
         }
         if (lane == 0) {
             if (!ok) *s_bad = 1;
@@ -1127,37 +1055,13 @@ __device__ void tail_backward(const DevSym& S, const View& w, int64_t rhs, int64
             __syncthreads();
         }
     }
-    // sparse part: slot indices four per lane at a time and the bus record
-    // of the step requested before any LDS work
-    for_tail_pf(S, 0, nT - KC, false, [&](int jl, const int4& t0, const int4& t1, const int4&,
-                                           int lane, int g) {
-        const int s1 = t1.x;
-        const int64_t brec = bus_off + 8 * (int64_t)t0.y;
-        Blk br = bzero();
-        bool pv = false;
-        if (UPDATE) {
-            br = w.blk(brec);
-            pv = type(t0.y);
-        }
-        int t = t0.w + lane;
-        int kk[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) kk[k] = S.t_slot[3 * (t + k * g < s1 ? t + k * g : 0)].y;
+    for_tail_range(S, 0, nT - KC, false, [&](int jl, int lane, int g) {
+        const int4 t0 = S.t_node[3 * jl];
+        const int4 t1 = S.t_node[3 * jl + 1];
         double a0 = 0.0, a1 = 0.0;
-        for (; t < s1; t += 4 * g) {
-            const int tn = t + 4 * g;
-            int kn[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) kn[k] = S.t_slot[3 * (tn + k * g < s1 ? tn + k * g : 0)].y;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (t + k * g < s1) {
-                    const int kl = kk[k];
-                    mvadd(a0, a1, bload(sLU + 8 * (t + k * g) + 4), sy[2 * kl], sy[2 * kl + 1]);
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) kk[k] = kn[k];
+        for (int t = t0.w + lane; t < t1.x; t += g) {
+            const int kl = S.t_slot[3 * t].y;
+            mvadd(a0, a1, bload(sLU + 8 * t + 4), sy[2 * kl], sy[2 * kl + 1]);
         }
         if (g > 1) {
             a0 = gsum(a0, g);
@@ -1168,7 +1072,7 @@ __device__ void tail_backward(const DevSym& S, const View& w, int64_t rhs, int64
             sy[2 * jl] = x0;
             sy[2 * jl + 1] = x1;
             w.put2(rhs + 2 * (int64_t)t0.x, make_double2(x0, x1));
-            if (UPDATE) apply_step_to(w, brec, br, pv, x0, x1);
+            if (UPDATE) apply_step(w, bus_off + 8 * (int64_t)t0.y, type(t0.y), x0, x1);
         }
     });
 }
@@ -1285,52 +1189,49 @@ struct CaseDesc {
 // Mismatch pass of one case: P + jQ into the bus records and F = calculated
 // - scheduled (F_Q = 0 at PV buses) into the rhs in position order, divided
 // by |V| with SCALE (the fast decoupled right-hand sides); the thread's max
-// |F| and NaN flag accumulate into mx and nan.
+// |F| and NaN flag accumulate into mx and nan.  Buses are taken in bus
+// order, two per thread per step, so that the admittance rows, row pointers,
+// positions and scheduled injections of a wavefront are adjacent in memory;
+// all loads of both buses are issued before either is summed.
 template <bool SCALE>
 __device__ __forceinline__ void mismatch_pass(const DevSym& S, const double* yv, const EFView& ef,
                                               const View& wb, const Off& o, const PvMask& pvm,
-                                              double& mx, int& nan)
+                                              const double* Psp, const double* Qsp, double& mx,
+                                              int& nan)
 {
-    // mismatch: two buses per thread per step, all of their loads issued
-    // before either is summed; the next step's records are in flight
     const int bd = blockDim.x;
-    int x = threadIdx.x;
-    int4 a0 = S.node_info[3 * (x < S.nn ? x : 0)];
-    int4 a2 = S.node_info[3 * (x < S.nn ? x : 0) + 2];
-    int4 b0 = S.node_info[3 * (x + bd < S.nn ? x + bd : 0)];
-    int4 b2 = S.node_info[3 * (x + bd < S.nn ? x + bd : 0) + 2];
-    for (; x < S.nn; x += 2 * bd) {
-        const bool two = x + bd < S.nn;
-        const int4 c0 = a0, c2 = a2, d0 = b0, d2 = b2;
-        const int xa = x + 2 * bd < S.nn ? x + 2 * bd : 0;
-        const int xb = x + 3 * bd < S.nn ? x + 3 * bd : 0;
-        a0 = S.node_info[3 * xa];
-        a2 = S.node_info[3 * xa + 2];
-        b0 = S.node_info[3 * xb];
-        b2 = S.node_info[3 * xb + 2];
-        const int64_t rc = o.BUS + 8 * (int64_t)c0.y, rd = o.BUS + 8 * (int64_t)d0.y;
+    for (int i = threadIdx.x; i < S.n; i += 2 * bd) {
+        const int i2 = i + bd;
+        const bool two = i2 < S.n;
+        const int ic = two ? i2 : i;
+        const int pc = S.pos[i], pd = S.pos[ic];
+        const int qc0 = S.yptr[i], qc1 = S.yptr[i + 1];
+        const int qd0 = S.yptr[ic], qd1 = S.yptr[ic + 1];
+        const double spc = Psp[i], sqc = Qsp[i], spd = Psp[ic], sqd = Qsp[ic];
+        const int64_t rc = o.BUS + 8 * (int64_t)i, rd = o.BUS + 8 * (int64_t)ic;
         const Blk vc = wb.blk(rc), vd = wb.blk(rd);
-        const double2 spc = wb.v2(rc + 6), spd = wb.v2(rd + 6);
-        const bool pvc = pvm(c0.y), pvd = pvm(d0.y);
+        const bool pvc = pvm(i), pvd = pvm(ic);
         int kc[4], kd[4];
         RowHead hc, hd;
-        row_head_idx<EFView>(S, yv, c2.x, c2.y, kc, hc);
-        row_head_idx<EFView>(S, yv, d2.x, d2.y, kd, hd);
+        row_head_idx<EFView>(S, yv, qc0, qc1, kc, hc);
+        row_head_idx<EFView>(S, yv, qd0, qd1, kd, hd);
         row_head_v(ef, kc, hc);
         row_head_v(ef, kd, hd);
         double p, q, p2, q2;
-        row_finish(S, yv, ef, c2.x, c2.y, hc, vc.a, vc.b, p, q);
-        row_finish(S, yv, ef, d2.x, d2.y, hd, vd.a, vd.b, p2, q2);
-        const double fp = p - spc.x, fq = pvc ? 0.0 : q - spc.y;
-        wb.put2(rc + 4, make_double2(p, q));
-        wb.put2(o.RHS + 2 * (int64_t)c0.x,
-                SCALE ? make_double2(fp / vc.c, fq / vc.c) : make_double2(fp, fq));
-        nan |= (fp != fp) | (fq != fq);
-        mx = fmax(mx, fmax(fabs(fp), fabs(fq)));
-        if (two) {
-            const double fp2 = p2 - spd.x, fq2 = pvd ? 0.0 : q2 - spd.y;
+        row_finish(S, yv, ef, qc0, qc1, hc, vc.a, vc.b, p, q);
+        row_finish(S, yv, ef, qd0, qd1, hd, vd.a, vd.b, p2, q2);
+        if (pc >= 0) {  // the slack is not a position
+            const double fp = p - spc, fq = pvc ? 0.0 : q - sqc;
+            wb.put2(rc + 4, make_double2(p, q));
+            wb.put2(o.RHS + 2 * (int64_t)pc,
+                    SCALE ? make_double2(fp / vc.c, fq / vc.c) : make_double2(fp, fq));
+            nan |= (fp != fp) | (fq != fq);
+            mx = fmax(mx, fmax(fabs(fp), fabs(fq)));
+        }
+        if (two && pd >= 0) {
+            const double fp2 = p2 - spd, fq2 = pvd ? 0.0 : q2 - sqd;
             wb.put2(rd + 4, make_double2(p2, q2));
-            wb.put2(o.RHS + 2 * (int64_t)d0.x, SCALE ? make_double2(fp2 / vd.c, fq2 / vd.c)
+            wb.put2(o.RHS + 2 * (int64_t)pd, SCALE ? make_double2(fp2 / vd.c, fq2 / vd.c)
                                                      : make_double2(fp2, fq2));
             nan |= (fp2 != fp2) | (fq2 != fq2);
             mx = fmax(mx, fmax(fabs(fp2), fabs(fq2)));
@@ -1353,7 +1254,6 @@ __device__ void newton_case(const DevSym& S, const double* yv, const int8_t* typ
         const double vm = Vm[i], va = Va[i];
         sincos(va, &sn, &cs);
         wb.put(o.BUS + 8 * (int64_t)i, {vm * cs, vm * sn, vm, va});
-        wb.put2(o.BUS + 8 * (int64_t)i + 6, make_double2(Psp[i], Qsp[i]));
     }
     pv_fill(S, type);
     if (threadIdx.x == 0) s_bad = 0;
@@ -1367,7 +1267,7 @@ __device__ void newton_case(const DevSym& S, const double* yv, const int8_t* typ
     for (;;) {
         double mx = 0.0;
         int nan = 0;
-        mismatch_pass<false>(S, yv, ef, wb, o, pvm, mx, nan);
+        mismatch_pass<false>(S, yv, ef, wb, o, pvm, Psp, Qsp, mx, nan);
         int any_nan = 0;
         nrm = block_max(mx, nan, any_nan);
         if (any_nan || !isfinite(nrm)) {
@@ -1669,7 +1569,6 @@ __device__ void fdpf_case(const DevSym& S, const double* yv, const int8_t* type,
         const double vm = Vm[i], va = Va[i];
         sincos(va, &sn, &cs);
         wb.put(o.BUS + 8 * (int64_t)i, {vm * cs, vm * sn, vm, va});
-        wb.put2(o.BUS + 8 * (int64_t)i + 6, make_double2(Psp[i], Qsp[i]));
     }
     pv_fill_at(fd_pv, S, type);
     __syncthreads();
@@ -1680,7 +1579,7 @@ __device__ void fdpf_case(const DevSym& S, const double* yv, const int8_t* type,
     for (;;) {
         double mx = 0.0;
         int nan = 0;
-        mismatch_pass<true>(S, yv, ef, wb, o, pvm, mx, nan);
+        mismatch_pass<true>(S, yv, ef, wb, o, pvm, Psp, Qsp, mx, nan);
         int any_nan = 0;
         nrm = block_max(mx, nan, any_nan);
         if (any_nan || !isfinite(nrm)) {
