@@ -280,6 +280,31 @@ def bench_fdpf(W, steps):
                      "to 1e-8 + branch flows")
 
 
+def bench_screen(W, outages, steps=3):
+    """N-1 screening on the base pattern (opened branches): fast decoupled
+    first with NR fallback, and NR only, both with branch flows."""
+    from paper_1811_02512_amd import contingency
+
+    P0, Q0 = W.t(W.g.Psp), W.t(W.g.Qsp)
+    out = {}
+    for key, first in (("fdpf_first", True), ("nr_only", False)):
+        box = {}
+
+        def step():
+            box["r"] = contingency.screen(W.sym, W.r, W.x, W.b, W.type, P0, Q0, W.Vm0, W.Va0,
+                                          outages, fdpf_first=first)
+
+        ms = timed(step, steps, 1)
+        res = box["r"]
+        ok = int((res.status == 0).sum().item())
+        out[key] = dict(solves_per_s=ok / ms * 1e3, ms=ms, cases=len(outages), converged=ok,
+                        fallback_to_nr=res.fallback,
+                        mean_iterations=float(res.iters.float().mean().item()))
+        log(f"[bench] N-1 screen {key}: {len(outages)} outages, {ms:.2f} ms, converged {ok}, "
+            f"fallback {res.fallback}")
+    return out
+
+
 def bench_multi(grids, label, steps=3):
     """One launch over cases with their own analyses; returns (solves/s, info)."""
     import torch
@@ -467,6 +492,7 @@ def main():
         outs = gridgen.n1_outages(W.g, 512, 3)
         n1 = [W.g.without_branch(int(e)) for e in outs]
         out["n1_10k_x512"] = bench_multi(n1, "N-1 10k x 512")
+        out["n1_screen_10k_x512"] = bench_screen(W, outs)
         spec = json.load(open(os.path.join(ROOT, "tests", "golden", "mixed_batch.json")))
         mixed = []
         for i, gs in enumerate(spec["grids"]):
