@@ -1416,38 +1416,60 @@ __device__ __forceinline__ void fd_factor_node(const DevSym& S, const NodeRec& r
 }
 
 // Forward substitution and normalisation on component comp of the rhs:
-//   y_j = (1/d_j) (b_j - sum_{i in R(j)} w_ji y_i), levels upward.
+//   y_j = (1/d_j) (b_j - sum_{i in R(j)} w_ji y_i), levels [0, l1) upward.
+// Four entries per lane per batch with the next batch's indices in flight;
+// the node's own b_j and 1/d_j are requested first.
 __device__ __forceinline__ void fd_forward(const DevSym& S, const double* m, const View& wb,
                                            int64_t rhs, int comp, int l1)
 {
     const double2* sl = reinterpret_cast<const double2*>(m + S.fd_lu);
     for_nodes(S, 0, l1, true, [&](int, const NodeRec& rec, int lane, int g) {
+        const int j = rec.a.x, r1 = rec.a.w;
+        const double bj = *wb.at(rhs + 2 * (int64_t)j + comp);
+        const double dj = m[j];
+        int r = rec.a.z + lane;
+        int2 e[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) e[k] = S.rl[r + k * g < r1 ? r + k * g : 0];
         double z = 0.0;
-        for (int r = rec.a.z + lane; r < rec.a.w; r += g) {
-            const int2 e = S.rl[r];
-            z = fma(sl[e.y].x, *wb.at(rhs + 2 * (int64_t)e.x + comp), z);
+        for (; r < r1; r += 4 * g) {
+            double w[4], y[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                w[k] = sl[e[k].y].x;
+                y[k] = *wb.at(rhs + 2 * (int64_t)e[k].x + comp);
+            }
+            const int rn = r + 4 * g;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) e[k] = S.rl[rn + k * g < r1 ? rn + k * g : 0];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (r + k * g < r1) z = fma(w[k], y[k], z);
         }
         if (g > 1) z = gsum(z, g);
-        if (lane == 0) {
-            double* bj = wb.at(rhs + 2 * (int64_t)rec.a.x + comp);
-            *bj = m[rec.a.x] * (*bj - z);
-        }
+        if (lane == 0) *wb.at(rhs + 2 * (int64_t)j + comp) = dj * (bj - z);
     });
 }
 
 // The half step at a bus: ANGLE: theta -= x; else |V| -= x at PQ buses.
 template <bool ANGLE>
-__device__ __forceinline__ void fd_half_step(const View& wb, int64_t bus_off, int bus,
-                                             const PvMask& pv, double x)
+__device__ __forceinline__ void fd_half_step_to(const View& wb, int64_t br, const Blk& v, int bus,
+                                                const PvMask& pv, double x)
 {
-    const int64_t br = bus_off + 8 * (int64_t)bus;
-    const Blk v = wb.blk(br);
     double vm = v.c, va = v.d;
     if (ANGLE) va -= x;
     else if (!pv(bus)) vm -= x;
     double sn, cs;
     sincos(va, &sn, &cs);
     wb.put(br, {vm * cs, vm * sn, vm, va});
+}
+
+template <bool ANGLE>
+__device__ __forceinline__ void fd_half_step(const View& wb, int64_t bus_off, int bus,
+                                             const PvMask& pv, double x)
+{
+    const int64_t br = bus_off + 8 * (int64_t)bus;
+    fd_half_step_to<ANGLE>(wb, br, wb.blk(br), bus, pv, x);
 }
 
 // The top of the tree (the LDS tail's levels) of a factored matrix, copied
@@ -1476,9 +1498,23 @@ __device__ __forceinline__ void fd_forward_tail(const DevSym& S, const double* m
     for (int jl = threadIdx.x; jl < S.tail_nodes; jl += blockDim.x) {
         const int4 a = S.t_node[3 * jl], b = S.t_node[3 * jl + 1];
         double z = *wb.at(rhs + 2 * (int64_t)a.x + comp);
-        for (int r = b.y; r < b.z; ++r) {
-            const int2 e = S.t_rl[r];
-            z = fma(-sl[e.y].x, *wb.at(rhs + 2 * (int64_t)e.x + comp), z);
+        const int r1 = b.z;
+        int r = b.y;
+        int2 e[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) e[k] = S.t_rl[r + k < r1 ? r + k : 0];
+        for (; r < r1; r += 4) {
+            double w[4], y[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                w[k] = sl[e[k].y].x;
+                y[k] = *wb.at(rhs + 2 * (int64_t)e[k].x + comp);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) e[k] = S.t_rl[r + 4 + k < r1 ? r + 4 + k : 0];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (r + k < r1) z = fma(-w[k], y[k], z);
         }
         sy[jl] = z;
     }
@@ -1520,7 +1556,8 @@ __device__ __forceinline__ void fd_backward_tail(const DevSym& S, const FdTail& 
 }
 
 // Backward substitution x_j = y_j - sum_{k in S(j)} u_jk x_k, levels
-// downward, and the half step at bus(j).
+// downward, and the half step at bus(j); four slots per lane per batch with
+// the next batch's indices in flight.
 template <bool ANGLE>
 __device__ __forceinline__ void fd_backward(const DevSym& S, const double* m, const View& wb,
                                             int64_t rhs, int64_t bus_off, const PvMask& pv,
@@ -1529,14 +1566,31 @@ __device__ __forceinline__ void fd_backward(const DevSym& S, const double* m, co
     const double2* sl = reinterpret_cast<const double2*>(m + S.fd_lu);
     const int comp = ANGLE ? 0 : 1;
     for_nodes(S, 0, l1, false, [&](int, const NodeRec& rec, int lane, int g) {
+        const int s1 = rec.b.y;
+        const double yj = *wb.at(rhs + 2 * (int64_t)rec.a.x + comp);
+        int s = rec.b.x + lane;
+        int kk[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) kk[k] = S.Li[s + k * g < s1 ? s + k * g : 0];
         double a = 0.0;
-        for (int s = rec.b.x + lane; s < rec.b.y; s += g)
-            a = fma(sl[s].y, *wb.at(rhs + 2 * (int64_t)S.Li[s] + comp), a);
+        for (; s < s1; s += 4 * g) {
+            double u[4], x[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                u[k] = sl[s + k * g < s1 ? s + k * g : 0].y;
+                x[k] = *wb.at(rhs + 2 * (int64_t)kk[k] + comp);
+            }
+            const int sn = s + 4 * g;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) kk[k] = S.Li[sn + k * g < s1 ? sn + k * g : 0];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (s + k * g < s1) a = fma(u[k], x[k], a);
+        }
         if (g > 1) a = gsum(a, g);
         if (lane == 0) {
-            double* yj = wb.at(rhs + 2 * (int64_t)rec.a.x + comp);
-            const double xj = *yj - a;
-            *yj = xj;
+            const double xj = yj - a;
+            *wb.at(rhs + 2 * (int64_t)rec.a.x + comp) = xj;
             fd_half_step<ANGLE>(wb, bus_off, rec.a.y, pv, xj);
         }
     });
