@@ -236,6 +236,35 @@ def cpu_baseline(W, wall_s=15.0):
                        f"{sum(s == 0 for s in sts)}/{count}")
 
 
+def bench_graph(W, steps):
+    """The whole step (Ybus, batched NR keeping the factors, adjoint) captured
+    once in a HIP graph and replayed; every replay's outputs are checked
+    against the eager step's."""
+    import torch
+
+    W.step()
+    torch.cuda.synchronize()
+    ref = (W.Vm.clone(), W.gP.clone(), W.gx.clone())
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        W.step()  # warm the allocator on the capture stream
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        W.step()
+    for _ in range(2):
+        graph.replay()
+        torch.cuda.synchronize()
+        same = (torch.equal(W.Vm, ref[0]) and torch.equal(W.gP, ref[1])
+                and torch.equal(W.gx, ref[2]))
+        assert same, "graph replay differs from the eager step"
+    ms = timed(graph.replay, steps, 1)
+    log(f"[bench] graph replay of the step: {ms:.3f} ms")
+    return dict(solves_per_s=W.B / ms * 1e3, ms_per_step=ms, replays_checked=2)
+
+
 def bench_fdpf(W, steps):
     """Fast decoupled power flow on the workload's grid and scenarios: one
     step = B' and B'' built and factored once for the batch (shared
@@ -424,6 +453,7 @@ def main():
     plain_ms = timed(lambda: W.step(adjoint=False, Bn=1), max(3, args.steps // 2), 1)
 
     fdpf = bench_fdpf(W, max(3, args.steps // 2))
+    graph = bench_graph(W, max(3, args.steps // 2))
 
     b_it = survey_bytes_per_iter(info)
     units = float(iters.sum())
@@ -462,6 +492,7 @@ def main():
             "from_file": bool(args.settings)},
         "kernel_sources": kernel_source_hash(),
         "fdpf_10k_x256": fdpf,
+        "graph_replay": graph,
         "roofline": {
             "bound": "hbm",
             "achieved": achieved,
