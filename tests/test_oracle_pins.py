@@ -789,3 +789,85 @@ def test_branch_flows_kcl_and_series_losses(oracle, n, seed):
     np.testing.assert_allclose(
         Qft + Qtf, g.x * np.abs(i_series) ** 2 - g.b / 2 * (r.Vm[g.f] ** 2 + r.Vm[g.t] ** 2),
         rtol=1e-9, atol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# WLS state estimation
+# --------------------------------------------------------------------------
+def _se():
+    from oracle import se
+
+    return se
+
+
+def test_se_jacobian_matches_finite_differences(oracle):
+    se = _se()
+    g = gridgen.make_grid(30, 2)
+    Y = oracle.grid_ybus(g)
+    rng = np.random.default_rng(1)
+    Vm = 1 + 0.05 * rng.standard_normal(g.n)
+    Va = 0.1 * rng.standard_normal(g.n)
+    kinds, locs = se.full_measurement_set(g)
+    H = se.jacobian(g, Y, Vm, Va, kinds, locs).toarray()
+    h = 1e-6
+    cols = [("a", b) for b in range(1, g.n)] + [("m", b) for b in range(g.n)]
+    for c, (which, b) in enumerate(cols):
+        Vp, Ap, Vn, An = Vm.copy(), Va.copy(), Vm.copy(), Va.copy()
+        if which == "a":
+            Ap[b] += h
+            An[b] -= h
+        else:
+            Vp[b] += h
+            Vn[b] -= h
+        fd = (se.measure(g, Y, Vp, Ap, kinds, locs) - se.measure(g, Y, Vn, An, kinds, locs)) / (2 * h)
+        np.testing.assert_allclose(H[:, c], fd, rtol=0, atol=1e-6)
+
+
+def test_se_recovers_the_power_flow_state(oracle):
+    """Noise-free measurements of a solved power flow: the estimate is that
+    state (the estimator and the power flow share no step)."""
+    se = _se()
+    g = gridgen.make_grid(200, 3)
+    ref = oracle.solve_grid(g)
+    kinds, locs = se.full_measurement_set(g)
+    z = se.measure(g, oracle.grid_ybus(g), ref.Vm, ref.Va, kinds, locs)
+    w = np.where(kinds == se.VM, 1 / 0.004 ** 2, 1 / 0.01 ** 2)
+    r = se.estimate(g, kinds, locs, z, w, np.ones(g.n), np.zeros(g.n))
+    assert r.status == 0
+    np.testing.assert_allclose(r.Vm, ref.Vm, rtol=0, atol=1e-10)
+    np.testing.assert_allclose(r.Va, ref.Va, rtol=0, atol=1e-10)
+
+
+def test_se_step_is_the_least_squares_step(oracle):
+    se = _se()
+    g = gridgen.make_grid(30, 4)
+    Y = oracle.grid_ybus(g)
+    kinds, locs = se.full_measurement_set(g)
+    rng = np.random.default_rng(2)
+    Vm, Va = 1 + 0.02 * rng.standard_normal(g.n), 0.05 * rng.standard_normal(g.n)
+    z = se.measure(g, Y, Vm, Va, kinds, locs) + 0.01 * rng.standard_normal(len(kinds))
+    w = rng.uniform(100, 10000, len(kinds))
+    H = se.jacobian(g, Y, np.ones(g.n), np.zeros(g.n), kinds, locs).toarray()
+    res = z - se.measure(g, Y, np.ones(g.n), np.zeros(g.n), kinds, locs)
+    dx_ne = np.linalg.solve(H.T @ (w[:, None] * H), H.T @ (w * res))
+    dx_ls = np.linalg.lstsq(np.sqrt(w)[:, None] * H, np.sqrt(w) * res, rcond=None)[0]
+    np.testing.assert_allclose(dx_ne, dx_ls, rtol=1e-8, atol=1e-10)
+    r1 = se.estimate(g, kinds, locs, z, w, np.ones(g.n), np.zeros(g.n), max_iter=1)
+    np.testing.assert_allclose(r1.Vm - 1.0, dx_ls[g.n - 1:], rtol=1e-8, atol=1e-10)
+
+
+def test_se_optimality_with_noise(oracle):
+    """At the noisy estimate the weighted residual is orthogonal to H."""
+    se = _se()
+    g = gridgen.make_grid(200, 5)
+    ref = oracle.solve_grid(g)
+    Y = oracle.grid_ybus(g)
+    kinds, locs = se.full_measurement_set(g)
+    sig = np.where(kinds == se.VM, 0.004, 0.01)
+    z = se.measure(g, Y, ref.Vm, ref.Va, kinds, locs)
+    z = z + sig * np.random.default_rng(7).standard_normal(len(z))
+    r = se.estimate(g, kinds, locs, z, 1 / sig ** 2, np.ones(g.n), np.zeros(g.n))
+    assert r.status == 0
+    H = se.jacobian(g, Y, r.Vm, r.Va, kinds, locs)
+    grad = H.T @ ((z - se.measure(g, Y, r.Vm, r.Va, kinds, locs)) / sig ** 2)
+    assert np.abs(grad).max() < 1e-6 * np.abs(H.T @ (z / sig ** 2)).max()
