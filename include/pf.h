@@ -292,6 +292,53 @@ int pf_branch_flows(const pf_symbolic sym, int B, const double* d_r, const doubl
                     const double* d_Va, int64_t v_stride, double* d_Pft, double* d_Qft,
                     double* d_Ptf, double* d_Qtf, int64_t out_stride, void* stream);
 
+/* ---- WLS state estimation ---------------------------------------------------
+ * Sec. IV lists state estimation among the applications run on the same
+ * graph machinery; the paper gives no formulation, so this is the textbook
+ * weighted-least-squares estimator (our reading).  Measurements
+ * z = h(x) + e, kind PF_MEAS_*: |V_i|, P_i, Q_i (bus loc), P_ft, Q_ft (flow
+ * at the from end of branch loc), weights w = 1/sigma^2.  State x = (theta
+ * of every bus but the reference (the slack argument), |V| of every bus).
+ * Gauss-Newton: G dx = H^T W (z - h(x)), G = H^T W H, x += dx, until the
+ * step's max|dx| < tol.  G is a 2x2 block per pair of buses that share a
+ * measurement; pf_se_analyze runs the library's analysis (minimum degree,
+ * filled graph, elimination tree, levels) on that graph and plans the
+ * assembly; each step assembles G in the filled layout, then runs the
+ * pf_factor and pf_solve kernels on it.
+ * pf_se_analyze: host arrays (network as pf_analyze; kind int8[M], loc
+ * int32[M]); PF_E_INVALID on bad input, PF_E_DISCONNECTED when the
+ * measurements leave buses unobservable.  pf_se_upload as
+ * pf_symbolic_upload (info.dev_bytes, 256-byte aligned).                   */
+enum { PF_MEAS_VM = 1, PF_MEAS_P = 2, PF_MEAS_Q = 3, PF_MEAS_PF = 4, PF_MEAS_QF = 5 };
+typedef struct pf_se_s* pf_se;
+typedef struct {
+    int32_t n, m;
+    int32_t measurements;
+    int64_t partials;        /* entries of H (measurement, support bus) pairs */
+    int64_t gain_nnz_l;      /* off-diagonal blocks of the factored G       */
+    int32_t gain_levels;
+    int64_t contributions;   /* (measurement, bus pair) terms of G           */
+    int64_t ws_doubles;      /* pf_se_estimate workspace per case            */
+    size_t dev_bytes;
+} pf_se_dims;
+int pf_se_analyze(int n, int m, const int32_t* from, const int32_t* to, int slack, int M,
+                  const int8_t* kind, const int32_t* loc, pf_se* out);
+int pf_se_info(const pf_se se, pf_se_dims* info);
+int pf_se_upload(pf_se se, void* d_buf, size_t bytes, void* stream);
+/* B cases: branch arrays as pf_build_ybus; d_z, d_w double[B][M] (z_stride,
+ * 0 = shared); d_Vm/d_Va in = start, out = estimate (v_stride); d_ws
+ * ws_stride >= ws_doubles (a multiple of 8), 16-byte aligned; d_iters,
+ * d_norm (last max|dx|), d_status[B] (PF_OK, PF_E_NOT_CONVERGED,
+ * PF_E_NONFINITE, the latter also for a singular gain matrix).  The host
+ * waits for the stream once per Gauss-Newton step to stop when every case
+ * has finished.                                                            */
+int pf_se_estimate(const pf_se se, int B, const double* d_r, const double* d_x,
+                   const double* d_b, int64_t branch_stride, const double* d_z,
+                   const double* d_w, int64_t z_stride, double* d_Vm, double* d_Va,
+                   int64_t v_stride, double tol, int max_iter, double* d_ws, int64_t ws_stride,
+                   int32_t* d_iters, double* d_norm, int32_t* d_status, void* stream);
+void pf_se_destroy(pf_se se);
+
 /* ---- adjoint right-hand side (beyond the paper) ----------------------------
  * Gathers the loss gradient with respect to the state into position order:
  * d_rhs[b][p] = (dL/dtheta, dL/d|V|) of bus perm[p], with the |V| entry set

@@ -52,6 +52,13 @@ import torch  # noqa: E402,F401
 lib = C.CDLL(LIB_PATH)
 
 _vp, _i, _i64, _d = C.c_void_p, C.c_int, C.c_int64, C.c_double
+class pf_se_dims(C.Structure):
+    _fields_ = [("n", C.c_int32), ("m", C.c_int32), ("measurements", C.c_int32),
+                ("partials", C.c_int64), ("gain_nnz_l", C.c_int64), ("gain_levels", C.c_int32),
+                ("contributions", C.c_int64), ("ws_doubles", C.c_int64),
+                ("dev_bytes", C.c_size_t)]
+
+
 _SIGS = {
     "pf_version": ([], C.c_char_p),
     "pf_status_string": ([_i], C.c_char_p),
@@ -90,6 +97,12 @@ _SIGS = {
                  _i, _vp, _i64, _vp, _vp, _vp, _vp], _i),
     "pf_branch_flows": ([_vp, _i, _vp, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp,
                          _i64, _vp], _i),
+    "pf_se_analyze": ([_i, _i, _vp, _vp, _i, _i, _vp, _vp, C.POINTER(_vp)], _i),
+    "pf_se_info": ([_vp, C.POINTER(pf_se_dims)], _i),
+    "pf_se_upload": ([_vp, _vp, C.c_size_t, _vp], _i),
+    "pf_se_estimate": ([_vp, _i, _vp, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _d, _i, _vp,
+                        _i64, _vp, _vp, _vp, _vp], _i),
+    "pf_se_destroy": ([_vp], None),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(lib, _name)
@@ -313,3 +326,42 @@ def pf_branch_flows(h, B, r, x, b, branch_stride, Vm, Va, v_stride, Pft, Qft, Pt
     check(lib.pf_branch_flows(h, B, ptr(r), ptr(x), ptr(b), branch_stride, ptr(Vm), ptr(Va),
                               v_stride, ptr(Pft), ptr(Qft), ptr(Ptf), ptr(Qtf), out_stride,
                               stream_ptr(stream)), "pf_branch_flows")
+
+
+PF_MEAS_VM, PF_MEAS_P, PF_MEAS_Q, PF_MEAS_PF, PF_MEAS_QF = 1, 2, 3, 4, 5
+
+
+def pf_se_analyze(n, from_, to, slack, kind, loc):
+    """Host arrays in; returns a pf_se handle (release with pf_se_destroy)."""
+    import numpy as _np
+
+    f = _np.ascontiguousarray(from_, _np.int32)
+    t = _np.ascontiguousarray(to, _np.int32)
+    k = _np.ascontiguousarray(kind, _np.int8)
+    l = _np.ascontiguousarray(loc, _np.int32)
+    h = _vp()
+    check(lib.pf_se_analyze(n, len(f), f.ctypes.data, t.ctypes.data, slack, len(k), k.ctypes.data,
+                            l.ctypes.data, C.byref(h)), "pf_se_analyze")
+    return h
+
+
+def pf_se_info(h):
+    d = pf_se_dims()
+    check(lib.pf_se_info(h, C.byref(d)), "pf_se_info")
+    return d
+
+
+def pf_se_upload(h, buf, nbytes, stream=None):
+    check(lib.pf_se_upload(h, ptr(buf), nbytes, stream_ptr(stream)), "pf_se_upload")
+
+
+def pf_se_estimate(h, B, r, x, b, branch_stride, z, w, z_stride, Vm, Va, v_stride, tol, max_iter,
+                   ws, ws_stride, iters, norm, status, stream=None):
+    check(lib.pf_se_estimate(h, B, ptr(r), ptr(x), ptr(b), branch_stride, ptr(z), ptr(w),
+                             z_stride, ptr(Vm), ptr(Va), v_stride, tol, max_iter, ptr(ws),
+                             ws_stride, ptr(iters), ptr(norm), ptr(status), stream_ptr(stream)),
+          "pf_se_estimate")
+
+
+def pf_se_destroy(h):
+    lib.pf_se_destroy(h)

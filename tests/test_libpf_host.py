@@ -169,3 +169,29 @@ def test_single_hip_runtime_whatever_the_import_order():
                          timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_state_estimation_analysis_sizes_and_errors():
+    """The WLS plan: one partial per (measurement, support bus), the gain
+    graph spans every bus, and unobservable or malformed sets are refused."""
+    from oracle import se
+
+    from paper_1811_02512_amd import binding as B
+
+    g = gridgen.make_grid(60, 2)
+    kinds, locs = se.full_measurement_set(g)
+    h = B.pf_se_analyze(g.n, g.f, g.t, 0, kinds, locs)
+    d = B.pf_se_info(h)
+    deg = np.bincount(np.concatenate([g.f, g.t]), minlength=g.n)
+    assert d.measurements == 3 * g.n + 2 * g.m
+    assert d.partials == g.n + 2 * (g.n + deg.sum()) + 4 * g.m
+    assert d.gain_levels > 0 and d.gain_nnz_l > 0 and d.ws_doubles % 32 == 0
+    B.pf_se_destroy(h)
+    only_v = np.full(g.n, B.PF_MEAS_VM, np.int8)
+    with pytest.raises(B.PfError, match="unobservable"):
+        B.pf_se_analyze(g.n, g.f, g.t, 0, only_v, np.arange(g.n))
+    with pytest.raises(B.PfError):
+        B.pf_se_analyze(g.n, g.f, g.t, 0, np.array([9], np.int8), np.array([0]))
+    with pytest.raises(B.PfError):
+        B.pf_se_analyze(g.n, g.f, g.t, 0, np.array([B.PF_MEAS_PF], np.int8),
+                        np.array([g.m + 3]))
