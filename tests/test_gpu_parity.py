@@ -273,7 +273,7 @@ def test_launch_shapes_and_lds_tail(O, threads, budget):
     s = staged(2000, 2)
     g = s.g
     s.sym.set_launch(threads, budget)
-    info = s.info
+    info = s.sym.info
     log(f"[launch] threads={threads} budget={budget} tail_levels={info.tail_levels} "
         f"tail_nodes={info.tail_nodes} lds={info.tail_lds_bytes}")
     ref = O.solve_grid(g)
