@@ -51,6 +51,16 @@ constexpr int kMaxThreads = 1024;
 // registers without spilling.
 constexpr int kLevelThreads = 512;
 constexpr int kXcds = 8;
+constexpr int kWave = 64;  // CDNA wavefront
+
+// Orders the LDS accesses of one wavefront's lanes (they run in lockstep,
+// and a wavefront's LDS operations are performed in issue order).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // One case's doubles inside an interleaved group of C cases: element d
 // lives at base + (d / K) * K C + K (case % C) + d % K, i.e. chunks of K
@@ -926,10 +936,13 @@ __device__ void tail_factor(const DevSym& S, const SRC& src, const View& w, int6
             }
         }
         __syncthreads();
-        // phase D: dense right-looking over the clique's pivots
+        // phase D: dense right-looking over the clique's pivots.  Pivots with a
+        // large trailing block use every thread, one barrier each; the last
+        // ones (at most two updates per lane of one wavefront) run on the
+        // first wavefront alone, without workgroup barriers.
         Blk Dprev = bzero();
         double yp0 = 0.0, yp1 = 0.0;
-        for (int a = 0; a <= KC; ++a) {
+        auto pivot = [&](int a, int stride) {
             const int m = KC - 1 - a;  // trailing size
             Blk Di = bzero();
             double ya0 = 0.0, ya1 = 0.0;
@@ -942,9 +955,10 @@ __device__ void tail_factor(const DevSym& S, const SRC& src, const View& w, int6
             }
             const int nupd = (a < KC) ? m * m : 0;
             const int nnorm = (a > 0) ? (KC - a) + 1 : 0;  // row a-1 slots + its pivot
-            for (int it = threadIdx.x; it < nupd + nnorm; it += blockDim.x) {
+            for (int it = threadIdx.x; it < nupd + nnorm; it += stride) {
                 if (it < nupd) {
-                    const int k = a + 1 + it / m, l = a + 1 + it % m;
+                    const unsigned q = (unsigned)it / (unsigned)m;
+                    const int k = a + 1 + (int)q, l = a + 1 + (it - (int)q * m);
                     const Blk Wka = bload(sLU + 8 * clique_slot(c0, KC, a, k));
                     const Blk Ual = bmul(Di, bload(sLU + 8 * clique_slot(c0, KC, a, l) + 4));
                     const int jk = kf + k;
@@ -985,8 +999,19 @@ __device__ void tail_factor(const DevSym& S, const SRC& src, const View& w, int6
             Dprev = Di;
             yp0 = ya0;
             yp1 = ya1;
+        };
+        int a = 0;
+        for (; a <= KC && (KC - 1 - a) * (KC - 1 - a) > 2 * kWave; ++a) {
+            pivot(a, blockDim.x);
             __syncthreads();
         }
+        if (threadIdx.x < kWave) {
+            for (int b = a; b <= KC; ++b) {
+                pivot(b, kWave);
+                wave_sync();
+            }
+        }
+        __syncthreads();
     }
     if (WRITE) {
         for (int t = threadIdx.x; t < TS; t += blockDim.x) {
@@ -1021,10 +1046,12 @@ __device__ __forceinline__ void apply_step(const View& w, int64_t rec, bool pv, 
     apply_step_to(w, rec, w.blk(rec), pv, x0, x1);
 }
 
-// Backward substitution of the tail from LDS: x_j = y_j - sum U_jk x_k, the
-// x of tail nodes also written to the rhs for the levels below.  The clique
-// goes first, column-oriented: once x_a is final, y_k -= U_ka x_a for all
-// clique nodes k below a in parallel, one barrier per pivot.
+// Backward substitution of the tail from LDS: x_j = y_j - sum U_jk x_k.  The
+// clique goes first, on the first wavefront alone, column-oriented: once x_a
+// is final, y_k -= U_ka x_a for every clique node k below a.  The x of the
+// tail nodes are written to the rhs (for the levels below) and, with UPDATE,
+// applied to the bus records in one parallel pass at the end, so that no
+// level waits for a bus-record load.
 template <bool UPDATE>
 __device__ void tail_backward(const DevSym& S, const View& w, int64_t rhs, int64_t bus_off,
                               PvMask type)
@@ -1034,26 +1061,22 @@ __device__ void tail_backward(const DevSym& S, const View& w, int64_t rhs, int64
     const double* sLU = pf_smem;
     double* sy = pf_smem + 8 * TS + 4 * K;
     if (KC > 0) {
-        const int kf = K - KC;
-        const int c0 = S.t_node[3 * kf].w;
-        for (int a = KC - 1; a >= 0; --a) {
-            const int ja = kf + a;
-            const double x0 = sy[2 * ja], x1 = sy[2 * ja + 1];
-            for (int k = threadIdx.x; k <= a; k += blockDim.x) {
-                if (k < a) {
+        if (threadIdx.x < kWave) {
+            const int kf = K - KC;
+            const int c0 = S.t_node[3 * kf].w;
+            for (int a = KC - 1; a > 0; --a) {
+                const int ja = kf + a;
+                const double x0 = sy[2 * ja], x1 = sy[2 * ja + 1];
+                for (int k = threadIdx.x; k < a; k += kWave) {
                     const int jk = kf + k;
                     const Blk U = bload(sLU + 8 * clique_slot(c0, KC, k, a) + 4);
                     sy[2 * jk] = fma(-U.a, x0, fma(-U.b, x1, sy[2 * jk]));
                     sy[2 * jk + 1] = fma(-U.c, x0, fma(-U.d, x1, sy[2 * jk + 1]));
-                } else {
-                    const int4 t0 = S.t_node[3 * ja];
-                    w.put2(rhs + 2 * (int64_t)t0.x, make_double2(x0, x1));
-                    if (UPDATE)
-                        apply_step(w, bus_off + 8 * (int64_t)t0.y, type(t0.y), x0, x1);
                 }
+                wave_sync();
             }
-            __syncthreads();
         }
+        __syncthreads();
     }
     for_tail_range(S, 0, nT - KC, false, [&](int jl, int lane, int g) {
         const int4 t0 = S.t_node[3 * jl];
@@ -1068,13 +1091,17 @@ __device__ void tail_backward(const DevSym& S, const View& w, int64_t rhs, int64
             a1 = gsum(a1, g);
         }
         if (lane == 0) {
-            const double x0 = sy[2 * jl] - a0, x1 = sy[2 * jl + 1] - a1;
-            sy[2 * jl] = x0;
-            sy[2 * jl + 1] = x1;
-            w.put2(rhs + 2 * (int64_t)t0.x, make_double2(x0, x1));
-            if (UPDATE) apply_step(w, bus_off + 8 * (int64_t)t0.y, type(t0.y), x0, x1);
+            sy[2 * jl] -= a0;
+            sy[2 * jl + 1] -= a1;
         }
     });
+    for (int jl = threadIdx.x; jl < K; jl += blockDim.x) {
+        const int4 t0 = S.t_node[3 * jl];
+        const double x0 = sy[2 * jl], x1 = sy[2 * jl + 1];
+        w.put2(rhs + 2 * (int64_t)t0.x, make_double2(x0, x1));
+        if (UPDATE) apply_step(w, bus_off + 8 * (int64_t)t0.y, type(t0.y), x0, x1);
+    }
+    __syncthreads();
 }
 
 // Backward substitution of node record x: x_j = y_j - sum_{k in S(j)} U_jk x_k,
@@ -1532,8 +1559,9 @@ __device__ __forceinline__ void fd_forward_tail(const DevSym& S, const double* m
     });
 }
 
-// Backward substitution of the tail levels in LDS, downward; each tail x is
-// written to the rhs for the levels below and its bus takes the half step.
+// Backward substitution of the tail levels in LDS, downward; then, in one
+// parallel pass (so that no level waits for a bus-record load), each tail x
+// is written to the rhs for the levels below and its bus takes the half step.
 template <bool ANGLE>
 __device__ __forceinline__ void fd_backward_tail(const DevSym& S, const FdTail& t, double* sy,
                                                  const View& wb, int64_t rhs, int64_t bus_off,
@@ -1546,13 +1574,16 @@ __device__ __forceinline__ void fd_backward_tail(const DevSym& S, const FdTail& 
         double s = 0.0;
         for (int q = a.w + lane; q < b.x; q += g) s = fma(t.wu[q].y, sy[S.t_slot[3 * q].y], s);
         if (g > 1) s = gsum(s, g);
-        if (lane == 0) {
-            const double x = sy[jl] - s;
-            sy[jl] = x;
-            *wb.at(rhs + 2 * (int64_t)a.x + comp) = x;
-            fd_half_step<ANGLE>(wb, bus_off, a.y, pv, x);
-        }
+        if (lane == 0) sy[jl] -= s;
     });
+    __syncthreads();
+    for (int jl = threadIdx.x; jl < S.tail_nodes; jl += blockDim.x) {
+        const int4 a = S.t_node[3 * jl];
+        const double x = sy[jl];
+        *wb.at(rhs + 2 * (int64_t)a.x + comp) = x;
+        fd_half_step<ANGLE>(wb, bus_off, a.y, pv, x);
+    }
+    __syncthreads();
 }
 
 // Backward substitution x_j = y_j - sum_{k in S(j)} u_jk x_k, levels
@@ -2058,20 +2089,28 @@ __global__ void k_fd_matrices(DevSym S, const double* __restrict__ r,
 }
 
 // In-place LDL^T of B' and B'' of case blockIdx.x, level by level.
+// Two workgroups per case, one per matrix (B' and B'' are independent).  The
+// status is set to OK by k_fill_status beforehand; a workgroup that meets a
+// zero pivot stores ST_ZERO_PIVOT (both may, with the same value).
 __global__ __launch_bounds__(kLevelThreads) void k_fd_factor(DevSym S, double* mat,
                                                              int64_t mstride, int32_t* status)
 {
     __shared__ int s_bad;
-    const int c = blockIdx.x;
+    const int c = blockIdx.x >> 1, which = blockIdx.x & 1;
     if (threadIdx.x == 0) s_bad = 0;
     __syncthreads();
-    for (int which = 0; which < 2; ++which) {
-        double* m = mat + c * mstride + which * S.fd_mat;
-        for_nodes(S, 0, S.nlev, true, [&](int, const NodeRec& rec, int lane, int g) {
-            fd_factor_node(S, rec, lane, g, m, &s_bad);
-        });
-    }
-    if (threadIdx.x == 0 && status) status[c] = s_bad ? ST_ZERO_PIVOT : ST_OK;
+    double* m = mat + c * mstride + which * S.fd_mat;
+    for_nodes(S, 0, S.nlev, true, [&](int, const NodeRec& rec, int lane, int g) {
+        fd_factor_node(S, rec, lane, g, m, &s_bad);
+    });
+    __syncthreads();
+    if (threadIdx.x == 0 && status && s_bad) status[c] = ST_ZERO_PIVOT;
+}
+
+__global__ void k_fill_status(int B, int32_t* status, int32_t v)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < B) status[c] = v;
 }
 
 __global__ __launch_bounds__(kLevelThreads) void k_fdpf(DevSym S, NewtonArgs a,
@@ -2982,7 +3021,10 @@ int pf_fdpf_factor(const pf_symbolic s, int B, double* d_mat, int64_t mat_stride
     if (B > 1 && mat_stride < 2 * s->h.fd_mat())
         return fail(PF_E_WORKSPACE, "pf_fdpf_factor: mat_stride < fd_mat_doubles");
     if (B == 0) return PF_OK;
-    hipLaunchKernelGGL(k_fd_factor, dim3(B), dim3(launch_threads(s->h, B)), 0,
+    if (d_status)
+        hipLaunchKernelGGL(k_fill_status, dim3((B + 255) / 256), dim3(256), 0, as_stream(stream),
+                           B, d_status, (int32_t)ST_OK);
+    hipLaunchKernelGGL(k_fd_factor, dim3(2 * B), dim3(launch_threads(s->h, B)), 0,
                        as_stream(stream), s->h.dev, d_mat, mat_stride, d_status);
     return launch_check("pf_fdpf_factor");
 }
