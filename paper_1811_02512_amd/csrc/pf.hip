@@ -52,6 +52,7 @@ constexpr int kMaxThreads = 1024;
 constexpr int kLevelThreads = 512;
 constexpr int kXcds = 8;
 constexpr int kWave = 64;  // CDNA wavefront
+constexpr size_t kSolveLdsMax = 159 * 1024;  // of the 160 KB of LDS per workgroup on gfx950
 
 // Orders the LDS accesses of one wavefront's lanes (they run in lockstep,
 // and a wavefront's LDS operations are performed in issue order).
@@ -1855,8 +1856,13 @@ __global__ __launch_bounds__(kLevelThreads) void k_factor(DevSym S, double* vals
 //                x_j = y_j - sum_{k in S(j)} U_jk x_k            (levels down).
 // transpose = 1: p_j = g_j - sum_{i in R(j)} U_ij^T p_i           (levels up),
 //                l_j = D_j^-T (p_j - sum_{k in S(j)} W_kj^T l_k)  (levels down).
-template <bool TRANS>
-__global__ __launch_bounds__(kMaxThreads) void k_solve(DevSym S, const double* vals,
+// A node's g lanes take its list entries in strides of g, four per lane per
+// step with the step's blocks and x values requested together; absent
+// entries of a step re-read the node's first entry (in bounds whenever the
+// list is not empty) and add nothing.  LDSX keeps the case's whole vector
+// in LDS (nn x 16 bytes) for the two sweeps.
+template <bool TRANS, bool LDSX>
+__global__ __launch_bounds__(kLevelThreads) void k_solve(DevSym S, const double* vals,
                                                        int64_t vals_stride, int C, int B,
                                                        double* rhs, int64_t rhs_stride)
 {
@@ -1864,15 +1870,36 @@ __global__ __launch_bounds__(kMaxThreads) void k_solve(DevSym S, const double* v
     if (c < 0) return;
     const View w = case_view(const_cast<double*>(vals), vals_stride, C, c);
     const int64_t lu = S.lu_off;
-    double2* x2 = reinterpret_cast<double2*>(rhs + c * rhs_stride);
-    for_levels(S, 0, S.nlev, true, [&](int xi, int lane, int g) {
-        const int j = S.level_nodes[xi];
+    double2* xg = reinterpret_cast<double2*>(rhs + c * rhs_stride);
+    double2* x2 = LDSX ? reinterpret_cast<double2*>(pf_smem) : xg;
+    if (LDSX) {
+        for (int p = threadIdx.x; p < S.nn; p += blockDim.x) x2[p] = xg[p];
+        __syncthreads();
+    }
+    for_nodes(S, 0, S.nlev, true, [&](int, const NodeRec& rec, int lane, int g) {
+        const int j = rec.a.x, r0 = rec.a.z, r1 = rec.a.w;
         double z0 = 0.0, z1 = 0.0;
-        for (int r = S.Rp[j] + lane; r < S.Rp[j + 1]; r += g) {
-            const double2 xv = x2[S.Ri[r]];
-            const Blk M = w.blk(lu + 8 * (int64_t)S.Rs[r] + (TRANS ? 4 : 0));
-            if (TRANS) mtvadd(z0, z1, M, xv.x, xv.y);
-            else mvadd(z0, z1, M, xv.x, xv.y);
+        for (int base = r0 + lane; base < r1; base += 4 * g) {
+            int2 e[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int r = base + k * g;
+                e[k] = S.rl[r < r1 ? r : r0];
+            }
+            Blk M[4];
+            double2 xv[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                M[k] = w.blk(lu + 8 * (int64_t)e[k].y + (TRANS ? 4 : 0));
+                xv[k] = x2[e[k].x];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (base + k * g < r1) {
+                    if (TRANS) mtvadd(z0, z1, M[k], xv[k].x, xv[k].y);
+                    else mvadd(z0, z1, M[k], xv[k].x, xv[k].y);
+                }
+            }
         }
         if (g > 1) {
             z0 = gsum(z0, g);
@@ -1891,14 +1918,31 @@ __global__ __launch_bounds__(kMaxThreads) void k_solve(DevSym S, const double* v
             x2[j] = make_double2(u0, u1);
         }
     });
-    for_levels(S, 0, S.nlev, false, [&](int xi, int lane, int g) {
-        const int j = S.level_nodes[xi];
+    for_nodes(S, 0, S.nlev, false, [&](int, const NodeRec& rec, int lane, int g) {
+        const int j = rec.a.x, s0 = rec.b.x, s1 = rec.b.y;
         double a0 = 0.0, a1 = 0.0;
-        for (int s = S.Lp[j] + lane; s < S.Lp[j + 1]; s += g) {
-            const double2 xk = x2[S.Li[s]];
-            const Blk M = w.blk(lu + 8 * (int64_t)s + (TRANS ? 0 : 4));
-            if (TRANS) mtvadd(a0, a1, M, xk.x, xk.y);
-            else mvadd(a0, a1, M, xk.x, xk.y);
+        for (int base = s0 + lane; base < s1; base += 4 * g) {
+            int sk[4], kk[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int s = base + k * g;
+                sk[k] = s < s1 ? s : s0;
+                kk[k] = S.Li[sk[k]];
+            }
+            Blk M[4];
+            double2 xv[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                M[k] = w.blk(lu + 8 * (int64_t)sk[k] + (TRANS ? 0 : 4));
+                xv[k] = x2[kk[k]];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (base + k * g < s1) {
+                    if (TRANS) mtvadd(a0, a1, M[k], xv[k].x, xv[k].y);
+                    else mvadd(a0, a1, M[k], xv[k].x, xv[k].y);
+                }
+            }
         }
         if (g > 1) {
             a0 = gsum(a0, g);
@@ -1917,6 +1961,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_solve(DevSym S, const double* v
             x2[j] = make_double2(u0, u1);
         }
     });
+    if (LDSX)
+        for (int p = threadIdx.x; p < S.nn; p += blockDim.x) xg[p] = x2[p];
 }
 
 template <bool MULTI>
@@ -2466,7 +2512,9 @@ void allow_big_lds()
     }
     const void* kernels[] = {reinterpret_cast<const void*>(&k_newton<false>),
                              reinterpret_cast<const void*>(&k_newton<true>),
-                             reinterpret_cast<const void*>(&k_factor)};
+                             reinterpret_cast<const void*>(&k_factor),
+                             reinterpret_cast<const void*>(&k_solve<false, true>),
+                             reinterpret_cast<const void*>(&k_solve<true, true>)};
     for (const void* k : kernels) {
         hipFuncAttributes fa{};
         if (hipFuncGetAttributes(&fa, k) == hipSuccess) {
@@ -2954,12 +3002,21 @@ int pf_solve(const pf_symbolic s, int B, const double* d_vals, int64_t vals_stri
         return fail(PF_E_WORKSPACE, "pf_solve: rhs_stride < 2*nn");
     if (B == 0) return PF_OK;
     const dim3 grid(grid_blocks(B, vals_interleave)), block(launch_threads(s->h, B));
-    if (transpose)
-        hipLaunchKernelGGL(k_solve<true>, grid, block, 0, as_stream(stream), s->h.dev, d_vals,
+    // the case's vector in LDS when it fits beside nothing else (nn x 16 bytes)
+    const size_t xbytes = 16 * (size_t)s->h.nn;
+    const bool lds = xbytes <= kSolveLdsMax;
+    if (lds) allow_big_lds();
+    auto go = [&](auto kern, size_t shm) {
+        hipLaunchKernelGGL(kern, grid, block, shm, as_stream(stream), s->h.dev, d_vals,
                            vals_stride, vals_interleave, B, d_rhs, rhs_stride);
-    else
-        hipLaunchKernelGGL(k_solve<false>, grid, block, 0, as_stream(stream), s->h.dev, d_vals,
-                           vals_stride, vals_interleave, B, d_rhs, rhs_stride);
+    };
+    if (transpose) {
+        if (lds) go(k_solve<true, true>, xbytes);
+        else go(k_solve<true, false>, 0);
+    } else {
+        if (lds) go(k_solve<false, true>, xbytes);
+        else go(k_solve<false, false>, 0);
+    }
     return launch_check("pf_solve");
 }
 

@@ -129,8 +129,11 @@ def test_jacobian(O, n, seed):
     np.testing.assert_allclose(Up, oU, rtol=0, atol=1e-12 * scale)
 
 
-@pytest.mark.parametrize("n,seed,ordering", [(200, 1, 0), (2000, 1, 0), (300, 4, 1)])
+@pytest.mark.parametrize("n,seed,ordering", [(200, 1, 0), (2000, 1, 0), (300, 4, 1),
+                                             (12000, 2, 0)])
 def test_factor_and_solve(O, n, seed, ordering):
+    """Factors and both solves against the oracle; 12,000 buses puts the
+    solve vector beyond LDS (the global-memory variant of the solve)."""
     B = _B()
     s = staged(n, seed, ordering)
     g = s.g
@@ -167,6 +170,8 @@ def test_factor_and_solve(O, n, seed, ordering):
     got = r.cpu().numpy()
     xs = np.abs(ox).max()
     np.testing.assert_allclose(got[0], ox, rtol=0, atol=1e-9 * xs)
+    oxt = sym.solve_transpose(fD, fL, fU, rhs[1]).reshape(-1)
+    np.testing.assert_allclose(got[1], oxt, rtol=0, atol=1e-9 * np.abs(oxt).max())
     if A is not None:
         xt = np.linalg.solve(A.T, rhs[1])
         np.testing.assert_allclose(got[1], xt, rtol=0, atol=1e-9 * np.abs(xt).max())
