@@ -158,6 +158,16 @@ struct EFView {
         fk = t.y;
     }
 };
+// (e, f) of every bus copied into LDS (the Newton mismatch pass).
+struct EFLds {
+    double2* s;
+    __device__ __forceinline__ void get(int k, double& ek, double& fk) const
+    {
+        const double2 t = s[k];
+        ek = t.x;
+        fk = t.y;
+    }
+};
 struct EFPolar {
     const double* Vm;
     const double* Va;
@@ -240,7 +250,8 @@ struct PvMask {
 
 __device__ __forceinline__ uint32_t* pv_words(const DevSym& S)
 {
-    return reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(pf_smem) + S.tail_lds);
+    const int off = S.tail_lds > S.ef_lds ? S.tail_lds : S.ef_lds;
+    return reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(pf_smem) + off);
 }
 
 // Fills the mask m from the case's bus types (a ballot per wavefront); the
@@ -1221,8 +1232,8 @@ struct CaseDesc {
 // order, two per thread per step, so that the admittance rows, row pointers,
 // positions and scheduled injections of a wavefront are adjacent in memory;
 // all loads of both buses are issued before either is summed.
-template <bool SCALE>
-__device__ __forceinline__ void mismatch_pass(const DevSym& S, const double* yv, const EFView& ef,
+template <bool SCALE, class EF>
+__device__ __forceinline__ void mismatch_pass(const DevSym& S, const double* yv, const EF& ef,
                                               const View& wb, const Off& o, const PvMask& pvm,
                                               const double* Psp, const double* Qsp, double& mx,
                                               int& nan)
@@ -1237,12 +1248,20 @@ __device__ __forceinline__ void mismatch_pass(const DevSym& S, const double* yv,
         const int qd0 = S.yptr[ic], qd1 = S.yptr[ic + 1];
         const double spc = Psp[i], sqc = Qsp[i], spd = Psp[ic], sqd = Qsp[ic];
         const int64_t rc = o.BUS + 8 * (int64_t)i, rd = o.BUS + 8 * (int64_t)ic;
-        const Blk vc = wb.blk(rc), vd = wb.blk(rd);
+        Blk vc, vd;  // e, f, |V| (|V| only with SCALE)
+        if (SCALE) {
+            vc = wb.blk(rc);
+            vd = wb.blk(rd);
+        } else {
+            ef.get(i, vc.a, vc.b);
+            ef.get(ic, vd.a, vd.b);
+            vc.c = vd.c = 1.0;
+        }
         const bool pvc = pvm(i), pvd = pvm(ic);
         int kc[4], kd[4];
         RowHead hc, hd;
-        row_head_idx<EFView>(S, yv, qc0, qc1, kc, hc);
-        row_head_idx<EFView>(S, yv, qd0, qd1, kd, hd);
+        row_head_idx<EF>(S, yv, qc0, qc1, kc, hc);
+        row_head_idx<EF>(S, yv, qd0, qd1, kd, hd);
         row_head_v(ef, kc, hc);
         row_head_v(ef, kd, hd);
         double p, q, p2, q2;
@@ -1295,7 +1314,17 @@ __device__ void newton_case(const DevSym& S, const double* yv, const int8_t* typ
     for (;;) {
         double mx = 0.0;
         int nan = 0;
-        mismatch_pass<false>(S, yv, ef, wb, o, pvm, Psp, Qsp, mx, nan);
+        if (S.ef_lds) {
+            // every bus's (e, f) into LDS (free until the tail), so that the
+            // admittance rows' voltages are LDS reads
+            const EFLds efl{reinterpret_cast<double2*>(pf_smem)};
+            for (int i = threadIdx.x; i < S.n; i += blockDim.x)
+                efl.s[i] = wb.v2(o.BUS + 8 * (int64_t)i);
+            __syncthreads();
+            mismatch_pass<false>(S, yv, efl, wb, o, pvm, Psp, Qsp, mx, nan);
+        } else {
+            mismatch_pass<false>(S, yv, ef, wb, o, pvm, Psp, Qsp, mx, nan);
+        }
         int any_nan = 0;
         nrm = block_max(mx, nan, any_nan);
         if (any_nan || !isfinite(nrm)) {
@@ -2469,6 +2498,13 @@ size_t fd_lds_bytes(const HostSym& h)
     return mask + 8 * (4 * (size_t)h.tail_slots + 3 * (size_t)h.tail_nodes);
 }
 
+// Dynamic LDS of the Newton kernel: the tail and the (e, f) copy share the
+// front, the PV mask follows the larger of the two.
+int newton_lds(const HostSym& h)
+{
+    return std::max(h.tail_lds, h.ef_lds) + (int)pv_mask_bytes(h.n);
+}
+
 int launch_threads(const HostSym& h, int B)
 {
     if (h.threads > 0) return h.threads;
@@ -2893,6 +2929,7 @@ int pf_symbolic_upload(pf_symbolic s, void* d_buf, size_t bytes, void* stream)
     d.tail_slots = h.tail_slots;
     d.tail_lds = h.tail_lds;
     d.tail_clique = h.tail_clique;
+    d.ef_lds = 0;
     d.t_node = reinterpret_cast<const int4*>(put(h.t_node));
     d.t_slot = reinterpret_cast<const int4*>(put(h.t_slot));
     d.t_rl = reinterpret_cast<const int2*>(put(h.t_rl));
@@ -2904,12 +2941,19 @@ int pf_symbolic_upload(pf_symbolic s, void* d_buf, size_t bytes, void* stream)
     if (off > info.dev_bytes) return fail(PF_E_WORKSPACE, "pf_symbolic_upload: size mismatch");
     {
         int dev = 0, lds_max = 0;
+        h.ef_lds = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) ==
-                hipSuccess &&
-            h.tail_lds + pv_mask_bytes(h.n) + 2048 > lds_max)
-            return fail(PF_E_WORKSPACE, "pf_symbolic_upload: LDS tail larger than the device's "
-                                        "LDS; lower it with pf_symbolic_set_launch");
+                hipSuccess) {
+            if (h.tail_lds + pv_mask_bytes(h.n) + 2048 > lds_max)
+                return fail(PF_E_WORKSPACE, "pf_symbolic_upload: LDS tail larger than the "
+                                            "device's LDS; lower it with pf_symbolic_set_launch");
+            const int64_t efb = 16 * (int64_t)h.n;
+            if (efb + pv_mask_bytes(h.n) + 2048 <= lds_max) h.ef_lds = (int32_t)efb;
+        } else {
+            (void)hipGetLastError();
+        }
+        d.ef_lds = h.ef_lds;
     }
     int rc = hip_check(hipMemcpyAsync(d_buf, stage.data(), off, hipMemcpyHostToDevice,
                                       as_stream(stream)),
@@ -3044,7 +3088,7 @@ int pf_newton(const pf_symbolic s, int B, const double* d_yval, int64_t y_stride
                  d_status};
     allow_big_lds();
     hipLaunchKernelGGL(k_newton<false>, dim3(grid_blocks(B, C)), dim3(launch_threads(s->h, B)),
-                       s->h.tail_lds + pv_mask_bytes(s->h.n), as_stream(stream), s->h.dev, (const CaseDesc*)nullptr,
+                       newton_lds(s->h), as_stream(stream), s->h.dev, (const CaseDesc*)nullptr,
                        (const int32_t*)nullptr, a);
     return launch_check("pf_newton");
 }
@@ -3291,7 +3335,7 @@ int pf_newton_multi(const pf_multi p, const double* d_yval, const int8_t* d_type
     DevSym none{};
     int lds = 0, threads = 0;
     for (auto* sy : p->syms) {
-        lds = std::max(lds, (int)(sy->h.tail_lds + pv_mask_bytes(sy->h.n)));
+        lds = std::max(lds, newton_lds(sy->h));
         threads = std::max(threads, sy->h.threads);
     }
     if (threads == 0) threads = (p->syms.size() <= 512) ? 512 : 256;

@@ -86,7 +86,8 @@ struct DevSym {
     const int2* upd;         // n_upd
     // LDS tail
     int32_t tail_level, tail_nodes, tail_slots, tail_lds;
-    int32_t tail_clique, pad1;
+    int32_t tail_clique;
+    int32_t ef_lds;  // bytes of the LDS copy of (e, f) per bus the Newton mismatch reads, 0 = none
     const int4* t_node;      // 3 K
     const int4* t_slot;      // 3 TS
     const int2* t_rl;
@@ -109,6 +110,7 @@ struct HostSym {
     int32_t tail_level = 0, tail_nodes = 0, tail_slots = 0, tail_lds = 0, tail_clique = 0;
     int64_t tail_budget = 64 * 1024;
     std::vector<int32_t> t_node, t_slot, t_rl, t_upd, t_lptr, t_pk;
+    int32_t ef_lds = 0;  // set at upload: 16 n when it fits in the device's LDS, else 0
     int32_t max_width = 0;
     int32_t threads = 0;  // 0: chosen per launch from the batch size
     int32_t interleave = 4;  // cases per interleaved workspace group
