@@ -350,6 +350,9 @@ struct SrcState {
     PvMask type;
     View w;
     int64_t bus_off;
+    // (e, f) of every bus in LDS, or null: off_in then reads a neighbour's
+    // (e, f) there and off_of takes |V_k| = sqrt(e^2 + f^2)
+    const double2* efs;
     struct DiagIn {
         double2 y;
         Blk r;  // e, f, |V|, theta of the node's bus
@@ -375,8 +378,14 @@ struct SrcState {
     {
         const double2* y2 = reinterpret_cast<const double2*>(yv);
         const bool fill = ylo < 0;
-        return {w.blk(bus_off + 8 * (int64_t)bk), y2[fill ? 0 : ylo], y2[fill ? 0 : yup],
-                type(bk), fill};
+        Blk rk;
+        if (efs) {
+            const double2 t = efs[bk];
+            rk = {t.x, t.y, 0.0, 0.0};
+        } else {
+            rk = w.blk(bus_off + 8 * (int64_t)bk);
+        }
+        return {rk, y2[fill ? 0 : ylo], y2[fill ? 0 : yup], type(bk), fill};
     }
     __device__ __forceinline__ void off_of(const DiagIn& dj, const OffIn& o, Blk& lo,
                                            Blk& up) const
@@ -386,8 +395,9 @@ struct SrcState {
             up = bzero();
             return;
         }
+        const double vk = efs ? sqrt(fma(o.rk.a, o.rk.a, o.rk.b * o.rk.b)) : o.rk.c;
         lo = jac_off(o.yl.x, o.yl.y, o.rk.a, o.rk.b, dj.r.a, dj.r.b, dj.r.c, o.pk, dj.pv);
-        up = jac_off(o.yu.x, o.yu.y, dj.r.a, dj.r.b, o.rk.a, o.rk.b, o.rk.c, dj.pv, o.pk);
+        up = jac_off(o.yu.x, o.yu.y, dj.r.a, dj.r.b, o.rk.a, o.rk.b, vk, dj.pv, o.pk);
     }
     __device__ __forceinline__ Blk diag(int, int bus, int yd) const
     {
@@ -1306,7 +1316,11 @@ __device__ void newton_case(const DevSym& S, const double* yv, const int8_t* typ
     if (threadIdx.x == 0) s_bad = 0;
     __syncthreads();
     const PvMask pvm{pv_words(S)};
-    const SrcState src{yv, pvm, wb, o.BUS};
+    // the global levels of the factorisation sweep read neighbours' (e, f)
+    // from the LDS copy the mismatch pass just made (the tail reuses that LDS
+    // afterwards and reads them from the bus records)
+    const SrcState src{yv, pvm, wb, o.BUS,
+                       S.ef_lds ? reinterpret_cast<const double2*>(pf_smem) : nullptr};
     const EFView ef{wb, o.BUS};
     const bool tail = S.tail_nodes > 0;
     int it = 0, st = ST_NOT_CONVERGED;
