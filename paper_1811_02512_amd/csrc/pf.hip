@@ -350,8 +350,8 @@ struct SrcState {
     PvMask type;
     View w;
     int64_t bus_off;
-    // (e, f) of every bus in LDS, or null: off_in then reads a neighbour's
-    // (e, f) there and off_of takes |V_k| = sqrt(e^2 + f^2)
+    // (e, f) of every bus in LDS, or null: diag_in / off_in then read (e, f)
+    // there and |V| is taken as sqrt(e^2 + f^2)
     const double2* efs;
     struct DiagIn {
         double2 y;
@@ -368,11 +368,22 @@ struct SrcState {
     {
         const double2* y2 = reinterpret_cast<const double2*>(yv);
         const int64_t rec = bus_off + 8 * (int64_t)bus;
-        return {y2[yd], w.blk(rec), w.v2(rec + 4), type(bus)};
+        Blk r;
+        if (efs) {
+            const double2 t = efs[bus];
+            r = {t.x, t.y, 0.0, 0.0};
+        } else {
+            r = w.blk(rec);
+        }
+        return {y2[yd], r, w.v2(rec + 4), type(bus)};
+    }
+    __device__ __forceinline__ double vm_of(const Blk& r) const
+    {
+        return efs ? sqrt(fma(r.a, r.a, r.b * r.b)) : r.c;
     }
     __device__ __forceinline__ Blk diag_of(const DiagIn& d) const
     {
-        return jac_diag(d.y.x, d.y.y, d.s.x, d.s.y, d.r.c, d.pv);
+        return jac_diag(d.y.x, d.y.y, d.s.x, d.s.y, vm_of(d.r), d.pv);
     }
     __device__ __forceinline__ OffIn off_in(int, int bk, int ylo, int yup) const
     {
@@ -395,8 +406,8 @@ struct SrcState {
             up = bzero();
             return;
         }
-        const double vk = efs ? sqrt(fma(o.rk.a, o.rk.a, o.rk.b * o.rk.b)) : o.rk.c;
-        lo = jac_off(o.yl.x, o.yl.y, o.rk.a, o.rk.b, dj.r.a, dj.r.b, dj.r.c, o.pk, dj.pv);
+        const double vk = vm_of(o.rk);
+        lo = jac_off(o.yl.x, o.yl.y, o.rk.a, o.rk.b, dj.r.a, dj.r.b, vm_of(dj.r), o.pk, dj.pv);
         up = jac_off(o.yu.x, o.yu.y, dj.r.a, dj.r.b, o.rk.a, o.rk.b, vk, dj.pv, o.pk);
     }
     __device__ __forceinline__ Blk diag(int, int bus, int yd) const
