@@ -1084,10 +1084,13 @@ __device__ __forceinline__ void apply_step(const View& w, int64_t rec, bool pv, 
 // is final, y_k -= U_ka x_a for every clique node k below a.  The x of the
 // tail nodes are written to the rhs (for the levels below) and, with UPDATE,
 // applied to the bus records in one parallel pass at the end, so that no
-// level waits for a bus-record load.
+// level waits for a bus-record load.  With xs (the solution vector in LDS by
+// position, over the tail's own LDS; at most four tail nodes per thread) the
+// x go there instead of the rhs: each thread takes its x into registers,
+// and writes them after a barrier.
 template <bool UPDATE>
 __device__ void tail_backward(const DevSym& S, const View& w, int64_t rhs, int64_t bus_off,
-                              PvMask type)
+                              PvMask type, double2* xs)
 {
     const int K = S.tail_nodes, TS = S.tail_slots, KC = S.tail_clique;
     const int nT = S.nlev - S.tail_level;
@@ -1128,11 +1131,31 @@ __device__ void tail_backward(const DevSym& S, const View& w, int64_t rhs, int64
             sy[2 * jl + 1] -= a1;
         }
     });
-    for (int jl = threadIdx.x; jl < K; jl += blockDim.x) {
-        const int4 t0 = S.t_node[3 * jl];
-        const double x0 = sy[2 * jl], x1 = sy[2 * jl + 1];
-        w.put2(rhs + 2 * (int64_t)t0.x, make_double2(x0, x1));
-        if (UPDATE) apply_step(w, bus_off + 8 * (int64_t)t0.y, type(t0.y), x0, x1);
+    if (xs) {
+        double2 xr[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int jl = threadIdx.x + r * blockDim.x;
+            xr[r] = jl < K ? make_double2(sy[2 * jl], sy[2 * jl + 1]) : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int jl = threadIdx.x + r * blockDim.x;
+            if (jl < K) {
+                const int4 t0 = S.t_node[3 * jl];
+                xs[t0.x] = xr[r];
+                if (UPDATE)
+                    apply_step(w, bus_off + 8 * (int64_t)t0.y, type(t0.y), xr[r].x, xr[r].y);
+            }
+        }
+    } else {
+        for (int jl = threadIdx.x; jl < K; jl += blockDim.x) {
+            const int4 t0 = S.t_node[3 * jl];
+            const double x0 = sy[2 * jl], x1 = sy[2 * jl + 1];
+            w.put2(rhs + 2 * (int64_t)t0.x, make_double2(x0, x1));
+            if (UPDATE) apply_step(w, bus_off + 8 * (int64_t)t0.y, type(t0.y), x0, x1);
+        }
     }
     __syncthreads();
 }
@@ -1143,7 +1166,8 @@ __device__ void tail_backward(const DevSym& S, const View& w, int64_t rhs, int64
 template <bool UPDATE>
 __device__ __forceinline__ void back_node(const DevSym& S, const NodeRec& rec, int lane, int g,
                                           const View& w, int64_t lu, const View& wb,
-                                          int64_t rhs, int64_t bus_off, PvMask type)
+                                          int64_t rhs, int64_t bus_off, PvMask type,
+                                          double2* xs)
 {
     const int4 n0 = rec.a;
     const int4 n1 = rec.b;
@@ -1168,7 +1192,7 @@ __device__ __forceinline__ void back_node(const DevSym& S, const NodeRec& rec, i
         for (int k = 0; k < 4; ++k) {
             const int sk = s + k * g < s1 ? s + k * g : 0;
             u[k] = w.blk(lu + 8 * (int64_t)sk + 4);
-            xk[k] = wb.v2(rhs + 2 * (int64_t)kk[k]);
+            xk[k] = xs ? xs[kk[k]] : wb.v2(rhs + 2 * (int64_t)kk[k]);
         }
         const int sn = s + 4 * g;
 #pragma unroll
@@ -1183,7 +1207,8 @@ __device__ __forceinline__ void back_node(const DevSym& S, const NodeRec& rec, i
     }
     if (lane == 0) {
         const double x0 = y.x - a0, x1 = y.y - a1;
-        wb.put2(rhs + 2 * (int64_t)n0.x, make_double2(x0, x1));
+        if (xs) xs[n0.x] = make_double2(x0, x1);
+        else wb.put2(rhs + 2 * (int64_t)n0.x, make_double2(x0, x1));
         if (UPDATE) apply_step_to(wb, brec, br, pv, x0, x1);
     }
 }
@@ -1332,6 +1357,11 @@ __device__ void newton_case(const DevSym& S, const double* yv, const int8_t* typ
     // afterwards and reads them from the bus records)
     const SrcState src{yv, pvm, wb, o.BUS,
                        S.ef_lds ? reinterpret_cast<const double2*>(pf_smem) : nullptr};
+    // the backward sweep keeps x in that LDS too (free again once the tail's
+    // backward substitution has read its values)
+    double2* const xs = (S.ef_lds && S.tail_nodes <= 4 * (int)blockDim.x)
+                            ? reinterpret_cast<double2*>(pf_smem)
+                            : nullptr;
     const EFView ef{wb, o.BUS};
     const bool tail = S.tail_nodes > 0;
     int it = 0, st = ST_NOT_CONVERGED;
@@ -1372,9 +1402,9 @@ __device__ void newton_case(const DevSym& S, const double* yv, const int8_t* typ
             st = ST_ZERO_PIVOT;
             break;
         }
-        if (tail) tail_backward<true>(S, wb, o.RHS, o.BUS, pvm);
+        if (tail) tail_backward<true>(S, wb, o.RHS, o.BUS, pvm, xs);
         for_nodes(S, 0, S.tail_level, false, [&](int, const NodeRec& r, int lane, int g) {
-            back_node<true>(S, r, lane, g, w, o.LU, wb, o.RHS, o.BUS, pvm);
+            back_node<true>(S, r, lane, g, w, o.LU, wb, o.RHS, o.BUS, pvm, xs);
         });
         ++it;
     }
