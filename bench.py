@@ -334,7 +334,7 @@ def bench_screen(W, outages, steps=3):
     return out
 
 
-def bench_se(W, cases=64, steps=3):
+def bench_se(W, cases=256, steps=3):
     """WLS state estimation on the workload's grid: the measurements are the
     NR solutions of the first `cases` load scenarios (|V|, P, Q at every bus,
     P, Q at the from end of every branch, all computed on the device) plus
@@ -369,10 +369,10 @@ def bench_se(W, cases=64, steps=3):
     z = (h + sig * torch.randn(h.shape, generator=gen, dtype=torch.float64, device=dev))
     w = 1.0 / sig ** 2
     t0 = time.time()
-    est = api.StateEstimator(n, g.f, g.t, kinds, locs)
+    est = api.StateEstimator(n, g.f, g.t, kinds, locs, tail_lds_budget=161792)
     t_an = time.time() - t0
     d = est.dims
-    ws = torch.empty(cases, d.ws_doubles, dtype=torch.float64, device=dev)
+    ws = est.workspace(cases, dev)
     eVm = torch.empty_like(Vm)
     eVa = torch.empty_like(Va)
     box = {}
@@ -595,7 +595,7 @@ def main():
             if i % 8 == 7:
                 log(f"[bench] generated {i + 1}/64 mixed grids")
         out["mixed_64_grids"] = bench_multi(mixed, "mixed 64 grids 500-20k buses")
-        out["wls_se_10k_x64"] = bench_se(W)
+        out["wls_se_10k_x256"] = bench_se(W)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W)
     print(json.dumps(out))

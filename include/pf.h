@@ -318,25 +318,31 @@ typedef struct {
     int64_t gain_nnz_l;      /* off-diagonal blocks of the factored G       */
     int32_t gain_levels;
     int64_t contributions;   /* (measurement, bus pair) terms of G           */
-    int64_t ws_doubles;      /* pf_se_estimate workspace per case            */
+    int64_t ws_doubles;      /* pf_se_estimate scratch per case (see there)  */
     size_t dev_bytes;
 } pf_se_dims;
 int pf_se_analyze(int n, int m, const int32_t* from, const int32_t* to, int slack, int M,
                   const int8_t* kind, const int32_t* loc, pf_se* out);
 int pf_se_info(const pf_se se, pf_se_dims* info);
 int pf_se_upload(pf_se se, void* d_buf, size_t bytes, void* stream);
+/* Launch shape of the gain matrix's factor and solve kernels (threads and
+ * LDS tail budget as pf_symbolic_set_launch); call before pf_se_upload (the
+ * upload size changes with the tail).                                      */
+int pf_se_set_launch(pf_se se, int threads, int64_t tail_lds_budget);
 /* B cases: branch arrays as pf_build_ybus; d_z, d_w double[B][M] (z_stride,
- * 0 = shared); d_Vm/d_Va in = start, out = estimate (v_stride); d_ws
- * ws_stride >= ws_doubles (a multiple of 8), 16-byte aligned; d_iters,
+ * w_stride; 0 = shared); d_Vm/d_Va in = start, out = estimate (v_stride);
+ * d_ws: scratch of at least ceil(B/4)*4 * ws_doubles doubles, 16-byte
+ * aligned (ws_size = doubles available), its layout internal; d_iters,
  * d_norm (last max|dx|), d_status[B] (PF_OK, PF_E_NOT_CONVERGED,
  * PF_E_NONFINITE, the latter also for a singular gain matrix).  The host
  * waits for the stream once per Gauss-Newton step to stop when every case
  * has finished.                                                            */
 int pf_se_estimate(const pf_se se, int B, const double* d_r, const double* d_x,
                    const double* d_b, int64_t branch_stride, const double* d_z,
-                   const double* d_w, int64_t z_stride, double* d_Vm, double* d_Va,
-                   int64_t v_stride, double tol, int max_iter, double* d_ws, int64_t ws_stride,
-                   int32_t* d_iters, double* d_norm, int32_t* d_status, void* stream);
+                   int64_t z_stride, const double* d_w, int64_t w_stride, double* d_Vm,
+                   double* d_Va, int64_t v_stride, double tol, int max_iter, double* d_ws,
+                   int64_t ws_size, int32_t* d_iters, double* d_norm, int32_t* d_status,
+                   void* stream);
 void pf_se_destroy(pf_se se);
 
 /* ---- adjoint right-hand side (beyond the paper) ----------------------------

@@ -183,10 +183,12 @@ class StateEstimator:
     """WLS state estimation on the device for a fixed measurement set
     (kinds PF_MEAS_*, locations bus or branch)."""
 
-    def __init__(self, n, from_, to, kind, loc, slack=0, device=None):
+    def __init__(self, n, from_, to, kind, loc, slack=0, device=None, threads=0,
+                 tail_lds_budget=65536):
         import numpy as np
 
         self.h = B.pf_se_analyze(n, np.asarray(from_), np.asarray(to), slack, kind, loc)
+        B.pf_se_set_launch(self.h, threads, tail_lds_budget)
         self.dims = B.pf_se_info(self.h)
         self.device = _dev(device)
         self.buf = torch.empty(self.dims.dev_bytes + 256, dtype=torch.uint8, device=self.device)
@@ -194,21 +196,23 @@ class StateEstimator:
         self._off = (-base) % 256
         B.pf_se_upload(self.h, self.buf[self._off:], self.dims.dev_bytes)
 
+    def workspace(self, Bn, device=None):
+        """Scratch for Bn cases: whole groups of four cases of ws_doubles each."""
+        rows = -(-Bn // 4) * 4
+        return torch.empty(rows * self.dims.ws_doubles, dtype=torch.float64,
+                           device=_dev(device or self.device))
+
     def estimate(self, r, x, b, z, w, Vm, Va, tol=1e-8, max_iter=20, ws=None):
-        """In place on Vm, Va ([B, n]); z, w: [M] shared or [B, M].
-        Returns (iters, norm, status, ws)."""
+        """In place on Vm, Va ([B, n]); z, w: [M] shared or [B, M]; r, x, b:
+        [m] shared or [B, m].  Returns (iters, norm, status, ws)."""
         Bn = Vm.shape[0]
-        d = self.dims
         if ws is None:
-            ws = torch.empty(Bn, d.ws_doubles, dtype=torch.float64, device=Vm.device)
+            ws = self.workspace(Bn, Vm.device)
         iters = torch.empty(Bn, dtype=torch.int32, device=Vm.device)
         norm = torch.empty(Bn, dtype=torch.float64, device=Vm.device)
         status = torch.empty(Bn, dtype=torch.int32, device=Vm.device)
-        M = d.measurements
-        z = z.expand(Bn, M).contiguous() if z.dim() == 1 and Bn > 1 else z
-        w = w.expand(Bn, M).contiguous() if w.dim() == 1 and Bn > 1 else w
-        B.pf_se_estimate(self.h, Bn, r, x, b, _stride(r), z, w, 0 if Bn == 1 else M, Vm, Va,
-                         Vm.shape[-1], tol, max_iter, ws, d.ws_doubles, iters, norm, status)
+        B.pf_se_estimate(self.h, Bn, r, x, b, _stride(r), z, _stride(z), w, _stride(w), Vm, Va,
+                         Vm.shape[-1], tol, max_iter, ws, ws.numel(), iters, norm, status)
         return iters, norm, status, ws
 
     def __del__(self):

@@ -100,8 +100,9 @@ _SIGS = {
     "pf_se_analyze": ([_i, _i, _vp, _vp, _i, _i, _vp, _vp, C.POINTER(_vp)], _i),
     "pf_se_info": ([_vp, C.POINTER(pf_se_dims)], _i),
     "pf_se_upload": ([_vp, _vp, C.c_size_t, _vp], _i),
-    "pf_se_estimate": ([_vp, _i, _vp, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _d, _i, _vp,
-                        _i64, _vp, _vp, _vp, _vp], _i),
+    "pf_se_set_launch": ([_vp, _i, _i64], _i),
+    "pf_se_estimate": ([_vp, _i, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _d,
+                        _i, _vp, _i64, _vp, _vp, _vp, _vp], _i),
     "pf_se_destroy": ([_vp], None),
 }
 for _name, (_args, _res) in _SIGS.items():
@@ -351,15 +352,20 @@ def pf_se_info(h):
     return d
 
 
+def pf_se_set_launch(h, threads, tail_lds_budget):
+    check(lib.pf_se_set_launch(h, int(threads), int(tail_lds_budget)), "pf_se_set_launch")
+
+
 def pf_se_upload(h, buf, nbytes, stream=None):
     check(lib.pf_se_upload(h, ptr(buf), nbytes, stream_ptr(stream)), "pf_se_upload")
 
 
-def pf_se_estimate(h, B, r, x, b, branch_stride, z, w, z_stride, Vm, Va, v_stride, tol, max_iter,
-                   ws, ws_stride, iters, norm, status, stream=None):
-    check(lib.pf_se_estimate(h, B, ptr(r), ptr(x), ptr(b), branch_stride, ptr(z), ptr(w),
-                             z_stride, ptr(Vm), ptr(Va), v_stride, tol, max_iter, ptr(ws),
-                             ws_stride, ptr(iters), ptr(norm), ptr(status), stream_ptr(stream)),
+def pf_se_estimate(h, B, r, x, b, branch_stride, z, z_stride, w, w_stride, Vm, Va, v_stride,
+                   tol, max_iter, ws, ws_size, iters, norm, status, stream=None):
+    check(lib.pf_se_estimate(h, B, ptr(r), ptr(x), ptr(b), branch_stride, ptr(z), z_stride,
+                             ptr(w), w_stride, ptr(Vm), ptr(Va), v_stride, tol, max_iter,
+                             ptr(ws), ws_size, ptr(iters), ptr(norm), ptr(status),
+                             stream_ptr(stream)),
           "pf_se_estimate")
 
 

@@ -2313,45 +2313,76 @@ struct SeDev {
     const int2* rent;     // (m, partial of the bus)
     const int32_t* from;  // network branch ends
     const int32_t* to;
-    int64_t off_rhs, off_par, off_res, off_y;  // workspace offsets (doubles)
 };
 
-// Measurement values (residual z - h) and partials d h / d(theta_b, |V_b|)
-// for every bus b of the support, stored as pairs in the support's order.
-__global__ void k_se_eval(DevSym N, SeDev E, const double* __restrict__ r,
-                          const double* __restrict__ x, const double* __restrict__ b,
-                          int64_t bstride, const double* __restrict__ z, int64_t zstride,
-                          const double* __restrict__ Vm, const double* __restrict__ Va,
-                          int64_t vstride, double* ws, int64_t ws_stride,
-                          const int32_t* __restrict__ status)
+// The estimator's workspace for a batch of B cases.  Per-measurement data
+// are case-minor (entry e of case c at e * B + c) so that a wavefront whose
+// lanes are 64 cases of one measurement or one position reads them
+// coalesced; the gain matrix is in the filled layout of its analysis in
+// interleaved groups of C cases, the rhs plain per case.
+struct SeWs {
+    int B, C;
+    double* vals;   // gain matrix, groups of C cases, stride vs
+    int64_t vs;
+    double* rhs;    // [B][rs]: H^T W r, then the step
+    int64_t rs;
+    double* y;      // admittance values, [B][ys] (ys = 0: one copy for all)
+    int64_t ys;
+    double2* st;    // [n][B] x 2: (e, f), (|V|, theta)
+    double2* par;   // [P][B]: (dh/dtheta_b, dh/d|V|_b)
+    double* res;    // [M][B]: z - h
+};
+
+// Case-minor state of every bus: (e, f, |V|, theta) from the caller's |V|, theta.
+__global__ __launch_bounds__(64) void k_se_state(int n, SeWs X, const double* __restrict__ Vm,
+                                                 const double* __restrict__ Va, int64_t vstride,
+                                                 const int32_t* __restrict__ status)
 {
-    const int mi = blockIdx.x * blockDim.x + threadIdx.x;
-    const int c = blockIdx.y;
-    if (mi >= E.M || status[c] >= 0) return;
-    double* w = ws + c * ws_stride;
-    double2* par = reinterpret_cast<double2*>(w + E.off_par);
-    const double* vm = Vm + c * vstride;
-    const double* va = Va + c * vstride;
+    const int i = blockIdx.x;
+    const int c = blockIdx.y * 64 + threadIdx.x;
+    if (c >= X.B || status[c] >= 0) return;
+    const double vm = Vm[c * vstride + i], va = Va[c * vstride + i];
+    double sn, cs;
+    sincos(va, &sn, &cs);
+    double2* s = X.st + 2 * ((int64_t)i * X.B + c);
+    s[0] = make_double2(vm * cs, vm * sn);
+    s[1] = make_double2(vm, va);
+}
+
+// Measurement values (residual z - h) and partials d h / d(theta_b, |V_b|)
+// for every bus b of the support, in the support's order; one measurement
+// per workgroup, lanes over cases.
+__global__ __launch_bounds__(64) void k_se_eval(DevSym N, SeDev E, SeWs X,
+                                                const double* __restrict__ r,
+                                                const double* __restrict__ x,
+                                                const double* __restrict__ b, int64_t bstride,
+                                                const double* __restrict__ z, int64_t zstride,
+                                                const int32_t* __restrict__ status)
+{
+    const int mi = blockIdx.x;
+    const int c = blockIdx.y * 64 + threadIdx.x;
+    if (c >= X.B || status[c] >= 0) return;
+    const int B = X.B;
+    auto ef = [&](int bus) { return X.st[2 * ((int64_t)bus * B + c)]; };
+    auto vm = [&](int bus) { return X.st[2 * ((int64_t)bus * B + c) + 1].x; };
+    auto par = [&](int p) -> double2& { return X.par[(int64_t)p * B + c]; };
     const int kind = E.kind[mi], loc = E.loc[mi], p0 = E.sup[mi];
     double h = 0.0;
     if (kind == 1) {
-        h = vm[loc];
-        par[p0] = make_double2(0.0, 1.0);
+        h = vm(loc);
+        par(p0) = make_double2(0.0, 1.0);
     } else if (kind == 2 || kind == 3) {
-        const double2* yv = reinterpret_cast<const double2*>(w + E.off_y);
+        const double2* yv = reinterpret_cast<const double2*>(X.y + c * X.ys);
         const int i = loc, q0 = N.yptr[i], q1 = N.yptr[i + 1];
-        double si, ci;
-        sincos(va[i], &si, &ci);
-        const double ei = vm[i] * ci, fi = vm[i] * si;
+        const double2 vi = ef(i);
+        const double ei = vi.x, fi = vi.y;
         double ir = 0.0, ii = 0.0, gd = 0.0, bd = 0.0;
         for (int q = q0; q < q1; ++q) {
             const int k = N.ycol[q];
             const double2 y = yv[q];
-            double sk, ck;
-            sincos(va[k], &sk, &ck);
-            const double ek = vm[k] * ck, fk = vm[k] * sk;
-            ir = fma(y.x, ek, fma(-y.y, fk, ir));
-            ii = fma(y.x, fk, fma(y.y, ek, ii));
+            const double2 vk = ef(k);
+            ir = fma(y.x, vk.x, fma(-y.y, vk.y, ir));
+            ii = fma(y.x, vk.y, fma(y.y, vk.x, ii));
             if (k == i) {
                 gd = y.x;
                 bd = y.y;
@@ -2363,14 +2394,13 @@ __global__ void k_se_eval(DevSym N, SeDev E, const double* __restrict__ r,
             const int k = N.ycol[q];
             Blk J;
             if (k == i) {
-                J = jac_diag(gd, bd, P, Q, vm[i], false);
+                J = jac_diag(gd, bd, P, Q, vm(i), false);
             } else {
                 const double2 y = yv[q];
-                double sk, ck;
-                sincos(va[k], &sk, &ck);
-                J = jac_off(y.x, y.y, ei, fi, vm[k] * ck, vm[k] * sk, vm[k], false, false);
+                const double2 vk = ef(k);
+                J = jac_off(y.x, y.y, ei, fi, vk.x, vk.y, vm(k), false, false);
             }
-            par[p0 + (q - q0)] = kind == 2 ? make_double2(J.a, J.b) : make_double2(J.c, J.d);
+            par(p0 + (q - q0)) = kind == 2 ? make_double2(J.a, J.b) : make_double2(J.c, J.d);
         }
     } else {
         // S_f = |V_f|^2 conj(y_ff) + V_f conj(c), c = y_ft V_t, y_ff = y + jb/2,
@@ -2382,48 +2412,49 @@ __global__ void k_se_eval(DevSym N, SeDev E, const double* __restrict__ r,
         const double hb = b[c * bstride + e] / 2.0;
         const double den = rr * rr + xx * xx;
         const double yg = rr / den, yb = -xx / den;
-        double sf, cf, st, ct;
-        sincos(va[fb], &sf, &cf);
-        sincos(va[tb], &st, &ct);
-        const double vf = vm[fb], vt = vm[tb];
-        const double ef = vf * cf, ff = vf * sf, et = vt * ct, ft = vt * st;
+        const double2 Vf = ef(fb), Vt = ef(tb);
+        const double vf = vm(fb), vt = vm(tb);
+        const double ef_ = Vf.x, ff = Vf.y, et = Vt.x, ft = Vt.y;
         const double cr = -(yg * et - yb * ft), ci = -(yg * ft + yb * et);  // c = -y V_t
-        const double ar = ef * cr + ff * ci, ai = ff * cr - ef * ci;      // V_f conj(c)
+        const double ar = ef_ * cr + ff * ci, ai = ff * cr - ef_ * ci;     // V_f conj(c)
         const double Sr = vf * vf * yg + ar, Si = -vf * vf * (yb + hb) + ai;
         // partials as complex numbers (re, im)
         const double dthf_r = -ai, dthf_i = ar;                  // j a
         const double dvf_r = 2 * vf * yg + ar / vf, dvf_i = -2 * vf * (yb + hb) + ai / vf;
         const double dvt_r = ar / vt, dvt_i = ai / vt;
-        const bool P = kind == 4;
-        h = P ? Sr : Si;
-        const double tf = P ? dthf_r : dthf_i, vff = P ? dvf_r : dvf_i;
-        const double tt = -tf, vtt = P ? dvt_r : dvt_i;
+        const bool Pm = kind == 4;
+        h = Pm ? Sr : Si;
+        const double tf = Pm ? dthf_r : dthf_i, vff = Pm ? dvf_r : dvf_i;
+        const double tt = -tf, vtt = Pm ? dvt_r : dvt_i;
         const int lo = fb < tb ? 0 : 1;  // the support is (min, max) of the ends
-        par[p0 + lo] = make_double2(tf, vff);
-        par[p0 + 1 - lo] = make_double2(tt, vtt);
+        par(p0 + lo) = make_double2(tf, vff);
+        par(p0 + 1 - lo) = make_double2(tt, vtt);
     }
-    w[E.off_res + mi] = z[c * zstride + mi] - h;
+    X.res[(int64_t)mi * B + c] = z[c * zstride + mi] - h;
 }
 
-// G = H^T W H and H^T W (z - h) into the filled layout of the gain analysis,
-// one thread per position: its diagonal block, the blocks of its slots and
-// its rhs entry.  The reference bus's angle row and column become identity.
-__global__ void k_se_assemble(DevSym S, SeDev E, const double* __restrict__ wt, int64_t zstride,
-                              double* ws, int64_t ws_stride, const int32_t* __restrict__ status)
+// G = H^T W H and H^T W (z - h) into the filled layout of the gain analysis:
+// one position per workgroup (its diagonal block, the blocks of its slots and
+// its rhs entry), lanes over cases.  The reference bus's angle row and
+// column become identity.
+__global__ __launch_bounds__(64) void k_se_assemble(DevSym S, SeDev E, SeWs X,
+                                                    const double* __restrict__ wt,
+                                                    int64_t wstride,
+                                                    const int32_t* __restrict__ status)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int c = blockIdx.y;
-    if (j >= S.nn || status[c] >= 0) return;
-    double* w = ws + c * ws_stride;
-    const double2* par = reinterpret_cast<const double2*>(w + E.off_par);
-    const double* res = w + E.off_res;
-    const double* wc = wt + c * zstride;
+    const int j = blockIdx.x;
+    const int c = blockIdx.y * 64 + threadIdx.x;
+    if (c >= X.B || status[c] >= 0) return;
+    const int B = X.B;
+    const View w = case_view(X.vals, X.vs, X.C, c);
+    const double* wc = wt + c * wstride;
+    auto par = [&](int p) { return X.par[(int64_t)p * B + c]; };
     auto block = [&](int q) {
         Blk g = bzero();
         for (int t = E.blk[q]; t < E.blk[q + 1]; ++t) {
             const int4 en = E.ent[t];
             const double wm = wc[en.x];
-            const double2 a = par[en.y], bb = par[en.z];
+            const double2 a = par(en.y), bb = par(en.z);
             g.a = fma(wm * a.x, bb.x, g.a);
             g.b = fma(wm * a.x, bb.y, g.b);
             g.c = fma(wm * a.y, bb.x, g.c);
@@ -2436,8 +2467,8 @@ __global__ void k_se_assemble(DevSym S, SeDev E, const double* __restrict__ wt, 
     double r0 = 0.0, r1 = 0.0;
     for (int t = E.rptr[j]; t < E.rptr[j + 1]; ++t) {
         const int2 en = E.rent[t];
-        const double v = wc[en.x] * res[en.x];
-        const double2 a = par[en.y];
+        const double v = wc[en.x] * X.res[(int64_t)en.x * B + c];
+        const double2 a = par(en.y);
         r0 = fma(v, a.x, r0);
         r1 = fma(v, a.y, r1);
     }
@@ -2445,8 +2476,8 @@ __global__ void k_se_assemble(DevSym S, SeDev E, const double* __restrict__ wt, 
         D = {1.0, 0.0, 0.0, D.d};
         r0 = 0.0;
     }
-    bstore(w + 4 * (int64_t)j, D);
-    reinterpret_cast<double2*>(w + E.off_rhs)[j] = make_double2(r0, r1);
+    w.put(4 * (int64_t)j, D);
+    reinterpret_cast<double2*>(X.rhs + c * X.rs)[j] = make_double2(r0, r1);
     for (int s = S.Lp[j]; s < S.Lp[j + 1]; ++s) {
         Blk L = block(S.nn + s);  // block (k, j), k = Li[s]
         const bool refk = S.perm[S.Li[s]] == E.ref;
@@ -2458,8 +2489,8 @@ __global__ void k_se_assemble(DevSym S, SeDev E, const double* __restrict__ wt, 
             L.a = 0.0;
             L.b = 0.0;
         }
-        bstore(w + S.lu_off + 8 * (int64_t)s, L);
-        bstore(w + S.lu_off + 8 * (int64_t)s + 4, btrans(L));
+        w.put(S.lu_off + 8 * (int64_t)s, L);
+        w.put(S.lu_off + 8 * (int64_t)s + 4, btrans(L));
     }
 }
 
@@ -2467,12 +2498,12 @@ __global__ void k_se_assemble(DevSym S, SeDev E, const double* __restrict__ wt, 
 // |dx| decides: converged (< tol), not converged after max_iter steps, or
 // non-finite.  Cases already decided are left alone.
 __global__ __launch_bounds__(kLevelThreads) void k_se_update(
-    DevSym S, SeDev E, double* ws, int64_t ws_stride, double* Vm, double* Va, int64_t vstride,
-    double tol, int it, int max_iter, int32_t* iters, double* norm, int32_t* status)
+    DevSym S, SeDev E, SeWs X, double* Vm, double* Va, int64_t vstride, double tol, int it,
+    int max_iter, int32_t* iters, double* norm, int32_t* status)
 {
     const int c = blockIdx.x;
     if (status[c] >= 0) return;
-    const double2* dx = reinterpret_cast<const double2*>(ws + c * ws_stride + E.off_rhs);
+    const double2* dx = reinterpret_cast<const double2*>(X.rhs + c * X.rs);
     double* vm = Vm + c * vstride;
     double* va = Va + c * vstride;
     double mx = 0.0;
@@ -2645,7 +2676,7 @@ struct pf_se_s {
     size_t net_bytes = 0, gain_bytes = 0, arr_bytes = 0;
     SeDev dev{};
     bool uploaded = false;
-    int64_t off_rhs = 0, off_par = 0, off_res = 0, off_y = 0, ws = 0;
+    int64_t vs = 0, rs = 0, ys = 0, ws = 0;  // workspace sections per case (doubles)
 };
 
 namespace {
@@ -2763,12 +2794,12 @@ int se_plan(pf_se_s& E, int n, int m, const int32_t* from, const int32_t* to, in
     E.rent.assign(2 * (size_t)rc_cnt.back(), 0);
     std::vector<int32_t> pb(cnt.begin(), cnt.end() - 1), pr(rc_cnt.begin(), rc_cnt.end() - 1);
     visit(true, pb, pr);
-    // workspace per case: gain values | rhs | partials | residuals | admittances
-    E.off_rhs = round8(G.vals_doubles());
-    E.off_par = round8(E.off_rhs + 2 * (int64_t)nn);
-    E.off_res = round8(E.off_par + 2 * E.P);
-    E.off_y = round8(E.off_res + M);
-    E.ws = (E.off_y + 2 * (int64_t)N.ycol.size() + 31) & ~(int64_t)31;
+    // workspace per case: gain values | rhs | admittances | state (4 per bus) |
+    // partials | residuals (the last three case-minor across the batch)
+    E.vs = round8(G.vals_doubles());
+    E.rs = round8(2 * (int64_t)nn);
+    E.ys = round8(2 * (int64_t)N.ycol.size());
+    E.ws = round8(E.vs + E.rs + E.ys + 4 * (int64_t)n + 2 * E.P + M);
     return PF_OK;
 }
 
@@ -3442,6 +3473,14 @@ int pf_se_info(const pf_se s, pf_se_dims* info)
     return PF_OK;
 }
 
+int pf_se_set_launch(pf_se s, int threads, int64_t tail_lds_budget)
+{
+    if (!s) return fail(PF_E_INVALID, "pf_se_set_launch: NULL argument");
+    const int rc = pf_symbolic_set_launch(&s->gain, threads, tail_lds_budget, 1);
+    if (rc == PF_OK) s->uploaded = false;
+    return rc;
+}
+
 int pf_se_upload(pf_se s, void* d_buf, size_t bytes, void* stream)
 {
     if (!s || !d_buf) return fail(PF_E_INVALID, "pf_se_upload: NULL argument");
@@ -3480,10 +3519,6 @@ int pf_se_upload(pf_se s, void* d_buf, size_t bytes, void* stream)
     d.rent = static_cast<const int2*>(put(s->rent.data(), 4 * s->rent.size()));
     d.from = s->net.d_from;
     d.to = s->net.d_to;
-    d.off_rhs = s->off_rhs;
-    d.off_par = s->off_par;
-    d.off_res = s->off_res;
-    d.off_y = s->off_y;
     rc = hip_check(hipMemcpyAsync(arr, stage.data(), off, hipMemcpyHostToDevice,
                                   as_stream(stream)),
                    "pf_se_upload: hipMemcpyAsync");
@@ -3495,46 +3530,68 @@ int pf_se_upload(pf_se s, void* d_buf, size_t bytes, void* stream)
     return PF_OK;
 }
 
+// Cases per interleaved group of the gain matrix.
+constexpr int kSeGroup = 4;
+
 int pf_se_estimate(const pf_se s, int B, const double* d_r, const double* d_x,
                    const double* d_b, int64_t branch_stride, const double* d_z,
-                   const double* d_w, int64_t z_stride, double* d_Vm, double* d_Va,
-                   int64_t v_stride, double tol, int max_iter, double* d_ws, int64_t ws_stride,
-                   int32_t* d_iters, double* d_norm, int32_t* d_status, void* stream)
+                   int64_t z_stride, const double* d_w, int64_t w_stride, double* d_Vm,
+                   double* d_Va, int64_t v_stride, double tol, int max_iter, double* d_ws,
+                   int64_t ws_size, int32_t* d_iters, double* d_norm, int32_t* d_status,
+                   void* stream)
 {
     if (!s || !s->uploaded) return fail(PF_E_INVALID, "pf_se_estimate: not uploaded");
     if (B < 0 || B > 65535 || max_iter < 1 || !(tol >= 0.0) || !d_r || !d_x || !d_b || !d_z ||
-        !d_w || !d_Vm || !d_Va || !d_ws || !d_iters || !d_norm || !d_status)
+        !d_w || !d_Vm || !d_Va || !d_ws || !d_iters || !d_norm || !d_status || z_stride < 0 ||
+        w_stride < 0 || branch_stride < 0)
         return fail(PF_E_INVALID, "pf_se_estimate: bad arguments");
-    if (B > 1 && (v_stride < s->n || (z_stride != 0 && z_stride < s->M)))
+    if (B > 1 && (v_stride < s->n || (z_stride != 0 && z_stride < s->M) ||
+                  (w_stride != 0 && w_stride < s->M) ||
+                  (branch_stride != 0 && branch_stride < s->m)))
         return fail(PF_E_WORKSPACE, "pf_se_estimate: stride too small");
-    if (ws_stride < s->ws || (ws_stride & 7) || (reinterpret_cast<uintptr_t>(d_ws) & 15))
-        return fail(PF_E_WORKSPACE, "pf_se_estimate: ws_stride must be >= ws_doubles, a "
-                                    "multiple of 8, and d_ws 16-byte aligned");
+    const int Bg = (B + kSeGroup - 1) / kSeGroup * kSeGroup;
+    if (ws_size < (int64_t)Bg * s->ws || (reinterpret_cast<uintptr_t>(d_ws) & 15))
+        return fail(PF_E_WORKSPACE, "pf_se_estimate: d_ws must hold ceil(B/4)*4 * ws_doubles "
+                                    "doubles and be 16-byte aligned");
     if (B == 0) return PF_OK;
     hipStream_t st = as_stream(stream);
     const HostSym& G = s->gain.h;
+    const int yb = branch_stride ? B : 1;  // admittance copies
+    SeWs X;
+    X.B = B;
+    X.C = kSeGroup;
+    X.vals = d_ws;
+    X.vs = s->vs;
+    X.rhs = X.vals + (int64_t)Bg * s->vs;
+    X.rs = s->rs;
+    X.y = X.rhs + (int64_t)B * s->rs;
+    X.ys = branch_stride ? s->ys : 0;
+    X.st = reinterpret_cast<double2*>(X.y + (int64_t)yb * s->ys);
+    X.par = X.st + 2 * (int64_t)s->n * B;
+    X.res = reinterpret_cast<double*>(X.par + s->P * B);
     hipLaunchKernelGGL(k_se_start, dim3((B + 255) / 256), dim3(256), 0, st, B, d_iters, d_norm,
                        d_status);
     int rc = launch_check("pf_se_estimate: start");
     if (rc) return rc;
-    rc = pf_build_ybus(&s->net, B, d_r, d_x, d_b, branch_stride, d_ws + s->off_y, ws_stride,
-                       stream);
+    rc = pf_build_ybus(&s->net, yb, d_r, d_x, d_b, branch_stride, X.y, s->ys, stream);
     if (rc) return rc;
+    const unsigned cg = (unsigned)((B + 63) / 64);
     std::vector<int32_t> host(B);
     for (int it = 0; it < max_iter; ++it) {
-        hipLaunchKernelGGL(k_se_eval, dim3((s->M + 255) / 256, B), dim3(256), 0, st, s->net.h.dev,
-                           s->dev, d_r, d_x, d_b, branch_stride, d_z, z_stride, d_Vm, d_Va,
-                           v_stride, d_ws, ws_stride, d_status);
+        hipLaunchKernelGGL(k_se_state, dim3(s->n, cg), dim3(64), 0, st, s->n, X, d_Vm, d_Va,
+                           v_stride, d_status);
+        if ((rc = launch_check("pf_se_estimate: state"))) return rc;
+        hipLaunchKernelGGL(k_se_eval, dim3(s->M, cg), dim3(64), 0, st, s->net.h.dev, s->dev, X,
+                           d_r, d_x, d_b, branch_stride, d_z, z_stride, d_status);
         if ((rc = launch_check("pf_se_estimate: eval"))) return rc;
-        hipLaunchKernelGGL(k_se_assemble, dim3((G.nn + 255) / 256, B), dim3(256), 0, st, G.dev,
-                           s->dev, d_w, z_stride, d_ws, ws_stride, d_status);
+        hipLaunchKernelGGL(k_se_assemble, dim3(G.nn, cg), dim3(64), 0, st, G.dev, s->dev, X, d_w,
+                           w_stride, d_status);
         if ((rc = launch_check("pf_se_estimate: assemble"))) return rc;
-        if ((rc = pf_factor(&s->gain, B, d_ws, ws_stride, 1, nullptr, stream))) return rc;
-        if ((rc = pf_solve(&s->gain, B, d_ws, ws_stride, 1, d_ws + s->off_rhs, ws_stride, 0,
-                           stream)))
+        if ((rc = pf_factor(&s->gain, B, X.vals, X.vs, kSeGroup, nullptr, stream))) return rc;
+        if ((rc = pf_solve(&s->gain, B, X.vals, X.vs, kSeGroup, X.rhs, X.rs, 0, stream)))
             return rc;
-        hipLaunchKernelGGL(k_se_update, dim3(B), dim3(256), 0, st, G.dev, s->dev, d_ws, ws_stride,
-                           d_Vm, d_Va, v_stride, tol, it, max_iter, d_iters, d_norm, d_status);
+        hipLaunchKernelGGL(k_se_update, dim3(B), dim3(256), 0, st, G.dev, s->dev, X, d_Vm, d_Va,
+                           v_stride, tol, it, max_iter, d_iters, d_norm, d_status);
         if ((rc = launch_check("pf_se_estimate: update"))) return rc;
         rc = hip_check(hipMemcpyAsync(host.data(), d_status, sizeof(int32_t) * B,
                                       hipMemcpyDeviceToHost, st),

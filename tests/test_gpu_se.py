@@ -124,3 +124,42 @@ def test_se_partial_measurement_set():
         assert r.status == 0 and st[c].item() == 0 and it[c].item() == r.iters
         np.testing.assert_allclose(Vm[c].cpu().numpy(), r.Vm, rtol=0, atol=1e-9)
         np.testing.assert_allclose(Va[c].cpu().numpy(), r.Va, rtol=0, atol=1e-9)
+
+
+def test_se_many_cases_per_case_branch_data():
+    """70 cases (two 64-case lane groups, a partial group of four) with their
+    own branch reactances and noise, each against the oracle on its grid."""
+    import dataclasses
+
+    from oracle import oracle as O
+    from oracle import se
+
+    g = grid(200, 6)
+    kinds, locs = se.full_measurement_set(g)
+    Bn = 70
+    rng = np.random.default_rng(21)
+    xs = g.x[None, :] * rng.uniform(0.9, 1.1, (Bn, g.m))
+    sig = np.where(kinds == se.VM, 0.004, 0.01)
+    w = 1.0 / sig ** 2
+    grids, zs = [], []
+    for c in range(Bn):
+        gc = dataclasses.replace(g, x=xs[c].copy())
+        ref = O.solve_grid(gc)
+        assert ref.status == 0
+        z0 = se.measure(gc, O.grid_ybus(gc), ref.Vm, ref.Va, kinds, locs)
+        grids.append(gc)
+        zs.append(z0 + sig * rng.standard_normal(len(z0)))
+    z = np.array(zs)
+    R = np.repeat(g.r[None, :], Bn, 0)
+    Bc = np.repeat(g.b[None, :], Bn, 0)
+    est = _setup(g, kinds, locs)
+    Vm = torch.ones(Bn, g.n, dtype=torch.float64, device="cuda")
+    Va = torch.zeros(Bn, g.n, dtype=torch.float64, device="cuda")
+    it, _, st, _ = est.estimate(dev(R), dev(xs), dev(Bc), dev(z), dev(w), Vm, Va)
+    it, st = it.cpu().numpy(), st.cpu().numpy()
+    Vm, Va = Vm.cpu().numpy(), Va.cpu().numpy()
+    for c in range(Bn):
+        r = se.estimate(grids[c], kinds, locs, z[c], w, np.ones(g.n), np.zeros(g.n))
+        assert r.status == 0 and st[c] == 0 and it[c] == r.iters, (c, st[c], it[c], r.iters)
+        np.testing.assert_allclose(Vm[c], r.Vm, rtol=0, atol=1e-9)
+        np.testing.assert_allclose(Va[c], r.Va, rtol=0, atol=1e-9)

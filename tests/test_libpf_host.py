@@ -185,7 +185,7 @@ def test_state_estimation_analysis_sizes_and_errors():
     deg = np.bincount(np.concatenate([g.f, g.t]), minlength=g.n)
     assert d.measurements == 3 * g.n + 2 * g.m
     assert d.partials == g.n + 2 * (g.n + deg.sum()) + 4 * g.m
-    assert d.gain_levels > 0 and d.gain_nnz_l > 0 and d.ws_doubles % 32 == 0
+    assert d.gain_levels > 0 and d.gain_nnz_l > 0 and d.ws_doubles % 8 == 0
     B.pf_se_destroy(h)
     only_v = np.full(g.n, B.PF_MEAS_VM, np.int8)
     with pytest.raises(B.PfError, match="unobservable"):
