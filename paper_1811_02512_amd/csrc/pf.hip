@@ -1720,16 +1720,20 @@ __device__ void fdpf_case(const DevSym& S, const double* yv, const int8_t* type,
                           const View& wb, const double* m1, const double* m2, double tol,
                           int max_iter, int32_t* o_iters, double* o_norm, int32_t* o_status)
 {
-    // LDS: PV mask | (w, u) of B' and B'' tails | 1/d of both | tail y
+    // LDS: PV mask, then either (ef_lds = 0) the (w, u) of the B' and B''
+    // tails | 1/d of both | tail y, loaded once; or the (e, f) copy of the
+    // mismatch pass, over which the tail of the matrix of the half step
+    // (w, u | 1/d | y) is loaded after each mismatch
     uint32_t* fd_pv = reinterpret_cast<uint32_t*>(pf_smem);
     double* lds = pf_smem + ((((S.n + 63) / 64) + 1) & ~1);  // mask: 8 bytes per 64 buses
     const int K = S.tail_nodes, TS = S.tail_slots;
-    const FdTail t1{reinterpret_cast<double2*>(lds), lds + 4 * TS};
-    const FdTail t2{reinterpret_cast<double2*>(lds + 2 * TS), lds + 4 * TS + K};
-    double* sy = lds + 4 * TS + 2 * K;
+    const bool efl = S.ef_lds != 0;
+    const FdTail t1{reinterpret_cast<double2*>(lds), lds + (efl ? 2 : 4) * TS};
+    const FdTail t2 = efl ? t1 : FdTail{reinterpret_cast<double2*>(lds + 2 * TS), lds + 4 * TS + K};
+    double* sy = efl ? lds + 2 * TS + K : lds + 4 * TS + 2 * K;
     const bool tail = K > 0;
     const int lg = tail ? S.tail_level : S.nlev;  // levels swept in global memory
-    if (tail) {
+    if (tail && !efl) {
         fd_tail_load(S, m1, t1);
         fd_tail_load(S, m2, t2);
     }
@@ -1749,7 +1753,15 @@ __device__ void fdpf_case(const DevSym& S, const double* yv, const int8_t* type,
     for (;;) {
         double mx = 0.0;
         int nan = 0;
-        mismatch_pass<true>(S, yv, ef, wb, o, pvm, Psp, Qsp, mx, nan);
+        if (efl) {
+            const EFLds efs{reinterpret_cast<double2*>(lds)};
+            for (int i = threadIdx.x; i < S.n; i += blockDim.x)
+                efs.s[i] = wb.v2(o.BUS + 8 * (int64_t)i);
+            __syncthreads();
+            mismatch_pass<true>(S, yv, efs, wb, o, pvm, Psp, Qsp, mx, nan);
+        } else {
+            mismatch_pass<true>(S, yv, ef, wb, o, pvm, Psp, Qsp, mx, nan);
+        }
         int any_nan = 0;
         nrm = block_max(mx, nan, any_nan);
         if (any_nan || !isfinite(nrm)) {
@@ -1759,6 +1771,10 @@ __device__ void fdpf_case(const DevSym& S, const double* yv, const int8_t* type,
         if (nrm < tol) {
             st = ST_OK;
             break;
+        }
+        if (efl && tail && (half != 0 || it < max_iter)) {
+            fd_tail_load(S, half == 0 ? m1 : m2, t1);
+            __syncthreads();
         }
         if (half == 0) {
             if (it >= max_iter) {
@@ -2581,6 +2597,9 @@ int launch_check(const char* what) { return hip_check(hipGetLastError(), what); 
 size_t fd_lds_bytes(const HostSym& h)
 {
     const size_t mask = ((pv_mask_bytes(h.n) + 15) / 16) * 16;
+    if (h.ef_lds)  // (e, f) copy, and one matrix's tail at a time over it
+        return mask + std::max((size_t)h.ef_lds,
+                               8 * (2 * (size_t)h.tail_slots + 2 * (size_t)h.tail_nodes));
     return mask + 8 * (4 * (size_t)h.tail_slots + 3 * (size_t)h.tail_nodes);
 }
 
@@ -2636,7 +2655,8 @@ void allow_big_lds()
                              reinterpret_cast<const void*>(&k_newton<true>),
                              reinterpret_cast<const void*>(&k_factor),
                              reinterpret_cast<const void*>(&k_solve<false, true>),
-                             reinterpret_cast<const void*>(&k_solve<true, true>)};
+                             reinterpret_cast<const void*>(&k_solve<true, true>),
+                             reinterpret_cast<const void*>(&k_fdpf)};
     for (const void* k : kernels) {
         hipFuncAttributes fa{};
         if (hipFuncGetAttributes(&fa, k) == hipSuccess) {
