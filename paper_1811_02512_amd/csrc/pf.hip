@@ -29,6 +29,7 @@
 #include <cstring>
 #include <numeric>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "pf.h"
@@ -1531,8 +1532,18 @@ __device__ __forceinline__ void fd_factor_node(const DevSym& S, const NodeRec& r
 //   y_j = (1/d_j) (b_j - sum_{i in R(j)} w_ji y_i), levels [0, l1) upward.
 // Four entries per lane per batch with the next batch's indices in flight;
 // the node's own b_j and 1/d_j are requested first.
+// The work vector of a half step: with VL in LDS by position (xv), else the
+// rhs component comp in the bus view.  The right-hand side b itself always
+// comes from the rhs (the mismatch pass writes it there).
+template <bool VL>
+__device__ __forceinline__ double& fd_x(double* xv, const View& wb, int64_t rhs, int comp, int p)
+{
+    return VL ? xv[p] : *wb.at(rhs + 2 * (int64_t)p + comp);
+}
+
+template <bool VL>
 __device__ __forceinline__ void fd_forward(const DevSym& S, const double* m, const View& wb,
-                                           int64_t rhs, int comp, int l1)
+                                           int64_t rhs, int comp, int l1, double* xv)
 {
     const double2* sl = reinterpret_cast<const double2*>(m + S.fd_lu);
     for_nodes(S, 0, l1, true, [&](int, const NodeRec& rec, int lane, int g) {
@@ -1549,7 +1560,7 @@ __device__ __forceinline__ void fd_forward(const DevSym& S, const double* m, con
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 w[k] = sl[e[k].y].x;
-                y[k] = *wb.at(rhs + 2 * (int64_t)e[k].x + comp);
+                y[k] = fd_x<VL>(xv, wb, rhs, comp, e[k].x);
             }
             const int rn = r + 4 * g;
 #pragma unroll
@@ -1559,7 +1570,7 @@ __device__ __forceinline__ void fd_forward(const DevSym& S, const double* m, con
                 if (r + k * g < r1) z = fma(w[k], y[k], z);
         }
         if (g > 1) z = gsum(z, g);
-        if (lane == 0) *wb.at(rhs + 2 * (int64_t)j + comp) = dj * (bj - z);
+        if (lane == 0) fd_x<VL>(xv, wb, rhs, comp, j) = dj * (bj - z);
     });
 }
 
@@ -1602,9 +1613,10 @@ __device__ __forceinline__ void fd_tail_load(const DevSym& S, const double* m, c
 // tail node first takes b_j and the terms of its descendants outside the
 // tail (global lists, all nodes at once), then the tail levels go upward
 // with the local lists.  y of the tail stays in sy for the backward sweep.
+template <bool VL>
 __device__ __forceinline__ void fd_forward_tail(const DevSym& S, const double* m, const FdTail& t,
                                                 double* sy, const View& wb, int64_t rhs,
-                                                int comp)
+                                                int comp, double* xv)
 {
     const double2* sl = reinterpret_cast<const double2*>(m + S.fd_lu);
     for (int jl = threadIdx.x; jl < S.tail_nodes; jl += blockDim.x) {
@@ -1620,7 +1632,7 @@ __device__ __forceinline__ void fd_forward_tail(const DevSym& S, const double* m
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 w[k] = sl[e[k].y].x;
-                y[k] = *wb.at(rhs + 2 * (int64_t)e[k].x + comp);
+                y[k] = fd_x<VL>(xv, wb, rhs, comp, e[k].x);
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k) e[k] = S.t_rl[r + 4 + k < r1 ? r + 4 + k : 0];
@@ -1647,10 +1659,10 @@ __device__ __forceinline__ void fd_forward_tail(const DevSym& S, const double* m
 // Backward substitution of the tail levels in LDS, downward; then, in one
 // parallel pass (so that no level waits for a bus-record load), each tail x
 // is written to the rhs for the levels below and its bus takes the half step.
-template <bool ANGLE>
+template <bool ANGLE, bool VL>
 __device__ __forceinline__ void fd_backward_tail(const DevSym& S, const FdTail& t, double* sy,
                                                  const View& wb, int64_t rhs, int64_t bus_off,
-                                                 const PvMask& pv)
+                                                 const PvMask& pv, double* xv)
 {
     const int comp = ANGLE ? 0 : 1;
     const int nT = S.nlev - S.tail_level;
@@ -1665,7 +1677,7 @@ __device__ __forceinline__ void fd_backward_tail(const DevSym& S, const FdTail& 
     for (int jl = threadIdx.x; jl < S.tail_nodes; jl += blockDim.x) {
         const int4 a = S.t_node[3 * jl];
         const double x = sy[jl];
-        *wb.at(rhs + 2 * (int64_t)a.x + comp) = x;
+        fd_x<VL>(xv, wb, rhs, comp, a.x) = x;
         fd_half_step<ANGLE>(wb, bus_off, a.y, pv, x);
     }
     __syncthreads();
@@ -1674,16 +1686,16 @@ __device__ __forceinline__ void fd_backward_tail(const DevSym& S, const FdTail& 
 // Backward substitution x_j = y_j - sum_{k in S(j)} u_jk x_k, levels
 // downward, and the half step at bus(j); four slots per lane per batch with
 // the next batch's indices in flight.
-template <bool ANGLE>
+template <bool ANGLE, bool VL>
 __device__ __forceinline__ void fd_backward(const DevSym& S, const double* m, const View& wb,
                                             int64_t rhs, int64_t bus_off, const PvMask& pv,
-                                            int l1)
+                                            int l1, double* xv)
 {
     const double2* sl = reinterpret_cast<const double2*>(m + S.fd_lu);
     const int comp = ANGLE ? 0 : 1;
     for_nodes(S, 0, l1, false, [&](int, const NodeRec& rec, int lane, int g) {
         const int s1 = rec.b.y;
-        const double yj = *wb.at(rhs + 2 * (int64_t)rec.a.x + comp);
+        const double yj = fd_x<VL>(xv, wb, rhs, comp, rec.a.x);
         int s = rec.b.x + lane;
         int kk[4];
 #pragma unroll
@@ -1694,7 +1706,7 @@ __device__ __forceinline__ void fd_backward(const DevSym& S, const double* m, co
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 u[k] = sl[s + k * g < s1 ? s + k * g : 0].y;
-                x[k] = *wb.at(rhs + 2 * (int64_t)kk[k] + comp);
+                x[k] = fd_x<VL>(xv, wb, rhs, comp, kk[k]);
             }
             const int sn = s + 4 * g;
 #pragma unroll
@@ -1706,7 +1718,7 @@ __device__ __forceinline__ void fd_backward(const DevSym& S, const double* m, co
         if (g > 1) a = gsum(a, g);
         if (lane == 0) {
             const double xj = yj - a;
-            *wb.at(rhs + 2 * (int64_t)rec.a.x + comp) = xj;
+            fd_x<VL>(xv, wb, rhs, comp, rec.a.x) = xj;
             fd_half_step<ANGLE>(wb, bus_off, rec.a.y, pv, xj);
         }
     });
@@ -1714,7 +1726,9 @@ __device__ __forceinline__ void fd_backward(const DevSym& S, const double* m, co
 
 // The fast decoupled iteration of one case (one workgroup): mismatch, angle
 // half step with B', mismatch, magnitude half step with B'', until max|F| <
-// tol; iters counts angle half steps and max_iter bounds them.
+// tol; iters counts angle half steps and max_iter bounds them.  VL: the
+// half step's work vector in LDS (after the tail of the half step's matrix).
+template <bool VL>
 __device__ void fdpf_case(const DevSym& S, const double* yv, const int8_t* type,
                           const double* Psp, const double* Qsp, double* Vm, double* Va,
                           const View& wb, const double* m1, const double* m2, double tol,
@@ -1731,6 +1745,7 @@ __device__ void fdpf_case(const DevSym& S, const double* yv, const int8_t* type,
     const FdTail t1{reinterpret_cast<double2*>(lds), lds + (efl ? 2 : 4) * TS};
     const FdTail t2 = efl ? t1 : FdTail{reinterpret_cast<double2*>(lds + 2 * TS), lds + 4 * TS + K};
     double* sy = efl ? lds + 2 * TS + K : lds + 4 * TS + 2 * K;
+    double* xv = lds + 2 * TS + 2 * K;  // VL only
     const bool tail = K > 0;
     const int lg = tail ? S.tail_level : S.nlev;  // levels swept in global memory
     if (tail && !efl) {
@@ -1781,20 +1796,20 @@ __device__ void fdpf_case(const DevSym& S, const double* yv, const int8_t* type,
                 st = ST_NOT_CONVERGED;
                 break;
             }
-            fd_forward(S, m1, wb, o.RHS, 0, lg);
+            fd_forward<VL>(S, m1, wb, o.RHS, 0, lg, xv);
             if (tail) {
-                fd_forward_tail(S, m1, t1, sy, wb, o.RHS, 0);
-                fd_backward_tail<true>(S, t1, sy, wb, o.RHS, o.BUS, pvm);
+                fd_forward_tail<VL>(S, m1, t1, sy, wb, o.RHS, 0, xv);
+                fd_backward_tail<true, VL>(S, t1, sy, wb, o.RHS, o.BUS, pvm, xv);
             }
-            fd_backward<true>(S, m1, wb, o.RHS, o.BUS, pvm, lg);
+            fd_backward<true, VL>(S, m1, wb, o.RHS, o.BUS, pvm, lg, xv);
             ++it;
         } else {
-            fd_forward(S, m2, wb, o.RHS, 1, lg);
+            fd_forward<VL>(S, m2, wb, o.RHS, 1, lg, xv);
             if (tail) {
-                fd_forward_tail(S, m2, t2, sy, wb, o.RHS, 1);
-                fd_backward_tail<false>(S, t2, sy, wb, o.RHS, o.BUS, pvm);
+                fd_forward_tail<VL>(S, m2, t2, sy, wb, o.RHS, 1, xv);
+                fd_backward_tail<false, VL>(S, t2, sy, wb, o.RHS, o.BUS, pvm, xv);
             }
-            fd_backward<false>(S, m2, wb, o.RHS, o.BUS, pvm, lg);
+            fd_backward<false, VL>(S, m2, wb, o.RHS, o.BUS, pvm, lg, xv);
         }
         half ^= 1;
     }
@@ -2269,10 +2284,18 @@ __global__ __launch_bounds__(kLevelThreads) void k_fdpf(DevSym S, NewtonArgs a,
     wb.sh = 2;
     wb.cs = 2;
     const double* m1 = mat + c * mstride;
-    fdpf_case(S, a.yval + c * a.y_stride, a.type + c * a.type_stride, a.Psp + c * a.inj_stride,
-              a.Qsp + c * a.inj_stride, a.Vm + c * a.v_stride, a.Va + c * a.v_stride, wb, m1,
-              m1 + S.fd_mat, a.tol, a.max_iter, a.iters ? a.iters + c : nullptr,
-              a.norm ? a.norm + c : nullptr, a.status ? a.status + c : nullptr);
+    // the work vector fits in LDS after one matrix's tail, within the (e, f) copy
+    const bool vl = S.ef_lds != 0 &&
+                    16 * ((int64_t)S.tail_slots + S.tail_nodes) + 8 * (int64_t)S.nn <= S.ef_lds;
+    auto run = [&](auto tag) {
+        fdpf_case<decltype(tag)::value>(
+            S, a.yval + c * a.y_stride, a.type + c * a.type_stride, a.Psp + c * a.inj_stride,
+            a.Qsp + c * a.inj_stride, a.Vm + c * a.v_stride, a.Va + c * a.v_stride, wb, m1,
+            m1 + S.fd_mat, a.tol, a.max_iter, a.iters ? a.iters + c : nullptr,
+            a.norm ? a.norm + c : nullptr, a.status ? a.status + c : nullptr);
+    };
+    if (vl) run(std::true_type{});
+    else run(std::false_type{});
 }
 
 // Branch flows (Sec. II-A: post-convergence, edge by edge): pi-model with
