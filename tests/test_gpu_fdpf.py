@@ -173,3 +173,34 @@ def test_branch_flows_match_oracle(n, seed):
         ref = O.branch_flows(g, Vm[c], Va[c])
         for got, want in zip(out, ref):
             np.testing.assert_allclose(got[c].cpu().numpy(), want, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("n,seed,budget,efl,vl", [(200, 1, 161792, True, False),
+                                                  (10000, 1, 161792, True, True),
+                                                  (12000, 3, 65536, False, False)])
+def test_fdpf_lds_layouts(n, seed, budget, efl, vl):
+    """The kernel's three LDS layouts: both matrix tails resident (no room
+    for the (e, f) copy), the copy with the work vector in global memory, and
+    the copy with the work vector in LDS; two cases each against the oracle."""
+    O = _O()
+    g = grid(n, seed)
+    s = Staged(g)
+    s.sym.set_launch(512, budget)
+    info = s.sym.info
+    K = info.tail_nodes
+    TS = (info.tail_lds_bytes - 48 * K) // 64
+    has_ef = 16 * n + 8 * ((n + 63) // 64) + 2048 <= 160 * 1024
+    has_vl = has_ef and 16 * (TS + K) + 8 * info.nn <= 16 * n
+    log(f"[fdpf] layout n={n} tail K={K} TS={TS} ef={has_ef} vector={has_vl}")
+    assert (has_ef, has_vl) == (efl, vl)
+    mat, st = s.sym.fdpf_factors(s.r, s.x, s.b, s.type)
+    assert st.item() == 0
+    Vm = s.Vm0.repeat(2, 1).contiguous()
+    Va = s.Va0.repeat(2, 1).contiguous()
+    it, nrm, status, _ = s.sym.fdpf(s.yval[0], s.type, s.Psp, s.Qsp, Vm, Va, mat)
+    ref = O.solve_grid_fdpf(g)
+    assert ref.status == 0
+    for c in range(2):
+        assert status[c].item() == 0 and it[c].item() == ref.iters
+        np.testing.assert_allclose(Vm[c].cpu().numpy(), ref.Vm, rtol=0, atol=1e-9)
+        np.testing.assert_allclose(Va[c].cpu().numpy(), ref.Va, rtol=0, atol=1e-9)
