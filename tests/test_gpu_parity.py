@@ -270,10 +270,12 @@ def test_two_bus_closed_form():
 
 
 @pytest.mark.parametrize("threads,budget", [(64, 0), (256, 4096), (512, 65536), (512, 161792),
-                                            (128, 20000)])
+                                            (128, 20000), (64, 161792)])
 def test_launch_shapes_and_lds_tail(O, threads, budget):
     """Every workgroup size and LDS-tail size gives the oracle's solution, and
-    the standalone factorisation (which writes the tail back) matches too."""
+    the standalone factorisation (which writes the tail back) matches too.
+    (64, 161792): more than four tail nodes per thread, so the backward sweep
+    keeps its vector in global memory."""
     B = _B()
     s = staged(2000, 2)
     g = s.g
