@@ -8,6 +8,9 @@
 //   k_solve       forward / normalisation / backward substitution  [III-C]
 //   k_newton      the whole Newton loop of one case per workgroup   [III]
 //   k_adj_*       adjoint parameter gradients (beyond the paper)
+//   k_fd_*, k_fdpf  fast decoupled matrices, LDL^T, iteration       [III, Table III]
+//   k_branch_flows  post-convergence branch flows                   [II-A]
+//   k_se_*        WLS state estimation: state, measurements, gain   [IV]
 //
 // Work decomposition inside a workgroup: hierarchical levels run one after
 // the other with a workgroup barrier between them; inside a level, each
@@ -15,14 +18,17 @@
 // the lanes of a group split the node's destinations and its descendant
 // list, and combine partial sums with a butterfly over the group.  The top
 // levels whose values fit (the "tail") run in LDS, the top clique of the
-// elimination tree as a dense block.
+// elimination tree as a dense block.  Outside the tail the Newton and fast
+// decoupled kernels reuse the same LDS for a copy of every bus's (e, f)
+// (mismatch, Jacobian) and for the sweeps' solution vector.
 //
 // Memory layout across cases: a batch is cut into groups of C cases whose
-// per-case arrays are interleaved every 32 bytes (one 2x2 block), so one
-// 128-byte line holds the same block of four cases.  The C workgroups of a
-// group are launched 8 blocks apart, which places them on the same XCD at
-// the same time: they walk the same pattern in near lockstep and share
-// every line they fetch through that XCD's L2.
+// per-case arrays are interleaved in chunks (64 bytes for filled values: one
+// slot record or two diagonal blocks; 32 bytes for bus records and the
+// rhs), so one 128-byte line holds the same record of two or four cases.
+// The C workgroups of a group are launched 8 blocks apart, which places them
+// on the same XCD at the same time: they walk the same pattern in near
+// lockstep and share every line they fetch through that XCD's L2.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -41,7 +47,7 @@ using namespace pf;
 // ===========================================================================
 // device helpers
 // ===========================================================================
-extern __shared__ double pf_smem[];  // LDS tail (dynamic size: DevSym::tail_lds)
+extern __shared__ double pf_smem[];  // dynamic LDS: tail, (e, f) copy, vectors, PV mask
 
 namespace {
 
