@@ -45,9 +45,11 @@
  *     per-case doubles with stride S (a multiple of 8) is cut into groups of
  *     C cases; element d of case c lives at
  *       (c / C) * C * S + (d / 8) * 8 C + 8 (c % C) + d % 8,
- *     i.e. the 64-byte chunks (one slot record, two D blocks, one Newton bus
- *     record) of the C cases of a group alternate: a case's record stays in
- *     one 128-byte line, and a line carries the same record of two cases.
+ *     i.e. the 64-byte chunks (one slot record, two D blocks) of the C cases
+ *     of a group alternate: a case's record stays in one 128-byte line, and
+ *     a line carries the same record of two cases.  (pf_newton's own part of
+ *     the workspace after the filled values, its bus records and rhs, is
+ *     internal; it is interleaved in 32-byte chunks.)
  *     The buffer holds ceil(B / C) * C * S doubles.  C = 1 is the plain
  *     [B][S] layout.  Kernels launch the C workgroups of a group 8 blocks
  *     apart, which puts them on the same XCD of the MI355X at the same time,
