@@ -444,7 +444,10 @@ struct SrcState {
 };
 
 // Jacobian source: an assembled matrix in the filled layout.
-struct SrcLoad {
+// LOWER_ONLY (a symmetric matrix, factorised with the upper factor taken
+// from the lower one): off_in reads the lower block alone.
+template <bool LOWER_ONLY>
+struct SrcLoadT {
     View w;
     int64_t lu_off;
     struct DiagIn {
@@ -460,7 +463,8 @@ struct SrcLoad {
     __device__ __forceinline__ Blk diag_of(const DiagIn& d) const { return d.a; }
     __device__ __forceinline__ OffIn off_in(int s, int, int, int) const
     {
-        return {w.blk(lu_off + 8 * (int64_t)s), w.blk(lu_off + 8 * (int64_t)s + 4)};
+        return {w.blk(lu_off + 8 * (int64_t)s),
+                LOWER_ONLY ? bzero() : w.blk(lu_off + 8 * (int64_t)s + 4)};
     }
     __device__ __forceinline__ void off_of(const DiagIn&, const OffIn& o, Blk& lo,
                                            Blk& up) const
@@ -475,6 +479,7 @@ struct SrcLoad {
         up = w.blk(lu_off + 8 * (int64_t)s + 4);
     }
 };
+using SrcLoad = SrcLoadT<false>;
 
 // Runs fn(x, lane, g) for the nodes of levels [l0, l1), x indexing the
 // level-ordered node records, up or down, with a barrier after every level.
@@ -630,6 +635,9 @@ __device__ __forceinline__ void apply_updates(const int2* __restrict__ upd, int 
 // The updates of two destinations at once, one pair of each per step, with
 // the first pairs (p, q) already loaded: both chains of loads are in flight
 // together.  The order of the updates of each destination is the list order.
+// SYM (symmetric matrix): only W is updated (V_jk = W_kj^T throughout), so
+// each pair reads two blocks instead of four.
+template <bool SYM = false>
 __device__ __forceinline__ void apply_updates2(const int2* __restrict__ upd, int u0, int u1,
                                                int v0, int v1, int2 p, int2 q, const View& w,
                                                int64_t lu, Blk& Wk, Blk& Vk, Blk& Wk2, Blk& Vk2)
@@ -638,17 +646,24 @@ __device__ __forceinline__ void apply_updates2(const int2* __restrict__ upd, int
         const bool hp = a < u1, hq = b < v1;
         const int2 pn = upd_at(upd, a + 1, u1);
         const int2 qn = upd_at(upd, b + 1, v1);
-        const Blk Wa = w.blk(lu + 8 * (int64_t)p.x), Ua = w.blk(lu + 8 * (int64_t)p.x + 4);
-        const Blk Wb = w.blk(lu + 8 * (int64_t)p.y), Ub = w.blk(lu + 8 * (int64_t)p.y + 4);
-        const Blk Wc = w.blk(lu + 8 * (int64_t)q.x), Uc = w.blk(lu + 8 * (int64_t)q.x + 4);
-        const Blk Wd = w.blk(lu + 8 * (int64_t)q.y), Ud = w.blk(lu + 8 * (int64_t)q.y + 4);
-        if (hp) {
-            bmsub(Wk, Wa, Ub);
-            bmsub(Vk, Wb, Ua);
-        }
-        if (hq) {
-            bmsub(Wk2, Wc, Ud);
-            bmsub(Vk2, Wd, Uc);
+        if (SYM) {
+            const Blk Wa = w.blk(lu + 8 * (int64_t)p.x), Ub = w.blk(lu + 8 * (int64_t)p.y + 4);
+            const Blk Wc = w.blk(lu + 8 * (int64_t)q.x), Ud = w.blk(lu + 8 * (int64_t)q.y + 4);
+            if (hp) bmsub(Wk, Wa, Ub);
+            if (hq) bmsub(Wk2, Wc, Ud);
+        } else {
+            const Blk Wa = w.blk(lu + 8 * (int64_t)p.x), Ua = w.blk(lu + 8 * (int64_t)p.x + 4);
+            const Blk Wb = w.blk(lu + 8 * (int64_t)p.y), Ub = w.blk(lu + 8 * (int64_t)p.y + 4);
+            const Blk Wc = w.blk(lu + 8 * (int64_t)q.x), Uc = w.blk(lu + 8 * (int64_t)q.x + 4);
+            const Blk Wd = w.blk(lu + 8 * (int64_t)q.y), Ud = w.blk(lu + 8 * (int64_t)q.y + 4);
+            if (hp) {
+                bmsub(Wk, Wa, Ub);
+                bmsub(Vk, Wb, Ua);
+            }
+            if (hq) {
+                bmsub(Wk2, Wc, Ud);
+                bmsub(Vk2, Wd, Uc);
+            }
         }
         p = pn;
         q = qn;
@@ -738,7 +753,9 @@ __device__ __forceinline__ void gsum_blk(Blk& v, int g)
 // four entries per lane at a time, then two destinations per step with both
 // update chains in flight together.  Every load is in bounds: absent items
 // read entry 0 and are masked out.
-template <class SRC, bool FWD, bool STORE_D>
+// SYM: a symmetric matrix (eq. 2 blockwise): only the lower blocks take
+// updates and U_jk = D_j^-1 W_kj^T.
+template <class SRC, bool FWD, bool STORE_D, bool SYM = false>
 __device__ __forceinline__ void factor_node(const DevSym& S, const SRC& src, const NodeRec& rec,
                                             int lane, int g, const View& w, int64_t lu,
                                             const View& wr, int64_t rhs, int* s_bad)
@@ -807,12 +824,12 @@ __device__ __forceinline__ void factor_node(const DevSym& S, const SRC& src, con
         Blk Wk, Vk, Wk2, Vk2;
         src.off_of(din, o1, Wk, Vk);
         src.off_of(din, o2, Wk2, Vk2);
-        apply_updates2(S.upd, u0, u1, v0, v1, p, q, w, lu, Wk, Vk, Wk2, Vk2);
+        apply_updates2<SYM>(S.upd, u0, u1, v0, v1, p, q, w, lu, Wk, Vk, Wk2, Vk2);
         w.put(lu + 8 * (int64_t)s, Wk);
-        w.put(lu + 8 * (int64_t)s + 4, bmul(Di, Vk));
+        w.put(lu + 8 * (int64_t)s + 4, bmul(Di, SYM ? btrans(Wk) : Vk));
         if (two) {
             w.put(lu + 8 * (int64_t)s2, Wk2);
-            w.put(lu + 8 * (int64_t)s2 + 4, bmul(Di, Vk2));
+            w.put(lu + 8 * (int64_t)s2 + 4, bmul(Di, SYM ? btrans(Wk2) : Vk2));
         }
     }
     if (lane == 0) {
@@ -1953,6 +1970,9 @@ __global__ void k_jacobian(DevSym S, const double* yval, int64_t y_stride, const
     }
 }
 
+// SYM: a symmetric matrix; the levels below the LDS tail update the lower
+// blocks only (the tail runs the general LDU, exact for it too).
+template <bool SYM>
 __global__ __launch_bounds__(kLevelThreads) void k_factor(DevSym S, double* vals,
                                                         int64_t vals_stride, int C, int B,
                                                         int32_t* status)
@@ -1964,11 +1984,11 @@ __global__ __launch_bounds__(kLevelThreads) void k_factor(DevSym S, double* vals
     const int64_t lu = S.lu_off;
     if (threadIdx.x == 0) s_bad = 0;
     __syncthreads();
-    const SrcLoad src{w, lu};
+    const SrcLoadT<SYM> src{w, lu};
     for_nodes(S, 0, S.tail_level, true, [&](int, const NodeRec& r, int lane, int g) {
-        factor_node<SrcLoad, false, true>(S, src, r, lane, g, w, lu, w, 0, &s_bad);
+        factor_node<SrcLoadT<SYM>, false, true, SYM>(S, src, r, lane, g, w, lu, w, 0, &s_bad);
     });
-    if (S.tail_nodes > 0) tail_factor<SrcLoad, false, true>(S, src, w, lu, w, 0, &s_bad);
+    if (S.tail_nodes > 0) tail_factor<SrcLoadT<SYM>, false, true>(S, src, w, lu, w, 0, &s_bad);
     __syncthreads();
     if (threadIdx.x == 0 && status) status[c] = s_bad ? ST_ZERO_PIVOT : ST_OK;
 }
@@ -2645,6 +2665,22 @@ int launch_threads(const HostSym& h, int B)
     return B <= 512 ? 512 : 256;
 }
 
+int grid_blocks(int B, int C);
+void allow_big_lds();
+
+// The level-scheduled factorisation of B matrices (sym: symmetric ones).
+void factor_launch(const HostSym& h, int B, double* vals, int64_t stride, int C,
+                   int32_t* status, hipStream_t st, bool sym)
+{
+    allow_big_lds();
+    if (sym)
+        hipLaunchKernelGGL(k_factor<true>, dim3(grid_blocks(B, C)), dim3(launch_threads(h, B)),
+                           h.tail_lds, st, h.dev, vals, stride, C, B, status);
+    else
+        hipLaunchKernelGGL(k_factor<false>, dim3(grid_blocks(B, C)), dim3(launch_threads(h, B)),
+                           h.tail_lds, st, h.dev, vals, stride, C, B, status);
+}
+
 // Blocks for B cases in groups of C placed one XCD round apart.
 int grid_blocks(int B, int C)
 {
@@ -2682,7 +2718,8 @@ void allow_big_lds()
     }
     const void* kernels[] = {reinterpret_cast<const void*>(&k_newton<false>),
                              reinterpret_cast<const void*>(&k_newton<true>),
-                             reinterpret_cast<const void*>(&k_factor),
+                             reinterpret_cast<const void*>(&k_factor<false>),
+                             reinterpret_cast<const void*>(&k_factor<true>),
                              reinterpret_cast<const void*>(&k_solve<false, true>),
                              reinterpret_cast<const void*>(&k_solve<true, true>),
                              reinterpret_cast<const void*>(&k_fdpf)};
@@ -3163,10 +3200,8 @@ int pf_factor(const pf_symbolic s, int B, double* d_vals, int64_t vals_stride,
     if (B > 1 && vals_stride < s->h.vals_doubles())
         return fail(PF_E_WORKSPACE, "pf_factor: vals_stride < vals_doubles");
     if (B == 0) return PF_OK;
-    allow_big_lds();
-    hipLaunchKernelGGL(k_factor, dim3(grid_blocks(B, vals_interleave)),
-                       dim3(launch_threads(s->h, B)), s->h.tail_lds, as_stream(stream), s->h.dev,
-                       d_vals, vals_stride, vals_interleave, B, d_status);
+    factor_launch(s->h, B, d_vals, vals_stride, vals_interleave, d_status, as_stream(stream),
+                  false);
     return launch_check("pf_factor");
 }
 
@@ -3636,7 +3671,9 @@ int pf_se_estimate(const pf_se s, int B, const double* d_r, const double* d_x,
         hipLaunchKernelGGL(k_se_assemble, dim3(G.nn, cg), dim3(64), 0, st, G.dev, s->dev, X, d_w,
                            w_stride, d_status);
         if ((rc = launch_check("pf_se_estimate: assemble"))) return rc;
-        if ((rc = pf_factor(&s->gain, B, X.vals, X.vs, kSeGroup, nullptr, stream))) return rc;
+        // G is symmetric: the lower blocks alone take the updates
+        factor_launch(G, B, X.vals, X.vs, kSeGroup, nullptr, st, true);
+        if ((rc = launch_check("pf_se_estimate: factor"))) return rc;
         if ((rc = pf_solve(&s->gain, B, X.vals, X.vs, kSeGroup, X.rhs, X.rs, 0, stream)))
             return rc;
         hipLaunchKernelGGL(k_se_update, dim3(B), dim3(256), 0, st, G.dev, s->dev, X, d_Vm, d_Va,
