@@ -411,6 +411,7 @@ def bench_multi(grids, label, steps=3):
         syms = list(ex.map(lambda g: api.Symbolic(g.n, g.f, g.t), grids))
     t_an = time.time() - t0
     for s in syms:
+        s.set_launch(0, 161792)  # the largest LDS tail: the launch waits for its largest grid
         s.upload()
     plan = api.MultiPlan(syms)
     f64 = np.float64
