@@ -16,11 +16,16 @@ def _needs_gpu():
         pytest.skip("no GPU")
 
 
-def solve_multi(grids, tol=1e-8, max_iter=20):
+def solve_multi(grids, tol=1e-8, max_iter=20, tail_budget=None):
     from paper_1811_02512_amd import api
     from paper_1811_02512_amd import binding as B
 
-    syms = [api.Symbolic(g.n, g.f, g.t).upload() for g in grids]
+    syms = []
+    for g in grids:
+        s = api.Symbolic(g.n, g.f, g.t)
+        if tail_budget is not None:
+            s.set_launch(0, tail_budget)
+        syms.append(s.upload())
     plan = api.MultiPlan(syms)
     f64 = np.float64
     r = plan.concat([g.r for g in grids], "branch", f64)
@@ -111,3 +116,20 @@ def test_multi_matches_shared_pattern_path():
     np.testing.assert_array_equal(Vms[0], Vm[0].cpu().numpy())
     np.testing.assert_array_equal(Vms[1], Vm[0].cpu().numpy())
     np.testing.assert_array_equal(Vas[0], Va[0].cpu().numpy())
+
+
+def test_mixed_launch_with_the_largest_grids():
+    """The two largest grids of the mixed range (~18-19k buses, too large for
+    the LDS copy of (e, f)) and the two smallest in one launch with the
+    largest LDS tail, each against the oracle."""
+    import json
+    import os
+
+    spec = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "mixed_batch.json")))
+    by_size = sorted(spec["grids"], key=lambda gs: gs["n"])
+    chosen = by_size[-2:] + by_size[:2]
+    log(f"[mixed] sizes {[gs['n'] for gs in chosen]}")
+    grids = [gridgen.make_grid(gs["n"], gs["seed"], load_scale=spec["load_scale"])
+             for gs in chosen]
+    Vms, Vas, it, st, plan = solve_multi(grids, tail_budget=161792)
+    check_against_oracle(grids, Vms, Vas, it, st)
