@@ -1666,9 +1666,9 @@ __device__ __forceinline__ void fd_forward_tail(const DevSym& S, const double* m
         sy[jl] = z;
     }
     __syncthreads();
-    const int nT = S.nlev - S.tail_level;
-    for_tail_pf(S, 0, nT, true, [&](int jl, const int4&, const int4& b, const int4&, int lane,
-                                    int g) {
+    const int nT = S.nlev - S.tail_level, KC = S.tail_clique;
+    for_tail_pf(S, 0, nT - KC, true, [&](int jl, const int4&, const int4& b, const int4&,
+                                         int lane, int g) {
         double z = 0.0;
         for (int r = b.z + lane; r < b.w; r += g) {
             const int2 e = S.t_rl[r];
@@ -1677,6 +1677,34 @@ __device__ __forceinline__ void fd_forward_tail(const DevSym& S, const double* m
         if (g > 1) z = gsum(z, g);
         if (lane == 0) sy[jl] = t.d[jl] * (sy[jl] - z);
     });
+    if (KC > 0) {
+        // the clique (every node adjacent to all above it): first the terms of
+        // the tail nodes below it, all clique nodes at once; then the clique
+        // column by column on the first wavefront (no workgroup barriers)
+        const int kf = S.tail_nodes - KC;
+        for (int c = threadIdx.x; c < KC; c += blockDim.x) {
+            const int jl = kf + c;
+            const int4 b = S.t_node[3 * jl + 1], cm = S.t_node[3 * jl + 2];
+            double z = 0.0;
+            for (int r = b.z; r < cm.x; ++r) {
+                const int2 e = S.t_rl[r];
+                z = fma(t.wu[e.y].x, sy[e.x], z);
+            }
+            sy[jl] -= z;
+        }
+        __syncthreads();
+        if (threadIdx.x < kWave) {
+            const int c0 = S.t_node[3 * kf].w;
+            for (int q = 0; q < KC; ++q) {
+                const double yq = t.d[kf + q] * sy[kf + q];
+                for (int k = q + 1 + threadIdx.x; k < KC; k += kWave)
+                    sy[kf + k] = fma(-t.wu[clique_slot(c0, KC, q, k)].x, yq, sy[kf + k]);
+                if (threadIdx.x == 0) sy[kf + q] = yq;
+                wave_sync();
+            }
+        }
+        __syncthreads();
+    }
 }
 
 // Backward substitution of the tail levels in LDS, downward; then, in one
@@ -1688,9 +1716,23 @@ __device__ __forceinline__ void fd_backward_tail(const DevSym& S, const FdTail& 
                                                  const PvMask& pv, double* xv)
 {
     const int comp = ANGLE ? 0 : 1;
-    const int nT = S.nlev - S.tail_level;
-    for_tail_pf(S, 0, nT, false, [&](int jl, const int4& a, const int4& b, const int4&, int lane,
-                                     int g) {
+    const int nT = S.nlev - S.tail_level, KC = S.tail_clique;
+    if (KC > 0) {
+        // the clique first, column by column on the first wavefront: once x_q
+        // is final, y_k -= u_kq x_q for every clique node k below q
+        if (threadIdx.x < kWave) {
+            const int kf = S.tail_nodes - KC, c0 = S.t_node[3 * kf].w;
+            for (int q = KC - 1; q > 0; --q) {
+                const double xq = sy[kf + q];
+                for (int k = threadIdx.x; k < q; k += kWave)
+                    sy[kf + k] = fma(-t.wu[clique_slot(c0, KC, k, q)].y, xq, sy[kf + k]);
+                wave_sync();
+            }
+        }
+        __syncthreads();
+    }
+    for_tail_pf(S, 0, nT - KC, false, [&](int jl, const int4& a, const int4& b, const int4&,
+                                          int lane, int g) {
         double s = 0.0;
         for (int q = a.w + lane; q < b.x; q += g) s = fma(t.wu[q].y, sy[S.t_slot[3 * q].y], s);
         if (g > 1) s = gsum(s, g);
