@@ -26,8 +26,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ("paper_1811_02512_amd/csrc/pf.hip", "paper_1811_02512_amd/csrc/pf_kernels.h",
-                  "paper_1811_02512_amd/csrc/pf_internal.h", "paper_1811_02512_amd/csrc/analyze.cpp")
+KERNEL_SOURCES = tuple("paper_1811_02512_amd/csrc/" + f for f in (
+    "pf_abi.hip", "pf_newton.hip", "pf_fdpf.hip", "pf_se.hip", "pf_device.h", "pf_host.h",
+    "pf_kernels.h", "pf_internal.h", "analyze.cpp"))
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_newton_10k_x256_hbm_traffic.md")
 
 

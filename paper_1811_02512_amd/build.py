@@ -14,6 +14,8 @@ LIB = os.path.join(PKG, "libpf.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 ARCH = "gfx950"
+# HIP translation units: shared host ABI, Newton path, fast decoupled, state estimation
+KERNEL_FILES = ("pf_abi.hip", "pf_newton.hip", "pf_fdpf.hip", "pf_se.hip")
 # Packed fp32 instructions are kept off for every device compile.
 DEVICE_FLAGS = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang",
                 "-packed-fp32-ops"]
@@ -37,7 +39,7 @@ def build(verbose: bool = False) -> str:
         obj = os.path.join(BUILD, src + ".o")
         _run([HIPCC, *COMMON, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
-    for src in ("pf.hip",):
+    for src in KERNEL_FILES:
         obj = os.path.join(BUILD, src + ".o")
         _run([HIPCC, *COMMON, *DEVICE_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)

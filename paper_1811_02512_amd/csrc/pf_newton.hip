@@ -1,0 +1,912 @@
+// libpf Newton-Raphson path: admittance matrix, mismatch, Jacobian, block
+// LDU, solves, the fused Newton kernel, the adjoint and multi-pattern
+// batches (kernels and their C ABI entry points).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "pf.h"
+#include "pf_device.h"
+#include "pf_host.h"
+
+using namespace pf::abi;
+
+namespace {
+
+// The whole Newton-Raphson loop of one case, run by one workgroup.  The
+// case's voltages and injections are copied into its bus records first and
+// the solution copied back at the end.
+__device__ void newton_case(const DevSym& S, const double* yv, const int8_t* type,
+                            const double* Psp, const double* Qsp, double* Vm, double* Va,
+                            const View& w, const View& wb, double tol, int max_iter,
+                            int flags, int32_t* o_iters, double* o_norm, int32_t* o_status)
+{
+    __shared__ int s_bad;
+    const Off o = ws_off(S);
+    for (int i = threadIdx.x; i < S.n; i += blockDim.x) {
+        double sn, cs;
+        const double vm = Vm[i], va = Va[i];
+        sincos(va, &sn, &cs);
+        wb.put(o.BUS + 8 * (int64_t)i, {vm * cs, vm * sn, vm, va});
+    }
+    pv_fill(S, type);
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
+    const PvMask pvm{pv_words(S)};
+    // the global levels of the factorisation sweep read neighbours' (e, f)
+    // from the LDS copy the mismatch pass just made (the tail reuses that LDS
+    // afterwards and reads them from the bus records)
+    const SrcState src{yv, pvm, wb, o.BUS,
+                       S.ef_lds ? reinterpret_cast<const double2*>(pf_smem) : nullptr};
+    // the backward sweep keeps x in that LDS too (free again once the tail's
+    // backward substitution has read its values)
+    double2* const xs = (S.ef_lds && S.tail_nodes <= 4 * (int)blockDim.x)
+                            ? reinterpret_cast<double2*>(pf_smem)
+                            : nullptr;
+    const EFView ef{wb, o.BUS};
+    const bool tail = S.tail_nodes > 0;
+    int it = 0, st = ST_NOT_CONVERGED;
+    double nrm = 0.0;
+    for (;;) {
+        double mx = 0.0;
+        int nan = 0;
+        if (S.ef_lds) {
+            // every bus's (e, f) into LDS (free until the tail), so that the
+            // admittance rows' voltages are LDS reads
+            const EFLds efl{reinterpret_cast<double2*>(pf_smem)};
+            for (int i = threadIdx.x; i < S.n; i += blockDim.x)
+                efl.s[i] = wb.v2(o.BUS + 8 * (int64_t)i);
+            __syncthreads();
+            mismatch_pass<false>(S, yv, efl, wb, o, pvm, Psp, Qsp, mx, nan);
+        } else {
+            mismatch_pass<false>(S, yv, ef, wb, o, pvm, Psp, Qsp, mx, nan);
+        }
+        int any_nan = 0;
+        nrm = block_max(mx, nan, any_nan);
+        if (any_nan || !isfinite(nrm)) {
+            st = ST_NONFINITE;
+            break;
+        }
+        if (nrm < tol) {
+            st = ST_OK;
+            break;
+        }
+        if (it >= max_iter) {
+            st = ST_NOT_CONVERGED;
+            break;
+        }
+        for_nodes(S, 0, S.tail_level, true, [&](int, const NodeRec& r, int lane, int g) {
+            factor_node<SrcState, true, false>(S, src, r, lane, g, w, o.LU, wb, o.RHS, &s_bad);
+        });
+        if (tail) tail_factor<SrcState, true, false>(S, src, w, o.LU, wb, o.RHS, &s_bad);
+        if (s_bad) {
+            st = ST_ZERO_PIVOT;
+            break;
+        }
+        if (tail) tail_backward<true>(S, wb, o.RHS, o.BUS, pvm, xs);
+        for_nodes(S, 0, S.tail_level, false, [&](int, const NodeRec& r, int lane, int g) {
+            back_node<true>(S, r, lane, g, w, o.LU, wb, o.RHS, o.BUS, pvm, xs);
+        });
+        ++it;
+    }
+    if ((flags & PF_NEWTON_KEEP_FACTORS) && st == ST_OK) {
+        for_nodes(S, 0, S.tail_level, true, [&](int, const NodeRec& r, int lane, int g) {
+            factor_node<SrcState, false, true>(S, src, r, lane, g, w, o.LU, wb, o.RHS, &s_bad);
+        });
+        if (tail) tail_factor<SrcState, false, true>(S, src, w, o.LU, wb, o.RHS, &s_bad);
+        if (s_bad) st = ST_ZERO_PIVOT;
+    }
+    for (int i = threadIdx.x; i < S.n; i += blockDim.x) {
+        const Blk r = wb.blk(o.BUS + 8 * (int64_t)i);
+        Vm[i] = r.c;
+        Va[i] = r.d;
+    }
+    if (threadIdx.x == 0) {
+        if (o_iters) *o_iters = it;
+        if (o_norm) *o_norm = nrm;
+        if (o_status) *o_status = st;
+    }
+}
+
+// Jacobian assembly straight from polar voltages (standalone kernel).
+struct AsmPolar {
+    const DevSym* S;
+    const double* yv;
+    const int8_t* type;
+    const double* Vm;
+    EFPolar ef;
+    __device__ __forceinline__ Blk diag(int j) const
+    {
+        const int bus = S->perm[j];
+        const double2 y = reinterpret_cast<const double2*>(yv)[S->ydiag[j]];
+        double p, q;
+        injection(*S, yv, ef, bus, p, q);
+        return jac_diag(y.x, y.y, p, q, Vm[bus], type[bus] == T_PV);
+    }
+    __device__ __forceinline__ void off(int j, int s, Blk& lo, Blk& up) const
+    {
+        const int ylo = S->ylo[s];
+        if (ylo < 0) {
+            lo = bzero();
+            up = bzero();
+            return;
+        }
+        const int bj = S->perm[j], bk = S->perm[S->Li[s]];
+        double ej, fj, ek, fk;
+        ef.get(bj, ej, fj);
+        ef.get(bk, ek, fk);
+        const bool pj = type[bj] == T_PV, pk = type[bk] == T_PV;
+        const double2 yl = reinterpret_cast<const double2*>(yv)[ylo];
+        const double2 yu = reinterpret_cast<const double2*>(yv)[S->yup[s]];
+        lo = jac_off(yl.x, yl.y, ek, fk, ej, fj, Vm[bj], pk, pj);
+        up = jac_off(yu.x, yu.y, ej, fj, ek, fk, Vm[bk], pj, pk);
+    }
+};
+
+}  // namespace
+
+// ===========================================================================
+// kernels
+// ===========================================================================
+__global__ void k_ybus(DevSym S, const double* __restrict__ r, const double* __restrict__ x,
+                       const double* __restrict__ bc, int64_t bstride,
+                       double* __restrict__ yval, int64_t ystride)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (i >= S.n) return;
+    const double* rc = r + c * bstride;
+    const double* xc = x + c * bstride;
+    const double* bcc = bc + c * bstride;
+    double* yc = yval + c * ystride;
+    for (int q = S.yptr[i]; q < S.yptr[i + 1]; ++q) {
+        const bool diag = S.ycol[q] == i;
+        double G = 0.0, Bv = 0.0;
+        for (int t = S.ybr_ptr[q]; t < S.ybr_ptr[q + 1]; ++t) {
+            const int e = S.ybr[t];
+            const double rr = rc[e], xx = xc[e];
+            const double den = rr * rr + xx * xx;
+            const double yg = rr / den, yb = -xx / den;
+            if (diag) {
+                G += yg;
+                Bv += yb + 0.5 * bcc[e];
+            } else {
+                G -= yg;
+                Bv -= yb;
+            }
+        }
+        reinterpret_cast<double2*>(yc)[q] = make_double2(G, Bv);
+    }
+}
+
+__global__ void k_ybus_multi(const CaseDesc* __restrict__ descs, const double* __restrict__ r,
+                             const double* __restrict__ x, const double* __restrict__ bc,
+                             double* __restrict__ yval)
+{
+    const CaseDesc& cd = descs[blockIdx.x];
+    const DevSym& S = cd.sym;
+    const double* rc = r + cd.br_off;
+    const double* xc = x + cd.br_off;
+    const double* bcc = bc + cd.br_off;
+    double* yc = yval + cd.y_off;
+    for (int i = threadIdx.x; i < S.n; i += blockDim.x) {
+        for (int q = S.yptr[i]; q < S.yptr[i + 1]; ++q) {
+            const bool diag = S.ycol[q] == i;
+            double G = 0.0, Bv = 0.0;
+            for (int t = S.ybr_ptr[q]; t < S.ybr_ptr[q + 1]; ++t) {
+                const int e = S.ybr[t];
+                const double rr = rc[e], xx = xc[e];
+                const double den = rr * rr + xx * xx;
+                const double yg = rr / den, yb = -xx / den;
+                if (diag) {
+                    G += yg;
+                    Bv += yb + 0.5 * bcc[e];
+                } else {
+                    G -= yg;
+                    Bv -= yb;
+                }
+            }
+            reinterpret_cast<double2*>(yc)[q] = make_double2(G, Bv);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kMaxThreads) void k_mismatch(
+    DevSym S, const double* yval, int64_t y_stride, const int8_t* type, int64_t type_stride,
+    const double* Psp, const double* Qsp, int64_t inj_stride, const double* Vm,
+    const double* Va, int64_t v_stride, double* rhs, int64_t rhs_stride, double* norm,
+    double* PQ)
+{
+    const int c = blockIdx.x;
+    const EFPolar ef{Vm + c * v_stride, Va + c * v_stride};
+    int any_nan = 0;
+    double* pq = PQ ? PQ + (int64_t)c * 2 * S.n : nullptr;
+    double m = 0.0;
+    int nan = 0;
+    const double* yv = yval + c * y_stride;
+    const int8_t* ty = type + c * type_stride;
+    const double* ps = Psp + c * inj_stride;
+    const double* qs = Qsp + c * inj_stride;
+    double* rh = rhs + c * rhs_stride;
+    for (int i = threadIdx.x; i < S.n; i += blockDim.x) {
+        double p, q;
+        injection(S, yv, ef, i, p, q);
+        if (pq) reinterpret_cast<double2*>(pq)[i] = make_double2(p, q);
+        const int po = S.pos[i];
+        if (po >= 0) {
+            const double fp = p - ps[i];
+            const double fq = (ty[i] == T_PV) ? 0.0 : q - qs[i];
+            reinterpret_cast<double2*>(rh)[po] = make_double2(fp, fq);
+            nan |= (fp != fp) | (fq != fq);
+            m = fmax(m, fmax(fabs(fp), fabs(fq)));
+        }
+    }
+    const double r = block_max(m, nan, any_nan);
+    if (threadIdx.x == 0 && norm) norm[c] = any_nan ? __builtin_nan("") : r;
+}
+
+__global__ void k_jacobian(DevSym S, const double* yval, int64_t y_stride, const int8_t* type,
+                           int64_t type_stride, const double* Vm, const double* Va,
+                           int64_t v_stride, double* vals, int64_t vals_stride, int C)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (j >= S.nn) return;
+    const EFPolar ef{Vm + c * v_stride, Va + c * v_stride};
+    const AsmPolar A{&S, yval + c * y_stride, type + c * type_stride, Vm + c * v_stride, ef};
+    const View w = case_view(vals, vals_stride, C, c);
+    const int64_t lu = S.lu_off;
+    w.put(4 * (int64_t)j, A.diag(j));
+    for (int s = S.Lp[j]; s < S.Lp[j + 1]; ++s) {
+        Blk lo, up;
+        A.off(j, s, lo, up);
+        w.put(lu + 8 * (int64_t)s, lo);
+        w.put(lu + 8 * (int64_t)s + 4, up);
+    }
+}
+
+// SYM: a symmetric matrix; the levels below the LDS tail update the lower
+// blocks only (the tail runs the general LDU, exact for it too).
+template <bool SYM>
+__global__ __launch_bounds__(kLevelThreads) void k_factor(DevSym S, double* vals,
+                                                        int64_t vals_stride, int C, int B,
+                                                        int32_t* status)
+{
+    __shared__ int s_bad;
+    const int c = case_of_block(blockIdx.x, C, B);
+    if (c < 0) return;
+    const View w = case_view(vals, vals_stride, C, c);
+    const int64_t lu = S.lu_off;
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
+    const SrcLoadT<SYM> src{w, lu};
+    for_nodes(S, 0, S.tail_level, true, [&](int, const NodeRec& r, int lane, int g) {
+        factor_node<SrcLoadT<SYM>, false, true, SYM>(S, src, r, lane, g, w, lu, w, 0, &s_bad);
+    });
+    if (S.tail_nodes > 0) tail_factor<SrcLoadT<SYM>, false, true>(S, src, w, lu, w, 0, &s_bad);
+    __syncthreads();
+    if (threadIdx.x == 0 && status) status[c] = s_bad ? ST_ZERO_PIVOT : ST_OK;
+}
+
+// transpose = 0: y_j = D_j^-1 (b_j - sum_{i in R(j)} W_ji y_i)  (levels up),
+//                x_j = y_j - sum_{k in S(j)} U_jk x_k            (levels down).
+// transpose = 1: p_j = g_j - sum_{i in R(j)} U_ij^T p_i           (levels up),
+//                l_j = D_j^-T (p_j - sum_{k in S(j)} W_kj^T l_k)  (levels down).
+// A node's g lanes take its list entries in strides of g, four per lane per
+// step with the step's blocks and x values requested together; absent
+// entries of a step re-read the node's first entry (in bounds whenever the
+// list is not empty) and add nothing.  LDSX keeps the case's whole vector
+// in LDS (nn x 16 bytes) for the two sweeps.
+template <bool TRANS, bool LDSX>
+__global__ __launch_bounds__(kLevelThreads) void k_solve(DevSym S, const double* vals,
+                                                       int64_t vals_stride, int C, int B,
+                                                       double* rhs, int64_t rhs_stride)
+{
+    const int c = case_of_block(blockIdx.x, C, B);
+    if (c < 0) return;
+    const View w = case_view(const_cast<double*>(vals), vals_stride, C, c);
+    const int64_t lu = S.lu_off;
+    double2* xg = reinterpret_cast<double2*>(rhs + c * rhs_stride);
+    double2* x2 = LDSX ? reinterpret_cast<double2*>(pf_smem) : xg;
+    if (LDSX) {
+        for (int p = threadIdx.x; p < S.nn; p += blockDim.x) x2[p] = xg[p];
+        __syncthreads();
+    }
+    for_nodes(S, 0, S.nlev, true, [&](int, const NodeRec& rec, int lane, int g) {
+        const int j = rec.a.x, r0 = rec.a.z, r1 = rec.a.w;
+        double z0 = 0.0, z1 = 0.0;
+        for (int base = r0 + lane; base < r1; base += 4 * g) {
+            int2 e[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int r = base + k * g;
+                e[k] = S.rl[r < r1 ? r : r0];
+            }
+            Blk M[4];
+            double2 xv[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                M[k] = w.blk(lu + 8 * (int64_t)e[k].y + (TRANS ? 4 : 0));
+                xv[k] = x2[e[k].x];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (base + k * g < r1) {
+                    if (TRANS) mtvadd(z0, z1, M[k], xv[k].x, xv[k].y);
+                    else mvadd(z0, z1, M[k], xv[k].x, xv[k].y);
+                }
+            }
+        }
+        if (g > 1) {
+            z0 = gsum(z0, g);
+            z1 = gsum(z1, g);
+        }
+        if (lane == 0) {
+            const double2 b = x2[j];
+            double u0 = b.x - z0, u1 = b.y - z1;
+            if (!TRANS) {
+                const Blk Di = w.blk(4 * (int64_t)j);
+                double y0 = 0.0, y1 = 0.0;
+                mvadd(y0, y1, Di, u0, u1);
+                u0 = y0;
+                u1 = y1;
+            }
+            x2[j] = make_double2(u0, u1);
+        }
+    });
+    for_nodes(S, 0, S.nlev, false, [&](int, const NodeRec& rec, int lane, int g) {
+        const int j = rec.a.x, s0 = rec.b.x, s1 = rec.b.y;
+        double a0 = 0.0, a1 = 0.0;
+        for (int base = s0 + lane; base < s1; base += 4 * g) {
+            int sk[4], kk[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int s = base + k * g;
+                sk[k] = s < s1 ? s : s0;
+                kk[k] = S.Li[sk[k]];
+            }
+            Blk M[4];
+            double2 xv[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                M[k] = w.blk(lu + 8 * (int64_t)sk[k] + (TRANS ? 0 : 4));
+                xv[k] = x2[kk[k]];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (base + k * g < s1) {
+                    if (TRANS) mtvadd(a0, a1, M[k], xv[k].x, xv[k].y);
+                    else mvadd(a0, a1, M[k], xv[k].x, xv[k].y);
+                }
+            }
+        }
+        if (g > 1) {
+            a0 = gsum(a0, g);
+            a1 = gsum(a1, g);
+        }
+        if (lane == 0) {
+            const double2 y = x2[j];
+            double u0 = y.x - a0, u1 = y.y - a1;
+            if (TRANS) {
+                const Blk Di = w.blk(4 * (int64_t)j);
+                double l0 = 0.0, l1 = 0.0;
+                mtvadd(l0, l1, Di, u0, u1);
+                u0 = l0;
+                u1 = l1;
+            }
+            x2[j] = make_double2(u0, u1);
+        }
+    });
+    if (LDSX)
+        for (int p = threadIdx.x; p < S.nn; p += blockDim.x) xg[p] = x2[p];
+}
+
+template <bool MULTI>
+__global__ __launch_bounds__(kLevelThreads) void k_newton(DevSym Sarg,
+                                                        const CaseDesc* __restrict__ descs,
+                                                        const int32_t* __restrict__ order,
+                                                        NewtonArgs a)
+{
+    if (MULTI) {
+        const int c = order[blockIdx.x];
+        const CaseDesc& cd = descs[c];
+        const DevSym S = cd.sym;
+        const View w = case_view(a.ws + cd.ws_off, 0, 1, 0);
+        const View wb = case_bus_view(a.ws + cd.ws_off, 0, 1, 0, S.vals_doubles);
+        newton_case(S, a.yval + cd.y_off, a.type + cd.bus_off, a.Psp + cd.bus_off,
+                    a.Qsp + cd.bus_off, a.Vm + cd.bus_off, a.Va + cd.bus_off, w, wb, a.tol,
+                    a.max_iter, a.flags, a.iters ? a.iters + c : nullptr,
+                    a.norm ? a.norm + c : nullptr, a.status ? a.status + c : nullptr);
+    } else {
+        const int c = case_of_block(blockIdx.x, a.interleave, a.B);
+        if (c < 0) return;
+        const View w = case_view(a.ws, a.ws_stride, a.interleave, c);
+        const View wb = case_bus_view(a.ws, a.ws_stride, a.interleave, c, Sarg.vals_doubles);
+        newton_case(Sarg, a.yval + c * a.y_stride, a.type + c * a.type_stride,
+                    a.Psp + c * a.inj_stride, a.Qsp + c * a.inj_stride, a.Vm + c * a.v_stride,
+                    a.Va + c * a.v_stride, w, wb, a.tol, a.max_iter, a.flags,
+                    a.iters ? a.iters + c : nullptr, a.norm ? a.norm + c : nullptr,
+                    a.status ? a.status + c : nullptr);
+    }
+}
+
+__global__ void k_adj_rhs(DevSym S, const double* gVm, const double* gVa, int64_t v_stride,
+                          const int8_t* type, int64_t type_stride, double* rhs,
+                          int64_t rhs_stride)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (p >= S.nn) return;
+    const int bus = S.perm[p];
+    const double ga = gVa[c * v_stride + bus];
+    const double gm = (type[c * type_stride + bus] == T_PV) ? 0.0 : gVm[c * v_stride + bus];
+    reinterpret_cast<double2*>(rhs + c * rhs_stride)[p] = make_double2(ga, gm);
+}
+
+__global__ void k_adj_bus(DevSym S, const double* lam, int64_t lam_stride, const int8_t* type,
+                          int64_t type_stride, double* gP, double* gQ, int64_t g_stride)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (i >= S.n) return;
+    const int p = S.pos[i];
+    double lp = 0.0, lq = 0.0;
+    if (p >= 0) {
+        const double2 l = reinterpret_cast<const double2*>(lam + c * lam_stride)[p];
+        lp = l.x;
+        lq = (type[c * type_stride + i] == T_PV) ? 0.0 : l.y;
+    }
+    gP[c * g_stride + i] = lp;
+    gQ[c * g_stride + i] = lq;
+}
+
+// dL/dx_e for one case: dS_f = V_f conj(dy (V_f - V_t)), dS_t = V_t conj(dy (V_t - V_f)),
+// dy = -j y^2, gx = -(lamP_f Re dS_f + lamQ_f Im dS_f + same at t).
+__device__ __forceinline__ double adj_branch(const DevSym& S, int fb, int tb,
+                                             const double* lam, const int8_t* type,
+                                             const double* Vm, const double* Va, double r,
+                                             double x)
+{
+    const double den = r * r + x * x;
+    const double yr = r / den, yi = -x / den;
+    const double dyr = 2.0 * yr * yi, dyi = -(yr * yr - yi * yi);
+    double sf, cf, st, ct;
+    sincos(Va[fb], &sf, &cf);
+    sincos(Va[tb], &st, &ct);
+    const double ef = Vm[fb] * cf, ff = Vm[fb] * sf;
+    const double et = Vm[tb] * ct, ft = Vm[tb] * st;
+    const double dr = ef - et, di = ff - ft;
+    const double cr = dyr * dr - dyi * di, ci = dyr * di + dyi * dr;
+    double acc = 0.0;
+    const int pf_ = S.pos[fb], pt_ = S.pos[tb];
+    const double2* l2 = reinterpret_cast<const double2*>(lam);
+    if (pf_ >= 0) {
+        const double2 l = l2[pf_];
+        const double lq = (type[fb] == T_PV) ? 0.0 : l.y;
+        acc += l.x * (ef * cr + ff * ci) + lq * (ff * cr - ef * ci);
+    }
+    if (pt_ >= 0) {
+        const double2 l = l2[pt_];
+        const double lq = (type[tb] == T_PV) ? 0.0 : l.y;
+        acc += l.x * (-(et * cr + ft * ci)) + lq * (-(ft * cr - et * ci));
+    }
+    return -acc;
+}
+
+// mode 1 (x shared by the cases): one workgroup per 64 branches, its waves
+// split the cases and combine them in a fixed order, so no atomics are
+// needed and the sum is reproducible.  mode 0: one thread per (case, branch).
+__global__ void k_adj_branch(DevSym S, const int32_t* __restrict__ from,
+                             const int32_t* __restrict__ to, int B, const double* lam,
+                             int64_t lam_stride, const int8_t* type, int64_t type_stride,
+                             const double* Vm, const double* Va, int64_t v_stride,
+                             const double* r, const double* x, int64_t branch_stride,
+                             double* gx, int mode)
+{
+    if (mode == 1) {
+        __shared__ double part[16][64];
+        const int e = blockIdx.x * 64 + (threadIdx.x & 63);
+        const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+        double acc = 0.0;
+        if (e < S.m) {
+            const int fb = from[e], tb = to[e];
+            for (int c = wv; c < B; c += nw)
+                acc += adj_branch(S, fb, tb, lam + c * lam_stride, type + c * type_stride,
+                                  Vm + c * v_stride, Va + c * v_stride,
+                                  r[c * branch_stride + e], x[c * branch_stride + e]);
+        }
+        part[wv][threadIdx.x & 63] = acc;
+        __syncthreads();
+        if (wv == 0 && e < S.m) {
+            double s = 0.0;
+            for (int k = 0; k < nw; ++k) s += part[k][threadIdx.x];
+            gx[e] = s;
+        }
+    } else {
+        const int e = blockIdx.x * blockDim.x + threadIdx.x;
+        const int c = blockIdx.y;
+        if (e >= S.m) return;
+        gx[(int64_t)c * S.m + e] =
+            adj_branch(S, from[e], to[e], lam + c * lam_stride, type + c * type_stride,
+                       Vm + c * v_stride, Va + c * v_stride, r[c * branch_stride + e],
+                       x[c * branch_stride + e]);
+    }
+}
+
+
+struct pf_multi_s {
+
+    std::vector<pf_symbolic> syms;
+    std::vector<int64_t> bus_off, br_off, y_off, ws_off;
+    std::vector<int32_t> order;
+    const CaseDesc* d_desc = nullptr;
+    const int32_t* d_order = nullptr;
+    bool uploaded = false;
+};
+
+
+namespace {
+
+// Dynamic LDS of the Newton kernel: the tail and the (e, f) copy share the
+// front, the PV mask follows the larger of the two.
+int newton_lds(const HostSym& h)
+{
+    return std::max(h.tail_lds, h.ef_lds) + (int)pv_mask_bytes(h.n);
+}
+
+// Raises the dynamic-LDS limit of the level-scheduled kernels to what the
+// device allows (160 KB per workgroup on gfx950) minus their static LDS.
+// Failures only keep the default limit; the sticky error is cleared so that
+// it is not reported by the next launch check.
+void allow_big_lds()
+{
+    static bool done = false;
+    if (done) return;
+    done = true;
+    int dev = 0, lds_max = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+            hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    const void* kernels[] = {reinterpret_cast<const void*>(&k_newton<false>),
+                             reinterpret_cast<const void*>(&k_newton<true>),
+                             reinterpret_cast<const void*>(&k_factor<false>),
+                             reinterpret_cast<const void*>(&k_factor<true>),
+                             reinterpret_cast<const void*>(&k_solve<false, true>),
+                             reinterpret_cast<const void*>(&k_solve<true, true>)};
+    for (const void* k : kernels) {
+        hipFuncAttributes fa{};
+        if (hipFuncGetAttributes(&fa, k) == hipSuccess) {
+            const int dyn = lds_max - (int)fa.sharedSizeBytes;
+            if (dyn > 0)
+                (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+        }
+    }
+    (void)hipGetLastError();
+}
+
+}  // namespace
+
+namespace pf {
+namespace abi {
+
+// The level-scheduled factorisation of B matrices (sym: symmetric ones).
+void factor_launch(const HostSym& h, int B, double* vals, int64_t stride, int C,
+                   int32_t* status, hipStream_t st, bool sym)
+{
+    allow_big_lds();
+    if (sym)
+        hipLaunchKernelGGL(k_factor<true>, dim3(grid_blocks(B, C)), dim3(launch_threads(h, B)),
+                           h.tail_lds, st, h.dev, vals, stride, C, B, status);
+    else
+        hipLaunchKernelGGL(k_factor<false>, dim3(grid_blocks(B, C)), dim3(launch_threads(h, B)),
+                           h.tail_lds, st, h.dev, vals, stride, C, B, status);
+}
+
+}  // namespace abi
+}  // namespace pf
+
+extern "C" {
+int pf_build_ybus(const pf_symbolic s, int B, const double* d_r, const double* d_x,
+                  const double* d_b, int64_t branch_stride, double* d_yval, int64_t y_stride,
+                  void* stream)
+{
+    if (!ready(s, "pf_build_ybus")) return PF_E_INVALID;
+    if (B < 0 || B > 65535 || !d_r || !d_x || !d_b || !d_yval)
+        return fail(PF_E_INVALID, "pf_build_ybus: bad arguments");
+    if (B > 1 && y_stride < 2 * (int64_t)s->h.ycol.size())
+        return fail(PF_E_WORKSPACE, "pf_build_ybus: y_stride < 2*nnz_y");
+    if (B == 0) return PF_OK;
+    dim3 grid((s->h.n + 255) / 256, B);
+    hipLaunchKernelGGL(k_ybus, grid, dim3(256), 0, as_stream(stream), s->h.dev, d_r, d_x, d_b,
+                       branch_stride, d_yval, y_stride);
+    return launch_check("pf_build_ybus");
+}
+
+int pf_mismatch(const pf_symbolic s, int B, const double* d_yval, int64_t y_stride,
+                const int8_t* d_type, int64_t type_stride, const double* d_Psp,
+                const double* d_Qsp, int64_t inj_stride, const double* d_Vm, const double* d_Va,
+                int64_t v_stride, double* d_rhs, int64_t rhs_stride, double* d_norm,
+                double* d_PQ, void* stream)
+{
+    if (!ready(s, "pf_mismatch")) return PF_E_INVALID;
+    if (B < 0 || !d_yval || !d_type || !d_Psp || !d_Qsp || !d_Vm || !d_Va || !d_rhs)
+        return fail(PF_E_INVALID, "pf_mismatch: bad arguments");
+    if (B == 0) return PF_OK;
+    hipLaunchKernelGGL(k_mismatch, dim3(B), dim3(256), 0, as_stream(stream), s->h.dev, d_yval,
+                       y_stride, d_type, type_stride, d_Psp, d_Qsp, inj_stride, d_Vm, d_Va,
+                       v_stride, d_rhs, rhs_stride, d_norm, d_PQ);
+    return launch_check("pf_mismatch");
+}
+
+int pf_jacobian(const pf_symbolic s, int B, const double* d_yval, int64_t y_stride,
+                const int8_t* d_type, int64_t type_stride, const double* d_Vm, const double* d_Va,
+                int64_t v_stride, double* d_vals, int64_t vals_stride, int vals_interleave,
+                void* stream)
+{
+    if (!ready(s, "pf_jacobian")) return PF_E_INVALID;
+    if (B < 0 || B > 65535 || !d_yval || !d_type || !d_Vm || !d_Va || !d_vals ||
+        !valid_interleave(vals_interleave) || (vals_stride & 7))
+        return fail(PF_E_INVALID, "pf_jacobian: bad arguments");
+    if (B > 1 && vals_stride < s->h.vals_doubles())
+        return fail(PF_E_WORKSPACE, "pf_jacobian: vals_stride < vals_doubles");
+    if (B == 0 || s->h.nn == 0) return PF_OK;
+    dim3 grid((s->h.nn + 255) / 256, B);
+    hipLaunchKernelGGL(k_jacobian, grid, dim3(256), 0, as_stream(stream), s->h.dev, d_yval,
+                       y_stride, d_type, type_stride, d_Vm, d_Va, v_stride, d_vals, vals_stride,
+                       vals_interleave);
+    return launch_check("pf_jacobian");
+}
+
+int pf_factor(const pf_symbolic s, int B, double* d_vals, int64_t vals_stride,
+              int vals_interleave, int32_t* d_status, void* stream)
+{
+    if (!ready(s, "pf_factor")) return PF_E_INVALID;
+    if (B < 0 || !d_vals || !valid_interleave(vals_interleave) || (vals_stride & 7))
+        return fail(PF_E_INVALID, "pf_factor: bad arguments");
+    if (B > 1 && vals_stride < s->h.vals_doubles())
+        return fail(PF_E_WORKSPACE, "pf_factor: vals_stride < vals_doubles");
+    if (B == 0) return PF_OK;
+    factor_launch(s->h, B, d_vals, vals_stride, vals_interleave, d_status, as_stream(stream),
+                  false);
+    return launch_check("pf_factor");
+}
+
+int pf_solve(const pf_symbolic s, int B, const double* d_vals, int64_t vals_stride,
+             int vals_interleave, double* d_rhs, int64_t rhs_stride, int transpose, void* stream)
+{
+    if (!ready(s, "pf_solve")) return PF_E_INVALID;
+    if (B < 0 || !d_vals || !d_rhs || (transpose != 0 && transpose != 1) ||
+        !valid_interleave(vals_interleave) || (vals_stride & 7))
+        return fail(PF_E_INVALID, "pf_solve: bad arguments");
+    if (B > 1 && rhs_stride < 2 * (int64_t)s->h.nn)
+        return fail(PF_E_WORKSPACE, "pf_solve: rhs_stride < 2*nn");
+    if (B == 0) return PF_OK;
+    const dim3 grid(grid_blocks(B, vals_interleave)), block(launch_threads(s->h, B));
+    // the case's vector in LDS when it fits beside nothing else (nn x 16 bytes)
+    const size_t xbytes = 16 * (size_t)s->h.nn;
+    const bool lds = xbytes <= kSolveLdsMax;
+    if (lds) allow_big_lds();
+    auto go = [&](auto kern, size_t shm) {
+        hipLaunchKernelGGL(kern, grid, block, shm, as_stream(stream), s->h.dev, d_vals,
+                           vals_stride, vals_interleave, B, d_rhs, rhs_stride);
+    };
+    if (transpose) {
+        if (lds) go(k_solve<true, true>, xbytes);
+        else go(k_solve<true, false>, 0);
+    } else {
+        if (lds) go(k_solve<false, true>, xbytes);
+        else go(k_solve<false, false>, 0);
+    }
+    return launch_check("pf_solve");
+}
+
+int pf_newton(const pf_symbolic s, int B, const double* d_yval, int64_t y_stride,
+              const int8_t* d_type, int64_t type_stride, const double* d_Psp,
+              const double* d_Qsp, int64_t inj_stride, double* d_Vm, double* d_Va,
+              int64_t v_stride, double tol, int max_iter, int flags, double* d_ws,
+              int64_t ws_stride, int32_t* d_iters, double* d_norm, int32_t* d_status,
+              void* stream)
+{
+    if (!ready(s, "pf_newton")) return PF_E_INVALID;
+    if (B < 0 || max_iter < 0 || !(tol >= 0.0) || !d_yval || !d_type || !d_Psp || !d_Qsp ||
+        !d_Vm || !d_Va || !d_ws)
+        return fail(PF_E_INVALID, "pf_newton: bad arguments");
+    if (B > 1 && v_stride < s->h.n)
+        return fail(PF_E_WORKSPACE, "pf_newton: v_stride too small");
+    if (ws_stride < s->h.ws_doubles() || (ws_stride & 7))
+        return fail(PF_E_WORKSPACE, "pf_newton: ws_stride must be >= ws_doubles, a multiple of 8");
+    if (reinterpret_cast<uintptr_t>(d_ws) & 15)
+        return fail(PF_E_WORKSPACE, "pf_newton: workspace must be 16-byte aligned");
+    if (B == 0) return PF_OK;
+    const int C = newton_interleave(s->h, B);
+    NewtonArgs a{d_yval, y_stride, d_type, type_stride, d_Psp, d_Qsp, inj_stride, d_Vm, d_Va,
+                 v_stride, d_ws, ws_stride, tol, max_iter, flags, C, B, d_iters, d_norm,
+                 d_status};
+    allow_big_lds();
+    hipLaunchKernelGGL(k_newton<false>, dim3(grid_blocks(B, C)), dim3(launch_threads(s->h, B)),
+                       newton_lds(s->h), as_stream(stream), s->h.dev, (const CaseDesc*)nullptr,
+                       (const int32_t*)nullptr, a);
+    return launch_check("pf_newton");
+}
+
+int pf_adjoint_params(const pf_symbolic s, int B, const double* d_lam, int64_t lam_stride,
+                      const int8_t* d_type, int64_t type_stride, const double* d_Vm,
+                      const double* d_Va, int64_t v_stride, const double* d_r,
+                      const double* d_x, int64_t branch_stride, double* d_gP, double* d_gQ,
+                      int64_t g_stride, double* d_gx, int gx_mode, void* stream)
+{
+    if (!ready(s, "pf_adjoint_params")) return PF_E_INVALID;
+    if (B < 0 || B > 65535 || !d_lam || !d_type || !d_Vm || !d_Va ||
+        (gx_mode != 0 && gx_mode != 1))
+        return fail(PF_E_INVALID, "pf_adjoint_params: bad arguments");
+    if (B == 0) return PF_OK;
+    if (d_gP && d_gQ) {
+        dim3 grid((s->h.n + 255) / 256, B);
+        hipLaunchKernelGGL(k_adj_bus, grid, dim3(256), 0, as_stream(stream), s->h.dev, d_lam,
+                           lam_stride, d_type, type_stride, d_gP, d_gQ, g_stride);
+        int rc = launch_check("pf_adjoint_params");
+        if (rc) return rc;
+    }
+    if (d_gx && s->h.m > 0) {
+        if (!d_r || !d_x) return fail(PF_E_INVALID, "pf_adjoint_params: need r and x");
+        const dim3 grid(gx_mode == 1 ? (s->h.m + 63) / 64 : (s->h.m + 255) / 256,
+                        gx_mode == 1 ? 1 : B);
+        const dim3 block(gx_mode == 1 ? 1024 : 256);
+        hipLaunchKernelGGL(k_adj_branch, grid, block, 0, as_stream(stream), s->h.dev,
+                           s->d_from, s->d_to, B, d_lam, lam_stride, d_type, type_stride, d_Vm,
+                           d_Va, v_stride, d_r, d_x, branch_stride, d_gx, gx_mode);
+        return launch_check("pf_adjoint_params");
+    }
+    return PF_OK;
+}
+
+int pf_adjoint_rhs(const pf_symbolic s, int B, const double* d_gVm, const double* d_gVa,
+                   int64_t v_stride, const int8_t* d_type, int64_t type_stride, double* d_rhs,
+                   int64_t rhs_stride, void* stream)
+{
+    if (!ready(s, "pf_adjoint_rhs")) return PF_E_INVALID;
+    if (B < 0 || B > 65535 || !d_gVm || !d_gVa || !d_type || !d_rhs)
+        return fail(PF_E_INVALID, "pf_adjoint_rhs: bad arguments");
+    if (B > 1 && rhs_stride < 2 * (int64_t)s->h.nn)
+        return fail(PF_E_WORKSPACE, "pf_adjoint_rhs: rhs_stride < 2*nn");
+    if (B == 0) return PF_OK;
+    dim3 grid((s->h.nn + 255) / 256, B);
+    hipLaunchKernelGGL(k_adj_rhs, grid, dim3(256), 0, as_stream(stream), s->h.dev, d_gVm,
+                       d_gVa, v_stride, d_type, type_stride, d_rhs, rhs_stride);
+    return launch_check("pf_adjoint_rhs");
+}
+
+// ---- multi-pattern batches -----------------------------------------------
+int pf_multi_create(int G, const pf_symbolic* syms, pf_multi* out)
+{
+    if (!out || G < 0 || (G > 0 && !syms)) return fail(PF_E_INVALID, "pf_multi_create: bad args");
+    *out = nullptr;
+    pf_multi p = new pf_multi_s();
+    p->syms.assign(syms, syms + G);
+    p->bus_off.assign(G + 1, 0);
+    p->br_off.assign(G + 1, 0);
+    p->y_off.assign(G + 1, 0);
+    p->ws_off.assign(G + 1, 0);
+    std::vector<int64_t> work(G);
+    for (int g = 0; g < G; ++g) {
+        if (!syms[g]) {
+            delete p;
+            return fail(PF_E_INVALID, "pf_multi_create: NULL symbolic");
+        }
+        const HostSym& h = syms[g]->h;
+        p->bus_off[g + 1] = p->bus_off[g] + h.n;
+        p->br_off[g + 1] = p->br_off[g] + h.m;
+        p->y_off[g + 1] = p->y_off[g] + 2 * (int64_t)h.ycol.size();
+        p->ws_off[g + 1] = p->ws_off[g] + h.ws_doubles();
+        work[g] = (int64_t)h.Ua.size() + 4 * (int64_t)h.Li.size() + 8 * (int64_t)h.n +
+                  64 * (int64_t)(h.level_ptr.size());
+    }
+    p->order.resize(G);
+    std::iota(p->order.begin(), p->order.end(), 0);
+    std::stable_sort(p->order.begin(), p->order.end(),
+                     [&](int a, int b) { return work[a] > work[b]; });
+    *out = p;
+    return PF_OK;
+}
+
+int pf_multi_info(const pf_multi p, size_t* dev_bytes, int64_t* bus_off, int64_t* branch_off,
+                  int64_t* y_off, int64_t* ws_off)
+{
+    if (!p) return fail(PF_E_INVALID, "pf_multi_info: NULL plan");
+    size_t G = p->syms.size();
+    if (dev_bytes)
+        *dev_bytes = ((G * sizeof(CaseDesc) + 255) & ~(size_t)255) +
+                     ((std::max<size_t>(G, 1) * 4 + 255) & ~(size_t)255);
+    auto cp = [&](int64_t* dst, const std::vector<int64_t>& v) {
+        if (dst) std::memcpy(dst, v.data(), v.size() * sizeof(int64_t));
+    };
+    cp(bus_off, p->bus_off);
+    cp(branch_off, p->br_off);
+    cp(y_off, p->y_off);
+    cp(ws_off, p->ws_off);
+    return PF_OK;
+}
+
+int pf_multi_upload(pf_multi p, void* d_buf, size_t bytes, void* stream)
+{
+    if (!p || !d_buf) return fail(PF_E_INVALID, "pf_multi_upload: NULL argument");
+    size_t need;
+    pf_multi_info(p, &need, nullptr, nullptr, nullptr, nullptr);
+    if (bytes < need) return fail(PF_E_WORKSPACE, "pf_multi_upload: buffer too small");
+    if (reinterpret_cast<uintptr_t>(d_buf) & 255)
+        return fail(PF_E_WORKSPACE, "pf_multi_upload: buffer not 256-byte aligned");
+    size_t G = p->syms.size();
+    std::vector<char> stage(need, 0);
+    CaseDesc* cd = reinterpret_cast<CaseDesc*>(stage.data());
+    for (size_t g = 0; g < G; ++g) {
+        if (!p->syms[g]->h.uploaded)
+            return fail(PF_E_INVALID, "pf_multi_upload: a symbolic is not uploaded");
+        cd[g].sym = p->syms[g]->h.dev;
+        cd[g].bus_off = p->bus_off[g];
+        cd[g].br_off = p->br_off[g];
+        cd[g].y_off = p->y_off[g];
+        cd[g].ws_off = p->ws_off[g];
+    }
+    size_t ooff = (G * sizeof(CaseDesc) + 255) & ~(size_t)255;
+    if (G) std::memcpy(stage.data() + ooff, p->order.data(), G * sizeof(int32_t));
+    int rc = hip_check(hipMemcpyAsync(d_buf, stage.data(), need, hipMemcpyHostToDevice,
+                                      as_stream(stream)),
+                       "pf_multi_upload: hipMemcpyAsync");
+    if (rc) return rc;
+    rc = hip_check(hipStreamSynchronize(as_stream(stream)), "pf_multi_upload: sync");
+    if (rc) return rc;
+    p->d_desc = reinterpret_cast<const CaseDesc*>(d_buf);
+    p->d_order = reinterpret_cast<const int32_t*>(static_cast<char*>(d_buf) + ooff);
+    p->uploaded = true;
+    return PF_OK;
+}
+
+int pf_build_ybus_multi(const pf_multi p, const double* d_r, const double* d_x,
+                        const double* d_b, double* d_yval, void* stream)
+{
+    if (!p || !p->uploaded) return fail(PF_E_INVALID, "pf_build_ybus_multi: plan not uploaded");
+    if (!d_r || !d_x || !d_b || !d_yval) return fail(PF_E_INVALID, "pf_build_ybus_multi: NULL");
+    if (p->syms.empty()) return PF_OK;
+    hipLaunchKernelGGL(k_ybus_multi, dim3(p->syms.size()), dim3(256), 0, as_stream(stream),
+                       p->d_desc, d_r, d_x, d_b, d_yval);
+    return launch_check("pf_build_ybus_multi");
+}
+
+int pf_newton_multi(const pf_multi p, const double* d_yval, const int8_t* d_type,
+                    const double* d_Psp, const double* d_Qsp, double* d_Vm, double* d_Va,
+                    double tol, int max_iter, int flags, double* d_ws, int32_t* d_iters,
+                    double* d_norm, int32_t* d_status, void* stream)
+{
+    if (!p || !p->uploaded) return fail(PF_E_INVALID, "pf_newton_multi: plan not uploaded");
+    if (max_iter < 0 || !(tol >= 0.0) || !d_yval || !d_type || !d_Psp || !d_Qsp || !d_Vm ||
+        !d_Va || !d_ws)
+        return fail(PF_E_INVALID, "pf_newton_multi: bad arguments");
+    if (reinterpret_cast<uintptr_t>(d_ws) & 15)
+        return fail(PF_E_WORKSPACE, "pf_newton_multi: workspace must be 16-byte aligned");
+    if (p->syms.empty()) return PF_OK;
+    NewtonArgs a{d_yval, 0, d_type, 0, d_Psp, d_Qsp, 0, d_Vm, d_Va, 0, d_ws, 0, tol, max_iter,
+                 flags, 1, (int)p->syms.size(), d_iters, d_norm, d_status};
+    DevSym none{};
+    int lds = 0, threads = 0;
+    for (auto* sy : p->syms) {
+        lds = std::max(lds, newton_lds(sy->h));
+        threads = std::max(threads, sy->h.threads);
+    }
+    if (threads == 0) threads = (p->syms.size() <= 512) ? 512 : 256;
+    allow_big_lds();
+    hipLaunchKernelGGL(k_newton<true>, dim3(p->syms.size()), dim3(threads), lds,
+                       as_stream(stream), none, p->d_desc, p->d_order, a);
+    return launch_check("pf_newton_multi");
+}
+
+void pf_multi_destroy(pf_multi p) { delete p; }
+
+}  // extern "C"
