@@ -362,10 +362,13 @@ struct SrcState {
     // (e, f) of every bus in LDS, or null: diag_in / off_in then read (e, f)
     // there and |V| is taken as sqrt(e^2 + f^2)
     const double2* efs;
+    // the right-hand side of the Newton step sits in the bus record beside P, Q
+    static constexpr bool kRhsInRecord = true;
     struct DiagIn {
         double2 y;
         Blk r;  // e, f, |V|, theta of the node's bus
-        double2 s;
+        double2 s;  // P, Q
+        double2 f;  // F_P, F_Q (the rhs)
         bool pv;
     };
     struct OffIn {
@@ -384,7 +387,12 @@ struct SrcState {
         } else {
             r = w.blk(rec);
         }
-        return {y2[yd], r, w.v2(rec + 4), type(bus)};
+        const Blk pqf = w.blk(rec + 4);  // P, Q, F_P, F_Q
+        return {y2[yd], r, {pqf.a, pqf.b}, {pqf.c, pqf.d}, type(bus)};
+    }
+    __device__ __forceinline__ double2 rhs_at(int bus) const
+    {
+        return w.v2(bus_off + 8 * (int64_t)bus + 6);
     }
     __device__ __forceinline__ double vm_of(const Blk& r) const
     {
@@ -450,6 +458,7 @@ struct SrcState {
 // from the lower one): off_in reads the lower block alone.
 template <bool LOWER_ONLY>
 struct SrcLoadT {
+    static constexpr bool kRhsInRecord = false;
     View w;
     int64_t lu_off;
     struct DiagIn {
@@ -768,7 +777,10 @@ __device__ __forceinline__ void factor_node(const DevSym& S, const SRC& src, con
     const int r1 = n0.w, s1 = n1.y;
     const typename SRC::DiagIn din = src.diag_in(j, bus, n1.z);
     double2 bj = make_double2(0.0, 0.0);
-    if (FWD) bj = wr.v2(rhs + 2 * (int64_t)j);
+    if constexpr (FWD) {
+        if constexpr (SRC::kRhsInRecord) bj = din.f;
+        else bj = wr.v2(rhs + 2 * (int64_t)j);
+    }
     int s = n1.x + lane;
     int sc = s < s1 ? s : 0, sc2 = s + g < s1 ? s + g : 0;
     int4 sa = S.slot_info[2 * sc], sb = S.slot_info[2 * sc + 1];
@@ -878,8 +890,10 @@ __device__ void tail_factor(const DevSym& S, const SRC& src, const View& w, int6
             const int4 t1 = S.t_node[3 * it + 1];
             Blk acc = src.diag(t0.x, t0.y, t0.z);
             double z0 = 0.0, z1 = 0.0;
-            if (FWD) {
-                const double2 b = wr.v2(rhs + 2 * (int64_t)t0.x);
+            if constexpr (FWD) {
+                double2 b;
+                if constexpr (SRC::kRhsInRecord) b = src.rhs_at(t0.y);
+                else b = wr.v2(rhs + 2 * (int64_t)t0.x);
                 z0 = b.x;
                 z1 = b.y;
             }
@@ -1297,9 +1311,10 @@ struct CaseDesc {
     int64_t bus_off, br_off, y_off, ws_off;
 };
 
-// Mismatch pass of one case: P + jQ into the bus records and F = calculated
-// - scheduled (F_Q = 0 at PV buses) into the rhs in position order, divided
-// by |V| with SCALE (the fast decoupled right-hand sides); the thread's max
+// Mismatch pass of one case: F = calculated - scheduled (F_Q = 0 at PV buses)
+// and P + jQ.  Without SCALE (Newton) P, Q, F_P, F_Q go into the second half
+// of the bus record in one store; with SCALE (the fast decoupled right-hand
+// sides) P, Q into the record and F / |V| into the rhs in position order.  The thread's max
 // |F| and NaN flag accumulate into mx and nan.  Buses are taken in bus
 // order, two per thread per step, so that the admittance rows, row pointers,
 // positions and scheduled injections of a wavefront are adjacent in memory;
@@ -1341,17 +1356,23 @@ __device__ __forceinline__ void mismatch_pass(const DevSym& S, const double* yv,
         row_finish(S, yv, ef, qd0, qd1, hd, vd.a, vd.b, p2, q2);
         if (pc >= 0) {  // the slack is not a position
             const double fp = p - spc, fq = pvc ? 0.0 : q - sqc;
-            wb.put2(rc + 4, make_double2(p, q));
-            wb.put2(o.RHS + 2 * (int64_t)pc,
-                    SCALE ? make_double2(fp / vc.c, fq / vc.c) : make_double2(fp, fq));
+            if (SCALE) {
+                wb.put2(rc + 4, make_double2(p, q));
+                wb.put2(o.RHS + 2 * (int64_t)pc, make_double2(fp / vc.c, fq / vc.c));
+            } else {  // P, Q and the Newton rhs F in one store of the bus record
+                wb.put(rc + 4, {p, q, fp, fq});
+            }
             nan |= (fp != fp) | (fq != fq);
             mx = fmax(mx, fmax(fabs(fp), fabs(fq)));
         }
         if (two && pd >= 0) {
             const double fp2 = p2 - spd, fq2 = pvd ? 0.0 : q2 - sqd;
-            wb.put2(rd + 4, make_double2(p2, q2));
-            wb.put2(o.RHS + 2 * (int64_t)pd, SCALE ? make_double2(fp2 / vd.c, fq2 / vd.c)
-                                                     : make_double2(fp2, fq2));
+            if (SCALE) {
+                wb.put2(rd + 4, make_double2(p2, q2));
+                wb.put2(o.RHS + 2 * (int64_t)pd, make_double2(fp2 / vd.c, fq2 / vd.c));
+            } else {
+                wb.put(rd + 4, {p2, q2, fp2, fq2});
+            }
             nan |= (fp2 != fp2) | (fq2 != fq2);
             mx = fmax(mx, fmax(fabs(fp2), fabs(fq2)));
         }
