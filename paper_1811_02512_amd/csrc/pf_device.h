@@ -681,25 +681,30 @@ __device__ __forceinline__ void apply_updates2(const int2* __restrict__ upd, int
     }
 }
 
-// Same with the blocks in LDS (tail-local slot numbering).
+// Same with the blocks in LDS (tail-local slot numbering): four pairs per
+// step, the next four pairs' indices in flight (clamped to the list's last
+// entry, never past it); updates in list order.
 __device__ __forceinline__ void apply_updates_lds(const int2* __restrict__ upd, int u0, int u1,
                                                   const double* sLU, Blk& Wk, Blk& Vk)
 {
     if (u0 >= u1) return;
-    int2 p = upd[u0];
-    int2 q = (u0 + 1 < u1) ? upd[u0 + 1] : make_int2(0, 0);
-    for (int u = u0; u < u1; u += 2) {
-        const bool has_q = u + 1 < u1;
-        const int2 pn = (u + 2 < u1) ? upd[u + 2] : make_int2(0, 0);
-        const int2 qn = (u + 3 < u1) ? upd[u + 3] : make_int2(0, 0);
-        bmsub(Wk, bload(sLU + 8 * p.x), bload(sLU + 8 * p.y + 4));
-        bmsub(Vk, bload(sLU + 8 * p.y), bload(sLU + 8 * p.x + 4));
-        if (has_q) {
-            bmsub(Wk, bload(sLU + 8 * q.x), bload(sLU + 8 * q.y + 4));
-            bmsub(Vk, bload(sLU + 8 * q.y), bload(sLU + 8 * q.x + 4));
+    const int last = u1 - 1;
+    int2 e[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) e[k] = upd[min(u0 + k, last)];
+    for (int u = u0; u < u1; u += 4) {
+        int2 nx[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) nx[k] = upd[min(u + 4 + k, last)];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (u + k < u1) {
+                bmsub(Wk, bload(sLU + 8 * e[k].x), bload(sLU + 8 * e[k].y + 4));
+                bmsub(Vk, bload(sLU + 8 * e[k].y), bload(sLU + 8 * e[k].x + 4));
+            }
         }
-        p = pn;
-        q = qn;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) e[k] = nx[k];
     }
 }
 
