@@ -748,12 +748,20 @@ __device__ __forceinline__ void apply_packed2_lds(const uint4* __restrict__ pk, 
     }
 }
 
-__device__ __forceinline__ void gsum_blk(Blk& v, int g)
+// Group sums of a block and, with rhs, of a 2-vector, all six interleaved.
+__device__ __forceinline__ void gsum_blk(Blk& v, double& z0, double& z1, bool rhs, int g)
 {
-    v.a = gsum(v.a, g);
-    v.b = gsum(v.b, g);
-    v.c = gsum(v.c, g);
-    v.d = gsum(v.d, g);
+    if (rhs) {
+        double t[6] = {v.a, v.b, v.c, v.d, z0, z1};
+        gsum_n(t, g);
+        v = {t[0], t[1], t[2], t[3]};
+        z0 = t[4];
+        z1 = t[5];
+    } else {
+        double t[4] = {v.a, v.b, v.c, v.d};
+        gsum_n(t, g);
+        v = {t[0], t[1], t[2], t[3]};
+    }
 }
 
 // Left-looking block LDU of node record x (FactorizeGraphA, pull form):
@@ -817,11 +825,7 @@ __device__ __forceinline__ void factor_node(const DevSym& S, const SRC& src, con
         }
     }
     if (g > 1) {
-        gsum_blk(ds, g);
-        if (FWD) {
-            z0 = gsum(z0, g);
-            z1 = gsum(z1, g);
-        }
+        gsum_blk(ds, z0, z1, FWD, g);
     }
     const Blk Ajj = src.diag_of(din);
     bool ok;
@@ -902,14 +906,37 @@ __device__ void tail_factor(const DevSym& S, const SRC& src, const View& w, int6
                 z0 = b.x;
                 z1 = b.y;
             }
-            for (int r = t1.y; r < t1.z; ++r) {
-                const int2 e = S.t_rl[r];
-                const Blk wv = w.blk(lu + 8 * (int64_t)e.y);
-                bmsub(acc, wv, w.blk(lu + 8 * (int64_t)e.y + 4));
-                if (FWD) {
-                    const double2 yi = wr.v2(rhs + 2 * (int64_t)e.x);
-                    z0 = fma(-wv.a, yi.x, fma(-wv.b, yi.y, z0));
-                    z1 = fma(-wv.c, yi.x, fma(-wv.d, yi.y, z1));
+            // lower neighbours outside the tail: four per step, their blocks
+            // and y requested together, the next four indices in flight
+            if (t1.y < t1.z) {
+                const int rlast = t1.z - 1;
+                int2 e[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) e[k] = S.t_rl[min(t1.y + k, rlast)];
+                for (int r = t1.y; r < t1.z; r += 4) {
+                    int2 nx[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) nx[k] = S.t_rl[min(r + 4 + k, rlast)];
+                    Blk wv[4], uv[4];
+                    double2 yi[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        wv[k] = w.blk(lu + 8 * (int64_t)e[k].y);
+                        uv[k] = w.blk(lu + 8 * (int64_t)e[k].y + 4);
+                        if (FWD) yi[k] = wr.v2(rhs + 2 * (int64_t)e[k].x);
+                    }
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        if (r + k < t1.z) {
+                            bmsub(acc, wv[k], uv[k]);
+                            if (FWD) {
+                                z0 = fma(-wv[k].a, yi[k].x, fma(-wv[k].b, yi[k].y, z0));
+                                z1 = fma(-wv[k].c, yi[k].x, fma(-wv[k].d, yi[k].y, z1));
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) e[k] = nx[k];
                 }
             }
             bstore(sD + 4 * it, acc);
@@ -940,11 +967,7 @@ __device__ void tail_factor(const DevSym& S, const SRC& src, const View& w, int6
             if (FWD) mvadd(z0, z1, wv, sy[2 * e.x], sy[2 * e.x + 1]);
         }
         if (g > 1) {
-            gsum_blk(ds, g);
-            if (FWD) {
-                z0 = gsum(z0, g);
-                z1 = gsum(z1, g);
-            }
+            gsum_blk(ds, z0, z1, FWD, g);
         }
         const Blk A = bload(sD + 4 * jl);
         bool ok;
@@ -1168,8 +1191,7 @@ __device__ void tail_backward(const DevSym& S, const View& w, int64_t rhs, int64
             mvadd(a0, a1, bload(sLU + 8 * t + 4), sy[2 * kl], sy[2 * kl + 1]);
         }
         if (g > 1) {
-            a0 = gsum(a0, g);
-            a1 = gsum(a1, g);
+            gsum2(a0, a1, g);
         }
         if (lane == 0) {
             sy[2 * jl] -= a0;
@@ -1247,8 +1269,7 @@ __device__ __forceinline__ void back_node(const DevSym& S, const NodeRec& rec, i
             if (s + k * g < s1) mvadd(a0, a1, u[k], xk[k].x, xk[k].y);
     }
     if (g > 1) {
-        a0 = gsum(a0, g);
-        a1 = gsum(a1, g);
+        gsum2(a0, a1, g);
     }
     if (lane == 0) {
         const double x0 = y.x - a0, x1 = y.y - a1;

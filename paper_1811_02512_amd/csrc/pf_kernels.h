@@ -81,13 +81,76 @@ __device__ __forceinline__ Blk binv(const Blk& x, bool& ok)
     return {x.d * r, -x.b * r, -x.c * r, x.a * r};
 }
 
-// Sum over the g lanes of a lane group (g a power of two <= 64, groups
-// aligned inside the wavefront).  Butterfly: every lane ends with the same
-// bits because each step adds the same two operands on both sides.
+// The value of the lane that DPP control CTRL selects (all rows and banks;
+// the selected lane always lies in the caller's lane group).
+template <int CTRL>
+__device__ __forceinline__ double dpp_peer(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// The value of lane (i xor 16) within each half-wavefront (swizzle, bit mode:
+// and-mask 31, or-mask 0, xor-mask 16).
+__device__ __forceinline__ double swz_xor16(double v)
+{
+    const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), 0x401F);
+    const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), 0x401F);
+    return __hiloint2double(hi, lo);
+}
+
+// Sums of N values over the g lanes of a lane group (g a power of two <= 64,
+// groups aligned inside the wavefront), the N reductions interleaved.
+// Butterfly with partners inside a row of 16 lanes taken by DPP moves (no
+// LDS round trip): lane xor 1 and xor 2 of a quad, then the mirrored lane
+// within 8 and within 16, which after the earlier steps holds the other
+// half's partial sum; across rows lane xor 16 (swizzle) and xor 32
+// (permute).  Each step adds the same two operands on both lanes of a pair,
+// so every lane of a group ends with the same bits.
+template <int N>
+__device__ __forceinline__ void gsum_n(double (&v)[N], int g)
+{
+    if (g >= 2) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) v[k] += dpp_peer<0xB1>(v[k]);  // quad_perm 1,0,3,2
+    }
+    if (g >= 4) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) v[k] += dpp_peer<0x4E>(v[k]);  // quad_perm 2,3,0,1
+    }
+    if (g >= 8) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) v[k] += dpp_peer<0x141>(v[k]);  // row_half_mirror
+    }
+    if (g >= 16) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) v[k] += dpp_peer<0x140>(v[k]);  // row_mirror
+    }
+    if (g >= 32) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) v[k] += swz_xor16(v[k]);
+    }
+    if (g >= 64) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) v[k] += __shfl_xor(v[k], 32, 64);
+    }
+}
+
 __device__ __forceinline__ double gsum(double v, int g)
 {
-    for (int off = g >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    double t[1] = {v};
+    gsum_n(t, g);
+    return t[0];
+}
+
+// Two sums at once (a 2-vector spread over the group).
+__device__ __forceinline__ void gsum2(double& a, double& b, int g)
+{
+    double t[2] = {a, b};
+    gsum_n(t, g);
+    a = t[0];
+    b = t[1];
 }
 
 // Off-diagonal Jacobian block (i, k) = d(P_i, Q_i)/d(theta_k, |V_k|) from

@@ -343,8 +343,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_solve(DevSym S, const double*
             }
         }
         if (g > 1) {
-            z0 = gsum(z0, g);
-            z1 = gsum(z1, g);
+            gsum2(z0, z1, g);
         }
         if (lane == 0) {
             const double2 b = x2[j];
@@ -386,8 +385,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_solve(DevSym S, const double*
             }
         }
         if (g > 1) {
-            a0 = gsum(a0, g);
-            a1 = gsum(a1, g);
+            gsum2(a0, a1, g);
         }
         if (lane == 0) {
             const double2 y = x2[j];
