@@ -1342,65 +1342,64 @@ struct CaseDesc {
 // of the bus record in one store; with SCALE (the fast decoupled right-hand
 // sides) P, Q into the record and F / |V| into the rhs in position order.  The thread's max
 // |F| and NaN flag accumulate into mx and nan.  Buses are taken in bus
-// order, two per thread per step, so that the admittance rows, row pointers,
-// positions and scheduled injections of a wavefront are adjacent in memory;
-// all loads of both buses are issued before either is summed.
-template <bool SCALE, class EF>
+// order, NB per thread per step (blockDim apart), so that the admittance
+// rows, row pointers, positions and scheduled injections of a wavefront are
+// adjacent in memory; all loads of a step's buses are issued before any of
+// them is summed.
+template <bool SCALE, class EF, int NB = 2>
 __device__ __forceinline__ void mismatch_pass(const DevSym& S, const double* yv, const EF& ef,
                                               const View& wb, const Off& o, const PvMask& pvm,
                                               const double* Psp, const double* Qsp, double& mx,
                                               int& nan)
 {
     const int bd = blockDim.x;
-    for (int i = threadIdx.x; i < S.n; i += 2 * bd) {
-        const int i2 = i + bd;
-        const bool two = i2 < S.n;
-        const int ic = two ? i2 : i;
-        const int pc = S.pos[i], pd = S.pos[ic];
-        const int qc0 = S.yptr[i], qc1 = S.yptr[i + 1];
-        const int qd0 = S.yptr[ic], qd1 = S.yptr[ic + 1];
-        const double spc = Psp[i], sqc = Qsp[i], spd = Psp[ic], sqd = Qsp[ic];
-        const int64_t rc = o.BUS + 8 * (int64_t)i, rd = o.BUS + 8 * (int64_t)ic;
-        Blk vc, vd;  // e, f, |V| (|V| only with SCALE)
-        if (SCALE) {
-            vc = wb.blk(rc);
-            vd = wb.blk(rd);
-        } else {
-            ef.get(i, vc.a, vc.b);
-            ef.get(ic, vd.a, vd.b);
-            vc.c = vd.c = 1.0;
+    for (int i0 = threadIdx.x; i0 < S.n; i0 += NB * bd) {
+        int ib[NB], pc[NB], q0[NB], q1[NB];
+        bool has[NB], pv[NB];
+        double sp[NB], sq[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            has[k] = i0 + k * bd < S.n;
+            ib[k] = has[k] ? i0 + k * bd : i0;
+            pc[k] = S.pos[ib[k]];
+            q0[k] = S.yptr[ib[k]];
+            q1[k] = S.yptr[ib[k] + 1];
+            sp[k] = Psp[ib[k]];
+            sq[k] = Qsp[ib[k]];
         }
-        const bool pvc = pvm(i), pvd = pvm(ic);
-        int kc[4], kd[4];
-        RowHead hc, hd;
-        row_head_idx<EF>(S, yv, qc0, qc1, kc, hc);
-        row_head_idx<EF>(S, yv, qd0, qd1, kd, hd);
-        row_head_v(ef, kc, hc);
-        row_head_v(ef, kd, hd);
-        double p, q, p2, q2;
-        row_finish(S, yv, ef, qc0, qc1, hc, vc.a, vc.b, p, q);
-        row_finish(S, yv, ef, qd0, qd1, hd, vd.a, vd.b, p2, q2);
-        if (pc >= 0) {  // the slack is not a position
-            const double fp = p - spc, fq = pvc ? 0.0 : q - sqc;
+        Blk v[NB];  // e, f, |V| (|V| only with SCALE)
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
             if (SCALE) {
-                wb.put2(rc + 4, make_double2(p, q));
-                wb.put2(o.RHS + 2 * (int64_t)pc, make_double2(fp / vc.c, fq / vc.c));
-            } else {  // P, Q and the Newton rhs F in one store of the bus record
-                wb.put(rc + 4, {p, q, fp, fq});
-            }
-            nan |= (fp != fp) | (fq != fq);
-            mx = fmax(mx, fmax(fabs(fp), fabs(fq)));
-        }
-        if (two && pd >= 0) {
-            const double fp2 = p2 - spd, fq2 = pvd ? 0.0 : q2 - sqd;
-            if (SCALE) {
-                wb.put2(rd + 4, make_double2(p2, q2));
-                wb.put2(o.RHS + 2 * (int64_t)pd, make_double2(fp2 / vd.c, fq2 / vd.c));
+                v[k] = wb.blk(o.BUS + 8 * (int64_t)ib[k]);
             } else {
-                wb.put(rd + 4, {p2, q2, fp2, fq2});
+                ef.get(ib[k], v[k].a, v[k].b);
+                v[k].c = 1.0;
             }
-            nan |= (fp2 != fp2) | (fq2 != fq2);
-            mx = fmax(mx, fmax(fabs(fp2), fabs(fq2)));
+            pv[k] = pvm(ib[k]);
+        }
+        int kk[NB][4];
+        RowHead h[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) row_head_idx<EF>(S, yv, q0[k], q1[k], kk[k], h[k]);
+#pragma unroll
+        for (int k = 0; k < NB; ++k) row_head_v(ef, kk[k], h[k]);
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            double p, q;
+            row_finish(S, yv, ef, q0[k], q1[k], h[k], v[k].a, v[k].b, p, q);
+            if (has[k] && pc[k] >= 0) {  // the slack is not a position
+                const int64_t rc = o.BUS + 8 * (int64_t)ib[k];
+                const double fp = p - sp[k], fq = pv[k] ? 0.0 : q - sq[k];
+                if (SCALE) {
+                    wb.put2(rc + 4, make_double2(p, q));
+                    wb.put2(o.RHS + 2 * (int64_t)pc[k], make_double2(fp / v[k].c, fq / v[k].c));
+                } else {  // P, Q and the Newton rhs F in one store of the bus record
+                    wb.put(rc + 4, {p, q, fp, fq});
+                }
+                nan |= (fp != fp) | (fq != fq);
+                mx = fmax(mx, fmax(fabs(fp), fabs(fq)));
+            }
         }
     }
 }

@@ -21,7 +21,7 @@ namespace {
 // The whole Newton-Raphson loop of one case, run by one workgroup.  The
 // case's voltages and injections are copied into its bus records first and
 // the solution copied back at the end.
-__device__ void newton_case(const DevSym& S, const double* yv, const int8_t* type,
+__device__ __forceinline__ void newton_case(const DevSym& S, const double* yv, const int8_t* type,
                             const double* Psp, const double* Qsp, double* Vm, double* Va,
                             const View& w, const View& wb, double tol, int max_iter,
                             int flags, int32_t* o_iters, double* o_norm, int32_t* o_status)
@@ -62,7 +62,7 @@ __device__ void newton_case(const DevSym& S, const double* yv, const int8_t* typ
             for (int i = threadIdx.x; i < S.n; i += blockDim.x)
                 efl.s[i] = wb.v2(o.BUS + 8 * (int64_t)i);
             __syncthreads();
-            mismatch_pass<false>(S, yv, efl, wb, o, pvm, Psp, Qsp, mx, nan);
+            mismatch_pass<false, EFLds, 4>(S, yv, efl, wb, o, pvm, Psp, Qsp, mx, nan);
         } else {
             mismatch_pass<false>(S, yv, ef, wb, o, pvm, Psp, Qsp, mx, nan);
         }
