@@ -36,7 +36,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def survey_bytes_per_iter(info):
+def algorithmic_bytes_per_iter(info):
     """Algorithmic bytes per NR iteration per case: 16 Y + 128 F + 96 n with
     Y = admittance entries, F = nn + 2 nnz(L) filled 2x2 blocks."""
     F = info.nn + 2 * info.nnz_l
@@ -553,7 +553,7 @@ def main():
     fdpf = bench_fdpf(W, max(3, args.steps // 2))
     graph = bench_graph(W, max(3, args.steps // 2))
 
-    b_it = survey_bytes_per_iter(info)
+    b_it = algorithmic_bytes_per_iter(info)
     units = float(iters.sum())
     alg_bytes = b_it * units  # per launch: bytes per case-iteration x case-iterations
     achieved = alg_bytes / (newton_ms * 1e-3) / 1e9
