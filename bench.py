@@ -495,7 +495,7 @@ def main():
                     help="run one plain 1 GiB copy first (PMC byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
               "(cases are independent, so a multi-GPU run would shard the batch).",
               file=sys.stderr)
         sys.exit(2)
