@@ -775,8 +775,10 @@ __device__ __forceinline__ void gsum_blk(Blk& v, double& z0, double& z1, bool rh
 // node stays short: the record's dependants first (diagonal inputs, rhs,
 // the first two destinations' slot records, the first R indices), then R(j)
 // four entries per lane at a time, then two destinations per step with both
-// update chains in flight together.  Every load is in bounds: absent items
-// read entry 0 and are masked out.
+// update chains in flight together.  Absent list entries and slots are not
+// loaded (a load no lane of the wavefront needs is skipped); inside an
+// update chain, pairs past a list's end read entry 0 (in bounds) and are
+// masked out.
 // SYM: a symmetric matrix (eq. 2 blockwise): only the lower blocks take
 // updates and U_jk = D_j^-1 W_kj^T.
 template <class SRC, bool FWD, bool STORE_D, bool SYM = false>
@@ -794,14 +796,27 @@ __device__ __forceinline__ void factor_node(const DevSym& S, const SRC& src, con
         if constexpr (SRC::kRhsInRecord) bj = din.f;
         else bj = wr.v2(rhs + 2 * (int64_t)j);
     }
+    // Absent list entries are not loaded at all (each guarded load is skipped
+    // when no lane of the wavefront needs it: the sweeps are bound by the
+    // number of vector-memory instructions, not by bytes).
     int s = n1.x + lane;
-    int sc = s < s1 ? s : 0, sc2 = s + g < s1 ? s + g : 0;
-    int4 sa = S.slot_info[2 * sc], sb = S.slot_info[2 * sc + 1];
-    int4 sa2 = S.slot_info[2 * sc2], sb2 = S.slot_info[2 * sc2 + 1];
+    const int4 z4 = make_int4(0, 0, 0, 0);
+    int4 sa = z4, sb = z4, sa2 = z4, sb2 = z4;
+    if (s < s1) {
+        sa = S.slot_info[2 * s];
+        sb = S.slot_info[2 * s + 1];
+    }
+    if (s + g < s1) {
+        sa2 = S.slot_info[2 * (s + g)];
+        sb2 = S.slot_info[2 * (s + g) + 1];
+    }
     int2 e[4];
     int r = n0.z + lane;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) e[k] = S.rl[r + k * g < r1 ? r + k * g : 0];
+    for (int k = 0; k < 4; ++k) {
+        e[k] = make_int2(0, 0);
+        if (r + k * g < r1) e[k] = S.rl[r + k * g];
+    }
     Blk ds = bzero();
     double z0 = 0.0, z1 = 0.0;
     for (; r < r1; r += 4 * g) {
@@ -809,13 +824,19 @@ __device__ __forceinline__ void factor_node(const DevSym& S, const SRC& src, con
         double2 yi[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            wv[k] = w.blk(lu + 8 * (int64_t)e[k].y);
-            uv[k] = w.blk(lu + 8 * (int64_t)e[k].y + 4);
-            if (FWD) yi[k] = wr.v2(rhs + 2 * (int64_t)e[k].x);
+            wv[k] = bzero();
+            uv[k] = bzero();
+            yi[k] = make_double2(0.0, 0.0);
+            if (r + k * g < r1) {
+                wv[k] = w.blk(lu + 8 * (int64_t)e[k].y);
+                uv[k] = w.blk(lu + 8 * (int64_t)e[k].y + 4);
+                if (FWD) yi[k] = wr.v2(rhs + 2 * (int64_t)e[k].x);
+            }
         }
         const int rn = r + 4 * g;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) e[k] = S.rl[rn + k * g < r1 ? rn + k * g : 0];
+        for (int k = 0; k < 4; ++k)
+            if (rn + k * g < r1) e[k] = S.rl[rn + k * g];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             if (r + k * g < r1) {
@@ -834,16 +855,21 @@ __device__ __forceinline__ void factor_node(const DevSym& S, const SRC& src, con
         const int s2 = s + g;
         const bool two = s2 < s1;
         const typename SRC::OffIn o1 = src.off_in(s, sa.y, sa.z, sa.w);
-        const typename SRC::OffIn o2 = src.off_in(two ? s2 : s, sa2.y, sa2.z, sa2.w);
+        typename SRC::OffIn o2{};
+        if (two) o2 = src.off_in(s2, sa2.y, sa2.z, sa2.w);
         const int u0 = sb.x, u1 = sb.y, v0 = two ? sb2.x : 0, v1 = two ? sb2.y : 0;
-        const int2 p = upd_at(S.upd, u0, u1), q = upd_at(S.upd, v0, v1);
+        int2 p = make_int2(0, 0), q = make_int2(0, 0);
+        if (u0 < u1) p = S.upd[u0];
+        if (v0 < v1) q = S.upd[v0];
         const int sn = s + 2 * g;
-        sc = sn < s1 ? sn : 0;
-        sc2 = sn + g < s1 ? sn + g : 0;
-        sa = S.slot_info[2 * sc];
-        sb = S.slot_info[2 * sc + 1];
-        sa2 = S.slot_info[2 * sc2];
-        sb2 = S.slot_info[2 * sc2 + 1];
+        if (sn < s1) {
+            sa = S.slot_info[2 * sn];
+            sb = S.slot_info[2 * sn + 1];
+        }
+        if (sn + g < s1) {
+            sa2 = S.slot_info[2 * (sn + g)];
+            sb2 = S.slot_info[2 * (sn + g) + 1];
+        }
         Blk Wk, Vk, Wk2, Vk2;
         src.off_of(din, o1, Wk, Vk);
         src.off_of(din, o2, Wk2, Vk2);
@@ -1247,23 +1273,31 @@ __device__ __forceinline__ void back_node(const DevSym& S, const NodeRec& rec, i
         br = wb.blk(brec);
         pv = type(n0.y);
     }
+    // absent entries are not loaded (skipped when no lane needs them)
     int s = n1.x + lane;
     int kk[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) kk[k] = S.Li[s + k * g < s1 ? s + k * g : 0];
+    for (int k = 0; k < 4; ++k) {
+        kk[k] = 0;
+        if (s + k * g < s1) kk[k] = S.Li[s + k * g];
+    }
     double a0 = 0.0, a1 = 0.0;
     for (; s < s1; s += 4 * g) {
         Blk u[4];
         double2 xk[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const int sk = s + k * g < s1 ? s + k * g : 0;
-            u[k] = w.blk(lu + 8 * (int64_t)sk + 4);
-            xk[k] = xs ? xs[kk[k]] : wb.v2(rhs + 2 * (int64_t)kk[k]);
+            u[k] = bzero();
+            xk[k] = make_double2(0.0, 0.0);
+            if (s + k * g < s1) {
+                u[k] = w.blk(lu + 8 * (int64_t)(s + k * g) + 4);
+                xk[k] = xs ? xs[kk[k]] : wb.v2(rhs + 2 * (int64_t)kk[k]);
+            }
         }
         const int sn = s + 4 * g;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) kk[k] = S.Li[sn + k * g < s1 ? sn + k * g : 0];
+        for (int k = 0; k < 4; ++k)
+            if (sn + k * g < s1) kk[k] = S.Li[sn + k * g];
 #pragma unroll
         for (int k = 0; k < 4; ++k)
             if (s + k * g < s1) mvadd(a0, a1, u[k], xk[k].x, xk[k].y);

@@ -299,9 +299,8 @@ __global__ __launch_bounds__(kLevelThreads) void k_factor(DevSym S, double* vals
 //                l_j = D_j^-T (p_j - sum_{k in S(j)} W_kj^T l_k)  (levels down).
 // A node's g lanes take its list entries in strides of g, four per lane per
 // step with the step's blocks and x values requested together; absent
-// entries of a step re-read the node's first entry (in bounds whenever the
-// list is not empty) and add nothing.  LDSX keeps the case's whole vector
-// in LDS (nn x 16 bytes) for the two sweeps.
+// entries of a step are not loaded and add nothing.  LDSX keeps the case's
+// whole vector in LDS (nn x 16 bytes) for the two sweeps.
 template <bool TRANS, bool LDSX>
 __global__ __launch_bounds__(kLevelThreads) void k_solve(DevSym S, const double* vals,
                                                        int64_t vals_stride, int C, int B,
@@ -324,15 +323,19 @@ __global__ __launch_bounds__(kLevelThreads) void k_solve(DevSym S, const double*
             int2 e[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const int r = base + k * g;
-                e[k] = S.rl[r < r1 ? r : r0];
+                e[k] = make_int2(0, 0);
+                if (base + k * g < r1) e[k] = S.rl[base + k * g];
             }
             Blk M[4];
             double2 xv[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                M[k] = w.blk(lu + 8 * (int64_t)e[k].y + (TRANS ? 4 : 0));
-                xv[k] = x2[e[k].x];
+                M[k] = bzero();
+                xv[k] = make_double2(0.0, 0.0);
+                if (base + k * g < r1) {
+                    M[k] = w.blk(lu + 8 * (int64_t)e[k].y + (TRANS ? 4 : 0));
+                    xv[k] = x2[e[k].x];
+                }
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -362,19 +365,22 @@ __global__ __launch_bounds__(kLevelThreads) void k_solve(DevSym S, const double*
         const int j = rec.a.x, s0 = rec.b.x, s1 = rec.b.y;
         double a0 = 0.0, a1 = 0.0;
         for (int base = s0 + lane; base < s1; base += 4 * g) {
-            int sk[4], kk[4];
+            int kk[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const int s = base + k * g;
-                sk[k] = s < s1 ? s : s0;
-                kk[k] = S.Li[sk[k]];
+                kk[k] = 0;
+                if (base + k * g < s1) kk[k] = S.Li[base + k * g];
             }
             Blk M[4];
             double2 xv[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                M[k] = w.blk(lu + 8 * (int64_t)sk[k] + (TRANS ? 0 : 4));
-                xv[k] = x2[kk[k]];
+                M[k] = bzero();
+                xv[k] = make_double2(0.0, 0.0);
+                if (base + k * g < s1) {
+                    M[k] = w.blk(lu + 8 * (int64_t)(base + k * g) + (TRANS ? 0 : 4));
+                    xv[k] = x2[kk[k]];
+                }
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
