@@ -104,20 +104,29 @@ __device__ __forceinline__ void fd_forward(const DevSym& S, const double* m, con
         const double bj = *wb.at(rhs + 2 * (int64_t)j + comp);
         const double dj = m[j];
         int r = rec.a.z + lane;
+        // absent entries are not loaded (skipped when no lane needs them)
         int2 e[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) e[k] = S.rl[r + k * g < r1 ? r + k * g : 0];
+        for (int k = 0; k < 4; ++k) {
+            e[k] = make_int2(0, 0);
+            if (r + k * g < r1) e[k] = S.rl[r + k * g];
+        }
         double z = 0.0;
         for (; r < r1; r += 4 * g) {
             double w[4], y[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                w[k] = sl[e[k].y].x;
-                y[k] = fd_x<VL>(xv, wb, rhs, comp, e[k].x);
+                w[k] = 0.0;
+                y[k] = 0.0;
+                if (r + k * g < r1) {
+                    w[k] = sl[e[k].y].x;
+                    y[k] = fd_x<VL>(xv, wb, rhs, comp, e[k].x);
+                }
             }
             const int rn = r + 4 * g;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) e[k] = S.rl[rn + k * g < r1 ? rn + k * g : 0];
+            for (int k = 0; k < 4; ++k)
+                if (rn + k * g < r1) e[k] = S.rl[rn + k * g];
 #pragma unroll
             for (int k = 0; k < 4; ++k)
                 if (r + k * g < r1) z = fma(w[k], y[k], z);
@@ -291,21 +300,30 @@ __device__ __forceinline__ void fd_backward(const DevSym& S, const double* m, co
     for_nodes(S, 0, l1, false, [&](int, const NodeRec& rec, int lane, int g) {
         const int s1 = rec.b.y;
         const double yj = fd_x<VL>(xv, wb, rhs, comp, rec.a.x);
+        // absent entries are not loaded (skipped when no lane needs them)
         int s = rec.b.x + lane;
         int kk[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) kk[k] = S.Li[s + k * g < s1 ? s + k * g : 0];
+        for (int k = 0; k < 4; ++k) {
+            kk[k] = 0;
+            if (s + k * g < s1) kk[k] = S.Li[s + k * g];
+        }
         double a = 0.0;
         for (; s < s1; s += 4 * g) {
             double u[4], x[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                u[k] = sl[s + k * g < s1 ? s + k * g : 0].y;
-                x[k] = fd_x<VL>(xv, wb, rhs, comp, kk[k]);
+                u[k] = 0.0;
+                x[k] = 0.0;
+                if (s + k * g < s1) {
+                    u[k] = sl[s + k * g].y;
+                    x[k] = fd_x<VL>(xv, wb, rhs, comp, kk[k]);
+                }
             }
             const int sn = s + 4 * g;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) kk[k] = S.Li[sn + k * g < s1 ? sn + k * g : 0];
+            for (int k = 0; k < 4; ++k)
+                if (sn + k * g < s1) kk[k] = S.Li[sn + k * g];
 #pragma unroll
             for (int k = 0; k < 4; ++k)
                 if (s + k * g < s1) a = fma(u[k], x[k], a);
