@@ -611,11 +611,30 @@ __device__ __forceinline__ void for_tail_pf(const DevSym& S, int t0, int t1, boo
 // Block updates of one destination slot from pairs (a, b) = (slot(i;k), slot(i;j)):
 //   W_kj -= W_ki U_ij,  V_jk -= W_ji U_ik.
 // Two pairs per step; the next step's indices are fetched before this
-// step's blocks so that index and value loads overlap.  Absent pairs read
-// entry 0 (always in bounds) and contribute nothing.
+// step's blocks so that index and value loads overlap.  Pairs past the end
+// of a list are not loaded (a load no lane of the wavefront needs is
+// skipped) and contribute nothing.
 __device__ __forceinline__ int2 upd_at(const int2* __restrict__ upd, int u, int u1)
 {
-    return upd[u < u1 ? u : 0];
+    int2 p = make_int2(0, 0);
+    if (u < u1) p = upd[u];
+    return p;
+}
+
+// The four blocks pair p reads: W_a = W(p.x), U_a = U(p.x), W_b, U_b of p.y.
+struct PairBlk {
+    Blk Wa, Ua, Wb, Ub;
+};
+__device__ __forceinline__ PairBlk pair_blocks(const View& w, int64_t lu, int2 p, bool has)
+{
+    PairBlk b{bzero(), bzero(), bzero(), bzero()};
+    if (has) {
+        b.Wa = w.blk(lu + 8 * (int64_t)p.x);
+        b.Ua = w.blk(lu + 8 * (int64_t)p.x + 4);
+        b.Wb = w.blk(lu + 8 * (int64_t)p.y);
+        b.Ub = w.blk(lu + 8 * (int64_t)p.y + 4);
+    }
+    return b;
 }
 
 __device__ __forceinline__ void apply_updates(const int2* __restrict__ upd, int u0, int u1,
@@ -628,15 +647,13 @@ __device__ __forceinline__ void apply_updates(const int2* __restrict__ upd, int 
         const bool has_q = u + 1 < u1;
         const int2 pn = upd_at(upd, u + 2, u1);
         const int2 qn = upd_at(upd, u + 3, u1);
-        const Blk Wa = w.blk(lu + 8 * (int64_t)p.x), Ua = w.blk(lu + 8 * (int64_t)p.x + 4);
-        const Blk Wb = w.blk(lu + 8 * (int64_t)p.y), Ub = w.blk(lu + 8 * (int64_t)p.y + 4);
-        const Blk Wc = w.blk(lu + 8 * (int64_t)q.x), Uc = w.blk(lu + 8 * (int64_t)q.x + 4);
-        const Blk Wd = w.blk(lu + 8 * (int64_t)q.y), Ud = w.blk(lu + 8 * (int64_t)q.y + 4);
-        bmsub(Wk, Wa, Ub);
-        bmsub(Vk, Wb, Ua);
+        const PairBlk a = pair_blocks(w, lu, p, true);
+        const PairBlk c = pair_blocks(w, lu, q, has_q);
+        bmsub(Wk, a.Wa, a.Ub);
+        bmsub(Vk, a.Wb, a.Ua);
         if (has_q) {
-            bmsub(Wk, Wc, Ud);
-            bmsub(Vk, Wd, Uc);
+            bmsub(Wk, c.Wa, c.Ub);
+            bmsub(Vk, c.Wb, c.Ua);
         }
         p = pn;
         q = qn;
@@ -658,22 +675,27 @@ __device__ __forceinline__ void apply_updates2(const int2* __restrict__ upd, int
         const int2 pn = upd_at(upd, a + 1, u1);
         const int2 qn = upd_at(upd, b + 1, v1);
         if (SYM) {
-            const Blk Wa = w.blk(lu + 8 * (int64_t)p.x), Ub = w.blk(lu + 8 * (int64_t)p.y + 4);
-            const Blk Wc = w.blk(lu + 8 * (int64_t)q.x), Ud = w.blk(lu + 8 * (int64_t)q.y + 4);
+            Blk Wa = bzero(), Ub = bzero(), Wc = bzero(), Ud = bzero();
+            if (hp) {
+                Wa = w.blk(lu + 8 * (int64_t)p.x);
+                Ub = w.blk(lu + 8 * (int64_t)p.y + 4);
+            }
+            if (hq) {
+                Wc = w.blk(lu + 8 * (int64_t)q.x);
+                Ud = w.blk(lu + 8 * (int64_t)q.y + 4);
+            }
             if (hp) bmsub(Wk, Wa, Ub);
             if (hq) bmsub(Wk2, Wc, Ud);
         } else {
-            const Blk Wa = w.blk(lu + 8 * (int64_t)p.x), Ua = w.blk(lu + 8 * (int64_t)p.x + 4);
-            const Blk Wb = w.blk(lu + 8 * (int64_t)p.y), Ub = w.blk(lu + 8 * (int64_t)p.y + 4);
-            const Blk Wc = w.blk(lu + 8 * (int64_t)q.x), Uc = w.blk(lu + 8 * (int64_t)q.x + 4);
-            const Blk Wd = w.blk(lu + 8 * (int64_t)q.y), Ud = w.blk(lu + 8 * (int64_t)q.y + 4);
+            const PairBlk x = pair_blocks(w, lu, p, hp);
+            const PairBlk y = pair_blocks(w, lu, q, hq);
             if (hp) {
-                bmsub(Wk, Wa, Ub);
-                bmsub(Vk, Wb, Ua);
+                bmsub(Wk, x.Wa, x.Ub);
+                bmsub(Vk, x.Wb, x.Ua);
             }
             if (hq) {
-                bmsub(Wk2, Wc, Ud);
-                bmsub(Vk2, Wd, Uc);
+                bmsub(Wk2, y.Wa, y.Ub);
+                bmsub(Vk2, y.Wb, y.Ua);
             }
         }
         p = pn;
@@ -682,20 +704,19 @@ __device__ __forceinline__ void apply_updates2(const int2* __restrict__ upd, int
 }
 
 // Same with the blocks in LDS (tail-local slot numbering): four pairs per
-// step, the next four pairs' indices in flight (clamped to the list's last
-// entry, never past it); updates in list order.
+// step, the next four pairs' indices in flight (indices past the list's end
+// are not loaded); updates in list order.
 __device__ __forceinline__ void apply_updates_lds(const int2* __restrict__ upd, int u0, int u1,
                                                   const double* sLU, Blk& Wk, Blk& Vk)
 {
     if (u0 >= u1) return;
-    const int last = u1 - 1;
     int2 e[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) e[k] = upd[min(u0 + k, last)];
+    for (int k = 0; k < 4; ++k) e[k] = upd_at(upd, u0 + k, u1);
     for (int u = u0; u < u1; u += 4) {
         int2 nx[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) nx[k] = upd[min(u + 4 + k, last)];
+        for (int k = 0; k < 4; ++k) nx[k] = upd_at(upd, u + 4 + k, u1);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             if (u + k < u1) {
@@ -934,22 +955,27 @@ __device__ void tail_factor(const DevSym& S, const SRC& src, const View& w, int6
             }
             // lower neighbours outside the tail: four per step, their blocks
             // and y requested together, the next four indices in flight
+            // (entries past the list's end are not loaded)
             if (t1.y < t1.z) {
-                const int rlast = t1.z - 1;
                 int2 e[4];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) e[k] = S.t_rl[min(t1.y + k, rlast)];
+                for (int k = 0; k < 4; ++k) e[k] = upd_at(S.t_rl, t1.y + k, t1.z);
                 for (int r = t1.y; r < t1.z; r += 4) {
                     int2 nx[4];
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) nx[k] = S.t_rl[min(r + 4 + k, rlast)];
+                    for (int k = 0; k < 4; ++k) nx[k] = upd_at(S.t_rl, r + 4 + k, t1.z);
                     Blk wv[4], uv[4];
                     double2 yi[4];
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
-                        wv[k] = w.blk(lu + 8 * (int64_t)e[k].y);
-                        uv[k] = w.blk(lu + 8 * (int64_t)e[k].y + 4);
-                        if (FWD) yi[k] = wr.v2(rhs + 2 * (int64_t)e[k].x);
+                        wv[k] = bzero();
+                        uv[k] = bzero();
+                        yi[k] = make_double2(0.0, 0.0);
+                        if (r + k < t1.z) {
+                            wv[k] = w.blk(lu + 8 * (int64_t)e[k].y);
+                            uv[k] = w.blk(lu + 8 * (int64_t)e[k].y + 4);
+                            if (FWD) yi[k] = wr.v2(rhs + 2 * (int64_t)e[k].x);
+                        }
                     }
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
