@@ -796,10 +796,9 @@ __device__ __forceinline__ void gsum_blk(Blk& v, double& z0, double& z1, bool rh
 // node stays short: the record's dependants first (diagonal inputs, rhs,
 // the first two destinations' slot records, the first R indices), then R(j)
 // four entries per lane at a time, then two destinations per step with both
-// update chains in flight together.  Absent list entries and slots are not
-// loaded (a load no lane of the wavefront needs is skipped); inside an
-// update chain, pairs past a list's end read entry 0 (in bounds) and are
-// masked out.
+// update chains in flight together.  Absent list entries, slots and update
+// pairs are not loaded (a load no lane of the wavefront needs is skipped)
+// and add nothing.
 // SYM: a symmetric matrix (eq. 2 blockwise): only the lower blocks take
 // updates and U_jk = D_j^-1 W_kj^T.
 template <class SRC, bool FWD, bool STORE_D, bool SYM = false>
