@@ -24,6 +24,9 @@ for them, see the case study in Section IV):
   branches can carry; with s = 1 Newton's method diverges from flat start on
   most grids of this family.
 * Scheduled injections: P_sp = P_g - P_d, Q_sp = -Q_d.
+* Bus shunts (g_sh + j b_sh per bus) are zero on these grids.  `with_shunts`
+  adds seeded ones (capacitor banks and reactors at a fraction of the
+  non-slack buses, with a small conductance) for the tests of the shunt term.
 
 Load scenarios multiply each bus load (P_d and Q_d together) by a seeded
 lognormal(0, 0.1) factor; generation is unchanged.  N-1 cases remove one
@@ -60,6 +63,23 @@ class Grid:
     pts: np.ndarray      # float64[n, 2] coordinates (topology provenance only)
     seed: int = 0
     load_scale: float = DEFAULT_LOAD_SCALE
+    gsh: np.ndarray = None  # float64[n] bus shunt conductance (None -> zeros)
+    bsh: np.ndarray = None  # float64[n] bus shunt susceptance (None -> zeros)
+
+    def __post_init__(self):
+        if self.gsh is None:
+            self.gsh = np.zeros(self.n)
+        if self.bsh is None:
+            self.bsh = np.zeros(self.n)
+
+    @property
+    def has_shunts(self) -> bool:
+        return bool(np.any(self.gsh != 0) or np.any(self.bsh != 0))
+
+    @property
+    def ysh(self) -> np.ndarray:
+        """Bus shunts as (g, b) pairs, float64[n, 2]."""
+        return np.stack([self.gsh, self.bsh], axis=1)
 
     @property
     def m(self) -> int:
@@ -163,6 +183,20 @@ def make_grid(n: int, seed: int, load_scale: float = DEFAULT_LOAD_SCALE,
         Pg[pv] = share / share.sum() * 1.02 * Pd.sum()
     return Grid(n=n, f=f, t=t, r=r, x=x, b=b, bus_type=bus_type, vset=vset,
                 Pd=Pd, Qd=Qd, Pg=Pg, pts=pts, seed=seed, load_scale=load_scale)
+
+
+def with_shunts(grid: Grid, seed: int, frac: float = 0.3) -> Grid:
+    """The grid with seeded bus shunts at round(frac * (n - 1)) non-slack buses:
+    susceptance b_sh ~ U(-0.05, 0.15) p.u. (reactors below zero, capacitor banks
+    above) and conductance g_sh ~ U(0, 0.01) p.u.; other buses keep none."""
+    rng = np.random.default_rng(seed)
+    k = min(grid.n - 1, int(round(frac * (grid.n - 1))))
+    at = 1 + rng.choice(grid.n - 1, k, replace=False)
+    gsh = np.zeros(grid.n)
+    bsh = np.zeros(grid.n)
+    bsh[at] = rng.uniform(-0.05, 0.15, k)
+    gsh[at] = rng.uniform(0.0, 0.01, k)
+    return dataclasses.replace(grid, gsh=gsh, bsh=bsh)
 
 
 def load_scenarios(grid: Grid, count: int, seed: int, sigma: float = 0.1):

@@ -45,8 +45,9 @@ def lib():
         i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
         i8p = np.ctypeslib.ndpointer(np.int8, flags="C_CONTIGUOUS")
         f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
-        L.or_ybus.argtypes = [C.c_int, C.c_int, i32p, i32p, f64p, f64p, f64p, i32p, i32p,
-                              f64p, f64p]
+        f64n = C.POINTER(C.c_double)  # nullable
+        L.or_ybus.argtypes = [C.c_int, C.c_int, i32p, i32p, f64p, f64p, f64p, f64n, f64n, i32p,
+                              i32p, f64p, f64p]
         L.or_ybus.restype = C.c_int
         L.or_injections.argtypes = [C.c_int, i32p, i32p, f64p, f64p, f64p, f64p, f64p, f64p]
         L.or_injections.restype = None
@@ -92,8 +93,8 @@ def lib():
                                         f64p, f64p, i8p, f64p, f64p, f64p, f64p, f64p, f64p,
                                         f64p]
         L.or_adjoint_sparse.restype = C.c_int
-        L.or_fdpf_matrices.argtypes = [C.c_void_p, C.c_int, i32p, i32p, f64p, f64p, f64p, i8p,
-                                       f64p, f64p, f64p, f64p]
+        L.or_fdpf_matrices.argtypes = [C.c_void_p, C.c_int, i32p, i32p, f64p, f64p, f64p, f64n,
+                                       i8p, f64p, f64p, f64p, f64p]
         L.or_fdpf_matrices.restype = None
         L.or_factor1.argtypes = [C.c_void_p, f64p, f64p, f64p]
         L.or_factor1.restype = C.c_int
@@ -134,20 +135,32 @@ class Ybus:
         return Y
 
 
-def ybus(n, f, t, r, x, b) -> Ybus:
+def _nullable(a):
+    """A C double pointer to a contiguous fp64 array, or NULL for None (the
+    array must outlive the call: callers keep it in a local)."""
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def ybus(n, f, t, r, x, b, gsh=None, bsh=None) -> Ybus:
+    """Admittance matrix with optional bus shunts gsh + j bsh (float64[n])."""
     m = len(f)
     rowptr = np.zeros(n + 1, np.int32)
     col = np.zeros(n + 4 * m + 1, np.int32)
     G = np.zeros(n + 4 * m + 1)
     B = np.zeros(n + 4 * m + 1)
-    nnz = lib().or_ybus(n, m, _i32(f), _i32(t), _f64(r), _f64(x), _f64(b), rowptr, col, G, B)
+    gs = None if gsh is None else _f64(gsh)
+    bs = None if bsh is None else _f64(bsh)
+    nnz = lib().or_ybus(n, m, _i32(f), _i32(t), _f64(r), _f64(x), _f64(b), _nullable(gs),
+                        _nullable(bs), rowptr, col, G, B)
     if nnz < 0:
         raise ValueError("invalid branch list")
     return Ybus(n, rowptr, col[:nnz].copy(), G[:nnz].copy(), B[:nnz].copy())
 
 
 def grid_ybus(grid) -> Ybus:
-    return ybus(grid.n, grid.f, grid.t, grid.r, grid.x, grid.b)
+    return ybus(grid.n, grid.f, grid.t, grid.r, grid.x, grid.b, grid.gsh, grid.bsh)
 
 
 def injections(Y: Ybus, Vm, Va):
@@ -321,9 +334,10 @@ class Sym:
         nn, nz = self.nn, max(self.nnzL, 1)
         d1, d2 = np.zeros(max(nn, 1)), np.zeros(max(nn, 1))
         a1, a2 = np.zeros(nz), np.zeros(nz)
+        bs = _f64(grid.bsh)
         lib().or_fdpf_matrices(self._h, grid.m, _i32(grid.f), _i32(grid.t),
                                _f64(grid.r if r is None else r), _f64(grid.x if x is None else x),
-                               _f64(grid.b if b is None else b),
+                               _f64(grid.b if b is None else b), _nullable(bs),
                                np.ascontiguousarray(grid.bus_type, np.int8), d1, a1, d2, a2)
         return d1[:nn], a1[: self.nnzL], d2[:nn], a2[: self.nnzL]
 

@@ -47,7 +47,9 @@
 #define OR_SLACK 3
 
 /* ------------------------------------------------------------------------ */
-/* Admittance matrix (FormMatrixA, Sec. III-A).                              */
+/* Admittance matrix (FormMatrixA, Sec. III-A: admittances on the edges,     */
+/* shunts on the vertices).  Every bus i starts its diagonal with its own    */
+/* shunt y_sh,i = gsh[i] + j bsh[i] (gsh, bsh may be NULL: no shunts).       */
 /* Branch e between f and t with series admittance y = 1/(r + jx) and total  */
 /* charging b adds y + jb/2 to both diagonals and -y to both off-diagonals. */
 /* Parallel branches are summed.  Output is CSR with sorted columns and an  */
@@ -69,14 +71,14 @@ static int coo_cmp(const void* a, const void* b)
 }
 
 int or_ybus(int n, int m, const int32_t* f, const int32_t* t, const double* r,
-            const double* x, const double* bc, int32_t* rowptr, int32_t* col,
-            double* G, double* B)
+            const double* x, const double* bc, const double* gsh, const double* bsh,
+            int32_t* rowptr, int32_t* col, double* G, double* B)
 {
     int cap = n + 4 * m, cnt = 0;
     or_coo* c = (or_coo*)malloc(sizeof(or_coo) * (size_t)(cap > 0 ? cap : 1));
     if (!c) return -1;
     for (int i = 0; i < n; ++i) {
-        or_coo z = {i, i, -1, 0.0, 0.0};
+        or_coo z = {i, i, -1, gsh ? gsh[i] : 0.0, bsh ? bsh[i] : 0.0};
         c[cnt++] = z;
     }
     for (int e = 0; e < m; ++e) {
@@ -1009,7 +1011,8 @@ int or_adjoint_sparse(const or_sym* s, int m, const int32_t* f, const int32_t* t
 /* Stott and Alsac with van Amerongen's choice of matrices (our reading):   */
 /*   B'  : branch reactances only, b'_ik = -sum_e 1/x_e over branches (i,k), */
 /*         b'_ii = sum_e 1/x_e over branches at i (slack branches included); */
-/*   B'' : -Im(Y) of the full pi-model (r, x and charging).                  */
+/*   B'' : -Im(Y) of the full pi-model (r, x and charging) and of the bus    */
+/*         shunts (bsh, may be NULL), so b''_ii also takes -bsh[i].          */
 /* Both are symmetric, so the paper's symmetric factorisation applies       */
 /* (Sec. III-B, eqs. 1-3).  Positions and slots are those of or_analyze:     */
 /* d[p] diagonal, a[q] = entry (p, Li[q]) = entry (Li[q], p).  B'' keeps    */
@@ -1017,14 +1020,16 @@ int or_adjoint_sparse(const or_sym* s, int m, const int32_t* f, const int32_t* t
 /* diagonals, which leaves the reduced system over PQ buses unchanged.       */
 /* ======================================================================== */
 void or_fdpf_matrices(const or_sym* s, int m, const int32_t* f, const int32_t* t,
-                      const double* r, const double* x, const double* b, const int8_t* type,
-                      double* d1, double* a1, double* d2, double* a2)
+                      const double* r, const double* x, const double* b, const double* bsh,
+                      const int8_t* type, double* d1, double* a1, double* d2, double* a2)
 {
     int nn = s->nn;
     memset(d1, 0, sizeof(double) * (size_t)nn);
     memset(d2, 0, sizeof(double) * (size_t)nn);
     memset(a1, 0, sizeof(double) * (size_t)s->nnzL);
     memset(a2, 0, sizeof(double) * (size_t)s->nnzL);
+    if (bsh)
+        for (int ni = 0; ni < nn; ++ni) d2[s->iperm[ni]] -= bsh[s->bus_of[ni]];
     for (int e = 0; e < m; ++e) {
         int nf = s->node_of[f[e]], nt = s->node_of[t[e]];
         int pf = nf >= 0 ? s->iperm[nf] : -1, pt = nt >= 0 ? s->iperm[nt] : -1;

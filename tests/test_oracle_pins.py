@@ -58,8 +58,9 @@ def branch_currents(grid, Vm, Va):
 
 
 def kcl_currents(grid, V):
-    """Bus current injections summed branch by branch (series + half charging)."""
-    I = np.zeros(grid.n, complex)
+    """Bus current injections summed element by element: each bus's own shunt
+    (g_sh + j b_sh) V_i, then every branch's series current and half charging."""
+    I = (grid.gsh + 1j * grid.bsh) * V
     z = grid.r + 1j * grid.x
     for e in range(grid.m):
         a, b = grid.f[e], grid.t[e]
@@ -67,6 +68,12 @@ def kcl_currents(grid, V):
         I[a] += Is + 1j * grid.b[e] / 2 * V[a]
         I[b] += -Is + 1j * grid.b[e] / 2 * V[b]
     return I
+
+
+def shunted(n, seed, shunt_seed=None):
+    """A generated grid, with seeded bus shunts when shunt_seed is given."""
+    g = gridgen.make_grid(n, seed)
+    return g if shunt_seed is None else gridgen.with_shunts(g, shunt_seed)
 
 
 def random_state(grid, rng, spread=0.3):
@@ -87,8 +94,12 @@ def reduced_residual(O, Y, grid, Vm, Va, Psp, Qsp):
 # --------------------------------------------------------------------------
 # admittance matrix and injections
 # --------------------------------------------------------------------------
-def test_ybus_matches_branchwise_kcl(oracle):
-    g = gridgen.make_grid(60, seed=11)
+@pytest.mark.parametrize("shunt_seed", [None, 31])
+def test_ybus_matches_branchwise_kcl(oracle, shunt_seed):
+    g = shunted(60, 11, shunt_seed)
+    if shunt_seed is not None:  # a shunt at the slack too
+        g.gsh[0], g.bsh[0] = 0.003, -0.02
+        assert np.count_nonzero(g.bsh) > 10
     Y = oracle.grid_ybus(g)
     rng = np.random.default_rng(0)
     Vm, Va = random_state(g, rng)
@@ -115,19 +126,20 @@ def test_ybus_rejects_self_loop(oracle):
                     np.ones(1), np.zeros(1))
 
 
-@pytest.mark.parametrize("seed", [3, 4])
-def test_power_balance_tellegen(oracle, seed):
-    """At any voltages: sum P_i = sum r|I|^2 and
-    sum Q_i = sum x|I|^2 - sum b/2 (|V_f|^2 + |V_t|^2)."""
-    g = gridgen.make_grid(80, seed=seed)
+@pytest.mark.parametrize("seed,shunt_seed", [(3, None), (4, None), (3, 41), (6, 42)])
+def test_power_balance_tellegen(oracle, seed, shunt_seed):
+    """At any voltages: sum P_i = sum r|I|^2 + sum g_sh |V_i|^2 and
+    sum Q_i = sum x|I|^2 - sum b/2 (|V_f|^2 + |V_t|^2) - sum b_sh |V_i|^2."""
+    g = shunted(80, seed, shunt_seed)
     Y = oracle.grid_ybus(g)
     rng = np.random.default_rng(seed)
     Vm, Va = random_state(g, rng)
     P, Q = oracle.injections(Y, Vm, Va)
     V, I = branch_currents(g, Vm, Va)
-    loss_p = np.sum(g.r * np.abs(I) ** 2)
-    loss_q = np.sum(g.x * np.abs(I) ** 2) - np.sum(g.b / 2 * (np.abs(V[g.f]) ** 2 +
-                                                             np.abs(V[g.t]) ** 2))
+    loss_p = np.sum(g.r * np.abs(I) ** 2) + np.sum(g.gsh * Vm ** 2)
+    loss_q = (np.sum(g.x * np.abs(I) ** 2) - np.sum(g.b / 2 * (np.abs(V[g.f]) ** 2 +
+                                                              np.abs(V[g.t]) ** 2))
+              - np.sum(g.bsh * Vm ** 2))
     assert np.sum(P) == pytest.approx(loss_p, rel=1e-11, abs=1e-11)
     assert np.sum(Q) == pytest.approx(loss_q, rel=1e-11, abs=1e-11)
     assert loss_p > 0
@@ -141,9 +153,10 @@ def test_lossless_injections_sum_to_zero(oracle):
     assert abs(np.sum(P)) < 1e-11
 
 
-def test_injection_single_bus_formula(oracle):
-    """S_i = V_i conj(I_i) with I from branch-wise KCL."""
-    g = gridgen.make_grid(40, seed=9)
+@pytest.mark.parametrize("shunt_seed", [None, 43])
+def test_injection_single_bus_formula(oracle, shunt_seed):
+    """S_i = V_i conj(I_i) with I from element-wise KCL."""
+    g = shunted(40, 9, shunt_seed)
     Y = oracle.grid_ybus(g)
     Vm, Va = random_state(g, np.random.default_rng(2))
     P, Q = oracle.injections(Y, Vm, Va)
@@ -182,6 +195,23 @@ def test_two_bus_pq_closed_form(oracle, case, sparse):
 
 
 @pytest.mark.parametrize("sparse", [False, True])
+@pytest.mark.parametrize("bsh", [0.07, -0.03])
+def test_two_bus_shunt_closed_form(oracle, sparse, bsh):
+    """A shunt susceptance b_sh at the load bus acts as extra charging there:
+    the closed form with beta = b/2 + b_sh (a capacitor bank or a reactor)."""
+    r, x, b, P, Q = 0.02, 0.08, 0.04, 0.9, 0.3
+    g = two_bus(r, x, b, P, Q)
+    g.bsh[1] = bsh
+    res = oracle.solve_grid(g, sparse=sparse, tol=1e-13, max_iter=30)
+    assert res.status == 0
+    vm, th = closed_form_pq(r, x, b + 2 * bsh, P, Q)
+    assert res.Vm[1] == pytest.approx(vm, abs=1e-12)
+    assert res.Va[1] == pytest.approx(th, abs=1e-12)
+    # and the shunt really moved the solution
+    assert abs(vm - closed_form_pq(r, x, b, P, Q)[0]) > 1e-3
+
+
+@pytest.mark.parametrize("sparse", [False, True])
 def test_two_bus_pv_closed_form(oracle, sparse):
     r, x, vs, Pinj = 0.02, 0.1, 1.03, 0.8
     g = two_bus(r, x, 0.03, 0.0, 0.0, pv=True, vs=vs)
@@ -192,9 +222,10 @@ def test_two_bus_pv_closed_form(oracle, sparse):
     assert res.Va[1] == pytest.approx(closed_form_pv(r, x, Pinj, vs), abs=1e-12)
 
 
-@pytest.mark.parametrize("n,seed", [(30, 1), (200, 1), (200, 2), (500, 3)])
-def test_sparse_paper_path_equals_dense_definition(oracle, n, seed):
-    g = gridgen.make_grid(n, seed)
+@pytest.mark.parametrize("n,seed,shunt_seed", [(30, 1, None), (200, 1, None), (200, 2, None),
+                                               (500, 3, None), (300, 4, 44)])
+def test_sparse_paper_path_equals_dense_definition(oracle, n, seed, shunt_seed):
+    g = shunted(n, seed, shunt_seed)
     d = oracle.solve_grid(g, sparse=False)
     s = oracle.solve_grid(g, sparse=True)
     nat = oracle.solve_grid(g, sparse=True, ordering=1)
@@ -205,9 +236,10 @@ def test_sparse_paper_path_equals_dense_definition(oracle, n, seed):
         np.testing.assert_allclose(r.Va, d.Va, atol=1e-12)
 
 
-def test_solution_zeroes_independent_residual(oracle):
-    """The converged state satisfies S = V conj(I) = S_sp computed branch-wise."""
-    g = gridgen.make_grid(300, 7)
+@pytest.mark.parametrize("shunt_seed", [None, 45])
+def test_solution_zeroes_independent_residual(oracle, shunt_seed):
+    """The converged state satisfies S = V conj(I) = S_sp computed element-wise."""
+    g = shunted(300, 7, shunt_seed)
     res = oracle.solve_grid(g)
     assert res.status == 0
     V = res.Vm * np.exp(1j * res.Va)
@@ -309,8 +341,9 @@ def block_fd(oracle, sym, Y, g, Vm, Va):
     return A
 
 
-def test_block_jacobian_fd_and_pattern(oracle):
-    g = gridgen.make_grid(35, 12)
+@pytest.mark.parametrize("shunt_seed", [None, 46])
+def test_block_jacobian_fd_and_pattern(oracle, shunt_seed):
+    g = shunted(35, 12, shunt_seed)
     Y = oracle.grid_ybus(g)
     sym = oracle.Sym(g.n, g.f, g.t)
     Vm, Va = random_state(g, np.random.default_rng(5))
@@ -530,7 +563,7 @@ def test_slack_articulation_forest(oracle):
 # adjoint
 # --------------------------------------------------------------------------
 def solve_tight(oracle, g, Psp, Qsp, x):
-    Y = oracle.ybus(g.n, g.f, g.t, g.r, x, g.b)
+    Y = oracle.ybus(g.n, g.f, g.t, g.r, x, g.b, g.gsh, g.bsh)
     Vm0, Va0 = g.flat_start()
     r = oracle.newton_dense(Y, g.bus_type, Psp, Qsp, Vm0, Va0, tol=1e-13, max_iter=40)
     assert r.status in (0, 6) and r.norm < 1e-11
@@ -543,8 +576,9 @@ def loss_grad(g, Vm, w):
     return gVm
 
 
-def test_adjoint_matches_central_fd(oracle):
-    g = gridgen.make_grid(40, 21)
+@pytest.mark.parametrize("shunt_seed", [None, 47])
+def test_adjoint_matches_central_fd(oracle, shunt_seed):
+    g = shunted(40, 21, shunt_seed)
     rng = np.random.default_rng(6)
     w = rng.uniform(0, 1, g.n)
     Y = oracle.grid_ybus(g)
@@ -594,8 +628,8 @@ def test_adjoint_two_bus_closed_form(oracle):
 
 
 def test_sparse_adjoint_equals_dense_adjoint(oracle):
-    for n, seed in [(60, 2), (250, 8)]:
-        g = gridgen.make_grid(n, seed)
+    for n, seed, shunt_seed in [(60, 2, None), (250, 8, None), (120, 5, 48)]:
+        g = shunted(n, seed, shunt_seed)
         Y = oracle.grid_ybus(g)
         res = oracle.solve_grid(g)
         rng = np.random.default_rng(seed)
@@ -642,6 +676,8 @@ def dense_xb(g):
                 if v in idx:
                     B1[idx[u], idx[v]] -= 1.0 / g.x[e]
                     B2[idx[u], idx[v]] -= -y.imag
+    for bus in keep:  # B'' = -Im(Y): a shunt susceptance lowers the diagonal
+        B2[idx[bus], idx[bus]] -= g.bsh[bus]
     for bus in keep:
         if g.bus_type[bus] == gridgen.BUS_PV:
             k = idx[bus]
@@ -658,14 +694,18 @@ def to_bus_order(s, A):
     return A[np.ix_(order, order)]
 
 
-@pytest.mark.parametrize("n,seed", [(60, 1), (200, 2)])
-def test_fdpf_matrices_match_definition(oracle, n, seed):
-    g = gridgen.make_grid(n, seed)
+@pytest.mark.parametrize("n,seed,shunt_seed", [(60, 1, None), (200, 2, None), (120, 3, 49)])
+def test_fdpf_matrices_match_definition(oracle, n, seed, shunt_seed):
+    g = shunted(n, seed, shunt_seed)
     s = oracle.Sym(g.n, g.f, g.t)
     d1, a1, d2, a2 = s.fdpf_matrices(g)
     keep, B1, B2 = dense_xb(g)
     np.testing.assert_allclose(to_bus_order(s, s.scalar_matrix(d1, a1)), B1, rtol=0, atol=1e-10)
     np.testing.assert_allclose(to_bus_order(s, s.scalar_matrix(d2, a2)), B2, rtol=0, atol=1e-10)
+    # B'' is -Im(Y) of the admittance matrix (shunts included) off the PV buses
+    Yd = oracle.grid_ybus(g).dense()[np.ix_(keep, keep)]
+    pq = g.bus_type[keep] == gridgen.BUS_PQ
+    np.testing.assert_allclose(B2[np.ix_(pq, pq)], -Yd.imag[np.ix_(pq, pq)], rtol=0, atol=1e-10)
     # lossless, charging-free branches make the two matrices agree away from PV buses
     g0 = gridgen.make_grid(n, seed)
     g0.r[:] = 0.0
@@ -735,9 +775,9 @@ def fdpf_dense(g, Psp, Qsp, tol=1e-8, max_iter=40):
         half ^= 1
 
 
-@pytest.mark.parametrize("n,seed", [(100, 1), (300, 4)])
-def test_fdpf_sparse_equals_dense_definition(oracle, n, seed):
-    g = gridgen.make_grid(n, seed)
+@pytest.mark.parametrize("n,seed,shunt_seed", [(100, 1, None), (300, 4, None), (200, 6, 50)])
+def test_fdpf_sparse_equals_dense_definition(oracle, n, seed, shunt_seed):
+    g = shunted(n, seed, shunt_seed)
     Vm, Va, it, st = fdpf_dense(g, g.Psp, g.Qsp)
     r = oracle.solve_grid_fdpf(g)
     assert st == 0 and r.status == 0
@@ -746,11 +786,11 @@ def test_fdpf_sparse_equals_dense_definition(oracle, n, seed):
     np.testing.assert_allclose(r.Va, Va, rtol=0, atol=1e-11)
 
 
-@pytest.mark.parametrize("n,seed", [(200, 1), (2000, 2)])
-def test_fdpf_reaches_the_newton_solution(oracle, n, seed):
+@pytest.mark.parametrize("n,seed,shunt_seed", [(200, 1, None), (2000, 2, None), (500, 3, 51)])
+def test_fdpf_reaches_the_newton_solution(oracle, n, seed, shunt_seed):
     """Both methods stop at max|F| < 1e-8 on the same equations, so they
     reach the same state up to that tolerance."""
-    g = gridgen.make_grid(n, seed)
+    g = shunted(n, seed, shunt_seed)
     a = oracle.solve_grid_fdpf(g)
     b = oracle.solve_grid(g)
     assert a.status == 0 and b.status == 0
@@ -767,11 +807,12 @@ def test_fdpf_not_converged_and_nonfinite(oracle):
     assert oracle.solve_grid_fdpf(g, Psp=P).status == 7
 
 
-@pytest.mark.parametrize("n,seed", [(200, 1), (1000, 3)])
-def test_branch_flows_kcl_and_series_losses(oracle, n, seed):
-    """Flows leaving each bus sum to its injection (Kirchhoff), and each
-    branch's losses equal the series-element loss minus the charging."""
-    g = gridgen.make_grid(n, seed)
+@pytest.mark.parametrize("n,seed,shunt_seed", [(200, 1, None), (1000, 3, None), (300, 2, 52)])
+def test_branch_flows_kcl_and_series_losses(oracle, n, seed, shunt_seed):
+    """Flows leaving each bus plus its shunt's consumption |V|^2 (g_sh - j b_sh)
+    sum to its injection (Kirchhoff), and each branch's losses equal the
+    series-element loss minus the charging."""
+    g = shunted(n, seed, shunt_seed)
     r = oracle.solve_grid(g)
     Pft, Qft, Ptf, Qtf = oracle.branch_flows(g, r.Vm, r.Va)
     P, Q = oracle.injections(oracle.grid_ybus(g), r.Vm, r.Va)
@@ -781,6 +822,8 @@ def test_branch_flows_kcl_and_series_losses(oracle, n, seed):
     np.add.at(sp, g.t, Ptf)
     np.add.at(sq, g.f, Qft)
     np.add.at(sq, g.t, Qtf)
+    sp += g.gsh * r.Vm ** 2
+    sq -= g.bsh * r.Vm ** 2
     np.testing.assert_allclose(sp, P, rtol=0, atol=1e-11)
     np.testing.assert_allclose(sq, Q, rtol=0, atol=1e-11)
     V = r.Vm * np.exp(1j * r.Va)
@@ -800,9 +843,10 @@ def _se():
     return se
 
 
-def test_se_jacobian_matches_finite_differences(oracle):
+@pytest.mark.parametrize("shunt_seed", [None, 54])
+def test_se_jacobian_matches_finite_differences(oracle, shunt_seed):
     se = _se()
-    g = gridgen.make_grid(30, 2)
+    g = shunted(30, 2, shunt_seed)
     Y = oracle.grid_ybus(g)
     rng = np.random.default_rng(1)
     Vm = 1 + 0.05 * rng.standard_normal(g.n)
@@ -823,11 +867,12 @@ def test_se_jacobian_matches_finite_differences(oracle):
         np.testing.assert_allclose(H[:, c], fd, rtol=0, atol=1e-6)
 
 
-def test_se_recovers_the_power_flow_state(oracle):
+@pytest.mark.parametrize("shunt_seed", [None, 53])
+def test_se_recovers_the_power_flow_state(oracle, shunt_seed):
     """Noise-free measurements of a solved power flow: the estimate is that
     state (the estimator and the power flow share no step)."""
     se = _se()
-    g = gridgen.make_grid(200, 3)
+    g = shunted(200, 3, shunt_seed)
     ref = oracle.solve_grid(g)
     kinds, locs = se.full_measurement_set(g)
     z = se.measure(g, oracle.grid_ybus(g), ref.Vm, ref.Va, kinds, locs)
