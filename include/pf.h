@@ -168,15 +168,21 @@ int pf_symbolic_get_mapping(const pf_symbolic sym, int32_t* lanes_per_level);
 int pf_symbolic_upload(pf_symbolic sym, void* d_buf, size_t bytes, void* stream);
 void pf_symbolic_destroy(pf_symbolic sym);
 
-/* ---- FormMatrixA (Sec. III-A), nodal parallel ---------------------------
- * One thread per (case, bus) gathers its row from incident branches:
- * Y_ii = sum (y_e + j b_e/2), Y_ik = -sum y_e, y_e = 1/(r_e + j x_e).
- * d_r, d_x, d_b: double[B][m] with branch_stride (0 = shared).
+/* ---- FormMatrixA (Sec. III-A: admittances on edges, shunts on vertices) --
+ * One thread per (case, bus) gathers its row from its shunt and incident
+ * branches: Y_ii = y_sh,i + sum (y_e + j b_e/2), Y_ik = -sum y_e,
+ * y_e = 1/(r_e + j x_e); parallel branches are summed in branch order.
+ * d_r, d_x, d_b: double[B][m] with branch_stride (0 = shared, else >= m).
+ * d_ysh: bus shunts y_sh = g + jb as (g, b) pairs, double[B][n][2] with
+ * ysh_stride in doubles (0 = shared, else even and >= 2n), 16-byte
+ * aligned; NULL = no shunts.
  * d_yval: out, complex as (G, B) pairs, double[B][nnz_y][2] with y_stride
- * (in doubles, >= 2*nnz_y), entries in the symbolic's CSR order.          */
+ * (in doubles, >= 2*nnz_y), entries in the symbolic's CSR order.
+ * Errors: PF_E_INVALID (NULL array, negative or odd stride, misaligned
+ * d_ysh), PF_E_WORKSPACE (a stride too small for B > 1).                */
 int pf_build_ybus(const pf_symbolic sym, int B, const double* d_r, const double* d_x,
-                  const double* d_b, int64_t branch_stride, double* d_yval,
-                  int64_t y_stride, void* stream);
+                  const double* d_b, int64_t branch_stride, const double* d_ysh,
+                  int64_t ysh_stride, double* d_yval, int64_t y_stride, void* stream);
 /* Copies the admittance CSR structure to host arrays yptr[n+1], ycol[nnz_y]. */
 int pf_symbolic_ybus_pattern(const pf_symbolic sym, int32_t* yptr, int32_t* ycol);
 
@@ -204,11 +210,16 @@ int pf_jacobian(const pf_symbolic sym, int B, const double* d_yval, int64_t y_st
  * In-place block LDU of B matrices in the filled layout, level by level
  * (hierarchical parallel), nodes of a level in parallel (nodal parallel).
  * Each node pulls the updates of its descendants (no atomics, results are
- * bitwise reproducible).  No pivoting: d_status[b] (int32, may be NULL) is
- * set to PF_OK or PF_E_ZERO_PIVOT when a pivot block is singular or
- * non-finite.                                                             */
+ * bitwise reproducible).  No pivoting (Sec. III-B divides by the pivot as
+ * it stands): d_status[b] (int32, may be NULL) is set to PF_OK, or to
+ * PF_E_ZERO_PIVOT when a pivot block's determinant is zero or not finite;
+ * d_pivot[b] (int32, may be NULL) to -1, or to the position of the first
+ * failing pivot in the order of a sequential factorisation over the
+ * partition (level by level, positions ascending within a level).  The
+ * failing pivot's descendants in the tree are still factorised; what
+ * follows it is not finite.                                              */
 int pf_factor(const pf_symbolic sym, int B, double* d_vals, int64_t vals_stride,
-              int vals_interleave, int32_t* d_status, void* stream);
+              int vals_interleave, int32_t* d_status, int32_t* d_pivot, void* stream);
 
 /* ---- forward substitution, normalisation, backward substitution ---------
  * (Sec. III-C, eq. 4.)  transpose = 0 solves A x = rhs; transpose = 1 solves
@@ -228,19 +239,23 @@ int pf_solve(const pf_symbolic sym, int B, const double* d_vals, int64_t vals_st
  * max_iter steps.  d_Vm/d_Va: in = start state (flat start is the caller's),
  * out = solution, double[B][n] (v_stride).  d_ws: workspace in groups of
  * C = pf_newton_interleave(sym, B) cases (see "Interleaved case groups"), ws_stride
- * >= info.ws_doubles and a multiple of 8, 16-byte aligned; each case's first
- * info.vals_doubles hold its last factors in the filled layout (at the
- * solution with PF_NEWTON_KEEP_FACTORS), so pf_solve can take d_ws with
- * vals_stride = ws_stride and vals_interleave = C.  Outputs:
- * d_iters[B] (steps applied), d_norm[B] (last max|F|), d_status[B]
- * (PF_OK, PF_E_ZERO_PIVOT, PF_E_NOT_CONVERGED, PF_E_NONFINITE); any may be
- * NULL.  The launch never fails because of one case.                      */
+ * >= info.ws_doubles and a multiple of 8, 16-byte aligned.  With
+ * PF_NEWTON_KEEP_FACTORS, each converged case's first info.vals_doubles hold
+ * the factors of J at the returned state in the filled layout (D^-1, L D,
+ * U), so pf_solve and pf_adjoint can take d_ws with vals_stride = ws_stride
+ * and vals_interleave = C.  Without the flag, or for a case that did not end
+ * PF_OK, that region holds intermediate values only (the iterations keep
+ * neither D^-1 nor the top levels' factors there).  Outputs: d_iters[B]
+ * (steps applied), d_norm[B] (last max|F|), d_status[B] (PF_OK,
+ * PF_E_ZERO_PIVOT, PF_E_NOT_CONVERGED, PF_E_NONFINITE), d_pivot[B] (-1, or
+ * with PF_E_ZERO_PIVOT the position of the first failing pivot, as
+ * pf_factor); any may be NULL.  The launch never fails because of one case.*/
 int pf_newton(const pf_symbolic sym, int B, const double* d_yval, int64_t y_stride,
               const int8_t* d_type, int64_t type_stride, const double* d_Psp,
               const double* d_Qsp, int64_t inj_stride, double* d_Vm, double* d_Va,
               int64_t v_stride, double tol, int max_iter, int flags, double* d_ws,
               int64_t ws_stride, int32_t* d_iters, double* d_norm, int32_t* d_status,
-              void* stream);
+              int32_t* d_pivot, void* stream);
 
 /* Case grouping pf_newton uses for a batch of B: info.ws_interleave halved
  * until it does not exceed B (1 for a single case).  Returns -1 on error.  */
@@ -259,12 +274,15 @@ int pf_newton_interleave(const pf_symbolic sym, int B);
  * up = l_kj (unit upper factor u_jk = l_kj, eq. 2).
  * pf_fdpf_matrices: branch arrays as pf_build_ybus; d_type int8[B][n];
  * d_mat 16-byte aligned, mat_stride a multiple of 8 (>= fd_mat_doubles if
- * B > 1).  pf_fdpf_factor: in place; d_status[B] (may be NULL) PF_OK or
- * PF_E_ZERO_PIVOT.  Matrices and factors depend on r, x, b and the bus
- * types only, so a batch of scenarios shares one (mat_stride = 0).        */
+ * B > 1).  Bus shunts d_ysh as pf_build_ybus (NULL = none): B'' takes
+ * -b_sh on its diagonal (B' takes none).  pf_fdpf_factor: in place;
+ * d_status[B] (may be NULL) PF_OK or PF_E_ZERO_PIVOT.  Matrices and factors
+ * depend on r, x, b, the shunts and the bus types only, so a batch of
+ * scenarios shares one (mat_stride = 0).                                   */
 int pf_fdpf_matrices(const pf_symbolic sym, int B, const double* d_r, const double* d_x,
-                     const double* d_b, int64_t branch_stride, const int8_t* d_type,
-                     int64_t type_stride, double* d_mat, int64_t mat_stride, void* stream);
+                     const double* d_b, int64_t branch_stride, const double* d_ysh,
+                     int64_t ysh_stride, const int8_t* d_type, int64_t type_stride,
+                     double* d_mat, int64_t mat_stride, void* stream);
 int pf_fdpf_factor(const pf_symbolic sym, int B, double* d_mat, int64_t mat_stride,
                    int32_t* d_status, void* stream);
 
@@ -331,7 +349,8 @@ int pf_se_upload(pf_se se, void* d_buf, size_t bytes, void* stream);
  * LDS tail budget as pf_symbolic_set_launch); call before pf_se_upload (the
  * upload size changes with the tail).                                      */
 int pf_se_set_launch(pf_se se, int threads, int64_t tail_lds_budget);
-/* B cases: branch arrays as pf_build_ybus; d_z, d_w double[B][M] (z_stride,
+/* B cases: branch arrays and bus shunts as pf_build_ybus (the injection
+ * measurements include the shunts' currents); d_z, d_w double[B][M] (z_stride,
  * w_stride; 0 = shared); d_Vm/d_Va in = start, out = estimate (v_stride);
  * d_ws: scratch of at least ceil(B/4)*4 * ws_doubles doubles, 16-byte
  * aligned (ws_size = doubles available), its layout internal; d_iters,
@@ -340,7 +359,8 @@ int pf_se_set_launch(pf_se se, int threads, int64_t tail_lds_budget);
  * waits for the stream once per Gauss-Newton step to stop when every case
  * has finished.                                                            */
 int pf_se_estimate(const pf_se se, int B, const double* d_r, const double* d_x,
-                   const double* d_b, int64_t branch_stride, const double* d_z,
+                   const double* d_b, int64_t branch_stride, const double* d_ysh,
+                   int64_t ysh_stride, const double* d_z,
                    int64_t z_stride, const double* d_w, int64_t w_stride, double* d_Vm,
                    double* d_Va, int64_t v_stride, double tol, int max_iter, double* d_ws,
                    int64_t ws_size, int32_t* d_iters, double* d_norm, int32_t* d_status,
@@ -371,6 +391,27 @@ int pf_adjoint_params(const pf_symbolic sym, int B, const double* d_lam, int64_t
                       const double* d_x, int64_t branch_stride, double* d_gP, double* d_gQ,
                       int64_t g_stride, double* d_gx, int gx_mode, void* stream);
 
+/* ---- fused adjoint backward (beyond the paper) -----------------------------
+ * The three steps above in two launches, on the factors pf_newton kept at
+ * the solution (PF_NEWTON_KEEP_FACTORS; d_ws and ws_stride as given to
+ * pf_newton with the same B, so the same case grouping): per case, the
+ * gradient g = (dL/dtheta, dL/d|V|) gathered into position order (the |V|
+ * entry zero at PV buses; d_gVm or d_gVa NULL = zero), the transposed
+ * solves J^T lam = g, d_lam <- lam (double[B][nn][2], lam_stride), d_gP,
+ * d_gQ (double[B][n], g_stride) as pf_adjoint_params; then d_gx (d_x, d_r
+ * and gx_mode as pf_adjoint_params; d_gx NULL = skipped).  d_status: the
+ * per-case status pf_newton wrote, or NULL; a case whose status is not PF_OK
+ * (its workspace holds no factors of a converged J) gets NaN gradients, and
+ * with gx_mode 1 the summed d_gx is NaN.  Errors: PF_E_INVALID (NULL
+ * output, bad mode or stride), PF_E_WORKSPACE (strides too small).       */
+int pf_adjoint(const pf_symbolic sym, int B, const double* d_ws, int64_t ws_stride,
+               const double* d_gVm, const double* d_gVa, int64_t gv_stride,
+               const int8_t* d_type, int64_t type_stride, const double* d_Vm,
+               const double* d_Va, int64_t v_stride, const double* d_r, const double* d_x,
+               int64_t branch_stride, const int32_t* d_status, double* d_lam,
+               int64_t lam_stride, double* d_gP, double* d_gQ, int64_t g_stride, double* d_gx,
+               int gx_mode, void* stream);
+
 /* ---- batches of cases with their own sparsity (N-1 outages, mixed grids) --
  * A plan binds G cases to uploaded symbolics (several cases may share one).
  * Per-case arrays are concatenated; pf_multi_info gives each case's element
@@ -383,12 +424,14 @@ int pf_multi_create(int G, const pf_symbolic* syms, pf_multi* out);
 int pf_multi_info(const pf_multi plan, size_t* dev_bytes, int64_t* bus_off,
                   int64_t* branch_off, int64_t* y_off, int64_t* ws_off);
 int pf_multi_upload(pf_multi plan, void* d_buf, size_t bytes, void* stream);
+/* d_ysh: bus shunts as (g, b) pairs at twice the bus offsets (16-byte
+ * aligned), or NULL for none.                                              */
 int pf_build_ybus_multi(const pf_multi plan, const double* d_r, const double* d_x,
-                        const double* d_b, double* d_yval, void* stream);
+                        const double* d_b, const double* d_ysh, double* d_yval, void* stream);
 int pf_newton_multi(const pf_multi plan, const double* d_yval, const int8_t* d_type,
                     const double* d_Psp, const double* d_Qsp, double* d_Vm, double* d_Va,
                     double tol, int max_iter, int flags, double* d_ws, int32_t* d_iters,
-                    double* d_norm, int32_t* d_status, void* stream);
+                    double* d_norm, int32_t* d_status, int32_t* d_pivot, void* stream);
 void pf_multi_destroy(pf_multi plan);
 
 #ifdef __cplusplus

@@ -68,13 +68,15 @@ class Symbolic:
         return self
 
     # -- helpers allocating outputs ------------------------------------------------
-    def build_ybus(self, r, x, b):
-        """r, x, b: [m] or [B, m] fp64 device tensors -> yval [B, 2*nnz_y]."""
+    def build_ybus(self, r, x, b, ysh=None):
+        """r, x, b: [m] or [B, m] fp64 device tensors; ysh: bus shunts (g, b)
+        as [n, 2] or [B, n, 2], or None -> yval [B, 2*nnz_y]."""
         info = self.info
-        Bn = r.shape[0] if r.dim() == 2 else 1
+        Bn = max(r.shape[0] if r.dim() == 2 else 1,
+                 ysh.shape[0] if ysh is not None and ysh.dim() == 3 else 1)
         bstride = r.shape[-1] if r.dim() == 2 else 0
         y = torch.empty(Bn, 2 * info.nnz_y, dtype=torch.float64, device=r.device)
-        B.pf_build_ybus(self.h, Bn, r, x, b, bstride, y, 2 * info.nnz_y)
+        B.pf_build_ybus(self.h, Bn, r, x, b, bstride, y, 2 * info.nnz_y, ysh, _shunt_stride(ysh))
         return y
 
     def workspace(self, Bn, device=None):
@@ -103,16 +105,16 @@ class Symbolic:
         return iters, norm, status, ws
 
     # -- fast decoupled power flow and branch flows ---------------------------
-    def fdpf_factors(self, r, x, b, bus_type):
+    def fdpf_factors(self, r, x, b, bus_type, ysh=None):
         """B' and B'' built and factored on the device.  r, x, b: [m] (shared)
-        or [B, m]; bus_type: [n] or [B, n].  Returns (mat, status) with mat
-        [1 or B, fd_mat_doubles]."""
+        or [B, m]; bus_type: [n] or [B, n]; ysh: bus shunts [n, 2] or None.
+        Returns (mat, status) with mat [1 or B, fd_mat_doubles]."""
         info = self.info
         Bn = 1 if r.dim() == 1 else r.shape[0]
         mat = torch.empty(Bn, info.fd_mat_doubles, dtype=torch.float64, device=r.device)
         status = torch.empty(Bn, dtype=torch.int32, device=r.device)
         B.pf_fdpf_matrices(self.h, Bn, r, x, b, _stride(r), bus_type, _stride(bus_type), mat,
-                           info.fd_mat_doubles)
+                           info.fd_mat_doubles, ysh, _shunt_stride(ysh))
         B.pf_fdpf_factor(self.h, Bn, mat, info.fd_mat_doubles, status)
         return mat, status
 
@@ -144,6 +146,12 @@ class Symbolic:
 def _stride(t):
     """0 for a shared [k] array, row length for a [B, k] array."""
     return 0 if t.dim() == 1 else t.shape[-1]
+
+
+def _shunt_stride(ysh):
+    """Doubles between cases of a bus-shunt array: 0 for a shared [n, 2]
+    array (or none), 2 n for [B, n, 2]."""
+    return 0 if ysh is None or ysh.dim() < 3 else 2 * ysh.shape[-2]
 
 
 class MultiPlan:
@@ -202,9 +210,10 @@ class StateEstimator:
         return torch.empty(rows * self.dims.ws_doubles, dtype=torch.float64,
                            device=_dev(device or self.device))
 
-    def estimate(self, r, x, b, z, w, Vm, Va, tol=1e-8, max_iter=20, ws=None):
+    def estimate(self, r, x, b, z, w, Vm, Va, tol=1e-8, max_iter=20, ws=None, ysh=None):
         """In place on Vm, Va ([B, n]); z, w: [M] shared or [B, M]; r, x, b:
-        [m] shared or [B, m].  Returns (iters, norm, status, ws)."""
+        [m] shared or [B, m]; ysh: bus shunts [n, 2] or [B, n, 2] or None.
+        Returns (iters, norm, status, ws)."""
         Bn = Vm.shape[0]
         if ws is None:
             ws = self.workspace(Bn, Vm.device)
@@ -212,7 +221,8 @@ class StateEstimator:
         norm = torch.empty(Bn, dtype=torch.float64, device=Vm.device)
         status = torch.empty(Bn, dtype=torch.int32, device=Vm.device)
         B.pf_se_estimate(self.h, Bn, r, x, b, _stride(r), z, _stride(z), w, _stride(w), Vm, Va,
-                         Vm.shape[-1], tol, max_iter, ws, ws.numel(), iters, norm, status)
+                         Vm.shape[-1], tol, max_iter, ws, ws.numel(), iters, norm, status, ysh,
+                         _shunt_stride(ysh))
         return iters, norm, status, ws
 
     def __del__(self):

@@ -73,25 +73,28 @@ _SIGS = {
     "pf_symbolic_upload": ([_vp, _vp, C.c_size_t, _vp], _i),
     "pf_symbolic_destroy": ([_vp], None),
     "pf_symbolic_ybus_pattern": ([_vp, _vp, _vp], _i),
-    "pf_build_ybus": ([_vp, _i, _vp, _vp, _vp, _i64, _vp, _i64, _vp], _i),
+    "pf_build_ybus": ([_vp, _i, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _i64, _vp], _i),
     "pf_mismatch": ([_vp, _i, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _i64,
                      _vp, _vp, _vp], _i),
     "pf_jacobian": ([_vp, _i, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _i64, _i, _vp], _i),
-    "pf_factor": ([_vp, _i, _vp, _i64, _i, _vp, _vp], _i),
+    "pf_factor": ([_vp, _i, _vp, _i64, _i, _vp, _vp, _vp], _i),
     "pf_solve": ([_vp, _i, _vp, _i64, _i, _vp, _i64, _i, _vp], _i),
     "pf_newton": ([_vp, _i, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _d, _i, _i,
-                   _vp, _i64, _vp, _vp, _vp, _vp], _i),
+                   _vp, _i64, _vp, _vp, _vp, _vp, _vp], _i),
     "pf_adjoint_params": ([_vp, _i, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _vp,
                            _vp, _i64, _vp, _i, _vp], _i),
     "pf_adjoint_rhs": ([_vp, _i, _vp, _vp, _i64, _vp, _i64, _vp, _i64, _vp], _i),
+    "pf_adjoint": ([_vp, _i, _vp, _i64, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _vp,
+                    _i64, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _i, _vp], _i),
     "pf_multi_create": ([_i, _vp, C.POINTER(_vp)], _i),
     "pf_multi_info": ([_vp, C.POINTER(C.c_size_t), _vp, _vp, _vp, _vp], _i),
     "pf_multi_upload": ([_vp, _vp, C.c_size_t, _vp], _i),
-    "pf_build_ybus_multi": ([_vp, _vp, _vp, _vp, _vp, _vp], _i),
+    "pf_build_ybus_multi": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], _i),
     "pf_newton_multi": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _d, _i, _i, _vp, _vp, _vp, _vp,
-                         _vp], _i),
+                         _vp, _vp], _i),
     "pf_multi_destroy": ([_vp], None),
-    "pf_fdpf_matrices": ([_vp, _i, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _i64, _vp], _i),
+    "pf_fdpf_matrices": ([_vp, _i, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp],
+                         _i),
     "pf_fdpf_factor": ([_vp, _i, _vp, _i64, _vp, _vp], _i),
     "pf_fdpf": ([_vp, _i, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _i64, _d,
                  _i, _vp, _i64, _vp, _vp, _vp, _vp], _i),
@@ -101,8 +104,8 @@ _SIGS = {
     "pf_se_info": ([_vp, C.POINTER(pf_se_dims)], _i),
     "pf_se_upload": ([_vp, _vp, C.c_size_t, _vp], _i),
     "pf_se_set_launch": ([_vp, _i, _i64], _i),
-    "pf_se_estimate": ([_vp, _i, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _d,
-                        _i, _vp, _i64, _vp, _vp, _vp, _vp], _i),
+    "pf_se_estimate": ([_vp, _i, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp,
+                        _i64, _d, _i, _vp, _i64, _vp, _vp, _vp, _vp], _i),
     "pf_se_destroy": ([_vp], None),
 }
 for _name, (_args, _res) in _SIGS.items():
@@ -211,9 +214,10 @@ def pf_symbolic_destroy(h):
     lib.pf_symbolic_destroy(h)
 
 
-def pf_build_ybus(h, B, r, x, b, branch_stride, yval, y_stride, stream=None):
-    check(lib.pf_build_ybus(h, B, ptr(r), ptr(x), ptr(b), branch_stride, ptr(yval), y_stride,
-                            stream_ptr(stream)), "pf_build_ybus")
+def pf_build_ybus(h, B, r, x, b, branch_stride, yval, y_stride, ysh=None, ysh_stride=0,
+                  stream=None):
+    check(lib.pf_build_ybus(h, B, ptr(r), ptr(x), ptr(b), branch_stride, ptr(ysh), ysh_stride,
+                            ptr(yval), y_stride, stream_ptr(stream)), "pf_build_ybus")
 
 
 def pf_mismatch(h, B, yval, y_stride, bus_type, type_stride, Psp, Qsp, inj_stride, Vm, Va,
@@ -230,9 +234,10 @@ def pf_jacobian(h, B, yval, y_stride, bus_type, type_stride, Vm, Va, v_stride, v
                           stream_ptr(stream)), "pf_jacobian")
 
 
-def pf_factor(h, B, vals, vals_stride, status=None, vals_interleave=1, stream=None):
+def pf_factor(h, B, vals, vals_stride, status=None, vals_interleave=1, pivot=None,
+              stream=None):
     check(lib.pf_factor(h, B, ptr(vals), vals_stride, int(vals_interleave), ptr(status),
-                        stream_ptr(stream)), "pf_factor")
+                        ptr(pivot), stream_ptr(stream)), "pf_factor")
 
 
 def pf_solve(h, B, vals, vals_stride, rhs, rhs_stride, transpose=0, vals_interleave=1,
@@ -243,11 +248,11 @@ def pf_solve(h, B, vals, vals_stride, rhs, rhs_stride, transpose=0, vals_interle
 
 def pf_newton(h, B, yval, y_stride, bus_type, type_stride, Psp, Qsp, inj_stride, Vm, Va,
               v_stride, tol, max_iter, flags, ws, ws_stride, iters=None, norm=None,
-              status=None, stream=None):
+              status=None, pivot=None, stream=None):
     check(lib.pf_newton(h, B, ptr(yval), y_stride, ptr(bus_type), type_stride, ptr(Psp),
                         ptr(Qsp), inj_stride, ptr(Vm), ptr(Va), v_stride, float(tol),
                         int(max_iter), int(flags), ptr(ws), ws_stride, ptr(iters), ptr(norm),
-                        ptr(status), stream_ptr(stream)), "pf_newton")
+                        ptr(status), ptr(pivot), stream_ptr(stream)), "pf_newton")
 
 
 def pf_adjoint_params(h, B, lam, lam_stride, bus_type, type_stride, Vm, Va, v_stride, r, x,
@@ -256,6 +261,15 @@ def pf_adjoint_params(h, B, lam, lam_stride, bus_type, type_stride, Vm, Va, v_st
                                 ptr(Vm), ptr(Va), v_stride, ptr(r), ptr(x), branch_stride,
                                 ptr(gP), ptr(gQ), g_stride, ptr(gx), int(gx_mode),
                                 stream_ptr(stream)), "pf_adjoint_params")
+
+
+def pf_adjoint(h, B, ws, ws_stride, gVm, gVa, gv_stride, bus_type, type_stride, Vm, Va,
+               v_stride, r, x, branch_stride, status, lam, lam_stride, gP, gQ, g_stride, gx,
+               gx_mode, stream=None):
+    check(lib.pf_adjoint(h, B, ptr(ws), ws_stride, ptr(gVm), ptr(gVa), gv_stride, ptr(bus_type),
+                         type_stride, ptr(Vm), ptr(Va), v_stride, ptr(r), ptr(x), branch_stride,
+                         ptr(status), ptr(lam), lam_stride, ptr(gP), ptr(gQ), g_stride, ptr(gx),
+                         int(gx_mode), stream_ptr(stream)), "pf_adjoint")
 
 
 def pf_adjoint_rhs(h, B, gVm, gVa, v_stride, bus_type, type_stride, rhs, rhs_stride,
@@ -284,17 +298,17 @@ def pf_multi_upload(p, buf, stream=None):
                               stream_ptr(stream)), "pf_multi_upload")
 
 
-def pf_build_ybus_multi(p, r, x, b, yval, stream=None):
-    check(lib.pf_build_ybus_multi(p, ptr(r), ptr(x), ptr(b), ptr(yval), stream_ptr(stream)),
-          "pf_build_ybus_multi")
+def pf_build_ybus_multi(p, r, x, b, yval, ysh=None, stream=None):
+    check(lib.pf_build_ybus_multi(p, ptr(r), ptr(x), ptr(b), ptr(ysh), ptr(yval),
+                                  stream_ptr(stream)), "pf_build_ybus_multi")
 
 
 def pf_newton_multi(p, yval, bus_type, Psp, Qsp, Vm, Va, tol, max_iter, flags, ws, iters=None,
-                    norm=None, status=None, stream=None):
+                    norm=None, status=None, pivot=None, stream=None):
     check(lib.pf_newton_multi(p, ptr(yval), ptr(bus_type), ptr(Psp), ptr(Qsp), ptr(Vm),
                               ptr(Va), float(tol), int(max_iter), int(flags), ptr(ws),
-                              ptr(iters), ptr(norm), ptr(status), stream_ptr(stream)),
-          "pf_newton_multi")
+                              ptr(iters), ptr(norm), ptr(status), ptr(pivot),
+                              stream_ptr(stream)), "pf_newton_multi")
 
 
 def pf_multi_destroy(p):
@@ -302,10 +316,10 @@ def pf_multi_destroy(p):
 
 
 def pf_fdpf_matrices(h, B, r, x, b, branch_stride, bus_type, type_stride, mat, mat_stride,
-                     stream=None):
-    check(lib.pf_fdpf_matrices(h, B, ptr(r), ptr(x), ptr(b), branch_stride, ptr(bus_type),
-                               type_stride, ptr(mat), mat_stride, stream_ptr(stream)),
-          "pf_fdpf_matrices")
+                     ysh=None, ysh_stride=0, stream=None):
+    check(lib.pf_fdpf_matrices(h, B, ptr(r), ptr(x), ptr(b), branch_stride, ptr(ysh),
+                               ysh_stride, ptr(bus_type), type_stride, ptr(mat), mat_stride,
+                               stream_ptr(stream)), "pf_fdpf_matrices")
 
 
 def pf_fdpf_factor(h, B, mat, mat_stride, status=None, stream=None):
@@ -361,8 +375,10 @@ def pf_se_upload(h, buf, nbytes, stream=None):
 
 
 def pf_se_estimate(h, B, r, x, b, branch_stride, z, z_stride, w, w_stride, Vm, Va, v_stride,
-                   tol, max_iter, ws, ws_size, iters, norm, status, stream=None):
-    check(lib.pf_se_estimate(h, B, ptr(r), ptr(x), ptr(b), branch_stride, ptr(z), z_stride,
+                   tol, max_iter, ws, ws_size, iters, norm, status, ysh=None, ysh_stride=0,
+                   stream=None):
+    check(lib.pf_se_estimate(h, B, ptr(r), ptr(x), ptr(b), branch_stride, ptr(ysh), ysh_stride,
+                             ptr(z), z_stride,
                              ptr(w), w_stride, ptr(Vm), ptr(Va), v_stride, tol, max_iter,
                              ptr(ws), ws_size, ptr(iters), ptr(norm), ptr(status),
                              stream_ptr(stream)),

@@ -51,17 +51,18 @@ def outage_branches(r, x, b, outages):
 
 
 def screen(sym, r, x, b, bus_type, Psp, Qsp, Vm0, Va0, outages, tol=1e-8, fdpf_iter=40,
-           nr_iter=20, fdpf_first=True):
+           nr_iter=20, fdpf_first=True, ysh=None):
     """Screens the outages of branches `outages` on the base symbolic `sym`
     (uploaded api.Symbolic).  r, x, b: [m]; bus_type, Psp, Qsp, Vm0, Va0: [n]
-    base-case inputs shared by all outages.  Returns a Screening."""
+    base-case inputs shared by all outages; ysh: bus shunts [n, 2] (g, b) or
+    None.  Returns a Screening."""
     info = sym.info
     dev = r.device
     C = len(outages)
     n, m = info.n, info.m
     rr, xx, bb = outage_branches(r, x, b, outages)
     yv = torch.empty(C, 2 * info.nnz_y, dtype=torch.float64, device=dev)
-    B.pf_build_ybus(sym.h, C, rr, xx, bb, m, yv, 2 * info.nnz_y)
+    B.pf_build_ybus(sym.h, C, rr, xx, bb, m, yv, 2 * info.nnz_y, ysh, 0)
     Vm = Vm0.expand(C, n).contiguous()
     Va = Va0.expand(C, n).contiguous()
     status = torch.full((C,), -1, dtype=torch.int32, device=dev)
@@ -71,7 +72,8 @@ def screen(sym, r, x, b, bus_type, Psp, Qsp, Vm0, Va0, outages, tol=1e-8, fdpf_i
     if fdpf_first:
         mat = torch.empty(C, info.fd_mat_doubles, dtype=torch.float64, device=dev)
         fst = torch.empty(C, dtype=torch.int32, device=dev)
-        B.pf_fdpf_matrices(sym.h, C, rr, xx, bb, m, bus_type, 0, mat, info.fd_mat_doubles)
+        B.pf_fdpf_matrices(sym.h, C, rr, xx, bb, m, bus_type, 0, mat, info.fd_mat_doubles,
+                           ysh, 0)
         B.pf_fdpf_factor(sym.h, C, mat, info.fd_mat_doubles, fst)
         ws = torch.empty(C, info.fd_ws_doubles, dtype=torch.float64, device=dev)
         B.pf_fdpf(sym.h, C, yv, 2 * info.nnz_y, bus_type, 0, Psp, Qsp, 0, Vm, Va, n, mat,

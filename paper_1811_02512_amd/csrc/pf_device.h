@@ -62,6 +62,13 @@ constexpr int kLevelThreads = 512;
 constexpr int kXcds = 8;
 constexpr int kWave = 64;  // CDNA wavefront
 constexpr size_t kSolveLdsMax = 159 * 1024;  // of the 160 KB of LDS per workgroup on gfx950
+// Value of the workgroup's zero-pivot marker while no pivot has failed; a
+// failing pivot lowers it to its node's level-ordered index, so that the
+// marker ends at the first failure in level order, then ascending position
+// (the order of a sequential factorisation over the partition).
+constexpr int kNoPivot = 0x7fffffff;
+
+__device__ __forceinline__ void mark_pivot(int* s_bad, int x) { atomicMin(s_bad, x); }
 
 // Orders the LDS accesses of one wavefront's lanes (they run in lockstep,
 // and a wavefront's LDS operations are performed in issue order).
@@ -801,10 +808,11 @@ __device__ __forceinline__ void gsum_blk(Blk& v, double& z0, double& z1, bool rh
 // and add nothing.
 // SYM: a symmetric matrix (eq. 2 blockwise): only the lower blocks take
 // updates and U_jk = D_j^-1 W_kj^T.
+// x: the node's level-ordered index (for the zero-pivot marker s_bad).
 template <class SRC, bool FWD, bool STORE_D, bool SYM = false>
-__device__ __forceinline__ void factor_node(const DevSym& S, const SRC& src, const NodeRec& rec,
-                                            int lane, int g, const View& w, int64_t lu,
-                                            const View& wr, int64_t rhs, int* s_bad)
+__device__ __forceinline__ void factor_node(const DevSym& S, const SRC& src, int x,
+                                            const NodeRec& rec, int lane, int g, const View& w,
+                                            int64_t lu, const View& wr, int64_t rhs, int* s_bad)
 {
     const int4 n0 = rec.a;
     const int4 n1 = rec.b;
@@ -902,7 +910,7 @@ __device__ __forceinline__ void factor_node(const DevSym& S, const SRC& src, con
         }
     }
     if (lane == 0) {
-        if (!ok) *s_bad = 1;
+        if (!ok) mark_pivot(s_bad, x);
         if (STORE_D) w.put(4 * (int64_t)j, Di);
         if (FWD) {
             double y0 = 0.0, y1 = 0.0;
@@ -1031,7 +1039,7 @@ __device__ void tail_factor(const DevSym& S, const SRC& src, const View& w, int6
             bstore(sLU + 8 * t + 4, bmul(Di, Vk));
         }
         if (lane == 0) {
-            if (!ok) *s_bad = 1;
+            if (!ok) mark_pivot(s_bad, S.level_ptr[S.tail_level] + jl);
             bstore(sD + 4 * jl, Di);
             if (FWD) {
                 double y0 = 0.0, y1 = 0.0;
@@ -1102,7 +1110,7 @@ __device__ void tail_factor(const DevSym& S, const SRC& src, const View& w, int6
                 const int ja = kf + a;
                 bool ok;
                 Di = binv(bload(sD + 4 * ja), ok);
-                if (!ok && threadIdx.x == 0) *s_bad = 1;
+                if (!ok && threadIdx.x == 0) mark_pivot(s_bad, S.level_ptr[S.tail_level] + ja);
                 if (FWD) mvadd(ya0, ya1, Di, sy[2 * ja], sy[2 * ja + 1]);
             }
             const int nupd = (a < KC) ? m * m : 0;
@@ -1389,6 +1397,26 @@ struct NewtonArgs {
     int32_t* iters;
     double* norm;
     int32_t* status;
+    int32_t* pivot;  // position of the first zero pivot, -1 if none (may be null)
+};
+
+// Arguments of the fused adjoint kernel (pf_adjoint).
+struct AdjArgs {
+    const double* ws;  // pf_newton's workspace: factors of J at the solution
+    int64_t ws_stride;
+    int C;  // interleave of the workspace
+    int B;
+    const double* gVm;  // dL/d|V| [B][n] or null
+    const double* gVa;  // dL/dtheta [B][n] or null
+    int64_t gv_stride;
+    const int8_t* type;
+    int64_t type_stride;
+    const int32_t* status;  // pf_newton's per-case status or null
+    double* lam;            // out: adjoint vector [B][nn][2]
+    int64_t lam_stride;
+    double* gP;
+    double* gQ;
+    int64_t g_stride;
 };
 
 struct CaseDesc {

@@ -446,7 +446,8 @@ __device__ void fdpf_case(const DevSym& S, const double* yv, const int8_t* type,
 // the scalar filled layout, lower and upper values equal.
 __global__ void k_fd_matrices(DevSym S, const double* __restrict__ r,
                               const double* __restrict__ x, const double* __restrict__ b,
-                              int64_t bstride, const int8_t* __restrict__ type,
+                              int64_t bstride, const double* __restrict__ ysh,
+                              int64_t sh_stride, const int8_t* __restrict__ type,
                               int64_t type_stride, double* __restrict__ mat, int64_t mstride)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -464,8 +465,10 @@ __global__ void k_fd_matrices(DevSym S, const double* __restrict__ r,
         return;
     }
     const bool pvj = tc[S.perm[p]] == T_PV;
+    // B'' = -Im(Y): the bus shunt's susceptance comes off the diagonal
+    const double bsh = ysh ? ysh[c * sh_stride + 2 * (int64_t)S.perm[p] + 1] : 0.0;
     m1[p] = fd_entry<false>(S, S.ydiag[p], true, rc, xc, bc);
-    m2[p] = pvj ? 1.0 : fd_entry<true>(S, S.ydiag[p], true, rc, xc, bc);
+    m2[p] = pvj ? 1.0 : fd_entry<true>(S, S.ydiag[p], true, rc, xc, bc) - bsh;
     double2* s1 = reinterpret_cast<double2*>(m1 + S.fd_lu);
     double2* s2 = reinterpret_cast<double2*>(m2 + S.fd_lu);
     for (int s = S.Lp[p]; s < S.Lp[p + 1]; ++s) {
@@ -601,12 +604,16 @@ void allow_big_lds_fdpf()
 
 extern "C" {
 int pf_fdpf_matrices(const pf_symbolic s, int B, const double* d_r, const double* d_x,
-                     const double* d_b, int64_t branch_stride, const int8_t* d_type,
-                     int64_t type_stride, double* d_mat, int64_t mat_stride, void* stream)
+                     const double* d_b, int64_t branch_stride, const double* d_ysh,
+                     int64_t ysh_stride, const int8_t* d_type, int64_t type_stride,
+                     double* d_mat, int64_t mat_stride, void* stream)
 {
     if (!ready(s, "pf_fdpf_matrices")) return PF_E_INVALID;
-    if (B < 0 || B > 65535 || !d_r || !d_x || !d_b || !d_type || !d_mat || (mat_stride & 7))
+    if (B < 0 || B > 65535 || !d_r || !d_x || !d_b || !d_type || !d_mat || (mat_stride & 7) ||
+        branch_stride < 0 || ysh_stride < 0)
         return fail(PF_E_INVALID, "pf_fdpf_matrices: bad arguments");
+    if (d_ysh && (ysh_stride & 1 || (B > 1 && ysh_stride != 0 && ysh_stride < 2 * s->h.n)))
+        return fail(PF_E_INVALID, "pf_fdpf_matrices: ysh_stride must be 0 or even and >= 2*n");
     if (reinterpret_cast<uintptr_t>(d_mat) & 15)
         return fail(PF_E_WORKSPACE, "pf_fdpf_matrices: d_mat must be 16-byte aligned");
     if (B > 1 && mat_stride < 2 * s->h.fd_mat())
@@ -614,7 +621,8 @@ int pf_fdpf_matrices(const pf_symbolic s, int B, const double* d_r, const double
     if (B == 0) return PF_OK;
     dim3 grid((unsigned)((s->h.fd_lu() + 255) / 256), B);
     hipLaunchKernelGGL(k_fd_matrices, grid, dim3(256), 0, as_stream(stream), s->h.dev, d_r, d_x,
-                       d_b, branch_stride, d_type, type_stride, d_mat, mat_stride);
+                       d_b, branch_stride, d_ysh, ysh_stride, d_type, type_stride, d_mat,
+                       mat_stride);
     return launch_check("pf_fdpf_matrices");
 }
 

@@ -37,9 +37,17 @@ int newton_interleave(const pf::HostSym& h, int B);
 // A symbolic that is non-null and uploaded (else records the error).
 bool ready(const pf_symbolic s, const char* fn);
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+// Branch gradients (and, with bus, the injection gradients) of B cases from
+// their adjoint vectors (pf_adjoint_params, pf_adjoint).
+int adjoint_branch_launch(const pf_symbolic s, int B, const double* d_lam, int64_t lam_stride,
+                          const int8_t* d_type, int64_t type_stride, const double* d_Vm,
+                          const double* d_Va, int64_t v_stride, const double* d_r,
+                          const double* d_x, int64_t branch_stride, const int32_t* d_status,
+                          double* d_gP, double* d_gQ, int64_t g_stride, double* d_gx,
+                          int gx_mode, void* stream, bool bus);
 // The level-scheduled factorisation of B matrices (sym: symmetric ones).
 void factor_launch(const pf::HostSym& h, int B, double* vals, int64_t stride, int C,
-                   int32_t* status, hipStream_t st, bool sym);
+                   int32_t* status, int32_t* pivot, hipStream_t st, bool sym);
 
 }  // namespace abi
 }  // namespace pf

@@ -24,7 +24,8 @@ namespace {
 __device__ __forceinline__ void newton_case(const DevSym& S, const double* yv, const int8_t* type,
                             const double* Psp, const double* Qsp, double* Vm, double* Va,
                             const View& w, const View& wb, double tol, int max_iter,
-                            int flags, int32_t* o_iters, double* o_norm, int32_t* o_status)
+                            int flags, int32_t* o_iters, double* o_norm, int32_t* o_status,
+                            int32_t* o_pivot)
 {
     __shared__ int s_bad;
     const Off o = ws_off(S);
@@ -35,7 +36,7 @@ __device__ __forceinline__ void newton_case(const DevSym& S, const double* yv, c
         wb.put(o.BUS + 8 * (int64_t)i, {vm * cs, vm * sn, vm, va});
     }
     pv_fill(S, type);
-    if (threadIdx.x == 0) s_bad = 0;
+    if (threadIdx.x == 0) s_bad = kNoPivot;
     __syncthreads();
     const PvMask pvm{pv_words(S)};
     // the global levels of the factorisation sweep read neighbours' (e, f)
@@ -80,11 +81,11 @@ __device__ __forceinline__ void newton_case(const DevSym& S, const double* yv, c
             st = ST_NOT_CONVERGED;
             break;
         }
-        for_nodes(S, 0, S.tail_level, true, [&](int, const NodeRec& r, int lane, int g) {
-            factor_node<SrcState, true, false>(S, src, r, lane, g, w, o.LU, wb, o.RHS, &s_bad);
+        for_nodes(S, 0, S.tail_level, true, [&](int x, const NodeRec& r, int lane, int g) {
+            factor_node<SrcState, true, false>(S, src, x, r, lane, g, w, o.LU, wb, o.RHS, &s_bad);
         });
         if (tail) tail_factor<SrcState, true, false>(S, src, w, o.LU, wb, o.RHS, &s_bad);
-        if (s_bad) {
+        if (s_bad != kNoPivot) {
             st = ST_ZERO_PIVOT;
             break;
         }
@@ -95,11 +96,11 @@ __device__ __forceinline__ void newton_case(const DevSym& S, const double* yv, c
         ++it;
     }
     if ((flags & PF_NEWTON_KEEP_FACTORS) && st == ST_OK) {
-        for_nodes(S, 0, S.tail_level, true, [&](int, const NodeRec& r, int lane, int g) {
-            factor_node<SrcState, false, true>(S, src, r, lane, g, w, o.LU, wb, o.RHS, &s_bad);
+        for_nodes(S, 0, S.tail_level, true, [&](int x, const NodeRec& r, int lane, int g) {
+            factor_node<SrcState, false, true>(S, src, x, r, lane, g, w, o.LU, wb, o.RHS, &s_bad);
         });
         if (tail) tail_factor<SrcState, false, true>(S, src, w, o.LU, wb, o.RHS, &s_bad);
-        if (s_bad) st = ST_ZERO_PIVOT;
+        if (s_bad != kNoPivot) st = ST_ZERO_PIVOT;
     }
     for (int i = threadIdx.x; i < S.n; i += blockDim.x) {
         const Blk r = wb.blk(o.BUS + 8 * (int64_t)i);
@@ -110,6 +111,7 @@ __device__ __forceinline__ void newton_case(const DevSym& S, const double* yv, c
         if (o_iters) *o_iters = it;
         if (o_norm) *o_norm = nrm;
         if (o_status) *o_status = st;
+        if (o_pivot) *o_pivot = s_bad == kNoPivot ? -1 : S.level_nodes[s_bad];
     }
 }
 
@@ -153,20 +155,22 @@ struct AsmPolar {
 // ===========================================================================
 // kernels
 // ===========================================================================
-__global__ void k_ybus(DevSym S, const double* __restrict__ r, const double* __restrict__ x,
-                       const double* __restrict__ bc, int64_t bstride,
-                       double* __restrict__ yval, int64_t ystride)
+// Row i of the admittance matrix (FormMatrixA): the diagonal starts from the
+// bus's shunt (ysh: (g, b) of bus i, or null), then every branch in the
+// entry's list adds y + jb/2 (diagonal) or -y (off-diagonal), in list order.
+__device__ __forceinline__ void ybus_row(const DevSym& S, int i, const double* __restrict__ rc,
+                                         const double* __restrict__ xc,
+                                         const double* __restrict__ bcc,
+                                         const double2* __restrict__ ysh, double* __restrict__ yc)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int c = blockIdx.y;
-    if (i >= S.n) return;
-    const double* rc = r + c * bstride;
-    const double* xc = x + c * bstride;
-    const double* bcc = bc + c * bstride;
-    double* yc = yval + c * ystride;
     for (int q = S.yptr[i]; q < S.yptr[i + 1]; ++q) {
         const bool diag = S.ycol[q] == i;
         double G = 0.0, Bv = 0.0;
+        if (diag && ysh) {
+            const double2 sh = ysh[i];
+            G = sh.x;
+            Bv = sh.y;
+        }
         for (int t = S.ybr_ptr[q]; t < S.ybr_ptr[q + 1]; ++t) {
             const int e = S.ybr[t];
             const double rr = rc[e], xx = xc[e];
@@ -184,36 +188,27 @@ __global__ void k_ybus(DevSym S, const double* __restrict__ r, const double* __r
     }
 }
 
+__global__ void k_ybus(DevSym S, const double* __restrict__ r, const double* __restrict__ x,
+                       const double* __restrict__ bc, int64_t bstride,
+                       const double* __restrict__ ysh, int64_t sh_stride,
+                       double* __restrict__ yval, int64_t ystride)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (i >= S.n) return;
+    const double2* sh = ysh ? reinterpret_cast<const double2*>(ysh + c * sh_stride) : nullptr;
+    ybus_row(S, i, r + c * bstride, x + c * bstride, bc + c * bstride, sh, yval + c * ystride);
+}
+
 __global__ void k_ybus_multi(const CaseDesc* __restrict__ descs, const double* __restrict__ r,
                              const double* __restrict__ x, const double* __restrict__ bc,
-                             double* __restrict__ yval)
+                             const double* __restrict__ ysh, double* __restrict__ yval)
 {
     const CaseDesc& cd = descs[blockIdx.x];
     const DevSym& S = cd.sym;
-    const double* rc = r + cd.br_off;
-    const double* xc = x + cd.br_off;
-    const double* bcc = bc + cd.br_off;
-    double* yc = yval + cd.y_off;
-    for (int i = threadIdx.x; i < S.n; i += blockDim.x) {
-        for (int q = S.yptr[i]; q < S.yptr[i + 1]; ++q) {
-            const bool diag = S.ycol[q] == i;
-            double G = 0.0, Bv = 0.0;
-            for (int t = S.ybr_ptr[q]; t < S.ybr_ptr[q + 1]; ++t) {
-                const int e = S.ybr[t];
-                const double rr = rc[e], xx = xc[e];
-                const double den = rr * rr + xx * xx;
-                const double yg = rr / den, yb = -xx / den;
-                if (diag) {
-                    G += yg;
-                    Bv += yb + 0.5 * bcc[e];
-                } else {
-                    G -= yg;
-                    Bv -= yb;
-                }
-            }
-            reinterpret_cast<double2*>(yc)[q] = make_double2(G, Bv);
-        }
-    }
+    const double2* sh = ysh ? reinterpret_cast<const double2*>(ysh) + cd.bus_off : nullptr;
+    for (int i = threadIdx.x; i < S.n; i += blockDim.x)
+        ybus_row(S, i, r + cd.br_off, x + cd.br_off, bc + cd.br_off, sh, yval + cd.y_off);
 }
 
 __global__ __launch_bounds__(kMaxThreads) void k_mismatch(
@@ -275,22 +270,25 @@ __global__ void k_jacobian(DevSym S, const double* yval, int64_t y_stride, const
 template <bool SYM>
 __global__ __launch_bounds__(kLevelThreads) void k_factor(DevSym S, double* vals,
                                                         int64_t vals_stride, int C, int B,
-                                                        int32_t* status)
+                                                        int32_t* status, int32_t* pivot)
 {
     __shared__ int s_bad;
     const int c = case_of_block(blockIdx.x, C, B);
     if (c < 0) return;
     const View w = case_view(vals, vals_stride, C, c);
     const int64_t lu = S.lu_off;
-    if (threadIdx.x == 0) s_bad = 0;
+    if (threadIdx.x == 0) s_bad = kNoPivot;
     __syncthreads();
     const SrcLoadT<SYM> src{w, lu};
-    for_nodes(S, 0, S.tail_level, true, [&](int, const NodeRec& r, int lane, int g) {
-        factor_node<SrcLoadT<SYM>, false, true, SYM>(S, src, r, lane, g, w, lu, w, 0, &s_bad);
+    for_nodes(S, 0, S.tail_level, true, [&](int x, const NodeRec& r, int lane, int g) {
+        factor_node<SrcLoadT<SYM>, false, true, SYM>(S, src, x, r, lane, g, w, lu, w, 0, &s_bad);
     });
     if (S.tail_nodes > 0) tail_factor<SrcLoadT<SYM>, false, true>(S, src, w, lu, w, 0, &s_bad);
     __syncthreads();
-    if (threadIdx.x == 0 && status) status[c] = s_bad ? ST_ZERO_PIVOT : ST_OK;
+    if (threadIdx.x == 0) {
+        if (status) status[c] = s_bad != kNoPivot ? ST_ZERO_PIVOT : ST_OK;
+        if (pivot) pivot[c] = s_bad == kNoPivot ? -1 : S.level_nodes[s_bad];
+    }
 }
 
 // transpose = 0: y_j = D_j^-1 (b_j - sum_{i in R(j)} W_ji y_i)  (levels up),
@@ -301,21 +299,12 @@ __global__ __launch_bounds__(kLevelThreads) void k_factor(DevSym S, double* vals
 // step with the step's blocks and x values requested together; absent
 // entries of a step are not loaded and add nothing.  LDSX keeps the case's
 // whole vector in LDS (nn x 16 bytes) for the two sweeps.
-template <bool TRANS, bool LDSX>
-__global__ __launch_bounds__(kLevelThreads) void k_solve(DevSym S, const double* vals,
-                                                       int64_t vals_stride, int C, int B,
-                                                       double* rhs, int64_t rhs_stride)
+// The two sweeps of one case on the vector x2 (position order, in LDS or
+// global memory), with the factors in view w.
+template <bool TRANS>
+__device__ __forceinline__ void solve_sweeps(const DevSym& S, const View& w, double2* x2)
 {
-    const int c = case_of_block(blockIdx.x, C, B);
-    if (c < 0) return;
-    const View w = case_view(const_cast<double*>(vals), vals_stride, C, c);
     const int64_t lu = S.lu_off;
-    double2* xg = reinterpret_cast<double2*>(rhs + c * rhs_stride);
-    double2* x2 = LDSX ? reinterpret_cast<double2*>(pf_smem) : xg;
-    if (LDSX) {
-        for (int p = threadIdx.x; p < S.nn; p += blockDim.x) x2[p] = xg[p];
-        __syncthreads();
-    }
     for_nodes(S, 0, S.nlev, true, [&](int, const NodeRec& rec, int lane, int g) {
         const int j = rec.a.x, r0 = rec.a.z, r1 = rec.a.w;
         double z0 = 0.0, z1 = 0.0;
@@ -406,8 +395,74 @@ __global__ __launch_bounds__(kLevelThreads) void k_solve(DevSym S, const double*
             x2[j] = make_double2(u0, u1);
         }
     });
-    if (LDSX)
+}
+
+template <bool TRANS, bool LDSX>
+__global__ __launch_bounds__(kLevelThreads) void k_solve(DevSym S, const double* vals,
+                                                       int64_t vals_stride, int C, int B,
+                                                       double* rhs, int64_t rhs_stride)
+{
+    const int c = case_of_block(blockIdx.x, C, B);
+    if (c < 0) return;
+    const View w = case_view(const_cast<double*>(vals), vals_stride, C, c);
+    double2* xg = reinterpret_cast<double2*>(rhs + c * rhs_stride);
+    double2* x2 = LDSX ? reinterpret_cast<double2*>(pf_smem) : xg;
+    if (LDSX) {
+        for (int p = threadIdx.x; p < S.nn; p += blockDim.x) x2[p] = xg[p];
+        __syncthreads();
+    }
+    solve_sweeps<TRANS>(S, w, x2);
+    if (LDSX) {
+        __syncthreads();
         for (int p = threadIdx.x; p < S.nn; p += blockDim.x) xg[p] = x2[p];
+    }
+}
+
+// Adjoint of one case with the factors of J at its solution (beyond the
+// paper): the loss gradient gathered into position order,
+//   g_p = (dL/dtheta, dL/d|V| or 0 at a PV bus) of bus perm[p]
+// (absent gVm / gVa read as zero), the transposed solves J^T lam = g, then
+// lam to the caller and the injection gradients dL/dPsp = lam_P (non-slack
+// buses), dL/dQsp = lam_Q (PQ buses), 0 elsewhere.  A case whose status is
+// not PF_OK (its factors are not those of a converged J) gets NaN
+// gradients.
+template <bool LDSX>
+__global__ __launch_bounds__(kLevelThreads) void k_adjoint(DevSym S, AdjArgs a)
+{
+    const int c = case_of_block(blockIdx.x, a.C, a.B);
+    if (c < 0) return;
+    const View w = case_view(const_cast<double*>(a.ws), a.ws_stride, a.C, c);
+    double2* lg = reinterpret_cast<double2*>(a.lam + c * a.lam_stride);
+    double2* x2 = LDSX ? reinterpret_cast<double2*>(pf_smem) : lg;
+    const double* gVm = a.gVm ? a.gVm + c * a.gv_stride : nullptr;
+    const double* gVa = a.gVa ? a.gVa + c * a.gv_stride : nullptr;
+    const int8_t* ty = a.type + c * a.type_stride;
+    for (int p = threadIdx.x; p < S.nn; p += blockDim.x) {
+        const int bus = S.perm[p];
+        const double ga = gVa ? gVa[bus] : 0.0;
+        const double gm = (gVm && ty[bus] != T_PV) ? gVm[bus] : 0.0;
+        x2[p] = make_double2(ga, gm);
+    }
+    __syncthreads();
+    solve_sweeps<true>(S, w, x2);
+    __syncthreads();
+    const bool ok = !a.status || a.status[c] == ST_OK;
+    const double nan = __builtin_nan("");
+    if (LDSX)
+        for (int p = threadIdx.x; p < S.nn; p += blockDim.x) lg[p] = x2[p];
+    double* gP = a.gP + c * a.g_stride;
+    double* gQ = a.gQ + c * a.g_stride;
+    for (int i = threadIdx.x; i < S.n; i += blockDim.x) {
+        const int p = S.pos[i];
+        double lp = 0.0, lq = 0.0;
+        if (p >= 0) {
+            const double2 l = x2[p];
+            lp = l.x;
+            lq = ty[i] == T_PV ? 0.0 : l.y;
+        }
+        gP[i] = ok ? lp : nan;
+        gQ[i] = ok ? lq : nan;
+    }
 }
 
 template <bool MULTI>
@@ -425,7 +480,8 @@ __global__ __launch_bounds__(kLevelThreads) void k_newton(DevSym Sarg,
         newton_case(S, a.yval + cd.y_off, a.type + cd.bus_off, a.Psp + cd.bus_off,
                     a.Qsp + cd.bus_off, a.Vm + cd.bus_off, a.Va + cd.bus_off, w, wb, a.tol,
                     a.max_iter, a.flags, a.iters ? a.iters + c : nullptr,
-                    a.norm ? a.norm + c : nullptr, a.status ? a.status + c : nullptr);
+                    a.norm ? a.norm + c : nullptr, a.status ? a.status + c : nullptr,
+                    a.pivot ? a.pivot + c : nullptr);
     } else {
         const int c = case_of_block(blockIdx.x, a.interleave, a.B);
         if (c < 0) return;
@@ -435,7 +491,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_newton(DevSym Sarg,
                     a.Psp + c * a.inj_stride, a.Qsp + c * a.inj_stride, a.Vm + c * a.v_stride,
                     a.Va + c * a.v_stride, w, wb, a.tol, a.max_iter, a.flags,
                     a.iters ? a.iters + c : nullptr, a.norm ? a.norm + c : nullptr,
-                    a.status ? a.status + c : nullptr);
+                    a.status ? a.status + c : nullptr, a.pivot ? a.pivot + c : nullptr);
     }
 }
 
@@ -505,13 +561,15 @@ __device__ __forceinline__ double adj_branch(const DevSym& S, int fb, int tb,
 // mode 1 (x shared by the cases): one workgroup per 64 branches, its waves
 // split the cases and combine them in a fixed order, so no atomics are
 // needed and the sum is reproducible.  mode 0: one thread per (case, branch).
+// A case whose status (if given) is not PF_OK contributes NaN.
 __global__ void k_adj_branch(DevSym S, const int32_t* __restrict__ from,
                              const int32_t* __restrict__ to, int B, const double* lam,
                              int64_t lam_stride, const int8_t* type, int64_t type_stride,
                              const double* Vm, const double* Va, int64_t v_stride,
                              const double* r, const double* x, int64_t branch_stride,
-                             double* gx, int mode)
+                             const int32_t* status, double* gx, int mode)
 {
+    const double nan = __builtin_nan("");
     if (mode == 1) {
         __shared__ double part[16][64];
         const int e = blockIdx.x * 64 + (threadIdx.x & 63);
@@ -520,9 +578,11 @@ __global__ void k_adj_branch(DevSym S, const int32_t* __restrict__ from,
         if (e < S.m) {
             const int fb = from[e], tb = to[e];
             for (int c = wv; c < B; c += nw)
-                acc += adj_branch(S, fb, tb, lam + c * lam_stride, type + c * type_stride,
-                                  Vm + c * v_stride, Va + c * v_stride,
-                                  r[c * branch_stride + e], x[c * branch_stride + e]);
+                acc += (status && status[c] != ST_OK)
+                           ? nan
+                           : adj_branch(S, fb, tb, lam + c * lam_stride, type + c * type_stride,
+                                        Vm + c * v_stride, Va + c * v_stride,
+                                        r[c * branch_stride + e], x[c * branch_stride + e]);
         }
         part[wv][threadIdx.x & 63] = acc;
         __syncthreads();
@@ -536,9 +596,11 @@ __global__ void k_adj_branch(DevSym S, const int32_t* __restrict__ from,
         const int c = blockIdx.y;
         if (e >= S.m) return;
         gx[(int64_t)c * S.m + e] =
-            adj_branch(S, from[e], to[e], lam + c * lam_stride, type + c * type_stride,
-                       Vm + c * v_stride, Va + c * v_stride, r[c * branch_stride + e],
-                       x[c * branch_stride + e]);
+            (status && status[c] != ST_OK)
+                ? nan
+                : adj_branch(S, from[e], to[e], lam + c * lam_stride, type + c * type_stride,
+                             Vm + c * v_stride, Va + c * v_stride, r[c * branch_stride + e],
+                             x[c * branch_stride + e]);
     }
 }
 
@@ -579,7 +641,8 @@ void allow_big_lds()
         (void)hipGetLastError();
         return;
     }
-    const void* kernels[] = {reinterpret_cast<const void*>(&k_newton<false>),
+    const void* kernels[] = {reinterpret_cast<const void*>(&k_adjoint<true>),
+                             reinterpret_cast<const void*>(&k_newton<false>),
                              reinterpret_cast<const void*>(&k_newton<true>),
                              reinterpret_cast<const void*>(&k_factor<false>),
                              reinterpret_cast<const void*>(&k_factor<true>),
@@ -603,15 +666,15 @@ namespace abi {
 
 // The level-scheduled factorisation of B matrices (sym: symmetric ones).
 void factor_launch(const HostSym& h, int B, double* vals, int64_t stride, int C,
-                   int32_t* status, hipStream_t st, bool sym)
+                   int32_t* status, int32_t* pivot, hipStream_t st, bool sym)
 {
     allow_big_lds();
     if (sym)
         hipLaunchKernelGGL(k_factor<true>, dim3(grid_blocks(B, C)), dim3(launch_threads(h, B)),
-                           h.tail_lds, st, h.dev, vals, stride, C, B, status);
+                           h.tail_lds, st, h.dev, vals, stride, C, B, status, pivot);
     else
         hipLaunchKernelGGL(k_factor<false>, dim3(grid_blocks(B, C)), dim3(launch_threads(h, B)),
-                           h.tail_lds, st, h.dev, vals, stride, C, B, status);
+                           h.tail_lds, st, h.dev, vals, stride, C, B, status, pivot);
 }
 
 }  // namespace abi
@@ -619,18 +682,25 @@ void factor_launch(const HostSym& h, int B, double* vals, int64_t stride, int C,
 
 extern "C" {
 int pf_build_ybus(const pf_symbolic s, int B, const double* d_r, const double* d_x,
-                  const double* d_b, int64_t branch_stride, double* d_yval, int64_t y_stride,
-                  void* stream)
+                  const double* d_b, int64_t branch_stride, const double* d_ysh,
+                  int64_t ysh_stride, double* d_yval, int64_t y_stride, void* stream)
 {
     if (!ready(s, "pf_build_ybus")) return PF_E_INVALID;
-    if (B < 0 || B > 65535 || !d_r || !d_x || !d_b || !d_yval)
+    if (B < 0 || B > 65535 || !d_r || !d_x || !d_b || !d_yval || branch_stride < 0 ||
+        ysh_stride < 0)
         return fail(PF_E_INVALID, "pf_build_ybus: bad arguments");
     if (B > 1 && y_stride < 2 * (int64_t)s->h.ycol.size())
         return fail(PF_E_WORKSPACE, "pf_build_ybus: y_stride < 2*nnz_y");
+    if (B > 1 && branch_stride != 0 && branch_stride < s->h.m)
+        return fail(PF_E_WORKSPACE, "pf_build_ybus: branch_stride < m");
+    if (d_ysh && ((ysh_stride & 1) || (B > 1 && ysh_stride != 0 && ysh_stride < 2 * s->h.n) ||
+                  (reinterpret_cast<uintptr_t>(d_ysh) & 15)))
+        return fail(PF_E_INVALID, "pf_build_ybus: ysh_stride must be 0 or even and >= 2*n, "
+                                  "d_ysh 16-byte aligned");
     if (B == 0) return PF_OK;
     dim3 grid((s->h.n + 255) / 256, B);
     hipLaunchKernelGGL(k_ybus, grid, dim3(256), 0, as_stream(stream), s->h.dev, d_r, d_x, d_b,
-                       branch_stride, d_yval, y_stride);
+                       branch_stride, d_ysh, ysh_stride, d_yval, y_stride);
     return launch_check("pf_build_ybus");
 }
 
@@ -670,7 +740,7 @@ int pf_jacobian(const pf_symbolic s, int B, const double* d_yval, int64_t y_stri
 }
 
 int pf_factor(const pf_symbolic s, int B, double* d_vals, int64_t vals_stride,
-              int vals_interleave, int32_t* d_status, void* stream)
+              int vals_interleave, int32_t* d_status, int32_t* d_pivot, void* stream)
 {
     if (!ready(s, "pf_factor")) return PF_E_INVALID;
     if (B < 0 || !d_vals || !valid_interleave(vals_interleave) || (vals_stride & 7))
@@ -678,8 +748,8 @@ int pf_factor(const pf_symbolic s, int B, double* d_vals, int64_t vals_stride,
     if (B > 1 && vals_stride < s->h.vals_doubles())
         return fail(PF_E_WORKSPACE, "pf_factor: vals_stride < vals_doubles");
     if (B == 0) return PF_OK;
-    factor_launch(s->h, B, d_vals, vals_stride, vals_interleave, d_status, as_stream(stream),
-                  false);
+    factor_launch(s->h, B, d_vals, vals_stride, vals_interleave, d_status, d_pivot,
+                  as_stream(stream), false);
     return launch_check("pf_factor");
 }
 
@@ -717,7 +787,7 @@ int pf_newton(const pf_symbolic s, int B, const double* d_yval, int64_t y_stride
               const double* d_Qsp, int64_t inj_stride, double* d_Vm, double* d_Va,
               int64_t v_stride, double tol, int max_iter, int flags, double* d_ws,
               int64_t ws_stride, int32_t* d_iters, double* d_norm, int32_t* d_status,
-              void* stream)
+              int32_t* d_pivot, void* stream)
 {
     if (!ready(s, "pf_newton")) return PF_E_INVALID;
     if (B < 0 || max_iter < 0 || !(tol >= 0.0) || !d_yval || !d_type || !d_Psp || !d_Qsp ||
@@ -733,7 +803,7 @@ int pf_newton(const pf_symbolic s, int B, const double* d_yval, int64_t y_stride
     const int C = newton_interleave(s->h, B);
     NewtonArgs a{d_yval, y_stride, d_type, type_stride, d_Psp, d_Qsp, inj_stride, d_Vm, d_Va,
                  v_stride, d_ws, ws_stride, tol, max_iter, flags, C, B, d_iters, d_norm,
-                 d_status};
+                 d_status, d_pivot};
     allow_big_lds();
     hipLaunchKernelGGL(k_newton<false>, dim3(grid_blocks(B, C)), dim3(launch_threads(s->h, B)),
                        newton_lds(s->h), as_stream(stream), s->h.dev, (const CaseDesc*)nullptr,
@@ -747,12 +817,66 @@ int pf_adjoint_params(const pf_symbolic s, int B, const double* d_lam, int64_t l
                       const double* d_x, int64_t branch_stride, double* d_gP, double* d_gQ,
                       int64_t g_stride, double* d_gx, int gx_mode, void* stream)
 {
+    return pf::abi::adjoint_branch_launch(s, B, d_lam, lam_stride, d_type, type_stride, d_Vm,
+                                          d_Va, v_stride, d_r, d_x, branch_stride, nullptr,
+                                          d_gP, d_gQ, g_stride, d_gx, gx_mode, stream, true);
+}
+
+int pf_adjoint(const pf_symbolic s, int B, const double* d_ws, int64_t ws_stride,
+               const double* d_gVm, const double* d_gVa, int64_t gv_stride, const int8_t* d_type,
+               int64_t type_stride, const double* d_Vm, const double* d_Va, int64_t v_stride,
+               const double* d_r, const double* d_x, int64_t branch_stride,
+               const int32_t* d_status, double* d_lam, int64_t lam_stride, double* d_gP,
+               double* d_gQ, int64_t g_stride, double* d_gx, int gx_mode, void* stream)
+{
+    if (!ready(s, "pf_adjoint")) return PF_E_INVALID;
+    if (B < 0 || B > 65535 || !d_ws || !d_type || !d_Vm || !d_Va || !d_lam || !d_gP || !d_gQ ||
+        (gx_mode != 0 && gx_mode != 1) || (ws_stride & 7) || gv_stride < 0 || v_stride < 0 ||
+        g_stride < 0 || lam_stride < 0 || branch_stride < 0)
+        return fail(PF_E_INVALID, "pf_adjoint: bad arguments");
+    if (ws_stride < s->h.ws_doubles())
+        return fail(PF_E_WORKSPACE, "pf_adjoint: ws_stride < ws_doubles");
+    if (B > 1 && (lam_stride < 2 * (int64_t)s->h.nn || g_stride < s->h.n ||
+                  v_stride < s->h.n || (gv_stride != 0 && gv_stride < s->h.n)))
+        return fail(PF_E_WORKSPACE, "pf_adjoint: a stride is too small");
+    if (B == 0) return PF_OK;
+    const int C = newton_interleave(s->h, B);
+    AdjArgs a{d_ws, ws_stride, C, B, d_gVm, d_gVa, gv_stride, d_type, type_stride, d_status,
+              d_lam, lam_stride, d_gP, d_gQ, g_stride};
+    const size_t xbytes = 16 * (size_t)s->h.nn;
+    const dim3 grid(grid_blocks(B, C)), block(launch_threads(s->h, B));
+    if (xbytes <= kSolveLdsMax) {
+        allow_big_lds();
+        hipLaunchKernelGGL(k_adjoint<true>, grid, block, xbytes, as_stream(stream), s->h.dev, a);
+    } else {
+        hipLaunchKernelGGL(k_adjoint<false>, grid, block, 0, as_stream(stream), s->h.dev, a);
+    }
+    int rc = launch_check("pf_adjoint");
+    if (rc) return rc;
+    return pf::abi::adjoint_branch_launch(s, B, d_lam, lam_stride, d_type, type_stride, d_Vm,
+                                          d_Va, v_stride, d_r, d_x, branch_stride, d_status,
+                                          nullptr, nullptr, 0, d_gx, gx_mode, stream, false);
+}
+
+}  // extern "C"
+
+namespace pf {
+namespace abi {
+// Branch gradients (and, with bus, the injection gradients) of B cases from
+// their adjoint vectors.
+int adjoint_branch_launch(const pf_symbolic s, int B, const double* d_lam, int64_t lam_stride,
+                          const int8_t* d_type, int64_t type_stride, const double* d_Vm,
+                          const double* d_Va, int64_t v_stride, const double* d_r,
+                          const double* d_x, int64_t branch_stride, const int32_t* d_status,
+                          double* d_gP, double* d_gQ, int64_t g_stride, double* d_gx,
+                          int gx_mode, void* stream, bool bus)
+{
     if (!ready(s, "pf_adjoint_params")) return PF_E_INVALID;
     if (B < 0 || B > 65535 || !d_lam || !d_type || !d_Vm || !d_Va ||
         (gx_mode != 0 && gx_mode != 1))
         return fail(PF_E_INVALID, "pf_adjoint_params: bad arguments");
     if (B == 0) return PF_OK;
-    if (d_gP && d_gQ) {
+    if (bus && d_gP && d_gQ) {
         dim3 grid((s->h.n + 255) / 256, B);
         hipLaunchKernelGGL(k_adj_bus, grid, dim3(256), 0, as_stream(stream), s->h.dev, d_lam,
                            lam_stride, d_type, type_stride, d_gP, d_gQ, g_stride);
@@ -766,11 +890,15 @@ int pf_adjoint_params(const pf_symbolic s, int B, const double* d_lam, int64_t l
         const dim3 block(gx_mode == 1 ? 1024 : 256);
         hipLaunchKernelGGL(k_adj_branch, grid, block, 0, as_stream(stream), s->h.dev,
                            s->d_from, s->d_to, B, d_lam, lam_stride, d_type, type_stride, d_Vm,
-                           d_Va, v_stride, d_r, d_x, branch_stride, d_gx, gx_mode);
+                           d_Va, v_stride, d_r, d_x, branch_stride, d_status, d_gx, gx_mode);
         return launch_check("pf_adjoint_params");
     }
     return PF_OK;
 }
+}  // namespace abi
+}  // namespace pf
+
+extern "C" {
 
 int pf_adjoint_rhs(const pf_symbolic s, int B, const double* d_gVm, const double* d_gVa,
                    int64_t v_stride, const int8_t* d_type, int64_t type_stride, double* d_rhs,
@@ -874,20 +1002,22 @@ int pf_multi_upload(pf_multi p, void* d_buf, size_t bytes, void* stream)
 }
 
 int pf_build_ybus_multi(const pf_multi p, const double* d_r, const double* d_x,
-                        const double* d_b, double* d_yval, void* stream)
+                        const double* d_b, const double* d_ysh, double* d_yval, void* stream)
 {
     if (!p || !p->uploaded) return fail(PF_E_INVALID, "pf_build_ybus_multi: plan not uploaded");
     if (!d_r || !d_x || !d_b || !d_yval) return fail(PF_E_INVALID, "pf_build_ybus_multi: NULL");
+    if (d_ysh && (reinterpret_cast<uintptr_t>(d_ysh) & 15))
+        return fail(PF_E_INVALID, "pf_build_ybus_multi: d_ysh must be 16-byte aligned");
     if (p->syms.empty()) return PF_OK;
     hipLaunchKernelGGL(k_ybus_multi, dim3(p->syms.size()), dim3(256), 0, as_stream(stream),
-                       p->d_desc, d_r, d_x, d_b, d_yval);
+                       p->d_desc, d_r, d_x, d_b, d_ysh, d_yval);
     return launch_check("pf_build_ybus_multi");
 }
 
 int pf_newton_multi(const pf_multi p, const double* d_yval, const int8_t* d_type,
                     const double* d_Psp, const double* d_Qsp, double* d_Vm, double* d_Va,
                     double tol, int max_iter, int flags, double* d_ws, int32_t* d_iters,
-                    double* d_norm, int32_t* d_status, void* stream)
+                    double* d_norm, int32_t* d_status, int32_t* d_pivot, void* stream)
 {
     if (!p || !p->uploaded) return fail(PF_E_INVALID, "pf_newton_multi: plan not uploaded");
     if (max_iter < 0 || !(tol >= 0.0) || !d_yval || !d_type || !d_Psp || !d_Qsp || !d_Vm ||
@@ -897,7 +1027,7 @@ int pf_newton_multi(const pf_multi p, const double* d_yval, const int8_t* d_type
         return fail(PF_E_WORKSPACE, "pf_newton_multi: workspace must be 16-byte aligned");
     if (p->syms.empty()) return PF_OK;
     NewtonArgs a{d_yval, 0, d_type, 0, d_Psp, d_Qsp, 0, d_Vm, d_Va, 0, d_ws, 0, tol, max_iter,
-                 flags, 1, (int)p->syms.size(), d_iters, d_norm, d_status};
+                 flags, 1, (int)p->syms.size(), d_iters, d_norm, d_status, d_pivot};
     DevSym none{};
     int lds = 0, threads = 0;
     for (auto* sy : p->syms) {

@@ -506,7 +506,8 @@ int pf_se_upload(pf_se s, void* d_buf, size_t bytes, void* stream)
 constexpr int kSeGroup = 4;
 
 int pf_se_estimate(const pf_se s, int B, const double* d_r, const double* d_x,
-                   const double* d_b, int64_t branch_stride, const double* d_z,
+                   const double* d_b, int64_t branch_stride, const double* d_ysh,
+                   int64_t ysh_stride, const double* d_z,
                    int64_t z_stride, const double* d_w, int64_t w_stride, double* d_Vm,
                    double* d_Va, int64_t v_stride, double tol, int max_iter, double* d_ws,
                    int64_t ws_size, int32_t* d_iters, double* d_norm, int32_t* d_status,
@@ -515,7 +516,7 @@ int pf_se_estimate(const pf_se s, int B, const double* d_r, const double* d_x,
     if (!s || !s->uploaded) return fail(PF_E_INVALID, "pf_se_estimate: not uploaded");
     if (B < 0 || B > 65535 || max_iter < 1 || !(tol >= 0.0) || !d_r || !d_x || !d_b || !d_z ||
         !d_w || !d_Vm || !d_Va || !d_ws || !d_iters || !d_norm || !d_status || z_stride < 0 ||
-        w_stride < 0 || branch_stride < 0)
+        w_stride < 0 || branch_stride < 0 || ysh_stride < 0)
         return fail(PF_E_INVALID, "pf_se_estimate: bad arguments");
     if (B > 1 && (v_stride < s->n || (z_stride != 0 && z_stride < s->M) ||
                   (w_stride != 0 && w_stride < s->M) ||
@@ -528,7 +529,9 @@ int pf_se_estimate(const pf_se s, int B, const double* d_r, const double* d_x,
     if (B == 0) return PF_OK;
     hipStream_t st = as_stream(stream);
     const HostSym& G = s->gain.h;
-    const int yb = branch_stride ? B : 1;  // admittance copies
+    // admittance copies: one per case when the branches or the shunts differ
+    const bool per_case_y = branch_stride != 0 || (d_ysh && ysh_stride != 0);
+    const int yb = per_case_y ? B : 1;
     SeWs X;
     X.B = B;
     X.C = kSeGroup;
@@ -537,7 +540,7 @@ int pf_se_estimate(const pf_se s, int B, const double* d_r, const double* d_x,
     X.rhs = X.vals + (int64_t)Bg * s->vs;
     X.rs = s->rs;
     X.y = X.rhs + (int64_t)B * s->rs;
-    X.ys = branch_stride ? s->ys : 0;
+    X.ys = per_case_y ? s->ys : 0;
     X.st = reinterpret_cast<double2*>(X.y + (int64_t)yb * s->ys);
     X.par = X.st + 2 * (int64_t)s->n * B;
     X.res = reinterpret_cast<double*>(X.par + s->P * B);
@@ -545,7 +548,8 @@ int pf_se_estimate(const pf_se s, int B, const double* d_r, const double* d_x,
                        d_status);
     int rc = launch_check("pf_se_estimate: start");
     if (rc) return rc;
-    rc = pf_build_ybus(&s->net, yb, d_r, d_x, d_b, branch_stride, X.y, s->ys, stream);
+    rc = pf_build_ybus(&s->net, yb, d_r, d_x, d_b, branch_stride, d_ysh, ysh_stride, X.y, s->ys,
+                       stream);
     if (rc) return rc;
     const unsigned cg = (unsigned)((B + 63) / 64);
     std::vector<int32_t> host(B);
@@ -560,7 +564,7 @@ int pf_se_estimate(const pf_se s, int B, const double* d_r, const double* d_x,
                            w_stride, d_status);
         if ((rc = launch_check("pf_se_estimate: assemble"))) return rc;
         // G is symmetric: the lower blocks alone take the updates
-        factor_launch(G, B, X.vals, X.vs, kSeGroup, nullptr, st, true);
+        factor_launch(G, B, X.vals, X.vs, kSeGroup, nullptr, nullptr, st, true);
         if ((rc = launch_check("pf_se_estimate: factor"))) return rc;
         if ((rc = pf_solve(&s->gain, B, X.vals, X.vs, kSeGroup, X.rhs, X.rs, 0, stream)))
             return rc;

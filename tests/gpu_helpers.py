@@ -20,6 +20,12 @@ def grid(n, seed):
     return gridgen.make_grid(n, seed)
 
 
+@functools.lru_cache(maxsize=None)
+def shunt_grid(n, seed, shunt_seed):
+    """The generated grid with seeded bus shunts (capacitors, reactors)."""
+    return gridgen.with_shunts(gridgen.make_grid(n, seed), shunt_seed)
+
+
 def dev(a, dtype=None):
     import torch
 
@@ -43,7 +49,9 @@ class Staged:
         self.r = dev(g.r)
         self.x = dev(g.x)
         self.b = dev(g.b)
-        self.yval = self.sym.build_ybus(self.r, self.x, self.b)
+        # bus shunts (g, b) per bus, or None when the grid has none
+        self.ysh = dev(g.ysh) if g.has_shunts else None
+        self.yval = self.sym.build_ybus(self.r, self.x, self.b, self.ysh)
         self.type = dev(g.bus_type.astype(np.int8))
         self.Psp = dev(g.Psp)
         self.Qsp = dev(g.Qsp)

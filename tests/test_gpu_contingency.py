@@ -50,6 +50,8 @@ def test_screening_matches_reanalysed_outages(fdpf_first):
         keep = np.arange(g.m) != e
         oP, oQ, oP2, oQ2 = O.branch_flows(ge, res.Vm[c].cpu().numpy(), res.Va[c].cpu().numpy())
         np.testing.assert_allclose(Pft[keep], oP, rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(Qft[keep], oQ, rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(Ptf[keep], oP2, rtol=1e-12, atol=1e-12)
         np.testing.assert_allclose(Qtf[keep], oQ2, rtol=1e-12, atol=1e-12)
 
 

@@ -119,12 +119,12 @@ def test_device_calls_need_upload(B):
     h = B.pf_analyze(g.n, g.f, g.t)
     buf = np.zeros(8)
     with pytest.raises(B.PfError) as ei:
-        B.check(B.lib.pf_factor(h, 1, buf.ctypes.data, 0, 1, None, None), "pf_factor")
+        B.check(B.lib.pf_factor(h, 1, buf.ctypes.data, 0, 1, None, None, None), "pf_factor")
     assert ei.value.code == B.PF_E_INVALID
     assert "not uploaded" in B.last_error()
     with pytest.raises(B.PfError):
         B.check(B.lib.pf_newton(None, 1, *([None, 0] * 2), None, None, 0, None, None, 0, 1e-8,
-                                20, 0, None, 0, None, None, None, None), "pf_newton")
+                                20, 0, None, 0, None, None, None, None, None), "pf_newton")
     B.pf_symbolic_destroy(h)
 
 
