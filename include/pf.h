@@ -257,6 +257,27 @@ int pf_newton(const pf_symbolic sym, int B, const double* d_yval, int64_t y_stri
               int64_t ws_stride, int32_t* d_iters, double* d_norm, int32_t* d_status,
               int32_t* d_pivot, void* stream);
 
+/* ---- pf_newton without a workspace argument --------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * launch as pf_newton with flags 0, its workspace taken from a scratch array
+ * of PF_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends.  The call allocates nothing.  Inputs and outputs
+ * as pf_newton.  The batch's workspace, ceil(B / C) * C * info.ws_doubles
+ * doubles with C = pf_newton_interleave(sym, B), must fit the array (about
+ * 24 cases of 10,000 buses, 140 of 2,000); a larger batch returns
+ * PF_E_WORKSPACE before any launch.  Every call on one GPU shares that
+ * GPU's array: calls that overlap in time on one GPU (other streams or
+ * threads) race and give wrong results.  Factors are not kept (no
+ * PF_NEWTON_KEEP_FACTORS): the array is overwritten by the next call.
+ * PF_E_HIP if the array's device address cannot be taken.                 */
+#define PF_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int pf_newton_noalloc(const pf_symbolic sym, int B, const double* d_yval, int64_t y_stride,
+                      const int8_t* d_type, int64_t type_stride, const double* d_Psp,
+                      const double* d_Qsp, int64_t inj_stride, double* d_Vm, double* d_Va,
+                      int64_t v_stride, double tol, int max_iter, int32_t* d_iters,
+                      double* d_norm, int32_t* d_status, int32_t* d_pivot, void* stream);
+
 /* Case grouping pf_newton uses for a batch of B: info.ws_interleave halved
  * until it does not exceed B (1 for a single case).  Returns -1 on error.  */
 int pf_newton_interleave(const pf_symbolic sym, int B);

@@ -84,6 +84,8 @@ _SIGS = {
     "pf_adjoint_params": ([_vp, _i, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _vp,
                            _vp, _i64, _vp, _i, _vp], _i),
     "pf_adjoint_rhs": ([_vp, _i, _vp, _vp, _i64, _vp, _i64, _vp, _i64, _vp], _i),
+    "pf_newton_noalloc": ([_vp, _i, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _d,
+                           _i, _vp, _vp, _vp, _vp, _vp], _i),
     "pf_adjoint": ([_vp, _i, _vp, _i64, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _vp,
                     _i64, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _i, _vp], _i),
     "pf_multi_create": ([_i, _vp, C.POINTER(_vp)], _i),
@@ -261,6 +263,18 @@ def pf_adjoint_params(h, B, lam, lam_stride, bus_type, type_stride, Vm, Va, v_st
                                 ptr(Vm), ptr(Va), v_stride, ptr(r), ptr(x), branch_stride,
                                 ptr(gP), ptr(gQ), g_stride, ptr(gx), int(gx_mode),
                                 stream_ptr(stream)), "pf_adjoint_params")
+
+
+PF_NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def pf_newton_noalloc(h, B, yval, y_stride, bus_type, type_stride, Psp, Qsp, inj_stride, Vm, Va,
+                      v_stride, tol, max_iter, iters=None, norm=None, status=None, pivot=None,
+                      stream=None):
+    check(lib.pf_newton_noalloc(h, B, ptr(yval), y_stride, ptr(bus_type), type_stride,
+                                ptr(Psp), ptr(Qsp), inj_stride, ptr(Vm), ptr(Va), v_stride,
+                                float(tol), int(max_iter), ptr(iters), ptr(norm), ptr(status),
+                                ptr(pivot), stream_ptr(stream)), "pf_newton_noalloc")
 
 
 def pf_adjoint(h, B, ws, ws_stride, gVm, gVa, gv_stride, bus_type, type_stride, Vm, Va,

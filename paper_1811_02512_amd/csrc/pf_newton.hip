@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <type_traits>
@@ -780,6 +781,79 @@ int pf_solve(const pf_symbolic s, int B, const double* d_vals, int64_t vals_stri
         else go(k_solve<false, false>, 0);
     }
     return launch_check("pf_solve");
+}
+
+}  // extern "C"
+
+// ---- the allocation-free Newton entry point -------------------------------
+// The Newton workspace of pf_newton_noalloc lives in this file-scope device
+// array (each GPU holds its own copy for the life of the process).  Host code
+// never passes the array's name to a kernel: its device address, taken once
+// per device with hipGetSymbolAddress, is what the launch receives.
+namespace {
+constexpr int64_t kScratchDoubles = PF_NOALLOC_SCRATCH_BYTES / 8;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array, or null (with the
+// error recorded) when it cannot be taken.
+double* scratch_ptr(const char* fn)
+{
+    int dev = 0;
+    if (hip_check(hipGetDevice(&dev), fn)) return nullptr;
+    if (dev < 0 || dev >= kMaxDevices) {
+        fail(PF_E_HIP, std::string(fn) + ": device index out of range");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), fn)) return nullptr;
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" {
+
+int pf_newton_noalloc(const pf_symbolic s, int B, const double* d_yval, int64_t y_stride,
+                      const int8_t* d_type, int64_t type_stride, const double* d_Psp,
+                      const double* d_Qsp, int64_t inj_stride, double* d_Vm, double* d_Va,
+                      int64_t v_stride, double tol, int max_iter, int32_t* d_iters,
+                      double* d_norm, int32_t* d_status, int32_t* d_pivot, void* stream)
+{
+    if (!ready(s, "pf_newton_noalloc")) return PF_E_INVALID;
+    if (B < 0 || B > 65535 || max_iter < 0 || !(tol >= 0.0) || !d_yval || !d_type || !d_Psp ||
+        !d_Qsp || !d_Vm || !d_Va)
+        return fail(PF_E_INVALID, "pf_newton_noalloc: bad arguments");
+    if (B > 1 && v_stride < s->h.n)
+        return fail(PF_E_WORKSPACE, "pf_newton_noalloc: v_stride too small");
+    if (B == 0) return PF_OK;
+    const int C = newton_interleave(s->h, B);
+    const int64_t ws_stride = s->h.ws_doubles();
+    // workspace rows of whole interleaved groups (the padding blocks of the
+    // grid own no case and touch no workspace)
+    const int64_t need = (int64_t)((B + C - 1) / C) * C * ws_stride;
+    if (need > kScratchDoubles)
+        return fail(PF_E_WORKSPACE,
+                    "pf_newton_noalloc: the batch needs " + std::to_string(need * 8) +
+                        " bytes of workspace, more than the " +
+                        std::to_string(PF_NOALLOC_SCRATCH_BYTES) +
+                        "-byte scratch array; split the batch or use pf_newton");
+    double* ws = scratch_ptr("pf_newton_noalloc");
+    if (!ws) return PF_E_HIP;
+    NewtonArgs a{d_yval, y_stride, d_type, type_stride, d_Psp, d_Qsp, inj_stride, d_Vm, d_Va,
+                 v_stride, ws, ws_stride, tol, max_iter, 0, C, B, d_iters, d_norm, d_status,
+                 d_pivot};
+    allow_big_lds();
+    hipLaunchKernelGGL(k_newton<false>, dim3(grid_blocks(B, C)), dim3(launch_threads(s->h, B)),
+                       newton_lds(s->h), as_stream(stream), s->h.dev, (const CaseDesc*)nullptr,
+                       (const int32_t*)nullptr, a);
+    return launch_check("pf_newton_noalloc");
 }
 
 int pf_newton(const pf_symbolic s, int B, const double* d_yval, int64_t y_stride,
