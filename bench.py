@@ -1,16 +1,25 @@
 """Benchmark: batched Newton-Raphson AC power flow with adjoint on MI355X.
 
-Default workload (one "step" = the whole hot path over one batch):
+Headline workload (one "step" = the whole hot path over one batch):
   10,000-bus synthetic grid (seed 1), 256 seeded load scenarios (seed 5):
   admittance assembly -> batched NR to 1e-8 p.u. keeping the factors at the
   solution -> adjoint backward (gather dL/dx, transposed level-scheduled
-  solves, parameter gradients) for loss = sum_i w_i (|V_i| - 1)^2.
+  solves, injection and branch gradients) for loss = sum_i w_i (|V_i| - 1)^2.
 value = cases per second, each case solved to 1e-8 p.u. with its gradient.
 
-Also reported: the plain one-case-per-launch rate on the same grid, the
-forward-only batched rate, the roofline of the Newton kernel and the CPU
-oracle timed on the host's cores.  --full adds the 2,000-bus x 1,024
-scenario batch, the 512 N-1 outages and the 64 mixed-size grids.
+Every other configuration is a leg of the same default run, each timed on
+the device and each checked against the CPU oracle on a seeded subset of its
+cases outside the timed region:
+  c1  200-bus grid, one case per launch
+  c2  10,000-bus grid, one case per launch, with factor and solve time per
+      Newton iteration and their bandwidth
+  c3  2,000-bus grid x 1,024 load scenarios, one shared analysis, autotuned
+  c4  10,000-bus grid x 512 N-1 outages (each re-analysed) and 64 grids of
+      500-20,000 buses, each in one launch
+  c5  the headline, also through the torch.autograd.Function
+plus the fast decoupled method, the step replayed from a HIP graph, N-1
+screening on the base pattern, WLS state estimation, and the CPU oracle on
+the host's cores.  --legs selects legs (e.g. --legs c1,c2 for profiling).
 """
 from __future__ import annotations
 
@@ -19,6 +28,8 @@ import json
 import os
 import sys
 import time
+import multiprocessing
+from concurrent.futures import ProcessPoolExecutor, ThreadPoolExecutor
 
 import numpy as np
 
@@ -30,20 +41,97 @@ KERNEL_SOURCES = tuple("paper_1811_02512_amd/csrc/" + f for f in (
     "pf_abi.hip", "pf_newton.hip", "pf_fdpf.hip", "pf_se.hip", "pf_device.h", "pf_host.h",
     "pf_kernels.h", "pf_internal.h", "analyze.cpp"))
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_newton_10k_x256_hbm_traffic.md")
+ALL_LEGS = ("c5", "c1", "c2", "c3", "c4", "fdpf", "graph", "screen", "se")
+HOST_THREADS = 16  # the GPU machine's CPU share; also the oracle's thread pool
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes_per_iter(info):
+def host_threads():
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return max(1, min(avail, HOST_THREADS))
+
+
+def newton_bytes_per_iter(info):
     """Algorithmic bytes per NR iteration per case: 16 Y + 128 F + 96 n with
     Y = admittance entries, F = nn + 2 nnz(L) filled 2x2 blocks."""
     F = info.nn + 2 * info.nnz_l
     return 16 * info.nnz_y + 128 * F + 96 * info.n
 
 
+def filled_blocks(info):
+    return info.nn + 2 * info.nnz_l
+
+
+def adjoint_bytes(info):
+    """Fused adjoint kernel per case: the factors read once (32 F), the
+    gradient gathered (16 n), lam written (16 nn) and dL/dP, dL/dQ written
+    (16 n)."""
+    return 32 * filled_blocks(info) + 32 * info.n + 16 * info.nn
+
+
+def branch_grad_bytes(info):
+    """Branch-gradient kernel per case: per branch the voltages and adjoint
+    entries of both ends (64 B) with r, x shared; per bus nothing else."""
+    return 64 * info.m
+
+
+def timed(fn, steps, warmup):
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def roofline(bytes_per_launch, ms, name, units, per_unit, traffic=None):
+    gbs = bytes_per_launch / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "traffic": traffic, "kernel": name,
+            "algorithmic_bytes_per_launch": bytes_per_launch, "units_per_launch": units,
+            "bytes_per_unit": per_unit, "kernel_ms": ms}
+
+
+def check_cases(results):
+    """Summary of per-case oracle comparisons (iters_equal, dV, dtheta[, dgrad])."""
+    out = {"cases": len(results),
+           "iterations_equal": bool(all(r[0] for r in results)),
+           "max_abs_dV": float(max(r[1] for r in results)),
+           "max_abs_dtheta": float(max(r[2] for r in results))}
+    if results and len(results[0]) > 3:
+        out["max_rel_dgrad"] = float(max(r[3] for r in results))
+    ok = out["iterations_equal"] and out["max_abs_dV"] < 1e-9 and out["max_abs_dtheta"] < 1e-9
+    if "max_rel_dgrad" in out:
+        ok = ok and out["max_rel_dgrad"] < 1e-8
+    out["pass"] = bool(ok)
+    if not ok:
+        raise AssertionError(f"oracle check failed: {out}")
+    return out
+
+
+def pick_cases(B, k, seed):
+    rng = np.random.default_rng(seed)
+    return sorted(int(c) for c in rng.choice(B, min(k, B), replace=False))
+
+
 class Workload:
+    """One grid with B load scenarios staged on the device, plus the buffers
+    of the batched step (symbolic tuned for the batch) and of one case per
+    launch (symbolic tuned for a single case)."""
+
     def __init__(self, n, seed, scen, scen_seed, load_scale=0.1):
         import torch
 
@@ -77,18 +165,19 @@ class Workload:
         self.pq = t((g.bus_type == 1).astype(np.float64))
         info = self.info
         Bn = scen
-        self.yval = torch.empty(1, 2 * info.nnz_y, dtype=torch.float64, device=dev)
-        self.Vm = torch.empty(Bn, g.n, dtype=torch.float64, device=dev)
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.yval = torch.empty(1, 2 * info.nnz_y, **f64)
+        self.Vm = torch.empty(Bn, g.n, **f64)
         self.Va = torch.empty_like(self.Vm)
         self.ws = self.sym.workspace(Bn)
         self.it = torch.empty(Bn, dtype=torch.int32, device=dev)
-        self.nrm = torch.empty(Bn, dtype=torch.float64, device=dev)
+        self.nrm = torch.empty(Bn, **f64)
         self.st = torch.empty(Bn, dtype=torch.int32, device=dev)
-        self.lam = torch.empty(Bn, 2 * info.nn, dtype=torch.float64, device=dev)
-        self.gP = torch.empty(Bn, g.n, dtype=torch.float64, device=dev)
+        self.lam = torch.empty(Bn, 2 * info.nn, **f64)
+        self.gP = torch.empty(Bn, g.n, **f64)
         self.gQ = torch.empty_like(self.gP)
-        self.gx = torch.empty(g.m, dtype=torch.float64, device=dev)
-        self.gVa = torch.zeros_like(self.Vm)
+        self.gx = torch.empty(g.m, **f64)
+        self.gVm = torch.empty_like(self.Vm)
 
     def autotune(self, Bn, sym):
         from paper_1811_02512_amd import autotune
@@ -98,7 +187,7 @@ class Workload:
         A0 = self.Va0.expand(Bn, g.n).contiguous()
         res = autotune.tune(sym, self.yval[0], self.type, self.Pt[:Bn].contiguous(),
                             self.Qt[:Bn].contiguous(), V0, A0)
-        log(f"[bench] autotune B={Bn}: T={res['threads']} tail={res['tail_budget']} "
+        log(f"[bench] autotune n={g.n} B={Bn}: T={res['threads']} tail={res['tail_budget']} "
             f"C={res['interleave']} best {res['ms']:.3f} ms, {res['launches']} launches in "
             f"{res['seconds']:.1f}s")
         self.info = self.sym.info
@@ -107,8 +196,10 @@ class Workload:
         return res
 
     def step(self, ev=None, adjoint=True, Bn=None):
-        """One pass of the hot path.  ev: optional (start, end) events around
-        the Newton kernel."""
+        """One pass of the hot path.  ev: optional dict of (start, end) event
+        pairs around the Newton kernel ('newton'), the fused adjoint kernel
+        ('adjoint') and the branch-gradient kernel ('branch'), each recorded on
+        the stream its kernel runs on (the current stream)."""
         from paper_1811_02512_amd import binding as B
 
         g = self.g
@@ -119,20 +210,55 @@ class Workload:
         self.Vm[:Bn].copy_(self.Vm0.expand(Bn, g.n))
         self.Va[:Bn].copy_(self.Va0.expand(Bn, g.n))
         if ev is not None:
-            ev[0].record()
+            ev["newton"][0].record()
         B.pf_newton(sym.h, Bn, self.yval, 0, self.type, 0, self.Pt, self.Qt, g.n, self.Vm,
                     self.Va, g.n, 1e-8, 20, B.PF_NEWTON_KEEP_FACTORS if adjoint else 0,
                     self.ws, info.ws_doubles, self.it, self.nrm, self.st)
         if ev is not None:
-            ev[1].record()
+            ev["newton"][1].record()
         if not adjoint:
             return
-        gVm = 2.0 * self.wt * self.pq * (self.Vm[:Bn] - 1.0)  # dLoss/d|V| of the user's loss
-        B.pf_adjoint_rhs(sym.h, Bn, gVm, self.gVa, g.n, self.type, 0, self.lam, 2 * info.nn)
-        B.pf_solve(sym.h, Bn, self.ws, info.ws_doubles, self.lam, 2 * info.nn, 1,
-                   B.pf_newton_interleave(sym.h, Bn))
+        # dLoss/d|V| of the caller's loss, written by the caller in torch
+        self.gVm[:Bn].copy_(self.Vm[:Bn]).sub_(1.0).mul_(self.wt * self.pq * 2.0)
+        if ev is not None:
+            ev["adjoint"][0].record()
+        B.pf_adjoint(sym.h, Bn, self.ws, info.ws_doubles, self.gVm, None, g.n, self.type, 0,
+                     self.Vm, self.Va, g.n, self.r, self.x, 0, self.st, self.lam, 2 * info.nn,
+                     self.gP, self.gQ, g.n, None, 1)
+        if ev is not None:
+            ev["adjoint"][1].record()
+            ev["branch"][0].record()
         B.pf_adjoint_params(sym.h, Bn, self.lam, 2 * info.nn, self.type, 0, self.Vm, self.Va,
-                            g.n, self.r, self.x, 0, self.gP, self.gQ, g.n, self.gx, 1)
+                            g.n, self.r, self.x, 0, None, None, g.n, self.gx, 1)
+        if ev is not None:
+            ev["branch"][1].record()
+
+    def oracle_check(self, cases, adjoint):
+        """Per-case comparison of the last step's results with the oracle's
+        sparse NR (and sparse adjoint) on the same inputs, in threads."""
+        from oracle import oracle as O
+
+        g = self.g
+        Y = O.grid_ybus(g)
+        osym = O.Sym(g.n, g.f, g.t)
+        Vm, Va = self.Vm.cpu().numpy(), self.Va.cpu().numpy()
+        it = self.it.cpu().numpy()
+        gP, gQ = self.gP.cpu().numpy(), self.gQ.cpu().numpy()
+        Vm0, Va0 = g.flat_start()
+
+        def one(c):
+            r = osym.newton(Y, g.bus_type, self.P[c], self.Q[c], Vm0, Va0)
+            res = [r.status == 0 and r.iters == it[c], float(np.abs(r.Vm - Vm[c]).max()),
+                   float(np.abs(r.Va - Va[c]).max())]
+            if adjoint:
+                gv = 2 * self.w * (Vm[c] - 1) * (g.bus_type == 1)
+                oP, oQ, _ = osym.adjoint(g, Y, Vm[c], Va[c], gv, np.zeros(g.n))
+                sc = max(np.abs(oP).max(), np.abs(oQ).max())
+                res.append(float(max(np.abs(oP - gP[c]).max(), np.abs(oQ - gQ[c]).max()) / sc))
+            return res
+
+        with ThreadPoolExecutor(host_threads()) as ex:
+            return check_cases(list(ex.map(one, cases)))
 
 
 def kernel_source_hash():
@@ -206,67 +332,268 @@ def host_cpu():
     return model, os.cpu_count()
 
 
-def timed(fn, steps, warmup):
+# ---------------------------------------------------------------------------
+# legs
+# ---------------------------------------------------------------------------
+def leg_headline(W, args, tuned):
+    """C5: Ybus + batched NR keeping the factors + fused adjoint, 10k x 256."""
     import torch
 
-    for _ in range(warmup):
-        fn()
+    info = W.info
+    names = ("newton", "adjoint", "branch")
+    evs = [{k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for k in names} for _ in range(args.steps)]
+    for _ in range(args.warmup):
+        W.step()
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(steps):
-        fn()
-    e1.record()
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    t_start.record()
+    for k in range(args.steps):
+        W.step(evs[k])
+    t_end.record()
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / steps
+    ms_step = t_start.elapsed_time(t_end) / args.steps
+    kms = {k: float(np.mean([e[k][0].elapsed_time(e[k][1]) for e in evs])) for k in names}
+    iters = W.it.cpu().numpy()
+    status = W.st.cpu().numpy()
+    assert (status == 0).all(), f"non-converged cases: {np.unique(status, return_counts=True)}"
+    check = W.oracle_check(pick_cases(W.B, 16, 21), adjoint=True)
+    log(f"[bench] c5 headline: {ms_step:.3f} ms/step, newton {kms['newton']:.3f} ms, adjoint "
+        f"{kms['adjoint']:.3f} ms, branch {kms['branch']:.3f} ms; oracle check {check}")
+    b_it = newton_bytes_per_iter(info)
+    units = float(iters.sum())
+    rf = roofline(b_it * units, kms["newton"], "k_newton (batched launch)", units, b_it,
+                  measured_traffic(tuned))
+    rf["launch"] = None if tuned is None else launch_tag(tuned)
+    adj = {
+        "k_adjoint": roofline(adjoint_bytes(info) * W.B, kms["adjoint"],
+                              "k_adjoint (gather + transposed solves + dL/dP, dL/dQ)", W.B,
+                              adjoint_bytes(info)),
+        "k_adj_branch": roofline(branch_grad_bytes(info) * W.B, kms["branch"],
+                                 "k_adj_branch (dL/dx summed over cases)", W.B,
+                                 branch_grad_bytes(info)),
+    }
+    return ms_step, iters, rf, adj, check, kms
 
 
-def cpu_baseline(W, wall_s=15.0):
-    """The oracle (paper-path sparse NR + sparse adjoint) over the load
-    scenarios on a thread pool of the host's cores (ctypes releases the GIL),
-    cycling through the scenarios until about `wall_s` seconds of wall time."""
-    from concurrent.futures import ThreadPoolExecutor
+def leg_autograd(W, steps):
+    """The headline step through the product API: autograd.power_flow (its
+    own Ybus, workspace and output buffers per call) and loss.backward()."""
+    import torch
 
-    from oracle import oracle as O
+    from paper_1811_02512_amd.autograd import power_flow
 
     g = W.g
-    Y = O.grid_ybus(g)
-    osym = O.Sym(g.n, g.f, g.t)
-    Vm0, Va0 = g.flat_start()
-    cores = min(os.cpu_count() or 1, 16)
+    P = W.Pt.clone().requires_grad_(True)
+    Q = W.Qt.clone().requires_grad_(True)
+    x = W.x.clone().requires_grad_(True)
+    box = {}
+
+    def step():
+        P.grad = Q.grad = x.grad = None
+        Vm, Va = power_flow(W.sym, P, Q, x, W.r, W.b, W.type, W.Vm0, W.Va0)
+        loss = (W.wt * W.pq * (Vm - 1.0) ** 2).sum()
+        loss.backward()
+        box["Vm"] = Vm
+
+    ms = timed(step, steps, 1)
+    # same answers as the direct-ABI step
+    dv = float((box["Vm"].detach() - W.Vm).abs().max().item())
+    dg = float((P.grad - W.gP).abs().max().item() / W.gP.abs().max().item())
+    dx = float((x.grad - W.gx).abs().max().item() / W.gx.abs().max().item())
+    log(f"[bench] c5 through torch.autograd: {ms:.3f} ms/step; vs direct ABI: dV {dv:.1e}, "
+        f"dgP {dg:.1e}, dgx {dx:.1e}")
+    assert dv < 1e-12 and dg < 1e-12 and dx < 1e-12
+    return dict(solves_per_s=W.B / ms * 1e3, ms_per_step=ms,
+                max_diff_vs_direct_abi={"Vm": dv, "gP_rel": dg, "gx_rel": dx},
+                step="power_flow(...) (Ybus, NR keeping the factors) + loss.backward() "
+                     "(pf_adjoint, branch gradients), buffers allocated per call by torch")
+
+
+def leg_plain(W, steps, label):
+    """One case per launch on W's grid: ms per solve and per iteration, and a
+    comparison with the oracle."""
+    ms = timed(lambda: W.step(adjoint=False, Bn=1), steps, 1)
+    it = int(W.it[0].item())
+    assert int(W.st[0].item()) == 0
+    from oracle import oracle as O
+
+    ref = O.solve_grid(W.g, Psp=W.P[0], Qsp=W.Q[0])
+    Vm, Va = W.Vm[0].cpu().numpy(), W.Va[0].cpu().numpy()
+    check = check_cases([(ref.iters == it, float(np.abs(ref.Vm - Vm).max()),
+                          float(np.abs(ref.Va - Va).max()))])
+    log(f"[bench] {label} one case per launch: {ms * 1e3:.1f} us/solve, {it} iterations, "
+        f"{ms * 1e3 / max(it, 1):.1f} us/iteration")
+    return dict(solves_per_s=1e3 / ms, ms_per_solve=ms, us_per_iteration=ms * 1e3 / max(it, 1),
+                iterations=it, kernel_launches_per_solve=2,
+                launches="k_ybus + k_newton (the whole NR loop in one launch); two 16n-byte "
+                         "device copies of the flat start",
+                oracle_check=check)
+
+
+def leg_c2_breakdown(W, steps):
+    """10k single case: the Jacobian at flat start factorised (pf_factor) and
+    solved (pf_solve) alone, one case per launch, with their bandwidth."""
+    import torch
+
+    from paper_1811_02512_amd import binding as B
+
+    sym, info, g = W.sym1, W.sym1.info, W.g
+    f64 = dict(dtype=torch.float64, device="cuda")
+    J = torch.zeros(1, info.vals_doubles, **f64)
+    B.pf_build_ybus(sym.h, 1, W.r, W.x, W.b, 0, W.yval, 2 * info.nnz_y)
+    B.pf_jacobian(sym.h, 1, W.yval, 0, W.type, 0, W.Vm0, W.Va0, 0, J, info.vals_doubles)
+    vals = J.clone()
+    rhs0 = torch.ones(1, 2 * info.nn, **f64)
+    rhs = rhs0.clone()
+    st = torch.empty(1, dtype=torch.int32, device="cuda")
+
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps + 1)]
+    for e0, e1 in evs:  # the first pair warms up
+        vals.copy_(J)
+        e0.record()
+        B.pf_factor(sym.h, 1, vals, info.vals_doubles, st)
+        e1.record()
+    torch.cuda.synchronize()
+    fac_ms = float(np.mean([a.elapsed_time(b) for a, b in evs[1:]]))
+    assert st.item() == 0
+    sol_ms = timed(lambda: B.pf_solve(sym.h, 1, vals, info.vals_doubles, rhs, 2 * info.nn, 0),
+                   steps, 1)
+    F = filled_blocks(info)
+    fb, sb = 64 * F, 32 * F + 32 * info.nn
+    log(f"[bench] c2 single case: factor {fac_ms * 1e3:.1f} us, solve {sol_ms * 1e3:.1f} us "
+        f"(F = {F} blocks)")
+    return dict(factor_us=fac_ms * 1e3, solve_us=sol_ms * 1e3,
+                factor_gbs=fb / (fac_ms * 1e-3) / 1e9, solve_gbs=sb / (sol_ms * 1e-3) / 1e9,
+                factor_bytes=fb, solve_bytes=sb, levels=int(info.nlevels),
+                note="one workgroup per case: each of the levels is a barrier-separated "
+                     "chain of dependent loads, so these are latency figures; the bandwidth "
+                     "is far below HBM by construction")
+
+
+def leg_c3(args, tuned_file):
+    """C3: 2,000-bus grid x 1,024 load scenarios, shared analysis, tuned."""
+    W2 = Workload(2000, 1, 1024, 2)
+    W2.step(adjoint=False)
+    if tuned_file is None and not args.no_tune:
+        W2.autotune(W2.B, W2.sym)
+        W2.autotune(1, W2.sym1)
+    ms = timed(lambda: W2.step(adjoint=False), max(3, args.steps // 2), 1)
+    assert (W2.st.cpu().numpy() == 0).all()
+    its = W2.it.cpu().numpy()
+    check = W2.oracle_check(pick_cases(W2.B, 16, 22), adjoint=False)
+    plain = leg_plain(W2, max(3, args.steps // 2), "c3 2k")
+    info = W2.sym.info
+    b_it = newton_bytes_per_iter(info)
+    log(f"[bench] c3 2k x 1024: {ms:.3f} ms/launch")
+    return dict(solves_per_s=W2.B / ms * 1e3, ms_per_step=ms, cases=W2.B,
+                mean_iterations=float(its.mean()),
+                speedup_vs_plain=(W2.B / ms) / plain["solves_per_s"] * 1e3,
+                plain_solves_per_s=plain["solves_per_s"],
+                hbm_frac=b_it * float(its.sum()) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                oracle_check=check,
+                step="Ybus + batched NR to 1e-8 (k_newton, one launch)")
+
+
+def _make_grid(spec):
+    import gridgen
+
+    n, seed, scale = spec
+    return gridgen.make_grid(n, seed, load_scale=scale)
+
+
+def bench_multi(grids, label, steps, check_idx):
+    """One launch over cases with their own analyses; timing, host analysis
+    time and an oracle check of the cases in check_idx."""
+    import torch
+
+    from oracle import oracle as O
+    from paper_1811_02512_amd import api
+    from paper_1811_02512_amd import binding as B
+
+    t0 = time.time()
+    with ThreadPoolExecutor(host_threads()) as ex:
+        syms = list(ex.map(lambda g: api.Symbolic(g.n, g.f, g.t), grids))
+    t_an = time.time() - t0
+    for s in syms:
+        s.set_launch(0, 161792)  # the largest LDS tail: the launch waits for its largest grid
+        s.upload()
+    plan = api.MultiPlan(syms)
+    f64 = np.float64
+    r = plan.concat([g.r for g in grids], "branch", f64)
+    x = plan.concat([g.x for g in grids], "branch", f64)
+    b = plan.concat([g.b for g in grids], "branch", f64)
+    yv = torch.empty(int(plan.offs["y"][-1]) + 2, dtype=torch.float64, device="cuda")
+    ty = plan.concat([g.bus_type for g in grids], "bus", np.int8)
+    P = plan.concat([g.Psp for g in grids], "bus", f64)
+    Q = plan.concat([g.Qsp for g in grids], "bus", f64)
+    V0 = plan.concat([g.flat_start()[0] for g in grids], "bus", f64)
+    A0 = plan.concat([g.flat_start()[1] for g in grids], "bus", f64)
+    Vm, Va = V0.clone(), A0.clone()
+    ws = torch.empty(int(plan.offs["ws"][-1]) + 32, dtype=torch.float64, device="cuda")
+    G = len(grids)
+    it = torch.empty(G, dtype=torch.int32, device="cuda")
+    st = torch.empty(G, dtype=torch.int32, device="cuda")
+
+    def step():
+        B.pf_build_ybus_multi(plan.p, r, x, b, yv)
+        Vm.copy_(V0)
+        Va.copy_(A0)
+        B.pf_newton_multi(plan.p, yv, ty, P, Q, Vm, Va, 1e-8, 20, 0, ws, it, None, st)
+
+    ms = timed(step, steps, 1)
+    sts = st.cpu().numpy()
+    its = it.cpu().numpy()
+    ok = int((sts == 0).sum())
+    Vms, Vas = plan.split(Vm, "bus"), plan.split(Va, "bus")
 
     def one(c):
-        c %= W.B
-        r = osym.newton(Y, g.bus_type, W.P[c], W.Q[c], Vm0, Va0)
-        gVm = 2 * W.w * (r.Vm - 1) * (g.bus_type == 1)
-        osym.adjoint(g, Y, r.Vm, r.Va, gVm, np.zeros(g.n))
-        return r.status
+        ref = O.solve_grid(grids[c])
+        return (ref.status == 0 and sts[c] == 0 and ref.iters == its[c],
+                float(np.abs(ref.Vm - Vms[c]).max()), float(np.abs(ref.Va - Vas[c]).max()))
 
-    one(0)  # warm-up
-    singles = []
-    for c in range(1, 6):
-        t0 = time.time()
-        one(c)
-        singles.append(time.time() - t0)
-    per_case = float(np.median(singles))
-    count = max(cores, int(wall_s * cores / max(per_case, 1e-6)))
-    log(f"[bench] cpu baseline: {per_case * 1e3:.1f} ms per case on one thread, "
-        f"{count} cases on {cores} threads")
+    with ThreadPoolExecutor(host_threads()) as ex:
+        check = check_cases(list(ex.map(one, check_idx)))
+    log(f"[bench] {label}: {G} cases, {ms:.2f} ms/launch, converged {ok}/{G}, host analysis "
+        f"{t_an:.2f}s; oracle check {check}")
+    # only converged cases count as solves
+    return dict(solves_per_s=ok / ms * 1e3, ms=ms, cases=G, converged=ok,
+                host_analysis_s=t_an, host_threads=host_threads(),
+                solves_per_s_with_host_analysis=ok / (ms * 1e-3 + t_an),
+                buses=int(sum(g.n for g in grids)),
+                bus_solves_per_s=sum(g.n for g, s in zip(grids, sts.tolist()) if s == 0) / ms * 1e3,
+                oracle_check=check)
+
+
+def leg_c4(W, args):
+    import gridgen
+
+    out = {}
+    outs = gridgen.n1_outages(W.g, 512, 3)
+    n1 = [W.g.without_branch(int(e)) for e in outs]
+    out["n1_10k_x512"] = bench_multi(n1, "c4 N-1 10k x 512", max(3, args.steps // 3),
+                                     pick_cases(512, 16, 23))
+    spec = json.load(open(os.path.join(ROOT, "tests", "golden", "mixed_batch.json")))
     t0 = time.time()
-    with ThreadPoolExecutor(cores) as ex:
-        sts = list(ex.map(one, range(count)))
-    wall = time.time() - t0
-    model, nproc = host_cpu()
-    return dict(value=count / wall, unit="solves/s", cores=cores, kind="oracle",
-                single_thread_ms_per_solve=per_case * 1e3, host_cpu=model, host_nproc=nproc,
-                sample=f"{count} solves cycling over the {W.B} load scenarios of the {g.n}-bus "
-                       f"grid: forward NR (sparse paper path, tol 1e-8) + sparse adjoint each, "
-                       f"{cores} threads, {wall:.1f}s wall, converged "
-                       f"{sum(s == 0 for s in sts)}/{count}")
+    jobs = [(gs["n"], gs["seed"], spec["load_scale"]) for gs in spec["grids"]]
+    order = sorted(range(len(jobs)), key=lambda i: -jobs[i][0])  # largest first
+    # fresh interpreters (spawn), so that no generator process holds this
+    # process's GPU handles; at most 15 of them beside this one
+    ctx = multiprocessing.get_context("spawn")
+    with ProcessPoolExecutor(min(host_threads(), 15), mp_context=ctx) as ex:
+        made = dict(zip(order, ex.map(_make_grid, [jobs[i] for i in order])))
+    mixed = [made[i] for i in range(len(jobs))]
+    log(f"[bench] c4 mixed: 64 grids generated in {time.time() - t0:.1f}s")
+    largest = int(np.argmax([g.n for g in mixed]))
+    idx = sorted(set(pick_cases(64, 8, 24)) | {largest})
+    out["mixed_64_grids"] = bench_multi(mixed, "c4 mixed 64 grids 500-20k buses",
+                                        max(3, args.steps // 3), idx)
+    return out
 
 
-def bench_graph(W, steps):
+def leg_graph(W, steps):
     """The whole step (Ybus, batched NR keeping the factors, adjoint) captured
     once in a HIP graph and replayed; every replay's outputs are checked
     against the eager step's."""
@@ -295,13 +622,14 @@ def bench_graph(W, steps):
     return dict(solves_per_s=W.B / ms * 1e3, ms_per_step=ms, replays_checked=2)
 
 
-def bench_fdpf(W, steps):
+def leg_fdpf(W, steps):
     """Fast decoupled power flow on the workload's grid and scenarios: one
     step = B' and B'' built and factored once for the batch (shared
     impedances) + the batched decoupled iteration to 1e-8 + branch flows of
     every case.  Also the one-case-per-launch rate."""
     import torch
 
+    from oracle import oracle as O
     from paper_1811_02512_amd import binding as B
 
     g, sym, info = W.g, W.sym1, W.sym1.info
@@ -329,17 +657,31 @@ def bench_fdpf(W, steps):
     status = st.cpu().numpy()
     ok = int((status == 0).sum())
     iters = it.cpu().numpy()
+    Vm, Va = W.Vm.cpu().numpy(), W.Va.cpu().numpy()
+    osym = O.Sym(g.n, g.f, g.t)
+    Y = O.grid_ybus(g)
+    d1, a1, d2, a2 = osym.fdpf_matrices(g)
+    f1, f2 = osym.factor1(d1, a1), osym.factor1(d2, a2)
+    facs = (f1[:3], f2[:3])
+
+    def one(c):
+        r = osym.fdpf(Y, g, W.P[c], W.Q[c], *g.flat_start(), factors=facs)
+        return (r.status == 0 and r.iters == iters[c], float(np.abs(r.Vm - Vm[c]).max()),
+                float(np.abs(r.Va - Va[c]).max()))
+
+    with ThreadPoolExecutor(host_threads()) as ex:
+        check = check_cases(list(ex.map(one, pick_cases(Bn, 16, 25))))
     plain = timed(lambda: step(1, False), max(3, steps // 2), 1)
     log(f"[bench] fdpf {Bn} cases: {ms:.2f} ms/step, converged {ok}/{Bn}, mean iterations "
-        f"{iters.mean():.2f}; one case {plain:.2f} ms")
+        f"{iters.mean():.2f}; one case {plain:.2f} ms; oracle check {check}")
     return dict(solves_per_s=ok / ms * 1e3, ms_per_step=ms, converged=ok, cases=Bn,
                 mean_iterations=float(iters.mean()), plain_solves_per_s=1e3 / plain,
-                plain_ms_per_solve=plain,
+                plain_ms_per_solve=plain, oracle_check=check,
                 step="Ybus + B', B'' built and factored once + batched decoupled iteration "
                      "to 1e-8 + branch flows")
 
 
-def bench_screen(W, outages, steps=3):
+def leg_screen(W, outages, steps=3):
     """N-1 screening on the base pattern (opened branches): fast decoupled
     first with NR fallback, and NR only, both with branch flows."""
     from paper_1811_02512_amd import contingency
@@ -364,7 +706,7 @@ def bench_screen(W, outages, steps=3):
     return out
 
 
-def bench_se(W, cases=256, steps=3):
+def leg_se(W, cases=256, steps=3):
     """WLS state estimation on the workload's grid: the measurements are the
     NR solutions of the first `cases` load scenarios (|V|, P, Q at every bus,
     P, Q at the from end of every branch, all computed on the device) plus
@@ -428,54 +770,46 @@ def bench_se(W, cases=256, steps=3):
                      "gain assembly, level-scheduled factor and solve per step)")
 
 
-def bench_multi(grids, label, steps=3):
-    """One launch over cases with their own analyses; returns (solves/s, info)."""
-    import torch
+def cpu_baseline(W, wall_s=15.0):
+    """The oracle (paper-path sparse NR + sparse adjoint) over the load
+    scenarios on a thread pool of the host's cores (ctypes releases the GIL),
+    cycling through the scenarios until about `wall_s` seconds of wall time."""
+    from oracle import oracle as O
 
-    from paper_1811_02512_amd import api
-    from paper_1811_02512_amd import binding as B
-    from concurrent.futures import ThreadPoolExecutor
+    g = W.g
+    Y = O.grid_ybus(g)
+    osym = O.Sym(g.n, g.f, g.t)
+    Vm0, Va0 = g.flat_start()
+    cores = host_threads()
 
+    def one(c):
+        c %= W.B
+        r = osym.newton(Y, g.bus_type, W.P[c], W.Q[c], Vm0, Va0)
+        gVm = 2 * W.w * (r.Vm - 1) * (g.bus_type == 1)
+        osym.adjoint(g, Y, r.Vm, r.Va, gVm, np.zeros(g.n))
+        return r.status
+
+    one(0)  # warm-up
+    singles = []
+    for c in range(1, 6):
+        t0 = time.time()
+        one(c)
+        singles.append(time.time() - t0)
+    per_case = float(np.median(singles))
+    count = max(cores, int(wall_s * cores / max(per_case, 1e-6)))
+    log(f"[bench] cpu baseline: {per_case * 1e3:.1f} ms per case on one thread, "
+        f"{count} cases on {cores} threads")
     t0 = time.time()
-    with ThreadPoolExecutor(min(os.cpu_count() or 1, 16)) as ex:
-        syms = list(ex.map(lambda g: api.Symbolic(g.n, g.f, g.t), grids))
-    t_an = time.time() - t0
-    for s in syms:
-        s.set_launch(0, 161792)  # the largest LDS tail: the launch waits for its largest grid
-        s.upload()
-    plan = api.MultiPlan(syms)
-    f64 = np.float64
-    r = plan.concat([g.r for g in grids], "branch", f64)
-    x = plan.concat([g.x for g in grids], "branch", f64)
-    b = plan.concat([g.b for g in grids], "branch", f64)
-    yv = torch.empty(int(plan.offs["y"][-1]) + 2, dtype=torch.float64, device="cuda")
-    ty = plan.concat([g.bus_type for g in grids], "bus", np.int8)
-    P = plan.concat([g.Psp for g in grids], "bus", f64)
-    Q = plan.concat([g.Qsp for g in grids], "bus", f64)
-    V0 = plan.concat([g.flat_start()[0] for g in grids], "bus", f64)
-    A0 = plan.concat([g.flat_start()[1] for g in grids], "bus", f64)
-    Vm, Va = V0.clone(), A0.clone()
-    ws = torch.empty(int(plan.offs["ws"][-1]) + 32, dtype=torch.float64, device="cuda")
-    G = len(grids)  # per-case patterns: plain (non-interleaved) workspace regions
-    it = torch.empty(G, dtype=torch.int32, device="cuda")
-    st = torch.empty(G, dtype=torch.int32, device="cuda")
-
-    def step():
-        B.pf_build_ybus_multi(plan.p, r, x, b, yv)
-        Vm.copy_(V0)
-        Va.copy_(A0)
-        B.pf_newton_multi(plan.p, yv, ty, P, Q, Vm, Va, 1e-8, 20, 0, ws, it, None, st)
-
-    ms = timed(step, steps, 1)
-    ok = int((st == 0).sum().item())
-    log(f"[bench] {label}: {G} cases, {ms:.2f} ms/launch, converged {ok}/{G}, host analysis "
-        f"{t_an:.2f}s")
-    # only converged cases count as solves
-    return dict(solves_per_s=ok / ms * 1e3, ms=ms, cases=G, converged=ok,
-                host_analysis_s=t_an,
-                solves_per_s_with_host_analysis=ok / (ms * 1e-3 + t_an),
-                buses=int(sum(g.n for g in grids)),
-                bus_solves_per_s=sum(g.n for g, s in zip(grids, st.tolist()) if s == 0) / ms * 1e3)
+    with ThreadPoolExecutor(cores) as ex:
+        sts = list(ex.map(one, range(count)))
+    wall = time.time() - t0
+    model, nproc = host_cpu()
+    return dict(value=count / wall, unit="solves/s", cores=cores, kind="oracle",
+                single_thread_ms_per_solve=per_case * 1e3, host_cpu=model, host_nproc=nproc,
+                sample=f"{count} solves cycling over the {W.B} load scenarios of the {g.n}-bus "
+                       f"grid: forward NR (sparse paper path, tol 1e-8) + sparse adjoint each, "
+                       f"{cores} threads, {wall:.1f}s wall, converged "
+                       f"{sum(s == 0 for s in sts)}/{count}")
 
 
 def main():
@@ -485,8 +819,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=10000)
     ap.add_argument("--scenarios", type=int, default=256)
+    ap.add_argument("--legs", default=",".join(ALL_LEGS),
+                    help="comma-separated legs to run: " + ",".join(ALL_LEGS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--full", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--settings", help="JSON of launch settings saved by --save-settings "
                     "(applied instead of tuning)")
@@ -499,10 +834,15 @@ def main():
               "(cases are independent, so a multi-GPU run would shard the batch).",
               file=sys.stderr)
         sys.exit(2)
+    legs = set(args.legs.split(","))
+    unknown = legs - set(ALL_LEGS)
+    if unknown:
+        sys.exit(f"bench.py: unknown legs {sorted(unknown)}")
 
     import torch
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    t_begin = time.time()
     if args.copy_calibration:
         copy_calibration()
     W = Workload(args.n, 1, args.scenarios, 5)
@@ -526,116 +866,74 @@ def main():
         json.dump({"batched": tuned, "plain": tuned1}, open(args.save_settings, "w"))
     info = W.info
 
-    # --- timed steps: whole hot path ---------------------------------------------
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    for _ in range(args.warmup):
-        W.step()
-    torch.cuda.synchronize()
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    t_start.record()
-    for k in range(args.steps):
-        W.step(evs[k])
-    t_end.record()
-    torch.cuda.synchronize()
-    ms_step = t_start.elapsed_time(t_end) / args.steps
-    newton_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
-    iters = W.it.cpu().numpy()
-    status = W.st.cpu().numpy()
-    assert (status == 0).all(), f"non-converged cases: {np.unique(status, return_counts=True)}"
-
-    # --- forward-only batched and plain one-case-per-launch rates ------------------
-    fwd_ms = timed(lambda: W.step(adjoint=False), max(3, args.steps // 2), 1)
-    plain_ms = timed(lambda: W.step(adjoint=False, Bn=1), max(3, args.steps // 2), 1)
-    plain_iters = int(W.it[0].item())
-
-    fdpf = bench_fdpf(W, max(3, args.steps // 2))
-    graph = bench_graph(W, max(3, args.steps // 2))
-
-    b_it = algorithmic_bytes_per_iter(info)
-    units = float(iters.sum())
-    alg_bytes = b_it * units  # per launch: bytes per case-iteration x case-iterations
-    achieved = alg_bytes / (newton_ms * 1e-3) / 1e9
-    traffic = measured_traffic(tuned)
-    copy_gbs = copy_bandwidth()
     out = {
         "metric": "NR power-flow solves/s to 1e-8 p.u. at 10k buses; batched & adjoint vs plain",
-        "value": W.B / ms_step * 1e3,
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
+        "value": None, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {
             "workload": f"{info.n}-bus synthetic grid (m={info.m}), {W.B} load scenarios, "
                         "Ybus + batched NR to 1e-8 + adjoint backward per step",
             "buses": info.n, "branches": info.m, "scenarios": W.B,
             "nnz_l": int(info.nnz_l), "levels": int(info.nlevels),
-            "mean_iterations": float(iters.mean()),
         },
-        "batched_fwd_solves_per_s": W.B / fwd_ms * 1e3,
-        "plain_solves_per_s": 1e3 / plain_ms,
-        "plain_ms_per_solve": plain_ms,
-        "plain_ms_per_iteration": plain_ms / max(plain_iters, 1),
-        "adjoint_grads_per_s": W.B / ms_step * 1e3,
-        "newton_kernel_ms": newton_ms,
-        "autotune": None if tuned is None else {
-            "batched": {k: tuned[k] for k in ("threads", "tail_budget", "interleave", "ms")},
-            "plain": {k: tuned1[k] for k in ("threads", "tail_budget", "interleave", "ms")},
-            "seconds": tuned["seconds"] + tuned1["seconds"],
-            "from_file": bool(args.settings)},
-        "kernel_sources": kernel_source_hash(),
-        "fdpf_10k_x256": fdpf,
-        "graph_replay": graph,
-        "roofline": {
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "kernel": "k_newton (batched launch)",
-            "algorithmic_bytes_per_launch": alg_bytes,
-            "bytes_per_case_iteration": b_it,
-            "case_iterations_per_launch": units,
-            "launch": None if tuned is None else launch_tag(tuned),
-            "copy_gbs": copy_gbs,
-            "frac_of_copy": achieved / copy_gbs,
-        },
-        "paper_context": "Table III: graph-based NR 119.22 ms per solve on a 10790-bus system, "
-                         "TigerGraph on 2x6-core x2-thread 2.10 GHz CPUs",
+        "legs": sorted(legs),
     }
-    if args.full:
+    if "c5" in legs:
+        ms_step, iters, rf, adj, check, kms = leg_headline(W, args, tuned)
+        out["value"] = W.B / ms_step * 1e3
+        out["ms_per_step"] = ms_step
+        out["config"]["mean_iterations"] = float(iters.mean())
+        out["adjoint_grads_per_s"] = W.B / ms_step * 1e3
+        out["kernel_ms"] = kms
+        out["newton_kernel_ms"] = kms["newton"]
+        out["oracle_check"] = check
+        out["batched_fwd_solves_per_s"] = W.B / timed(lambda: W.step(adjoint=False),
+                                                      max(3, args.steps // 2), 1) * 1e3
+        out["autograd_10k_x256"] = leg_autograd(W, max(3, args.steps // 2))
+        copy_gbs = copy_bandwidth()
+        rf["copy_gbs"] = copy_gbs
+        rf["frac_of_copy"] = rf["achieved"] / copy_gbs
+        out["roofline"] = rf
+        out["adjoint_roofline"] = adj
+    if "c2" in legs or "c5" in legs:
+        plain = leg_plain(W, max(3, args.steps // 2), "c2 10k")
+        out["plain_solves_per_s"] = plain["solves_per_s"]
+        out["plain_ms_per_solve"] = plain["ms_per_solve"]
+        out["plain_ms_per_iteration"] = plain["us_per_iteration"] * 1e-3
+        out["c2_plain_10k"] = plain
+        if "c2" in legs:
+            plain.update(leg_c2_breakdown(W, max(5, args.steps)))
+    if "c1" in legs:
+        W1 = Workload(200, 1, 4, 5)
+        W1.step(adjoint=False)
+        if not args.no_tune and args.settings is None:
+            W1.autotune(1, W1.sym1)
+        out["c1_plain_200"] = leg_plain(W1, max(20, args.steps * 2), "c1 200")
+    if "c3" in legs:
+        out["c3_2k_x1024"] = leg_c3(args, args.settings)
+    if "c4" in legs:
+        out.update({"c4_" + k: v for k, v in leg_c4(W, args).items()})
+    if "fdpf" in legs:
+        out["fdpf_10k_x256"] = leg_fdpf(W, max(3, args.steps // 2))
+    if "graph" in legs:
+        out["graph_replay"] = leg_graph(W, max(3, args.steps // 2))
+    if "screen" in legs:
         import gridgen
 
-        W2 = Workload(2000, 1, 1024, 2)
-        W2.step(adjoint=False)
-        if not args.no_tune:
-            W2.autotune(W2.B, W2.sym)
-            W2.autotune(1, W2.sym1)
-        ms2 = timed(lambda: W2.step(adjoint=False), 5, 1)
-        out["batch_2k_x1024_solves_per_s"] = 1024 / ms2 * 1e3
-        out["plain_2k_solves_per_s"] = 1e3 / timed(lambda: W2.step(adjoint=False, Bn=1), 5, 1)
-        outs = gridgen.n1_outages(W.g, 512, 3)
-        n1 = [W.g.without_branch(int(e)) for e in outs]
-        out["n1_10k_x512"] = bench_multi(n1, "N-1 10k x 512")
-        out["n1_screen_10k_x512"] = bench_screen(W, outs)
-        spec = json.load(open(os.path.join(ROOT, "tests", "golden", "mixed_batch.json")))
-        mixed = []
-        for i, gs in enumerate(spec["grids"]):
-            mixed.append(gridgen.make_grid(gs["n"], gs["seed"], load_scale=spec["load_scale"]))
-            if i % 8 == 7:
-                log(f"[bench] generated {i + 1}/64 mixed grids")
-        out["mixed_64_grids"] = bench_multi(mixed, "mixed 64 grids 500-20k buses")
-        out["wls_se_10k_x256"] = bench_se(W)
-    if not args.no_cpu_baseline:
+        out["n1_screen_10k_x512"] = leg_screen(W, gridgen.n1_outages(W.g, 512, 3))
+    if "se" in legs:
+        out["wls_se_10k_x256"] = leg_se(W)
+    out["autotune"] = None if tuned is None else {
+        "batched": {k: tuned[k] for k in ("threads", "tail_budget", "interleave", "ms")},
+        "plain": {k: tuned1[k] for k in ("threads", "tail_budget", "interleave", "ms")},
+        "seconds": tuned["seconds"] + tuned1["seconds"], "from_file": bool(args.settings)}
+    out["kernel_sources"] = kernel_source_hash()
+    out["paper_context"] = ("Table III: graph-based NR 119.22 ms per solve on a 10790-bus "
+                            "system, TigerGraph on 2x6-core x2-thread 2.10 GHz CPUs")
+    if not args.no_cpu_baseline and "c5" in legs:
         out["cpu_baseline"] = cpu_baseline(W)
+    out["bench_wall_s"] = time.time() - t_begin
     print(json.dumps(out))
 
 
