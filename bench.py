@@ -28,8 +28,7 @@ import json
 import os
 import sys
 import time
-import multiprocessing
-from concurrent.futures import ProcessPoolExecutor, ThreadPoolExecutor
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -497,13 +496,6 @@ def leg_c3(args, tuned_file):
                 step="Ybus + batched NR to 1e-8 (k_newton, one launch)")
 
 
-def _make_grid(spec):
-    import gridgen
-
-    n, seed, scale = spec
-    return gridgen.make_grid(n, seed, load_scale=scale)
-
-
 def bench_multi(grids, label, steps, check_idx):
     """One launch over cases with their own analyses; timing, host analysis
     time and an oracle check of the cases in check_idx."""
@@ -578,13 +570,9 @@ def leg_c4(W, args):
     spec = json.load(open(os.path.join(ROOT, "tests", "golden", "mixed_batch.json")))
     t0 = time.time()
     jobs = [(gs["n"], gs["seed"], spec["load_scale"]) for gs in spec["grids"]]
-    order = sorted(range(len(jobs)), key=lambda i: -jobs[i][0])  # largest first
-    # fresh interpreters (spawn), so that no generator process holds this
-    # process's GPU handles; at most 15 of them beside this one
-    ctx = multiprocessing.get_context("spawn")
-    with ProcessPoolExecutor(min(host_threads(), 15), mp_context=ctx) as ex:
-        made = dict(zip(order, ex.map(_make_grid, [jobs[i] for i in order])))
-    mixed = [made[i] for i in range(len(jobs))]
+    # spawned generator processes hold none of this process's GPU handles; at
+    # most 15 of them beside this one
+    mixed = gridgen.make_grids(jobs, processes=min(host_threads(), 15))
     log(f"[bench] c4 mixed: 64 grids generated in {time.time() - t0:.1f}s")
     largest = int(np.argmax([g.n for g in mixed]))
     idx = sorted(set(pick_cases(64, 8, 24)) | {largest})

@@ -271,3 +271,23 @@ def mixed_sizes(count: int, seed: int, lo: int = 500, hi: int = 20000) -> np.nda
     """Log-uniform grid sizes in [lo, hi]."""
     rng = np.random.default_rng(seed)
     return np.round(np.exp(rng.uniform(np.log(lo), np.log(hi), count))).astype(np.int64)
+
+
+def _grid_from_spec(spec):
+    n, seed, load_scale = spec
+    return make_grid(int(n), int(seed), load_scale=load_scale)
+
+
+def make_grids(specs, processes=8):
+    """make_grid over (n, seed, load_scale) specs in a pool of fresh
+    interpreter processes (spawned, so that they inherit no device handles of
+    the caller), largest grids first; returns the grids in spec order."""
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor
+
+    specs = [tuple(s) for s in specs]
+    order = sorted(range(len(specs)), key=lambda i: -specs[i][0])
+    ctx = multiprocessing.get_context("spawn")
+    with ProcessPoolExecutor(max(1, processes), mp_context=ctx) as ex:
+        made = dict(zip(order, ex.map(_grid_from_spec, [specs[i] for i in order])))
+    return [made[i] for i in range(len(specs))]
