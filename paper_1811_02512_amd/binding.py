@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libpf.so")
+# PF_LIBPF selects another build of the same sources (the sanitizer check)
+LIB_PATH = os.environ.get("PF_LIBPF") or os.path.join(_HERE, "libpf.so")
 
 PF_OK, PF_E_INVALID, PF_E_HIP, PF_E_WORKSPACE, PF_E_DISCONNECTED = 0, 1, 2, 3, 4
 PF_E_ZERO_PIVOT, PF_E_NOT_CONVERGED, PF_E_NONFINITE = 5, 6, 7

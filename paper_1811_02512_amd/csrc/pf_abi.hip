@@ -189,13 +189,14 @@ int pf_symbolic_set_mapping(pf_symbolic s, const int32_t* lanes)
 int pf_symbolic_set_launch(pf_symbolic s, int threads, int64_t tail_lds_budget, int interleave)
 {
     if (!s) return fail(PF_E_INVALID, "pf_symbolic_set_launch: NULL symbolic");
+    // every argument is checked before any setting changes
     if (!valid_interleave(interleave))
         return fail(PF_E_INVALID, "pf_symbolic_set_launch: interleave must be 1, 2, 4 or 8");
-    s->h.interleave = interleave;
     if (threads != 0 && threads != 64 && threads != 128 && threads != 256 && threads != 512)
         return fail(PF_E_INVALID, "pf_symbolic_set_launch: threads must be 0, 64, 128, 256 or 512");
     if (tail_lds_budget < 0 || tail_lds_budget > 158 * 1024)
         return fail(PF_E_INVALID, "pf_symbolic_set_launch: tail budget must be 0..161792 bytes");
+    s->h.interleave = interleave;
     s->h.threads = threads;
     if (tail_lds_budget != s->h.tail_budget) {
         s->h.tail_budget = tail_lds_budget;
@@ -229,6 +230,9 @@ int pf_symbolic_upload(pf_symbolic s, void* d_buf, size_t bytes, void* stream)
         return fail(PF_E_WORKSPACE, "pf_symbolic_upload: buffer smaller than info.dev_bytes");
     if (reinterpret_cast<uintptr_t>(d_buf) & 255)
         return fail(PF_E_WORKSPACE, "pf_symbolic_upload: buffer not 256-byte aligned");
+    // from here on the previous device copy may be overwritten: until this
+    // upload succeeds, calls on the symbolic are refused
+    h.uploaded = false;
     std::vector<char> stage(info.dev_bytes, 0);
     char* base = static_cast<char*>(d_buf);
     size_t off = 0;
@@ -289,9 +293,9 @@ int pf_symbolic_upload(pf_symbolic s, void* d_buf, size_t bytes, void* stream)
     s->d_from = put(h.from);
     s->d_to = put(h.to);
     if (off > info.dev_bytes) return fail(PF_E_WORKSPACE, "pf_symbolic_upload: size mismatch");
+    int32_t ef_lds = 0;
     {
         int dev = 0, lds_max = 0;
-        h.ef_lds = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) ==
                 hipSuccess) {
@@ -299,11 +303,11 @@ int pf_symbolic_upload(pf_symbolic s, void* d_buf, size_t bytes, void* stream)
                 return fail(PF_E_WORKSPACE, "pf_symbolic_upload: LDS tail larger than the "
                                             "device's LDS; lower it with pf_symbolic_set_launch");
             const int64_t efb = 16 * (int64_t)h.n;
-            if (efb + pv_mask_bytes(h.n) + 2048 <= lds_max) h.ef_lds = (int32_t)efb;
+            if (efb + pv_mask_bytes(h.n) + 2048 <= lds_max) ef_lds = (int32_t)efb;
         } else {
             (void)hipGetLastError();
         }
-        d.ef_lds = h.ef_lds;
+        d.ef_lds = ef_lds;
     }
     int rc = hip_check(hipMemcpyAsync(d_buf, stage.data(), off, hipMemcpyHostToDevice,
                                       as_stream(stream)),
@@ -311,8 +315,10 @@ int pf_symbolic_upload(pf_symbolic s, void* d_buf, size_t bytes, void* stream)
     if (rc) return rc;
     rc = hip_check(hipStreamSynchronize(as_stream(stream)), "pf_symbolic_upload: sync");
     if (rc) return rc;
+    h.ef_lds = ef_lds;
     h.dev = d;
     h.uploaded = true;
+    ++h.upload_gen;
     return PF_OK;
 }
 

@@ -117,6 +117,9 @@ struct HostSym {
     // device copy
     DevSym dev{};
     bool uploaded = false;
+    // counts uploads; a batch plan built over this symbolic records it and
+    // refuses to run once the device copy has been replaced or gone stale
+    uint64_t upload_gen = 0;
 
     // D [nn][4], zero padding to a multiple of 8 doubles, LU [nnz_l][8]: every
     // slot record (W, U) and bus record starts on a 64-byte boundary.

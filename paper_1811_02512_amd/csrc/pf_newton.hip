@@ -611,6 +611,7 @@ struct pf_multi_s {
     std::vector<pf_symbolic> syms;
     std::vector<int64_t> bus_off, br_off, y_off, ws_off;
     std::vector<int32_t> order;
+    std::vector<uint64_t> gens;  // each symbolic's upload count when the plan was uploaded
     const CaseDesc* d_desc = nullptr;
     const int32_t* d_order = nullptr;
     bool uploaded = false;
@@ -1052,10 +1053,13 @@ int pf_multi_upload(pf_multi p, void* d_buf, size_t bytes, void* stream)
     size_t G = p->syms.size();
     std::vector<char> stage(need, 0);
     CaseDesc* cd = reinterpret_cast<CaseDesc*>(stage.data());
+    p->uploaded = false;
+    p->gens.assign(G, 0);
     for (size_t g = 0; g < G; ++g) {
         if (!p->syms[g]->h.uploaded)
             return fail(PF_E_INVALID, "pf_multi_upload: a symbolic is not uploaded");
         cd[g].sym = p->syms[g]->h.dev;
+        p->gens[g] = p->syms[g]->h.upload_gen;
         cd[g].bus_off = p->bus_off[g];
         cd[g].br_off = p->br_off[g];
         cd[g].y_off = p->y_off[g];
@@ -1075,10 +1079,29 @@ int pf_multi_upload(pf_multi p, void* d_buf, size_t bytes, void* stream)
     return PF_OK;
 }
 
+// A plan whose members were all uploaded as they are now (else the descriptors
+// it copied to the device are stale).
+static bool plan_current(const pf_multi p, const char* fn)
+{
+    if (!p || !p->uploaded) {
+        fail(PF_E_INVALID, std::string(fn) + ": plan not uploaded");
+        return false;
+    }
+    for (size_t g = 0; g < p->syms.size(); ++g) {
+        const HostSym& h = p->syms[g]->h;
+        if (!h.uploaded || h.upload_gen != p->gens[g]) {
+            fail(PF_E_INVALID, std::string(fn) + ": symbolic " + std::to_string(g) +
+                                   " changed since pf_multi_upload; upload the plan again");
+            return false;
+        }
+    }
+    return true;
+}
+
 int pf_build_ybus_multi(const pf_multi p, const double* d_r, const double* d_x,
                         const double* d_b, const double* d_ysh, double* d_yval, void* stream)
 {
-    if (!p || !p->uploaded) return fail(PF_E_INVALID, "pf_build_ybus_multi: plan not uploaded");
+    if (!plan_current(p, "pf_build_ybus_multi")) return PF_E_INVALID;
     if (!d_r || !d_x || !d_b || !d_yval) return fail(PF_E_INVALID, "pf_build_ybus_multi: NULL");
     if (d_ysh && (reinterpret_cast<uintptr_t>(d_ysh) & 15))
         return fail(PF_E_INVALID, "pf_build_ybus_multi: d_ysh must be 16-byte aligned");
@@ -1093,7 +1116,7 @@ int pf_newton_multi(const pf_multi p, const double* d_yval, const int8_t* d_type
                     double tol, int max_iter, int flags, double* d_ws, int32_t* d_iters,
                     double* d_norm, int32_t* d_status, int32_t* d_pivot, void* stream)
 {
-    if (!p || !p->uploaded) return fail(PF_E_INVALID, "pf_newton_multi: plan not uploaded");
+    if (!plan_current(p, "pf_newton_multi")) return PF_E_INVALID;
     if (max_iter < 0 || !(tol >= 0.0) || !d_yval || !d_type || !d_Psp || !d_Qsp || !d_Vm ||
         !d_Va || !d_ws)
         return fail(PF_E_INVALID, "pf_newton_multi: bad arguments");

@@ -133,3 +133,27 @@ def test_mixed_launch_with_the_largest_grids():
              for gs in chosen]
     Vms, Vas, it, st, plan = solve_multi(grids, tail_budget=161792)
     check_against_oracle(grids, Vms, Vas, it, st)
+
+
+def test_plan_refuses_members_changed_since_its_upload():
+    """Re-uploading a member (its device copy may have moved or changed shape)
+    makes the plan stale until the plan itself is uploaded again."""
+    from paper_1811_02512_amd import api
+    from paper_1811_02512_amd import binding as B
+
+    grids = [grid(300, 1), grid(500, 2)]
+    Vms, Vas, it, st, plan = solve_multi(grids)
+    assert (st == 0).all()
+    syms = plan.syms
+    syms[1].set_launch(0, 16384)  # new tail: re-analysed and re-uploaded
+    f64 = np.float64
+    r = plan.concat([g.r for g in grids], "branch", f64)
+    x = plan.concat([g.x for g in grids], "branch", f64)
+    b = plan.concat([g.b for g in grids], "branch", f64)
+    yv = torch.empty(int(plan.offs["y"][-1]) + 2, dtype=torch.float64, device="cuda")
+    with pytest.raises(B.PfError) as ei:
+        B.pf_build_ybus_multi(plan.p, r, x, b, yv)
+    assert ei.value.code == B.PF_E_INVALID and "upload the plan again" in B.last_error()
+    B.pf_multi_upload(plan.p, plan.buf)
+    B.pf_build_ybus_multi(plan.p, r, x, b, yv)
+    torch.cuda.synchronize()

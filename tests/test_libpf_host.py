@@ -195,3 +195,20 @@ def test_state_estimation_analysis_sizes_and_errors():
     with pytest.raises(B.PfError):
         B.pf_se_analyze(g.n, g.f, g.t, 0, np.array([B.PF_MEAS_PF], np.int8),
                         np.array([g.m + 3]))
+
+
+def test_set_launch_checks_every_argument_before_changing_any(B):
+    g = gridgen.make_grid(80, 3)
+    h = B.pf_analyze(g.n, g.f, g.t)
+    before = B.pf_symbolic_info(h)
+    for threads, budget, inter in ((100, 65536, 2), (256, -1, 2), (256, 200000, 8),
+                                   (256, 65536, 3)):
+        with pytest.raises(B.PfError) as ei:
+            B.pf_symbolic_set_launch(h, threads, budget, inter)
+        assert ei.value.code == B.PF_E_INVALID
+        after = B.pf_symbolic_info(h)
+        assert (after.ws_interleave, after.threads, after.tail_nodes) == \
+            (before.ws_interleave, before.threads, before.tail_nodes)
+    B.pf_symbolic_set_launch(h, 256, 65536, 2)
+    assert B.pf_symbolic_info(h).ws_interleave == 2
+    B.pf_symbolic_destroy(h)
