@@ -710,36 +710,36 @@ __device__ __forceinline__ void apply_updates2(const int2* __restrict__ upd, int
     }
 }
 
-// Same with the blocks in LDS (tail-local slot numbering): four pairs per
-// step, the next four pairs' indices in flight (indices past the list's end
-// are not loaded); updates in list order.
-__device__ __forceinline__ void apply_updates_lds(const int2* __restrict__ upd, int u0, int u1,
-                                                  const double* sLU, Blk& Wk, Blk& Vk)
-{
-    if (u0 >= u1) return;
-    int2 e[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) e[k] = upd_at(upd, u0 + k, u1);
-    for (int u = u0; u < u1; u += 4) {
-        int2 nx[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) nx[k] = upd_at(upd, u + 4 + k, u1);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (u + k < u1) {
-                bmsub(Wk, bload(sLU + 8 * e[k].x), bload(sLU + 8 * e[k].y + 4));
-                bmsub(Vk, bload(sLU + 8 * e[k].y), bload(sLU + 8 * e[k].x + 4));
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) e[k] = nx[k];
-    }
-}
-
 // Word k of a 16-byte load of a packed list.
 __device__ __forceinline__ uint32_t pk_word(const uint4& q, int k)
 {
     return k == 0 ? q.x : k == 1 ? q.y : k == 2 ? q.z : q.w;
+}
+
+// Updates of one tail destination from its packed local pair list (np
+// pairs starting at load l, the first two loads q0, q1 already requested):
+// eight pairs per step, the next two loads in flight; updates in list order.
+__device__ __forceinline__ void apply_packed_lds(const uint4* __restrict__ pk, int l, int np,
+                                                 uint4 q0, uint4 q1, const double* sLU, Blk& Wk,
+                                                 Blk& Vk)
+{
+    for (int k = 0; k < np; k += 8) {
+        const int i = l + (k >> 2);
+        uint4 n0 = make_uint4(0, 0, 0, 0), n1 = n0;
+        if (k + 8 < np) n0 = pk[i + 2];
+        if (k + 12 < np) n1 = pk[i + 3];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            if (k + c < np) {
+                const uint32_t v = pk_word(c < 4 ? q0 : q1, c & 3);
+                const int a = v & 0xffff, b = v >> 16;
+                bmsub(Wk, bload(sLU + 8 * a), bload(sLU + 8 * b + 4));
+                bmsub(Vk, bload(sLU + 8 * b), bload(sLU + 8 * a + 4));
+            }
+        }
+        q0 = n0;
+        q1 = n1;
+    }
 }
 
 // Updates of two tail destinations from their packed local pair lists
@@ -1014,16 +1014,35 @@ __device__ void tail_factor(const DevSym& S, const SRC& src, const View& w, int6
         }
     }
     __syncthreads();
-    for_tail_range(S, 0, nT - KC, true, [&](int jl, int lane, int g) {
-        const int4 t0 = S.t_node[3 * jl];
-        const int4 t1 = S.t_node[3 * jl + 1];
+    // Each level's node records arrive before its barrier; a lane's first
+    // slot record and that slot's first packed pair loads are requested
+    // before the lower-neighbour sums, so the slot loop starts on indices
+    // already in registers.
+    for_tail_pf(S, 0, nT - KC, true, [&](int jl, const int4& t0, const int4& t1, const int4&,
+                                         int lane, int g) {
+        const int4 z4 = make_int4(0, 0, 0, 0);
+        const uint4 zq = make_uint4(0, 0, 0, 0);
+        int t = t0.w + lane;
+        int4 sb = z4, sc = z4;
+        if (t < t1.x) {
+            sb = S.t_slot[3 * t + 1];
+            sc = S.t_slot[3 * t + 2];
+        }
+        int r = t1.z + lane;
+        int2 e = make_int2(0, 0);
+        if (r < t1.w) e = S.t_rl[r];
+        int np = sb.w - sb.z;
+        uint4 q0 = zq, q1 = zq;
+        if (np > 0) q0 = S.t_pk[sc.w];
+        if (np > 4) q1 = S.t_pk[sc.w + 1];
         Blk ds = bzero();
         double z0 = 0.0, z1 = 0.0;
-        for (int r = t1.z + lane; r < t1.w; r += g) {
-            const int2 e = S.t_rl[r];
+        for (; r < t1.w; r += g) {
+            const int2 en = upd_at(S.t_rl, r + g, t1.w);
             const Blk wv = bload(sLU + 8 * e.y);
             bmadd(ds, wv, bload(sLU + 8 * e.y + 4));
             if (FWD) mvadd(z0, z1, wv, sy[2 * e.x], sy[2 * e.x + 1]);
+            e = en;
         }
         if (g > 1) {
             gsum_blk(ds, z0, z1, FWD, g);
@@ -1031,12 +1050,23 @@ __device__ void tail_factor(const DevSym& S, const SRC& src, const View& w, int6
         const Blk A = bload(sD + 4 * jl);
         bool ok;
         const Blk Di = binv({A.a - ds.a, A.b - ds.b, A.c - ds.c, A.d - ds.d}, ok);
-        for (int t = t0.w + lane; t < t1.x; t += g) {
-            const int4 b = S.t_slot[3 * t + 1];
+        for (; t < t1.x; t += g) {
+            const int tn = t + g;
+            int4 sbn = z4, scn = z4;
+            if (tn < t1.x) {
+                sbn = S.t_slot[3 * tn + 1];
+                scn = S.t_slot[3 * tn + 2];
+            }
             Blk Wk = bload(sLU + 8 * t), Vk = bload(sLU + 8 * t + 4);
-            apply_updates_lds(S.t_upd, b.z, b.w, sLU, Wk, Vk);
+            apply_packed_lds(S.t_pk, sc.w, np, q0, q1, sLU, Wk, Vk);
             bstore(sLU + 8 * t, Wk);
             bstore(sLU + 8 * t + 4, bmul(Di, Vk));
+            sc = scn;
+            np = sbn.w - sbn.z;
+            q0 = zq;
+            q1 = zq;
+            if (np > 0) q0 = S.t_pk[sc.w];
+            if (np > 4) q1 = S.t_pk[sc.w + 1];
         }
         if (lane == 0) {
             if (!ok) mark_pivot(s_bad, S.level_ptr[S.tail_level] + jl);
