@@ -67,6 +67,15 @@ def filled_blocks(info):
     return info.nn + 2 * info.nnz_l
 
 
+def kept_factor_bytes(info):
+    """The factorisation at the converged state that the launch adds per case
+    when it keeps the factors for the adjoint, priced with the iteration's
+    own terms less the substitutions and the vectors: 16 Y (admittances read
+    for the Jacobian) + 32 F (Jacobian into the filled slots) + 64 F (factor
+    read and write)."""
+    return 16 * info.nnz_y + 96 * filled_blocks(info)
+
+
 def adjoint_bytes(info):
     """Fused adjoint kernel per case: the factors read once (32 F), the
     gradient gathered (16 n), lam written (16 nn) and dL/dP, dL/dQ written
@@ -362,9 +371,12 @@ def leg_headline(W, args, tuned):
         f"{kms['adjoint']:.3f} ms, branch {kms['branch']:.3f} ms; oracle check {check}")
     b_it = newton_bytes_per_iter(info)
     units = float(iters.sum())
-    rf = roofline(b_it * units, kms["newton"], "k_newton (batched launch)", units, b_it,
+    kept = kept_factor_bytes(info) * W.B
+    rf = roofline(b_it * units + kept, kms["newton"], "k_newton (batched launch)", units, b_it,
                   measured_traffic(tuned))
     rf["launch"] = None if tuned is None else launch_tag(tuned)
+    rf["kept_factorisations"] = {"count": W.B, "bytes_each": kept_factor_bytes(info)}
+    rf["frac_iterations_only"] = b_it * units / (kms["newton"] * 1e-3) / 1e9 / HBM_PEAK_GBS
     adj = {
         "k_adjoint": roofline(adjoint_bytes(info) * W.B, kms["adjoint"],
                               "k_adjoint (gather + transposed solves + dL/dP, dL/dQ)", W.B,
