@@ -699,10 +699,12 @@ def leg_screen(W, outages, steps=3):
         res = box["r"]
         ok = int((res.status == 0).sum().item())
         out[key] = dict(solves_per_s=ok / ms * 1e3, ms=ms, cases=len(outages), converged=ok,
-                        fallback_to_nr=res.fallback,
+                        solved_by_nr=res.fallback,
                         mean_iterations=float(res.iters.float().mean().item()))
+        if first:
+            out[key]["fallback_to_nr"] = res.fallback
         log(f"[bench] N-1 screen {key}: {len(outages)} outages, {ms:.2f} ms, converged {ok}, "
-            f"fallback {res.fallback}")
+            f"solved by NR {res.fallback}")
     return out
 
 
