@@ -84,9 +84,10 @@ def adjoint_bytes(info):
 
 
 def branch_grad_bytes(info):
-    """Branch-gradient kernel per case: per branch the voltages and adjoint
-    entries of both ends (64 B) with r, x shared; per bus nothing else."""
-    return 64 * info.m
+    """Branch gradients inside the adjoint launch, per case: |V| and theta
+    read (16 n), the per-case dL/dx written and read back by the sum over
+    cases (16 m); r, x shared."""
+    return 16 * info.n + 16 * info.m
 
 
 def timed(fn, steps, warmup):
@@ -171,6 +172,7 @@ class Workload:
         self.Vm0, self.Va0 = t(Vm0), t(Va0)
         self.wt = t(self.w)
         self.pq = t((g.bus_type == 1).astype(np.float64))
+        self.gcoef = self.wt * self.pq * 2.0  # dLoss/d|V| = gcoef (|V| - 1)
         info = self.info
         Bn = scen
         f64 = dict(dtype=torch.float64, device=dev)
@@ -205,9 +207,12 @@ class Workload:
 
     def step(self, ev=None, adjoint=True, Bn=None):
         """One pass of the hot path.  ev: optional dict of (start, end) event
-        pairs around the Newton kernel ('newton'), the fused adjoint kernel
-        ('adjoint') and the branch-gradient kernel ('branch'), each recorded on
-        the stream its kernel runs on (the current stream)."""
+        pairs around the Newton kernel ('newton') and the fused adjoint call
+        ('adjoint': the adjoint kernel with the per-case branch gradients and
+        their sum over cases), each recorded on the stream its kernels run on
+        (the current stream)."""
+        import torch
+
         from paper_1811_02512_amd import binding as B
 
         g = self.g
@@ -227,19 +232,14 @@ class Workload:
         if not adjoint:
             return
         # dLoss/d|V| of the caller's loss, written by the caller in torch
-        self.gVm[:Bn].copy_(self.Vm[:Bn]).sub_(1.0).mul_(self.wt * self.pq * 2.0)
+        torch.sub(self.Vm[:Bn], 1.0, out=self.gVm[:Bn]).mul_(self.gcoef)
         if ev is not None:
             ev["adjoint"][0].record()
         B.pf_adjoint(sym.h, Bn, self.ws, info.ws_doubles, self.gVm, None, g.n, self.type, 0,
                      self.Vm, self.Va, g.n, self.r, self.x, 0, self.st, self.lam, 2 * info.nn,
-                     self.gP, self.gQ, g.n, None, 1)
+                     self.gP, self.gQ, g.n, self.gx, 1)
         if ev is not None:
             ev["adjoint"][1].record()
-            ev["branch"][0].record()
-        B.pf_adjoint_params(sym.h, Bn, self.lam, 2 * info.nn, self.type, 0, self.Vm, self.Va,
-                            g.n, self.r, self.x, 0, None, None, g.n, self.gx, 1)
-        if ev is not None:
-            ev["branch"][1].record()
 
     def oracle_check(self, cases, adjoint):
         """Per-case comparison of the last step's results with the oracle's
@@ -348,7 +348,7 @@ def leg_headline(W, args, tuned):
     import torch
 
     info = W.info
-    names = ("newton", "adjoint", "branch")
+    names = ("newton", "adjoint")
     evs = [{k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
             for k in names} for _ in range(args.steps)]
     for _ in range(args.warmup):
@@ -368,7 +368,7 @@ def leg_headline(W, args, tuned):
     assert (status == 0).all(), f"non-converged cases: {np.unique(status, return_counts=True)}"
     check = W.oracle_check(pick_cases(W.B, 16, 21), adjoint=True)
     log(f"[bench] c5 headline: {ms_step:.3f} ms/step, newton {kms['newton']:.3f} ms, adjoint "
-        f"{kms['adjoint']:.3f} ms, branch {kms['branch']:.3f} ms; oracle check {check}")
+        f"{kms['adjoint']:.3f} ms; oracle check {check}")
     b_it = newton_bytes_per_iter(info)
     units = float(iters.sum())
     kept = kept_factor_bytes(info) * W.B
@@ -377,13 +377,12 @@ def leg_headline(W, args, tuned):
     rf["launch"] = None if tuned is None else launch_tag(tuned)
     rf["kept_factorisations"] = {"count": W.B, "bytes_each": kept_factor_bytes(info)}
     rf["frac_iterations_only"] = b_it * units / (kms["newton"] * 1e-3) / 1e9 / HBM_PEAK_GBS
+    per_case = adjoint_bytes(info) + branch_grad_bytes(info)
     adj = {
-        "k_adjoint": roofline(adjoint_bytes(info) * W.B, kms["adjoint"],
-                              "k_adjoint (gather + transposed solves + dL/dP, dL/dQ)", W.B,
-                              adjoint_bytes(info)),
-        "k_adj_branch": roofline(branch_grad_bytes(info) * W.B, kms["branch"],
-                                 "k_adj_branch (dL/dx summed over cases)", W.B,
-                                 branch_grad_bytes(info)),
+        "pf_adjoint": roofline(per_case * W.B, kms["adjoint"],
+                               "pf_adjoint: k_adjoint (gather, transposed solves, dL/dP, dL/dQ, "
+                               "per-case dL/dx) + k_adj_gx_sum (dL/dx summed over cases)", W.B,
+                               per_case),
     }
     return ms_step, iters, rf, adj, check, kms
 

@@ -413,19 +413,23 @@ int pf_adjoint_params(const pf_symbolic sym, int B, const double* d_lam, int64_t
                       int64_t g_stride, double* d_gx, int gx_mode, void* stream);
 
 /* ---- fused adjoint backward (beyond the paper) -----------------------------
- * The three steps above in two launches, on the factors pf_newton kept at
- * the solution (PF_NEWTON_KEEP_FACTORS; d_ws and ws_stride as given to
- * pf_newton with the same B, so the same case grouping): per case, the
- * gradient g = (dL/dtheta, dL/d|V|) gathered into position order (the |V|
- * entry zero at PV buses; d_gVm or d_gVa NULL = zero), the transposed
- * solves J^T lam = g, d_lam <- lam (double[B][nn][2], lam_stride), d_gP,
- * d_gQ (double[B][n], g_stride) as pf_adjoint_params; then d_gx (d_x, d_r
- * and gx_mode as pf_adjoint_params; d_gx NULL = skipped).  d_status: the
- * per-case status pf_newton wrote, or NULL; a case whose status is not PF_OK
- * (its workspace holds no factors of a converged J) gets NaN gradients, and
- * with gx_mode 1 the summed d_gx is NaN.  Errors: PF_E_INVALID (NULL
- * output, bad mode or stride), PF_E_WORKSPACE (strides too small).       */
-int pf_adjoint(const pf_symbolic sym, int B, const double* d_ws, int64_t ws_stride,
+ * The three steps above in one launch (two with gx_mode 1), on the factors
+ * pf_newton kept at the solution (PF_NEWTON_KEEP_FACTORS; d_ws and ws_stride
+ * as given to pf_newton with the same B, so the same case grouping): per
+ * case, the gradient g = (dL/dtheta, dL/d|V|) gathered into position order
+ * (the |V| entry zero at PV buses; d_gVm or d_gVa NULL = zero), the
+ * transposed solves J^T lam = g, d_lam <- lam (double[B][nn][2],
+ * lam_stride), d_gP, d_gQ (double[B][n], g_stride) as pf_adjoint_params;
+ * then d_gx (d_x, d_r and gx_mode as pf_adjoint_params; d_gx NULL =
+ * skipped), bit for bit as pf_adjoint_params computes it.  The workspace's
+ * bus-record and rhs sections serve as scratch for the branch gradients
+ * (overwritten); its factors are left as they are, so pf_adjoint may be
+ * called again on the same workspace.  d_status: the per-case status
+ * pf_newton wrote, or NULL; a case whose status is not PF_OK (its workspace
+ * holds no factors of a converged J) gets NaN gradients, and with gx_mode 1
+ * the summed d_gx is NaN.  Errors: PF_E_INVALID (NULL output, bad mode or
+ * stride, d_gx without d_r and d_x), PF_E_WORKSPACE (strides too small). */
+int pf_adjoint(const pf_symbolic sym, int B, double* d_ws, int64_t ws_stride,
                const double* d_gVm, const double* d_gVa, int64_t gv_stride,
                const int8_t* d_type, int64_t type_stride, const double* d_Vm,
                const double* d_Va, int64_t v_stride, const double* d_r, const double* d_x,

@@ -1432,7 +1432,7 @@ struct NewtonArgs {
 
 // Arguments of the fused adjoint kernel (pf_adjoint).
 struct AdjArgs {
-    const double* ws;  // pf_newton's workspace: factors of J at the solution
+    double* ws;  // pf_newton's workspace: factors of J at the solution
     int64_t ws_stride;
     int C;  // interleave of the workspace
     int B;
@@ -1447,6 +1447,17 @@ struct AdjArgs {
     double* gP;
     double* gQ;
     int64_t g_stride;
+    // branch gradients in the same launch (gx null: none)
+    const int32_t* from;
+    const int32_t* to;
+    const double* Vm;
+    const double* Va;
+    int64_t v_stride;
+    const double* r;
+    const double* x;
+    int64_t branch_stride;
+    double* gx;   // gx_mode 0: dL/dx [B][m]; 1: null here, per-case parts to the workspace
+    int gx_mode;  // 0 per case, 1 summed over the cases (by k_adj_gx_sum)
 };
 
 struct CaseDesc {

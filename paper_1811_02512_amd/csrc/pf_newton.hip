@@ -427,6 +427,36 @@ __global__ __launch_bounds__(kLevelThreads) void k_solve(DevSym S, const double*
 // buses), dL/dQsp = lam_Q (PQ buses), 0 elsewhere.  A case whose status is
 // not PF_OK (its factors are not those of a converged J) gets NaN
 // gradients.
+// dL/dx_e of one case from the rectangular voltages of the branch's ends and
+// their adjoint entries (lam_Q already zero at PV buses); an end that is the
+// slack adds nothing:
+//   dS_f = V_f conj(dy (V_f - V_t)), dS_t = V_t conj(dy (V_t - V_f)),
+//   dy = -j y^2, dL/dx = -(lamP_f Re dS_f + lamQ_f Im dS_f + same at t).
+// Contraction into fused multiply-adds is off here, so that every kernel
+// that calls this gets the same bits.
+__device__ __forceinline__ double adj_branch_core(double r, double x, double ef, double ff,
+                                                  double et, double ft, double lpf, double lqf,
+                                                  double lpt, double lqt, bool f_in, bool t_in)
+{
+#pragma clang fp contract(off)
+    const double den = r * r + x * x;
+    const double yr = r / den, yi = -x / den;
+    const double dyr = 2.0 * yr * yi, dyi = -(yr * yr - yi * yi);
+    const double dr = ef - et, di = ff - ft;
+    const double cr = dyr * dr - dyi * di, ci = dyr * di + dyi * dr;
+    double acc = 0.0;
+    if (f_in) acc += lpf * (ef * cr + ff * ci) + lqf * (ff * cr - ef * ci);
+    if (t_in) acc += lpt * (-(et * cr + ft * ci)) + lqt * (-(ft * cr - et * ci));
+    return -acc;
+}
+
+// The same from the bus records (e, f, lam_P, lam_Q) of the two ends.
+__device__ __forceinline__ double adj_branch_rec(double r, double x, const Blk& F,
+                                                 const Blk& T, bool f_in, bool t_in)
+{
+    return adj_branch_core(r, x, F.a, F.b, T.a, T.b, F.c, F.d, T.c, T.d, f_in, t_in);
+}
+
 template <bool LDSX>
 __global__ __launch_bounds__(kLevelThreads) void k_adjoint(DevSym S, AdjArgs a)
 {
@@ -463,6 +493,39 @@ __global__ __launch_bounds__(kLevelThreads) void k_adjoint(DevSym S, AdjArgs a)
         }
         gP[i] = ok ? lp : nan;
         gQ[i] = ok ? lq : nan;
+    }
+    if (a.gx_mode < 0) return;
+    // dL/dx of this case's branches: per bus (e, f, lam_P, lam_Q) into the
+    // first half of its workspace bus record (the masks of the gradients
+    // above applied), then per branch the two records; with gx_mode 1 each
+    // case's values go to the workspace's rhs section for k_adj_gx_sum
+    const View wb = case_bus_view(a.ws, a.ws_stride, a.C, c, S.vals_doubles);
+    const Off o = ws_off(S);
+    const double* Vm = a.Vm + c * a.v_stride;
+    const double* Va = a.Va + c * a.v_stride;
+    for (int i = threadIdx.x; i < S.n; i += blockDim.x) {
+        double sn, cs;
+        sincos(Va[i], &sn, &cs);
+        const int p = S.pos[i];
+        double lp = 0.0, lq = 0.0;
+        if (p >= 0) {
+            const double2 l = x2[p];
+            lp = l.x;
+            lq = ty[i] == T_PV ? 0.0 : l.y;
+        }
+        wb.put(o.BUS + 8 * (int64_t)i, {Vm[i] * cs, Vm[i] * sn, lp, lq});
+    }
+    __syncthreads();
+    const double* r = a.r + c * a.branch_stride;
+    const double* x = a.x + c * a.branch_stride;
+    for (int e = threadIdx.x; e < S.m; e += blockDim.x) {
+        const int fb = a.from[e], tb = a.to[e];
+        const Blk F = wb.blk(o.BUS + 8 * (int64_t)fb);
+        const Blk T = wb.blk(o.BUS + 8 * (int64_t)tb);
+        const double v = ok ? adj_branch_rec(r[e], x[e], F, T, fb != S.slack, tb != S.slack)
+                            : nan;
+        if (a.gx_mode == 0) a.gx[(int64_t)c * S.m + e] = v;
+        else *wb.at(o.RHS + e) = v;
     }
 }
 
@@ -526,37 +589,56 @@ __global__ void k_adj_bus(DevSym S, const double* lam, int64_t lam_stride, const
     gQ[c * g_stride + i] = lq;
 }
 
-// dL/dx_e for one case: dS_f = V_f conj(dy (V_f - V_t)), dS_t = V_t conj(dy (V_t - V_f)),
-// dy = -j y^2, gx = -(lamP_f Re dS_f + lamQ_f Im dS_f + same at t).
+// dL/dx_e for one case from the case's |V|, theta and adjoint vector (by
+// position); the arithmetic of adj_branch_core.
 __device__ __forceinline__ double adj_branch(const DevSym& S, int fb, int tb,
                                              const double* lam, const int8_t* type,
                                              const double* Vm, const double* Va, double r,
                                              double x)
 {
-    const double den = r * r + x * x;
-    const double yr = r / den, yi = -x / den;
-    const double dyr = 2.0 * yr * yi, dyi = -(yr * yr - yi * yi);
     double sf, cf, st, ct;
     sincos(Va[fb], &sf, &cf);
     sincos(Va[tb], &st, &ct);
-    const double ef = Vm[fb] * cf, ff = Vm[fb] * sf;
-    const double et = Vm[tb] * ct, ft = Vm[tb] * st;
-    const double dr = ef - et, di = ff - ft;
-    const double cr = dyr * dr - dyi * di, ci = dyr * di + dyi * dr;
-    double acc = 0.0;
     const int pf_ = S.pos[fb], pt_ = S.pos[tb];
     const double2* l2 = reinterpret_cast<const double2*>(lam);
+    double lpf = 0.0, lqf = 0.0, lpt = 0.0, lqt = 0.0;
     if (pf_ >= 0) {
         const double2 l = l2[pf_];
-        const double lq = (type[fb] == T_PV) ? 0.0 : l.y;
-        acc += l.x * (ef * cr + ff * ci) + lq * (ff * cr - ef * ci);
+        lpf = l.x;
+        lqf = (type[fb] == T_PV) ? 0.0 : l.y;
     }
     if (pt_ >= 0) {
         const double2 l = l2[pt_];
-        const double lq = (type[tb] == T_PV) ? 0.0 : l.y;
-        acc += l.x * (-(et * cr + ft * ci)) + lq * (-(ft * cr - et * ci));
+        lpt = l.x;
+        lqt = (type[tb] == T_PV) ? 0.0 : l.y;
     }
-    return -acc;
+    return adj_branch_core(r, x, Vm[fb] * cf, Vm[fb] * sf, Vm[tb] * ct, Vm[tb] * st, lpf, lqf,
+                           lpt, lqt, pf_ >= 0, pt_ >= 0);
+}
+
+// dL/dx summed over the cases from the per-case values k_adjoint left in
+// each case's rhs section of the workspace, in the order of k_adj_branch's
+// mode 1 (wave w sums the cases w, w + 16, ..., then the 16 partial sums in
+// wave order), so both give the same bits.
+__global__ void k_adj_gx_sum(DevSym S, const double* ws, int64_t ws_stride, int C, int B,
+                             double* gx)
+{
+    __shared__ double part[16][64];
+    const int e = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const Off o = ws_off(S);
+    double acc = 0.0;
+    if (e < S.m)
+        for (int c = wv; c < B; c += nw)
+            acc += *case_bus_view(const_cast<double*>(ws), ws_stride, C, c, S.vals_doubles)
+                        .at(o.RHS + e);
+    part[wv][threadIdx.x & 63] = acc;
+    __syncthreads();
+    if (wv == 0 && e < S.m) {
+        double sum = 0.0;
+        for (int k = 0; k < nw; ++k) sum += part[k][threadIdx.x];
+        gx[e] = sum;
+    }
 }
 
 // mode 1 (x shared by the cases): one workgroup per 64 branches, its waves
@@ -897,7 +979,7 @@ int pf_adjoint_params(const pf_symbolic s, int B, const double* d_lam, int64_t l
                                           d_gP, d_gQ, g_stride, d_gx, gx_mode, stream, true);
 }
 
-int pf_adjoint(const pf_symbolic s, int B, const double* d_ws, int64_t ws_stride,
+int pf_adjoint(const pf_symbolic s, int B, double* d_ws, int64_t ws_stride,
                const double* d_gVm, const double* d_gVa, int64_t gv_stride, const int8_t* d_type,
                int64_t type_stride, const double* d_Vm, const double* d_Va, int64_t v_stride,
                const double* d_r, const double* d_x, int64_t branch_stride,
@@ -916,18 +998,31 @@ int pf_adjoint(const pf_symbolic s, int B, const double* d_ws, int64_t ws_stride
         return fail(PF_E_WORKSPACE, "pf_adjoint: a stride is too small");
     if (B == 0) return PF_OK;
     const int C = newton_interleave(s->h, B);
+    // the branch gradients run in the adjoint launch (their per-case values
+    // summed by k_adj_gx_sum for a shared x) when the workspace's rhs section
+    // holds a case's m values; otherwise in their own kernel afterwards
+    const HostSym& h = s->h;
+    const bool fuse = d_gx && h.m > 0 && (gx_mode == 0 || h.m <= 2 * (int64_t)h.nn);
+    if (d_gx && h.m > 0 && (!d_r || !d_x)) return fail(PF_E_INVALID, "pf_adjoint: need r and x");
     AdjArgs a{d_ws, ws_stride, C, B, d_gVm, d_gVa, gv_stride, d_type, type_stride, d_status,
-              d_lam, lam_stride, d_gP, d_gQ, g_stride};
-    const size_t xbytes = 16 * (size_t)s->h.nn;
-    const dim3 grid(grid_blocks(B, C)), block(launch_threads(s->h, B));
+              d_lam, lam_stride, d_gP, d_gQ, g_stride, s->d_from, s->d_to, d_Vm, d_Va, v_stride,
+              d_r, d_x, branch_stride, gx_mode == 0 ? d_gx : nullptr, fuse ? gx_mode : -1};
+    const size_t xbytes = 16 * (size_t)h.nn;
+    const dim3 grid(grid_blocks(B, C)), block(launch_threads(h, B));
     if (xbytes <= kSolveLdsMax) {
         allow_big_lds();
-        hipLaunchKernelGGL(k_adjoint<true>, grid, block, xbytes, as_stream(stream), s->h.dev, a);
+        hipLaunchKernelGGL(k_adjoint<true>, grid, block, xbytes, as_stream(stream), h.dev, a);
     } else {
-        hipLaunchKernelGGL(k_adjoint<false>, grid, block, 0, as_stream(stream), s->h.dev, a);
+        hipLaunchKernelGGL(k_adjoint<false>, grid, block, 0, as_stream(stream), h.dev, a);
     }
     int rc = launch_check("pf_adjoint");
     if (rc) return rc;
+    if (fuse) {
+        if (gx_mode == 0) return PF_OK;
+        hipLaunchKernelGGL(k_adj_gx_sum, dim3((h.m + 63) / 64), dim3(1024), 0, as_stream(stream),
+                           h.dev, d_ws, ws_stride, C, B, d_gx);
+        return launch_check("pf_adjoint");
+    }
     return pf::abi::adjoint_branch_launch(s, B, d_lam, lam_stride, d_type, type_stride, d_Vm,
                                           d_Va, v_stride, d_r, d_x, branch_stride, d_status,
                                           nullptr, nullptr, 0, d_gx, gx_mode, stream, false);

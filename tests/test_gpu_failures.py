@@ -182,38 +182,75 @@ def test_adjoint_not_converged_is_nan():
     assert torch.isnan(Pt.grad).all()
 
 
-def test_fused_adjoint_equals_the_three_step_path():
-    """pf_adjoint (gather + transposed solves + bus gradients in one launch,
-    then branch gradients) gives bitwise the results of pf_adjoint_rhs,
-    pf_solve(transpose = 1) and pf_adjoint_params."""
+def _fused_vs_three_step(g, Bn, mode, seed=3):
     B = _B()
-    g = grid(2000, 1)
     s = Staged(g)
-    Bn = 8
-    P, Q = gridgen.scenario_injections(g, Bn, 3)
+    P, Q = gridgen.scenario_injections(g, Bn, seed)
     Vm, Va, it, _, st, ws = s.newton(Bn, dev(P), dev(Q), keep=True)
     assert (st == 0).all()
     info = s.info
-    n, nn = g.n, info.nn
+    n, nn, m = g.n, info.nn, g.m
     rng = np.random.default_rng(5)
     gVm, gVa = dev(rng.standard_normal((Bn, n))), dev(rng.standard_normal((Bn, n)))
     C = B.pf_newton_interleave(s.sym.h, Bn)
     f64 = dict(dtype=torch.float64, device="cuda")
-    lam1 = torch.empty(Bn, 2 * nn, **f64)
-    gP1, gQ1, gx1 = torch.empty(Bn, n, **f64), torch.empty(Bn, n, **f64), torch.empty(g.m, **f64)
-    B.pf_adjoint(s.sym.h, Bn, ws, info.ws_doubles, gVm, gVa, n, s.type, 0, Vm, Va, n, s.r, s.x,
-                 0, st, lam1, 2 * nn, gP1, gQ1, n, gx1, 1)
+    xs = s.x if mode == 1 else s.x.repeat(Bn)
+    rs = s.r if mode == 1 else s.r.repeat(Bn)
+    bstride = 0 if mode == 1 else m
+    gxn = m if mode == 1 else Bn * m
+    out = []
+    for rep in range(2):  # twice on the same workspace: its scratch sections are rewritten
+        lam1 = torch.empty(Bn, 2 * nn, **f64)
+        gP1, gQ1, gx1 = (torch.empty(Bn, n, **f64), torch.empty(Bn, n, **f64),
+                         torch.empty(gxn, **f64))
+        B.pf_adjoint(s.sym.h, Bn, ws, info.ws_doubles, gVm, gVa, n, s.type, 0, Vm, Va, n, rs,
+                     xs, bstride, st, lam1, 2 * nn, gP1, gQ1, n, gx1, mode)
+        out.append((lam1, gP1, gQ1, gx1))
     lam2 = torch.empty(Bn, 2 * nn, **f64)
-    gP2, gQ2, gx2 = torch.empty(Bn, n, **f64), torch.empty(Bn, n, **f64), torch.empty(g.m, **f64)
+    gP2, gQ2, gx2 = torch.empty(Bn, n, **f64), torch.empty(Bn, n, **f64), torch.empty(gxn, **f64)
     B.pf_adjoint_rhs(s.sym.h, Bn, gVm, gVa, n, s.type, 0, lam2, 2 * nn)
     B.pf_solve(s.sym.h, Bn, ws, info.ws_doubles, lam2, 2 * nn, 1, C)
-    B.pf_adjoint_params(s.sym.h, Bn, lam2, 2 * nn, s.type, 0, Vm, Va, n, s.r, s.x, 0, gP2, gQ2,
-                        n, gx2, 1)
-    for a, b in ((lam1, lam2), (gP1, gP2), (gQ1, gQ2), (gx1, gx2)):
-        assert torch.equal(a, b)
+    B.pf_adjoint_params(s.sym.h, Bn, lam2, 2 * nn, s.type, 0, Vm, Va, n, rs, xs, bstride, gP2,
+                        gQ2, n, gx2, mode)
+    for got in out:
+        for a, b in zip(got, (lam2, gP2, gQ2, gx2)):
+            assert torch.equal(a, b)
+    return s, ws, Vm, Va, st, gVa
+
+
+@pytest.mark.parametrize("mode", [1, 0])
+def test_fused_adjoint_equals_the_three_step_path(mode):
+    """pf_adjoint (gather, transposed solves, bus and per-case branch
+    gradients in one launch, their sum over cases in a second) gives bitwise
+    the results of pf_adjoint_rhs, pf_solve(transpose = 1) and
+    pf_adjoint_params, also when called twice on one workspace."""
+    B = _B()
+    g = grid(2000, 1)
+    Bn = 8
+    s, ws, Vm, Va, st, gVa = _fused_vs_three_step(g, Bn, mode)
+    if mode == 0:
+        return
+    info = s.info
+    n, nn = g.n, info.nn
+    f64 = dict(dtype=torch.float64, device="cuda")
+    lam1, lam2 = torch.empty(Bn, 2 * nn, **f64), torch.empty(Bn, 2 * nn, **f64)
+    gP1, gQ1 = torch.empty(Bn, n, **f64), torch.empty(Bn, n, **f64)
+    gP2, gQ2 = torch.empty(Bn, n, **f64), torch.empty(Bn, n, **f64)
     # absent gradients read as zero
     B.pf_adjoint(s.sym.h, Bn, ws, info.ws_doubles, None, gVa, n, s.type, 0, Vm, Va, n, s.r,
                  s.x, 0, None, lam1, 2 * nn, gP1, gQ1, n, None, 1)
-    B.pf_adjoint(s.sym.h, Bn, ws, info.ws_doubles, torch.zeros_like(gVm), gVa, n, s.type, 0, Vm,
+    B.pf_adjoint(s.sym.h, Bn, ws, info.ws_doubles, torch.zeros_like(gVa), gVa, n, s.type, 0, Vm,
                  Va, n, s.r, s.x, 0, None, lam2, 2 * nn, gP2, gQ2, n, None, 1)
     assert torch.equal(lam1, lam2) and torch.equal(gP1, gP2)
+
+
+def test_fused_adjoint_with_more_branches_than_rhs_room():
+    """Every branch doubled (m > 2 nn): the workspace's rhs section cannot hold
+    a case's branch values, so the summed dL/dx takes its own kernel; the
+    results are still those of the three-step path."""
+    g = grid(60, 1)
+    g2 = dataclasses.replace(g, f=np.concatenate([g.f, g.f]), t=np.concatenate([g.t, g.t]),
+                             r=np.concatenate([g.r, g.r]) * 2, x=np.concatenate([g.x, g.x]) * 2,
+                             b=np.concatenate([g.b, g.b]) / 2)
+    assert g2.m > 2 * (g2.n - 1)
+    _fused_vs_three_step(g2, 4, 1)
