@@ -499,27 +499,6 @@ struct SrcLoadT {
 };
 using SrcLoad = SrcLoadT<false>;
 
-// Runs fn(x, lane, g) for the nodes of levels [l0, l1), x indexing the
-// level-ordered node records, up or down, with a barrier after every level.
-template <class F>
-__device__ __forceinline__ void for_levels(const DevSym& S, int l0, int l1, bool up, F&& fn)
-{
-    for (int li = l0; li < l1; ++li) {
-        const int l = up ? li : l1 - 1 - (li - l0);
-        const int g = S.level_g[l];
-        const int beg = S.level_ptr[l];
-        const int cnt = S.level_ptr[l + 1] - beg;
-        const int gpb = blockDim.x / g;
-        const int grp = threadIdx.x / g;
-        const int lane = threadIdx.x & (g - 1);
-        for (int base = 0; base < cnt; base += gpb) {
-            const int idx = base + grp;
-            if (idx < cnt) fn(beg + idx, lane, g);
-        }
-        __syncthreads();
-    }
-}
-
 // Level-ordered node record, the part the sweeps use ({j, bus, r0, r1},
 // {s0, s1, ydiag, 0}); the admittance-row range is read by the mismatch only.
 struct NodeRec {
@@ -531,9 +510,11 @@ __device__ __forceinline__ NodeRec load_rec(const DevSym& S, int x)
     return {S.node_info[3 * x], S.node_info[3 * x + 1]};
 }
 
-// As for_levels, passing fn(x, rec, lane, g) the node's record; the record
-// of the group's next node in the level is fetched before fn runs so that
-// its latency overlaps the current node's work.
+// Runs fn(x, rec, lane, g) for the nodes of levels [l0, l1), up or down,
+// with a workgroup barrier after every level: x indexes the level-ordered
+// node records, rec is x's record, and each node gets g lanes (the level's
+// mapping).  The record of the group's next node in the level is fetched
+// before fn runs so that its latency overlaps the current node's work.
 template <class F>
 __device__ __forceinline__ void for_nodes(const DevSym& S, int l0, int l1, bool up, F&& fn)
 {
