@@ -300,13 +300,13 @@ __global__ __launch_bounds__(kLevelThreads) void k_factor(DevSym S, double* vals
 // step with the step's blocks and x values requested together; absent
 // entries of a step are not loaded and add nothing.  LDSX keeps the case's
 // whole vector in LDS (nn x 16 bytes) for the two sweeps.
-// The two sweeps of one case on the vector x2 (position order, in LDS or
-// global memory), with the factors in view w.
+// The up sweep over levels [0, L) of one case on the vector x2 (position
+// order, in LDS or global memory), with the factors in view w.
 template <bool TRANS>
-__device__ __forceinline__ void solve_sweeps(const DevSym& S, const View& w, double2* x2)
+__device__ __forceinline__ void solve_up(const DevSym& S, const View& w, double2* x2, int L)
 {
     const int64_t lu = S.lu_off;
-    for_nodes(S, 0, S.nlev, true, [&](int, const NodeRec& rec, int lane, int g) {
+    for_nodes(S, 0, L, true, [&](int, const NodeRec& rec, int lane, int g) {
         const int j = rec.a.x, r0 = rec.a.z, r1 = rec.a.w;
         double z0 = 0.0, z1 = 0.0;
         for (int base = r0 + lane; base < r1; base += 4 * g) {
@@ -351,7 +351,14 @@ __device__ __forceinline__ void solve_sweeps(const DevSym& S, const View& w, dou
             x2[j] = make_double2(u0, u1);
         }
     });
-    for_nodes(S, 0, S.nlev, false, [&](int, const NodeRec& rec, int lane, int g) {
+}
+
+// The down sweep over levels [0, L), top-down.
+template <bool TRANS>
+__device__ __forceinline__ void solve_down(const DevSym& S, const View& w, double2* x2, int L)
+{
+    const int64_t lu = S.lu_off;
+    for_nodes(S, 0, L, false, [&](int, const NodeRec& rec, int lane, int g) {
         const int j = rec.a.x, s0 = rec.b.x, s1 = rec.b.y;
         double a0 = 0.0, a1 = 0.0;
         for (int base = s0 + lane; base < s1; base += 4 * g) {
@@ -398,6 +405,153 @@ __device__ __forceinline__ void solve_sweeps(const DevSym& S, const View& w, dou
     });
 }
 
+// Orders one wavefront's accesses to the vector (LDS, or global memory with
+// workgroup-scope fences).
+template <bool LDSX>
+__device__ __forceinline__ void sync_x()
+{
+    if (LDSX) {
+        wave_sync();
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+}
+
+// The clique chain at the top of the tree (KC single-node levels, each node
+// adjacent to every node above it; clique node b's higher neighbours are the
+// clique nodes above it in order, so the slot of (b; a), a > b, is entry
+// a - b - 1 of S(b)) in the transposed sweeps:
+//   up:   p_a = g_a - sum_{i in R(a)} U_ia^T p_i,
+//   down: l_a = D_a^-T (p_a - sum_{c > a} W_ca^T l_c).
+// The parts from below the clique in one parallel pass (16 lanes per clique
+// node); then the clique column by column on the first wavefront, lane a
+// owning clique node a, each lane's factor blocks requested four columns
+// ahead: up, once p_b is final, p_a -= U_ba^T p_b for a > b; down, l_c from
+// p_c, then p_a -= W_ca^T l_c for a < c.
+template <bool LDSX>
+__device__ void clique_solve_T(const DevSym& S, const View& w, double2* x2)
+{
+    constexpr int kAhead = 4;  // columns whose blocks are in flight
+    const int KC = S.tail_clique, kf = S.tail_nodes - KC;
+    const int64_t lu = S.lu_off;
+    {
+        constexpr int g = 16;
+        const int grp = threadIdx.x / g, lane = threadIdx.x & (g - 1);
+        for (int a0 = 0; a0 < KC; a0 += blockDim.x / g) {
+            const int a = a0 + grp;
+            double z0 = 0.0, z1 = 0.0;
+            const int jl = kf + (a < KC ? a : 0);
+            const int4 t1 = S.t_node[3 * jl + 1];
+            const int rmid = S.t_node[3 * jl + 2].x;
+            if (a < KC) {
+                for (int r = t1.y + lane; r < t1.z; r += g) {  // outside the tail
+                    const int2 e = S.t_rl[r];
+                    const double2 p = x2[e.x];
+                    mtvadd(z0, z1, w.blk(lu + 8 * (int64_t)e.y + 4), p.x, p.y);
+                }
+                for (int r = t1.z + lane; r < rmid; r += g) {  // the tail below the clique
+                    const int2 e = S.t_rl[r];
+                    const int i = S.t_node[3 * e.x].x;
+                    const int sl = S.t_slot[3 * e.y].x;
+                    const double2 p = x2[i];
+                    mtvadd(z0, z1, w.blk(lu + 8 * (int64_t)sl + 4), p.x, p.y);
+                }
+            }
+            gsum2(z0, z1, g);
+            if (a < KC && lane == 0) {
+                const int j = S.t_node[3 * jl].x;
+                const double2 v = x2[j];
+                x2[j] = make_double2(v.x - z0, v.y - z1);
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < kWave) {
+        const int lane = threadIdx.x;
+        const bool mine = lane < KC;
+        int ja = 0, lpa = 0;
+        if (mine) {
+            ja = S.t_node[3 * (kf + lane)].x;
+            lpa = S.Lp[ja];
+        }
+        // up: U_{b, lane}, the upper block of slot (b; lane)
+        auto u_of = [&](int b) {
+            const int lpb = __shfl(lpa, b);
+            Blk r = bzero();
+            if (mine && lane > b) r = w.blk(lu + 8 * (int64_t)(lpb + lane - b - 1) + 4);
+            return r;
+        };
+        Blk q[kAhead];
+#pragma unroll
+        for (int k = 0; k < kAhead; ++k) q[k] = k + 1 < KC ? u_of(k) : bzero();
+        for (int b = 0; b + 1 < KC; ++b) {
+            const Blk u = q[0];
+#pragma unroll
+            for (int k = 0; k + 1 < kAhead; ++k) q[k] = q[k + 1];
+            q[kAhead - 1] = b + kAhead + 1 < KC ? u_of(b + kAhead) : bzero();
+            const double2 pb = x2[__shfl(ja, b)];
+            if (mine && lane > b) {
+                double z0 = 0.0, z1 = 0.0;
+                mtvadd(z0, z1, u, pb.x, pb.y);
+                const double2 v = x2[ja];
+                x2[ja] = make_double2(v.x - z0, v.y - z1);
+            }
+            sync_x<LDSX>();
+        }
+        // down: W_{c, lane}, the lower block of slot (lane; c), and D_c^-1
+        auto w_of = [&](int c) {
+            Blk r = bzero();
+            if (lane < c) r = w.blk(lu + 8 * (int64_t)(lpa + c - lane - 1));
+            return r;
+        };
+        auto d_of = [&](int c) { return w.blk(4 * (int64_t)__shfl(ja, c)); };
+        Blk wq[kAhead], dq[kAhead];
+#pragma unroll
+        for (int k = 0; k < kAhead; ++k) {
+            wq[k] = KC - 1 - k >= 0 ? w_of(KC - 1 - k) : bzero();
+            dq[k] = KC - 1 - k >= 0 ? d_of(KC - 1 - k) : bzero();
+        }
+        for (int c = KC - 1; c >= 0; --c) {
+            const Blk Wc = wq[0], Dc = dq[0];
+#pragma unroll
+            for (int k = 0; k + 1 < kAhead; ++k) {
+                wq[k] = wq[k + 1];
+                dq[k] = dq[k + 1];
+            }
+            wq[kAhead - 1] = c - kAhead >= 0 ? w_of(c - kAhead) : bzero();
+            dq[kAhead - 1] = c - kAhead >= 0 ? d_of(c - kAhead) : bzero();
+            const double2 pc = x2[__shfl(ja, c)];
+            double l0 = 0.0, l1 = 0.0;
+            mtvadd(l0, l1, Dc, pc.x, pc.y);
+            if (lane < c) {
+                double z0 = 0.0, z1 = 0.0;
+                mtvadd(z0, z1, Wc, l0, l1);
+                const double2 v = x2[ja];
+                x2[ja] = make_double2(v.x - z0, v.y - z1);
+            } else if (lane == c) {
+                x2[ja] = make_double2(l0, l1);
+            }
+            sync_x<LDSX>();
+        }
+    }
+    __syncthreads();
+}
+
+// The two sweeps of one case on the vector x2 (position order, in LDS or
+// global memory), with the factors in view w; the transposed sweeps take the
+// clique chain at the top column by column.
+template <bool TRANS, bool LDSX>
+__device__ __forceinline__ void solve_sweeps(const DevSym& S, const View& w, double2* x2)
+{
+    const bool col = TRANS && S.tail_clique >= 3 && S.tail_clique <= kWave;
+    const int L = col ? S.nlev - S.tail_clique : S.nlev;
+    solve_up<TRANS>(S, w, x2, L);
+    if (TRANS && col) clique_solve_T<LDSX>(S, w, x2);
+    solve_down<TRANS>(S, w, x2, L);
+}
+
 template <bool TRANS, bool LDSX>
 __global__ __launch_bounds__(kLevelThreads) void k_solve(DevSym S, const double* vals,
                                                        int64_t vals_stride, int C, int B,
@@ -412,7 +566,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_solve(DevSym S, const double*
         for (int p = threadIdx.x; p < S.nn; p += blockDim.x) x2[p] = xg[p];
         __syncthreads();
     }
-    solve_sweeps<TRANS>(S, w, x2);
+    solve_sweeps<TRANS, LDSX>(S, w, x2);
     if (LDSX) {
         __syncthreads();
         for (int p = threadIdx.x; p < S.nn; p += blockDim.x) xg[p] = x2[p];
@@ -475,7 +629,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_adjoint(DevSym S, AdjArgs a)
         x2[p] = make_double2(ga, gm);
     }
     __syncthreads();
-    solve_sweeps<true>(S, w, x2);
+    solve_sweeps<true, LDSX>(S, w, x2);
     __syncthreads();
     const bool ok = !a.status || a.status[c] == ST_OK;
     const double nan = __builtin_nan("");
