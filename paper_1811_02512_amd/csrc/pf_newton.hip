@@ -422,18 +422,28 @@ __device__ __forceinline__ void sync_x()
 // The clique chain at the top of the tree (KC single-node levels, each node
 // adjacent to every node above it; clique node b's higher neighbours are the
 // clique nodes above it in order, so the slot of (b; a), a > b, is entry
-// a - b - 1 of S(b)) in the transposed sweeps:
-//   up:   p_a = g_a - sum_{i in R(a)} U_ia^T p_i,
-//   down: l_a = D_a^-T (p_a - sum_{c > a} W_ca^T l_c).
+// a - b - 1 of S(b)) in the two sweeps:
+//   transpose = 0: y_a = D_a^-1 (b_a - sum_{i in R(a)} W_ai y_i),
+//                  x_a = y_a - sum_{c > a} U_ac x_c;
+//   transpose = 1: p_a = g_a - sum_{i in R(a)} U_ia^T p_i,
+//                  l_a = D_a^-T (p_a - sum_{c > a} W_ca^T l_c).
 // The parts from below the clique in one parallel pass (16 lanes per clique
 // node); then the clique column by column on the first wavefront, lane a
-// owning clique node a, each lane's factor blocks requested four columns
-// ahead: up, once p_b is final, p_a -= U_ba^T p_b for a > b; down, l_c from
-// p_c, then p_a -= W_ca^T l_c for a < c.
-template <bool LDSX>
-__device__ void clique_solve_T(const DevSym& S, const View& w, double2* x2)
+// owning clique node a, each lane's blocks requested four columns ahead: up,
+// once node b is final (after its D^-1 when transpose = 0) every node a above
+// it takes node b's part; down, node c final (after its D^-T when
+// transpose = 1), every node a below takes node c's part.
+template <bool TRANS, bool LDSX>
+__device__ void clique_solve(const DevSym& S, const View& w, double2* x2)
 {
     constexpr int kAhead = 4;  // columns whose blocks are in flight
+    // the part of slot (i; k) that the up sweep reads (U_ik^T or W_ki) and
+    // the part of slot (a; c) the down sweep reads (W_ca^T or U_ac)
+    constexpr int kUp = TRANS ? 4 : 0, kDown = TRANS ? 0 : 4;
+    auto madd = [](double& y0, double& y1, const Blk& A, double x0, double x1) {
+        if (TRANS) mtvadd(y0, y1, A, x0, x1);
+        else mvadd(y0, y1, A, x0, x1);
+    };
     const int KC = S.tail_clique, kf = S.tail_nodes - KC;
     const int64_t lu = S.lu_off;
     {
@@ -449,14 +459,14 @@ __device__ void clique_solve_T(const DevSym& S, const View& w, double2* x2)
                 for (int r = t1.y + lane; r < t1.z; r += g) {  // outside the tail
                     const int2 e = S.t_rl[r];
                     const double2 p = x2[e.x];
-                    mtvadd(z0, z1, w.blk(lu + 8 * (int64_t)e.y + 4), p.x, p.y);
+                    madd(z0, z1, w.blk(lu + 8 * (int64_t)e.y + kUp), p.x, p.y);
                 }
                 for (int r = t1.z + lane; r < rmid; r += g) {  // the tail below the clique
                     const int2 e = S.t_rl[r];
                     const int i = S.t_node[3 * e.x].x;
                     const int sl = S.t_slot[3 * e.y].x;
                     const double2 p = x2[i];
-                    mtvadd(z0, z1, w.blk(lu + 8 * (int64_t)sl + 4), p.x, p.y);
+                    madd(z0, z1, w.blk(lu + 8 * (int64_t)sl + kUp), p.x, p.y);
                 }
             }
             gsum2(z0, z1, g);
@@ -476,42 +486,60 @@ __device__ void clique_solve_T(const DevSym& S, const View& w, double2* x2)
             ja = S.t_node[3 * (kf + lane)].x;
             lpa = S.Lp[ja];
         }
-        // up: U_{b, lane}, the upper block of slot (b; lane)
+        auto d_of = [&](int c) { return w.blk(4 * (int64_t)__shfl(ja, c)); };
+        // up: the block of slot (b; lane), and (transpose = 0) D_b^-1
         auto u_of = [&](int b) {
             const int lpb = __shfl(lpa, b);
             Blk r = bzero();
-            if (mine && lane > b) r = w.blk(lu + 8 * (int64_t)(lpb + lane - b - 1) + 4);
+            if (mine && lane > b) r = w.blk(lu + 8 * (int64_t)(lpb + lane - b - 1) + kUp);
             return r;
         };
-        Blk q[kAhead];
+        const int nb = TRANS ? KC - 1 : KC;  // columns of the up pass
+        Blk q[kAhead], qd[kAhead];
 #pragma unroll
-        for (int k = 0; k < kAhead; ++k) q[k] = k + 1 < KC ? u_of(k) : bzero();
-        for (int b = 0; b + 1 < KC; ++b) {
-            const Blk u = q[0];
+        for (int k = 0; k < kAhead; ++k) {
+            q[k] = k + 1 < KC ? u_of(k) : bzero();
+            qd[k] = bzero();
+            if (!TRANS && k < KC) qd[k] = d_of(k);
+        }
+        for (int b = 0; b < nb; ++b) {
+            const Blk u = q[0], Db = qd[0];
 #pragma unroll
-            for (int k = 0; k + 1 < kAhead; ++k) q[k] = q[k + 1];
+            for (int k = 0; k + 1 < kAhead; ++k) {
+                q[k] = q[k + 1];
+                qd[k] = qd[k + 1];
+            }
             q[kAhead - 1] = b + kAhead + 1 < KC ? u_of(b + kAhead) : bzero();
-            const double2 pb = x2[__shfl(ja, b)];
+            qd[kAhead - 1] = bzero();
+            if (!TRANS && b + kAhead < KC) qd[kAhead - 1] = d_of(b + kAhead);
+            double2 pb = x2[__shfl(ja, b)];
+            if (!TRANS) {
+                double y0 = 0.0, y1 = 0.0;
+                mvadd(y0, y1, Db, pb.x, pb.y);
+                pb = make_double2(y0, y1);
+            }
             if (mine && lane > b) {
                 double z0 = 0.0, z1 = 0.0;
-                mtvadd(z0, z1, u, pb.x, pb.y);
+                madd(z0, z1, u, pb.x, pb.y);
                 const double2 v = x2[ja];
                 x2[ja] = make_double2(v.x - z0, v.y - z1);
+            } else if (!TRANS && lane == b) {
+                x2[ja] = pb;
             }
             sync_x<LDSX>();
         }
-        // down: W_{c, lane}, the lower block of slot (lane; c), and D_c^-1
+        // down: the block of slot (lane; c), and (transpose = 1) D_c^-1
         auto w_of = [&](int c) {
             Blk r = bzero();
-            if (lane < c) r = w.blk(lu + 8 * (int64_t)(lpa + c - lane - 1));
+            if (lane < c) r = w.blk(lu + 8 * (int64_t)(lpa + c - lane - 1) + kDown);
             return r;
         };
-        auto d_of = [&](int c) { return w.blk(4 * (int64_t)__shfl(ja, c)); };
         Blk wq[kAhead], dq[kAhead];
 #pragma unroll
         for (int k = 0; k < kAhead; ++k) {
             wq[k] = KC - 1 - k >= 0 ? w_of(KC - 1 - k) : bzero();
-            dq[k] = KC - 1 - k >= 0 ? d_of(KC - 1 - k) : bzero();
+            dq[k] = bzero();
+            if (TRANS && KC - 1 - k >= 0) dq[k] = d_of(KC - 1 - k);
         }
         for (int c = KC - 1; c >= 0; --c) {
             const Blk Wc = wq[0], Dc = dq[0];
@@ -521,17 +549,21 @@ __device__ void clique_solve_T(const DevSym& S, const View& w, double2* x2)
                 dq[k] = dq[k + 1];
             }
             wq[kAhead - 1] = c - kAhead >= 0 ? w_of(c - kAhead) : bzero();
-            dq[kAhead - 1] = c - kAhead >= 0 ? d_of(c - kAhead) : bzero();
-            const double2 pc = x2[__shfl(ja, c)];
-            double l0 = 0.0, l1 = 0.0;
-            mtvadd(l0, l1, Dc, pc.x, pc.y);
+            dq[kAhead - 1] = bzero();
+            if (TRANS && c - kAhead >= 0) dq[kAhead - 1] = d_of(c - kAhead);
+            double2 pc = x2[__shfl(ja, c)];
+            if (TRANS) {
+                double l0 = 0.0, l1 = 0.0;
+                mtvadd(l0, l1, Dc, pc.x, pc.y);
+                pc = make_double2(l0, l1);
+            }
             if (lane < c) {
                 double z0 = 0.0, z1 = 0.0;
-                mtvadd(z0, z1, Wc, l0, l1);
+                madd(z0, z1, Wc, pc.x, pc.y);
                 const double2 v = x2[ja];
                 x2[ja] = make_double2(v.x - z0, v.y - z1);
-            } else if (lane == c) {
-                x2[ja] = make_double2(l0, l1);
+            } else if (TRANS && lane == c) {
+                x2[ja] = pc;
             }
             sync_x<LDSX>();
         }
@@ -540,15 +572,15 @@ __device__ void clique_solve_T(const DevSym& S, const View& w, double2* x2)
 }
 
 // The two sweeps of one case on the vector x2 (position order, in LDS or
-// global memory), with the factors in view w; the transposed sweeps take the
-// clique chain at the top column by column.
+// global memory), with the factors in view w; the clique chain at the top
+// column by column when it fits one wavefront.
 template <bool TRANS, bool LDSX>
 __device__ __forceinline__ void solve_sweeps(const DevSym& S, const View& w, double2* x2)
 {
-    const bool col = TRANS && S.tail_clique >= 3 && S.tail_clique <= kWave;
+    const bool col = S.tail_clique >= 3 && S.tail_clique <= kWave;
     const int L = col ? S.nlev - S.tail_clique : S.nlev;
     solve_up<TRANS>(S, w, x2, L);
-    if (TRANS && col) clique_solve_T<LDSX>(S, w, x2);
+    if (col) clique_solve<TRANS, LDSX>(S, w, x2);
     solve_down<TRANS>(S, w, x2, L);
 }
 
