@@ -405,7 +405,10 @@ int pf_adjoint_rhs(const pf_symbolic sym, int B, const double* d_gVm, const doub
  * dy_e/dx_e = -j y_e^2 (r_e held fixed).  d_lam: double[B][nn][2].
  * d_gP, d_gQ: out double[B][n] (g_stride).  d_gx: out; gx_mode 0 writes
  * double[B][m] (stride m), gx_mode 1 writes the sum over cases, double[m].
- * One thread per branch: no atomics.                                      */
+ * One thread per branch: no atomics.  Errors: PF_E_INVALID (NULL input, bad
+ * mode, negative stride, d_gx without d_r and d_x), PF_E_WORKSPACE (with
+ * B > 1, a stride below its row: lam 2 nn, Vm/Va and gP/gQ n, a non-zero
+ * type stride n, a non-zero branch stride m).                             */
 int pf_adjoint_params(const pf_symbolic sym, int B, const double* d_lam, int64_t lam_stride,
                       const int8_t* d_type, int64_t type_stride, const double* d_Vm,
                       const double* d_Va, int64_t v_stride, const double* d_r,
@@ -428,7 +431,9 @@ int pf_adjoint_params(const pf_symbolic sym, int B, const double* d_lam, int64_t
  * pf_newton wrote, or NULL; a case whose status is not PF_OK (its workspace
  * holds no factors of a converged J) gets NaN gradients, and with gx_mode 1
  * the summed d_gx is NaN.  Errors: PF_E_INVALID (NULL output, bad mode or
- * stride, d_gx without d_r and d_x), PF_E_WORKSPACE (strides too small). */
+ * negative stride, d_gx without d_r and d_x), PF_E_WORKSPACE (ws_stride
+ * below ws_doubles; with B > 1 a stride below its row, as
+ * pf_adjoint_params).                                                      */
 int pf_adjoint(const pf_symbolic sym, int B, double* d_ws, int64_t ws_stride,
                const double* d_gVm, const double* d_gVa, int64_t gv_stride,
                const int8_t* d_type, int64_t type_stride, const double* d_Vm,

@@ -1175,12 +1175,14 @@ int pf_adjoint(const pf_symbolic s, int B, double* d_ws, int64_t ws_stride,
     if (!ready(s, "pf_adjoint")) return PF_E_INVALID;
     if (B < 0 || B > 65535 || !d_ws || !d_type || !d_Vm || !d_Va || !d_lam || !d_gP || !d_gQ ||
         (gx_mode != 0 && gx_mode != 1) || (ws_stride & 7) || gv_stride < 0 || v_stride < 0 ||
-        g_stride < 0 || lam_stride < 0 || branch_stride < 0)
+        g_stride < 0 || lam_stride < 0 || branch_stride < 0 || type_stride < 0)
         return fail(PF_E_INVALID, "pf_adjoint: bad arguments");
     if (ws_stride < s->h.ws_doubles())
         return fail(PF_E_WORKSPACE, "pf_adjoint: ws_stride < ws_doubles");
     if (B > 1 && (lam_stride < 2 * (int64_t)s->h.nn || g_stride < s->h.n ||
-                  v_stride < s->h.n || (gv_stride != 0 && gv_stride < s->h.n)))
+                  v_stride < s->h.n || (gv_stride != 0 && gv_stride < s->h.n) ||
+                  (type_stride != 0 && type_stride < s->h.n) ||
+                  (branch_stride != 0 && branch_stride < s->h.m)))
         return fail(PF_E_WORKSPACE, "pf_adjoint: a stride is too small");
     if (B == 0) return PF_OK;
     const int C = newton_interleave(s->h, B);
@@ -1229,8 +1231,15 @@ int adjoint_branch_launch(const pf_symbolic s, int B, const double* d_lam, int64
 {
     if (!ready(s, "pf_adjoint_params")) return PF_E_INVALID;
     if (B < 0 || B > 65535 || !d_lam || !d_type || !d_Vm || !d_Va ||
-        (gx_mode != 0 && gx_mode != 1))
+        (gx_mode != 0 && gx_mode != 1) || lam_stride < 0 || type_stride < 0 || v_stride < 0 ||
+        branch_stride < 0 || g_stride < 0)
         return fail(PF_E_INVALID, "pf_adjoint_params: bad arguments");
+    const HostSym& h = s->h;
+    if (B > 1 && (lam_stride < 2 * (int64_t)h.nn || v_stride < h.n ||
+                  (type_stride != 0 && type_stride < h.n) ||
+                  (branch_stride != 0 && branch_stride < h.m) ||
+                  (bus && d_gP && d_gQ && g_stride < h.n)))
+        return fail(PF_E_WORKSPACE, "pf_adjoint_params: a stride is too small");
     if (B == 0) return PF_OK;
     if (bus && d_gP && d_gQ) {
         dim3 grid((s->h.n + 255) / 256, B);

@@ -254,3 +254,41 @@ def test_fused_adjoint_with_more_branches_than_rhs_room():
                              b=np.concatenate([g.b, g.b]) / 2)
     assert g2.m > 2 * (g2.n - 1)
     _fused_vs_three_step(g2, 4, 1)
+
+
+def test_adjoint_strides_are_checked_before_any_launch():
+    """Strides below a row are refused with PF_E_WORKSPACE by pf_adjoint and
+    pf_adjoint_params (B > 1), negative ones with PF_E_INVALID; the outputs
+    are left as they were."""
+    B = _B()
+    g = grid(200, 1)
+    s = Staged(g)
+    Bn = 2
+    P, Q = gridgen.scenario_injections(g, Bn, 3)
+    Vm, Va, it, _, st, ws = s.newton(Bn, dev(P), dev(Q), keep=True)
+    info = s.info
+    n, nn, m = g.n, info.nn, g.m
+    f64 = dict(dtype=torch.float64, device="cuda")
+    gVm = torch.ones(Bn, n, **f64)
+    lam = torch.full((Bn, 2 * nn), 7.0, **f64)
+    gP, gQ = torch.full((Bn, n), 7.0, **f64), torch.full((Bn, n), 7.0, **f64)
+    gx = torch.full((Bn * m,), 7.0, **f64)
+    xs, rs = s.x.repeat(Bn), s.r.repeat(Bn)
+    cases = [  # (type_stride, branch_stride, expected code)
+        (1, m, B.PF_E_WORKSPACE), (0, m - 1, B.PF_E_WORKSPACE), (-1, m, B.PF_E_INVALID)]
+    for ts, bs, code in cases:
+        with pytest.raises(B.PfError) as ei:
+            B.pf_adjoint(s.sym.h, Bn, ws, info.ws_doubles, gVm, None, n, s.type, ts, Vm, Va, n,
+                         rs, xs, bs, st, lam, 2 * nn, gP, gQ, n, gx, 0)
+        assert ei.value.code == code
+        with pytest.raises(B.PfError) as ei:
+            B.pf_adjoint_params(s.sym.h, Bn, lam, 2 * nn, s.type, ts, Vm, Va, n, rs, xs, bs, gP,
+                                gQ, n, gx, 0)
+        assert ei.value.code == code
+    with pytest.raises(B.PfError) as ei:
+        B.pf_adjoint_params(s.sym.h, Bn, lam, 2 * nn - 2, s.type, 0, Vm, Va, n, rs, xs, m, gP,
+                            gQ, n, gx, 0)
+    assert ei.value.code == B.PF_E_WORKSPACE
+    torch.cuda.synchronize()
+    for t in (lam, gP, gQ, gx):
+        assert (t == 7.0).all()
