@@ -40,7 +40,11 @@
  *     valid until the stream work completes.  libpf allocates no device
  *     memory; pf_symbolic_upload / pf_multi_upload copy into caller buffers.
  *   - "stride" arguments are in elements between consecutive cases; 0 means
- *     the array is shared by all cases (inputs only).
+ *     the array is shared by all cases (inputs only).  With B > 1 any other
+ *     stride must be at least the array's row (nnz_y pairs for admittance
+ *     values, n for bus arrays, m for branch arrays, 2 nn for mismatch and
+ *     adjoint vectors): a smaller one returns PF_E_WORKSPACE, a negative
+ *     one PF_E_INVALID or PF_E_WORKSPACE, in both cases before any launch.
  *   - Interleaved case groups ("interleave" C in 1, 2, 4, 8): an array of
  *     per-case doubles with stride S (a multiple of 8) is cut into groups of
  *     C cases; element d of case c lives at

@@ -618,6 +618,8 @@ int pf_fdpf_matrices(const pf_symbolic s, int B, const double* d_r, const double
         return fail(PF_E_WORKSPACE, "pf_fdpf_matrices: d_mat must be 16-byte aligned");
     if (B > 1 && mat_stride < 2 * s->h.fd_mat())
         return fail(PF_E_WORKSPACE, "pf_fdpf_matrices: mat_stride < fd_mat_doubles");
+    if (!shared_stride_ok(B, branch_stride, s->h.m) || !shared_stride_ok(B, type_stride, s->h.n))
+        return fail(PF_E_WORKSPACE, "pf_fdpf_matrices: a stride is too small or negative");
     if (B == 0) return PF_OK;
     dim3 grid((unsigned)((s->h.fd_lu() + 255) / 256), B);
     hipLaunchKernelGGL(k_fd_matrices, grid, dim3(256), 0, as_stream(stream), s->h.dev, d_r, d_x,
@@ -657,6 +659,10 @@ int pf_fdpf(const pf_symbolic s, int B, const double* d_yval, int64_t y_stride,
         !d_Vm || !d_Va || !d_mat || !d_ws || (mat_stride & 7))
         return fail(PF_E_INVALID, "pf_fdpf: bad arguments");
     if (B > 1 && v_stride < s->h.n) return fail(PF_E_WORKSPACE, "pf_fdpf: v_stride too small");
+    if (!shared_stride_ok(B, y_stride, 2 * (int64_t)s->h.ycol.size()) ||
+        !shared_stride_ok(B, type_stride, s->h.n) || !shared_stride_ok(B, inj_stride, s->h.n) ||
+        !shared_stride_ok(B, mat_stride, 2 * s->h.fd_mat()))
+        return fail(PF_E_WORKSPACE, "pf_fdpf: a stride is too small or negative");
     if (ws_stride < s->h.fd_ws_doubles() || (ws_stride & 7))
         return fail(PF_E_WORKSPACE,
                     "pf_fdpf: ws_stride must be >= fd_ws_doubles, a multiple of 8");
@@ -682,6 +688,8 @@ int pf_branch_flows(const pf_symbolic s, int B, const double* d_r, const double*
         return fail(PF_E_INVALID, "pf_branch_flows: bad arguments");
     if (B > 1 && (v_stride < s->h.n || out_stride < s->h.m))
         return fail(PF_E_WORKSPACE, "pf_branch_flows: stride too small");
+    if (!shared_stride_ok(B, branch_stride, s->h.m))
+        return fail(PF_E_WORKSPACE, "pf_branch_flows: branch_stride too small or negative");
     if (B == 0 || s->h.m == 0) return PF_OK;
     dim3 grid((s->h.m + 255) / 256, B);
     hipLaunchKernelGGL(k_branch_flows, grid, dim3(256), 0, as_stream(stream), s->h.m, s->d_from,

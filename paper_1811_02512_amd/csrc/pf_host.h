@@ -37,6 +37,12 @@ int newton_interleave(const pf::HostSym& h, int B);
 // A symbolic that is non-null and uploaded (else records the error).
 bool ready(const pf_symbolic s, const char* fn);
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+// A per-case stride of an input that the cases may also share: 0 (one array
+// for all cases) or, with more than one case, at least one row.
+inline bool shared_stride_ok(int B, int64_t stride, int64_t row)
+{
+    return stride >= 0 && (stride == 0 || B <= 1 || stride >= row);
+}
 // Branch gradients (and, with bus, the injection gradients) of B cases from
 // their adjoint vectors (pf_adjoint_params, pf_adjoint).
 int adjoint_branch_launch(const pf_symbolic s, int B, const double* d_lam, int64_t lam_stride,

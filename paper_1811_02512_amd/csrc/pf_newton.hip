@@ -981,8 +981,13 @@ int pf_mismatch(const pf_symbolic s, int B, const double* d_yval, int64_t y_stri
                 double* d_PQ, void* stream)
 {
     if (!ready(s, "pf_mismatch")) return PF_E_INVALID;
-    if (B < 0 || !d_yval || !d_type || !d_Psp || !d_Qsp || !d_Vm || !d_Va || !d_rhs)
+    if (B < 0 || !d_yval || !d_type || !d_Psp || !d_Qsp || !d_Vm || !d_Va || !d_rhs ||
+        v_stride < 0 || rhs_stride < 0)
         return fail(PF_E_INVALID, "pf_mismatch: bad arguments");
+    if (!shared_stride_ok(B, y_stride, 2 * (int64_t)s->h.ycol.size()) ||
+        !shared_stride_ok(B, type_stride, s->h.n) || !shared_stride_ok(B, inj_stride, s->h.n) ||
+        (B > 1 && (v_stride < s->h.n || rhs_stride < 2 * (int64_t)s->h.nn)))
+        return fail(PF_E_WORKSPACE, "pf_mismatch: a stride is too small or negative");
     if (B == 0) return PF_OK;
     hipLaunchKernelGGL(k_mismatch, dim3(B), dim3(256), 0, as_stream(stream), s->h.dev, d_yval,
                        y_stride, d_type, type_stride, d_Psp, d_Qsp, inj_stride, d_Vm, d_Va,
@@ -1001,6 +1006,10 @@ int pf_jacobian(const pf_symbolic s, int B, const double* d_yval, int64_t y_stri
         return fail(PF_E_INVALID, "pf_jacobian: bad arguments");
     if (B > 1 && vals_stride < s->h.vals_doubles())
         return fail(PF_E_WORKSPACE, "pf_jacobian: vals_stride < vals_doubles");
+    if (!shared_stride_ok(B, y_stride, 2 * (int64_t)s->h.ycol.size()) ||
+        !shared_stride_ok(B, type_stride, s->h.n) || v_stride < 0 ||
+        (B > 1 && v_stride < s->h.n))
+        return fail(PF_E_WORKSPACE, "pf_jacobian: a stride is too small or negative");
     if (B == 0 || s->h.nn == 0) return PF_OK;
     dim3 grid((s->h.nn + 255) / 256, B);
     hipLaunchKernelGGL(k_jacobian, grid, dim3(256), 0, as_stream(stream), s->h.dev, d_yval,
@@ -1101,6 +1110,9 @@ int pf_newton_noalloc(const pf_symbolic s, int B, const double* d_yval, int64_t 
         return fail(PF_E_INVALID, "pf_newton_noalloc: bad arguments");
     if (B > 1 && v_stride < s->h.n)
         return fail(PF_E_WORKSPACE, "pf_newton_noalloc: v_stride too small");
+    if (!shared_stride_ok(B, y_stride, 2 * (int64_t)s->h.ycol.size()) ||
+        !shared_stride_ok(B, type_stride, s->h.n) || !shared_stride_ok(B, inj_stride, s->h.n))
+        return fail(PF_E_WORKSPACE, "pf_newton_noalloc: a stride is too small or negative");
     if (B == 0) return PF_OK;
     const int C = newton_interleave(s->h, B);
     const int64_t ws_stride = s->h.ws_doubles();
@@ -1138,6 +1150,9 @@ int pf_newton(const pf_symbolic s, int B, const double* d_yval, int64_t y_stride
         return fail(PF_E_INVALID, "pf_newton: bad arguments");
     if (B > 1 && v_stride < s->h.n)
         return fail(PF_E_WORKSPACE, "pf_newton: v_stride too small");
+    if (!shared_stride_ok(B, y_stride, 2 * (int64_t)s->h.ycol.size()) ||
+        !shared_stride_ok(B, type_stride, s->h.n) || !shared_stride_ok(B, inj_stride, s->h.n))
+        return fail(PF_E_WORKSPACE, "pf_newton: a stride is too small or negative");
     if (ws_stride < s->h.ws_doubles() || (ws_stride & 7))
         return fail(PF_E_WORKSPACE, "pf_newton: ws_stride must be >= ws_doubles, a multiple of 8");
     if (reinterpret_cast<uintptr_t>(d_ws) & 15)

@@ -292,3 +292,43 @@ def test_adjoint_strides_are_checked_before_any_launch():
     torch.cuda.synchronize()
     for t in (lam, gP, gQ, gx):
         assert (t == 7.0).all()
+
+
+def test_shared_or_per_case_strides_are_checked():
+    """A per-case stride of an input the cases may share must be 0 or at least
+    one row (B > 1): pf_newton, pf_mismatch and pf_branch_flows refuse the
+    rest with PF_E_WORKSPACE and leave their outputs alone."""
+    B = _B()
+    g = grid(200, 1)
+    s = Staged(g)
+    Bn = 2
+    n, m, nn = g.n, g.m, s.info.nn
+    f64 = dict(dtype=torch.float64, device="cuda")
+    P, Q = gridgen.scenario_injections(g, Bn, 3)
+    Pt, Qt = dev(P), dev(Q)
+    Vm = torch.full((Bn, n), 7.0, **f64)
+    Va = torch.full((Bn, n), 7.0, **f64)
+    ws = torch.zeros(Bn * s.info.ws_doubles + 64, **f64)
+    it = torch.full((Bn,), -5, dtype=torch.int32, device="cuda")
+    st = torch.full((Bn,), -5, dtype=torch.int32, device="cuda")
+    nrm = torch.zeros(Bn, **f64)
+    for ys, ts, js in ((0, 1, n), (0, 0, n - 1), (1, 0, n)):
+        with pytest.raises(B.PfError) as ei:
+            B.pf_newton(s.sym.h, Bn, s.yval, ys, s.type, ts, Pt, Qt, js, Vm, Va, n, 1e-8, 20,
+                        0, ws, s.info.ws_doubles, it, nrm, st)
+        assert ei.value.code == B.PF_E_WORKSPACE
+    rhs = torch.full((Bn, 2 * nn), 7.0, **f64)
+    with pytest.raises(B.PfError) as ei:
+        B.pf_mismatch(s.sym.h, Bn, s.yval, 0, s.type, 0, Pt, Qt, n, Vm, Va, n, rhs, 2 * nn - 2,
+                      nrm)
+    assert ei.value.code == B.PF_E_WORKSPACE
+    out = [torch.full((Bn, m), 7.0, **f64) for _ in range(4)]
+    with pytest.raises(B.PfError) as ei:
+        B.pf_branch_flows(s.sym.h, Bn, s.r.repeat(Bn), s.x.repeat(Bn), s.b.repeat(Bn), m - 1,
+                          Vm, Va, n, *out, m)
+    assert ei.value.code == B.PF_E_WORKSPACE
+    torch.cuda.synchronize()
+    assert (Vm == 7.0).all() and (Va == 7.0).all() and (rhs == 7.0).all()
+    assert (it == -5).all() and (st == -5).all()
+    for t in out:
+        assert (t == 7.0).all()
