@@ -198,7 +198,8 @@ class Workload:
         res = autotune.tune(sym, self.yval[0], self.type, self.Pt[:Bn].contiguous(),
                             self.Qt[:Bn].contiguous(), V0, A0)
         log(f"[bench] autotune n={g.n} B={Bn}: T={res['threads']} tail={res['tail_budget']} "
-            f"C={res['interleave']} best {res['ms']:.3f} ms, {res['launches']} launches in "
+            f"C={res['interleave']} spread={res['spread']} best {res['ms']:.3f} ms, "
+            f"{res['launches']} launches in "
             f"{res['seconds']:.1f}s")
         self.info = self.sym.info
         if sym is self.sym:
@@ -433,23 +434,30 @@ def leg_plain(W, steps, label):
     Vm, Va = W.Vm[0].cpu().numpy(), W.Va[0].cpu().numpy()
     check = check_cases([(ref.iters == it, float(np.abs(ref.Vm - Vm).max()),
                           float(np.abs(ref.Va - Va).max()))])
+    spread = int(W.sym1.info.spread)
     log(f"[bench] {label} one case per launch: {ms * 1e3:.1f} us/solve, {it} iterations, "
-        f"{ms * 1e3 / max(it, 1):.1f} us/iteration")
+        f"{ms * 1e3 / max(it, 1):.1f} us/iteration, spread over {max(spread, 1)} workgroups")
+    if spread > 1:
+        launches = (3, f"k_ybus + k_spread_init + k_newton_spread (the whole NR loop in one "
+                       f"cooperative launch of {spread} workgroups); two 16n-byte device copies "
+                       f"of the flat start")
+    else:
+        launches = (2, "k_ybus + k_newton (the whole NR loop in one launch); two 16n-byte "
+                       "device copies of the flat start")
     return dict(solves_per_s=1e3 / ms, ms_per_solve=ms, us_per_iteration=ms * 1e3 / max(it, 1),
-                iterations=it, kernel_launches_per_solve=2,
-                launches="k_ybus + k_newton (the whole NR loop in one launch); two 16n-byte "
-                         "device copies of the flat start",
-                oracle_check=check)
+                iterations=it, workgroups=max(spread, 1), kernel_launches_per_solve=launches[0],
+                launches=launches[1], oracle_check=check)
 
 
 def leg_c2_breakdown(W, steps):
     """10k single case: the Jacobian at flat start factorised (pf_factor) and
-    solved (pf_solve) alone, one case per launch, with their bandwidth."""
+    solved (pf_solve) alone, one case per launch on one workgroup (the
+    batch's launch shape), with their bandwidth."""
     import torch
 
     from paper_1811_02512_amd import binding as B
 
-    sym, info, g = W.sym1, W.sym1.info, W.g
+    sym, info, g = W.sym, W.sym.info, W.g
     f64 = dict(dtype=torch.float64, device="cuda")
     J = torch.zeros(1, info.vals_doubles, **f64)
     B.pf_build_ybus(sym.h, 1, W.r, W.x, W.b, 0, W.yval, 2 * info.nnz_y)
@@ -927,7 +935,8 @@ def main():
         out["wls_se_10k_x256"] = leg_se(W)
     out["autotune"] = None if tuned is None else {
         "batched": {k: tuned[k] for k in ("threads", "tail_budget", "interleave", "ms")},
-        "plain": {k: tuned1[k] for k in ("threads", "tail_budget", "interleave", "ms")},
+        "plain": {k: tuned1.get(k, 0) for k in ("threads", "tail_budget", "interleave", "spread",
+                                                 "ms")},
         "seconds": tuned["seconds"] + tuned1["seconds"], "from_file": bool(args.settings)}
     out["kernel_sources"] = kernel_source_hash()
     out["paper_context"] = ("Table III: graph-based NR 119.22 ms per solve on a 10790-bus "

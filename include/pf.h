@@ -121,6 +121,8 @@ typedef struct {
     int64_t lu_offset;       /* doubles before the LU section (8*ceil(nn/2)) */
     int64_t fd_mat_doubles;  /* fast decoupled B' and B'' of one case        */
     int64_t fd_ws_doubles;   /* pf_fdpf workspace per case                   */
+    int32_t spread;          /* workgroups of a one-case pf_newton launch    */
+                             /* (0: one workgroup)                          */
 } pf_info;
 
 /* ---- status ------------------------------------------------------------ */
@@ -165,6 +167,18 @@ int pf_symbolic_set_mapping(pf_symbolic sym, const int32_t* lanes_per_level);
  * default 4) is the case grouping of pf_newton's workspace.               */
 int pf_symbolic_set_launch(pf_symbolic sym, int threads, int64_t tail_lds_budget,
                            int interleave);
+/* Workgroups a one-case pf_newton or pf_newton_noalloc launch spreads over
+ * (0 or 1: one workgroup, the default; at most 1024).  With more than one,
+ * the loops over buses and the levels below the LDS tail are shared out
+ * among that many workgroups of a cooperative launch, which meet at grid
+ * barriers, while the tail runs on the first (the paper's nodal parallelism
+ * across the device for one case, Sec. III); the count is capped by the
+ * workgroups the device keeps resident at once.  Results equal the
+ * one-workgroup path's to rounding: the arithmetic of every node is the
+ * same, but |V| is read from the bus record rather than recomputed from
+ * (e, f).  A launch recorded into a graph (stream capture) and every batch
+ * (B > 1) use the one-workgroup kernel.  Takes effect at the next call.    */
+int pf_symbolic_set_spread(pf_symbolic sym, int workgroups);
 int pf_symbolic_get_mapping(const pf_symbolic sym, int32_t* lanes_per_level);
 /* Copies the integer structure into the caller's device buffer d_buf
  * (>= info.dev_bytes, 256-byte aligned) on stream s.  The buffer must stay
@@ -243,7 +257,9 @@ int pf_solve(const pf_symbolic sym, int B, const double* d_vals, int64_t vals_st
  * max_iter steps.  d_Vm/d_Va: in = start state (flat start is the caller's),
  * out = solution, double[B][n] (v_stride).  d_ws: workspace in groups of
  * C = pf_newton_interleave(sym, B) cases (see "Interleaved case groups"), ws_stride
- * >= info.ws_doubles and a multiple of 8, 16-byte aligned.  With
+ * >= info.ws_doubles and a multiple of 8, 16-byte aligned (a one-case launch
+ * spread over several workgroups, pf_symbolic_set_spread, keeps its
+ * grid-barrier words in the last 384 bytes of the case's row).  With
  * PF_NEWTON_KEEP_FACTORS, each converged case's first info.vals_doubles hold
  * the factors of J at the returned state in the filled layout (D^-1, L D,
  * U), so pf_solve and pf_adjoint can take d_ws with vals_stride = ws_stride
@@ -253,7 +269,10 @@ int pf_solve(const pf_symbolic sym, int B, const double* d_vals, int64_t vals_st
  * (steps applied), d_norm[B] (last max|F|), d_status[B] (PF_OK,
  * PF_E_ZERO_PIVOT, PF_E_NOT_CONVERGED, PF_E_NONFINITE), d_pivot[B] (-1, or
  * with PF_E_ZERO_PIVOT the position of the first failing pivot, as
- * pf_factor); any may be NULL.  The launch never fails because of one case.*/
+ * pf_factor); any may be NULL.  The launch never fails because of one case.
+ * A spread launch whose workgroups lose step (one of them waits more than a
+ * second at a grid barrier) ends every workgroup early and reports
+ * PF_E_HIP in d_status.                                                    */
 int pf_newton(const pf_symbolic sym, int B, const double* d_yval, int64_t y_stride,
               const int8_t* d_type, int64_t type_stride, const double* d_Psp,
               const double* d_Qsp, int64_t inj_stride, double* d_Vm, double* d_Va,

@@ -58,6 +58,10 @@ class Symbolic:
         if self.buf is not None:
             self.upload(self.device)
 
+    def set_spread(self, workgroups):
+        """Workgroups of a one-case Newton launch (0: one workgroup)."""
+        B.pf_symbolic_set_spread(self.h, workgroups)
+
     def upload(self, device=None):
         dev = _dev(device)
         nbytes = self.info.dev_bytes

@@ -5,6 +5,8 @@ batch) with HIP events and keeps the fastest setting of:
   * threads per workgroup (256, 512),
   * LDS-tail budget (how many top levels run in LDS),
   * case interleave of the workspace (1, 2, 4, 8),
+  * for a single case, the workgroups its launch is spread over (one, or a
+    cooperative launch of 16 ... 256 sharing the levels below the LDS tail),
   * lanes per node for each level class (levels grouped by width), by
     coordinate descent over {1, 2, 4, ..., 64}.
 Every setting computes the same factorisation; the lanes per node only change
@@ -82,7 +84,8 @@ class _Timer:
 
 def tune(sym, yval, bus_type, Psp, Qsp, Vm0, Va0, tol=1e-8, max_iter=20, reps=2,
          threads=(256, 512), budgets=(32768, 65536, 114688, 161792),
-         interleaves=(1, 2, 4, 8), passes=2, verbose=False):
+         interleaves=(1, 2, 4, 8), spreads=(0, 16, 32, 64, 128, 256), passes=2,
+         verbose=False):
     """Tunes `sym` (an uploaded api.Symbolic) for this batch in place.
 
     Psp, Qsp: [B, n]; Vm0, Va0: [B, n] start states.  Returns a dict with the
@@ -93,17 +96,22 @@ def tune(sym, yval, bus_type, Psp, Qsp, Vm0, Va0, tol=1e-8, max_iter=20, reps=2,
     Bn = Psp.shape[0]
     if Bn == 1:
         interleaves = (1,)
+    else:
+        spreads = (0,)  # a batch always runs one workgroup per case
     base_map = sym.get_mapping().copy()
     best = (float("inf"), None)
     for T, bud, C in itertools.product(threads, budgets, interleaves):
         sym.set_launch(T, bud, C)
-        ms = timer()
-        if verbose:
-            print(f"[tune] T={T} budget={bud} C={C}: {ms:.3f} ms", flush=True)
-        if ms < best[0]:
-            best = (ms, (T, bud, C))
-    T, bud, C = best[1]
+        for G in spreads:
+            sym.set_spread(G)
+            ms = timer()
+            if verbose:
+                print(f"[tune] T={T} budget={bud} C={C} spread={G}: {ms:.3f} ms", flush=True)
+            if ms < best[0]:
+                best = (ms, (T, bud, C, G))
+    T, bud, C, G = best[1]
     sym.set_launch(T, bud, C)
+    sym.set_spread(G)
     mapping = base_map.copy()
     best_ms = best[0]
     classes = level_classes(sym)
@@ -126,11 +134,12 @@ def tune(sym, yval, bus_type, Psp, Qsp, Vm0, Va0, tol=1e-8, max_iter=20, reps=2,
         if not improved:
             break
     sym.set_mapping(mapping)
-    return dict(threads=T, tail_budget=bud, interleave=C, mapping=mapping.tolist(),
+    return dict(threads=T, tail_budget=bud, interleave=C, spread=G, mapping=mapping.tolist(),
                 ms=best_ms, launches=timer.runs, seconds=time.time() - t0)
 
 
 def apply(sym, settings):
     """Re-applies settings returned by :func:`tune` to a symbolic of the same grid."""
     sym.set_launch(settings["threads"], settings["tail_budget"], settings["interleave"])
+    sym.set_spread(settings.get("spread", 0))
     sym.set_mapping(np.asarray(settings["mapping"], np.int32))

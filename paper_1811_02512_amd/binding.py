@@ -38,7 +38,8 @@ class pf_info(C.Structure):
                 ("tail_nodes", C.c_int32), ("tail_lds_bytes", C.c_int32),
                 ("threads", C.c_int32), ("tail_clique", C.c_int32),
                 ("ws_interleave", C.c_int32), ("lu_offset", C.c_int64),
-                ("fd_mat_doubles", C.c_int64), ("fd_ws_doubles", C.c_int64)]
+                ("fd_mat_doubles", C.c_int64), ("fd_ws_doubles", C.c_int64),
+                ("spread", C.c_int32)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -70,6 +71,7 @@ _SIGS = {
     "pf_symbolic_set_mapping": ([_vp, _vp], _i),
     "pf_symbolic_get_mapping": ([_vp, _vp], _i),
     "pf_symbolic_set_launch": ([_vp, _i, _i64, _i], _i),
+    "pf_symbolic_set_spread": ([_vp, _i], _i),
     "pf_newton_interleave": ([_vp, _i], _i),
     "pf_symbolic_upload": ([_vp, _vp, C.c_size_t, _vp], _i),
     "pf_symbolic_destroy": ([_vp], None),
@@ -192,6 +194,10 @@ def pf_symbolic_set_mapping(h, lanes):
 def pf_symbolic_set_launch(h, threads=0, tail_lds_budget=65536, interleave=4):
     check(lib.pf_symbolic_set_launch(h, int(threads), int(tail_lds_budget), int(interleave)),
           "pf_symbolic_set_launch")
+
+
+def pf_symbolic_set_spread(h, workgroups):
+    check(lib.pf_symbolic_set_spread(h, int(workgroups)), "pf_symbolic_set_spread")
 
 
 def pf_newton_interleave(h, B):

@@ -143,6 +143,7 @@ int pf_symbolic_info(const pf_symbolic s, pf_info* info)
     info->tail_clique = h.tail_clique;
     info->ws_interleave = h.interleave;
     info->threads = h.threads;
+    info->spread = h.spread > 1 ? h.spread : 0;
     return PF_OK;
 }
 
@@ -203,6 +204,15 @@ int pf_symbolic_set_launch(pf_symbolic s, int threads, int64_t tail_lds_budget, 
         pf::build_tail(s->h, tail_lds_budget);
         s->h.uploaded = false;  // device copy is stale: upload again
     }
+    return PF_OK;
+}
+
+int pf_symbolic_set_spread(pf_symbolic s, int workgroups)
+{
+    if (!s) return fail(PF_E_INVALID, "pf_symbolic_set_spread: NULL symbolic");
+    if (workgroups < 0 || workgroups > 1024)
+        return fail(PF_E_INVALID, "pf_symbolic_set_spread: workgroups must be 0..1024");
+    s->h.spread = workgroups;
     return PF_OK;
 }
 

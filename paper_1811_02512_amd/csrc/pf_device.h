@@ -510,13 +510,91 @@ __device__ __forceinline__ NodeRec load_rec(const DevSym& S, int x)
     return {S.node_info[3 * x], S.node_info[3 * x + 1]};
 }
 
+// How one case's work is split over the workgroups of a launch.
+// OneGroup: the whole case in one workgroup, levels separated by workgroup
+// barriers.
+struct OneGroup {
+    static constexpr bool kSpread = false;
+    __device__ __forceinline__ int rank() const { return 0; }
+    __device__ __forceinline__ int size() const { return 1; }
+    __device__ __forceinline__ void sync() const { __syncthreads(); }
+};
+
+// Spread: the case's wide phases (loops over buses, the levels below the LDS
+// tail) over every workgroup of a cooperative launch, which meet at grid
+// barriers; the tail stays on workgroup 0 while the others wait.  The
+// barrier words live in three 128-byte lines of the case's workspace,
+// zeroed (the pivot marker set to kNoPivot) before the launch:
+//   line 0: arrivals (count of workgroups that reached a barrier, over all
+//           barriers so far); line 1: release (number of the last barrier
+//           every workgroup has reached); line 2: abort flag, zero-pivot
+//           marker, then per parity of the iteration count a NaN flag and
+//           the bits of the mismatch maximum (a non-negative double, whose
+//           bit patterns order as unsigned integers do).
+// A workgroup makes its writes visible before it arrives and discards stale
+// cached lines after it is released (agent-scope fences), so what any
+// workgroup wrote before a barrier is what every workgroup reads after it.
+// A wait that lasts longer than kSpreadWaitTicks of the constant 100 MHz
+// clock sets the abort flag; from then on no barrier waits, so every
+// workgroup runs to its end and the case reports the failure.
+constexpr unsigned long long kSpreadWaitTicks = 100000000ull;  // one second
+constexpr int kSpreadWords = 96;  // 32-bit words of the three lines
+
+struct Spread {
+    static constexpr bool kSpread = true;
+    unsigned* arrive;
+    unsigned* release;
+    int* flags;        // abort, pivot marker, NaN flag [2]
+    uint64_t* maxbits; // [2]
+    unsigned* count;   // LDS: barriers this workgroup has passed
+    __device__ __forceinline__ int rank() const { return blockIdx.x; }
+    __device__ __forceinline__ int size() const { return gridDim.x; }
+    __device__ __forceinline__ int* marker() const { return flags + 1; }
+    __device__ __forceinline__ bool aborted() const
+    {
+        return __hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    }
+    __device__ void sync() const
+    {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned k = ++*count;
+            __threadfence();
+            const unsigned before =
+                __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (!aborted()) {
+                if (before == k * gridDim.x - 1) {
+                    __hip_atomic_store(release, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                } else {
+                    const unsigned long long t0 = wall_clock64();
+                    while (__hip_atomic_load(release, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT) < k) {
+                        if (aborted()) break;
+                        if (wall_clock64() - t0 > kSpreadWaitTicks) {
+                            __hip_atomic_store(flags, 1, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                }
+            }
+            __threadfence();
+        }
+        __syncthreads();
+    }
+};
+
 // Runs fn(x, rec, lane, g) for the nodes of levels [l0, l1), up or down,
-// with a workgroup barrier after every level: x indexes the level-ordered
+// with a barrier of the split after every level: x indexes the level-ordered
 // node records, rec is x's record, and each node gets g lanes (the level's
-// mapping).  The record of the group's next node in the level is fetched
-// before fn runs so that its latency overlaps the current node's work.
-template <class F>
-__device__ __forceinline__ void for_nodes(const DevSym& S, int l0, int l1, bool up, F&& fn)
+// mapping); the groups of g lanes of all the split's workgroups take the
+// level's nodes in turn.  The record of the group's next node in the level
+// is fetched before fn runs so that its latency overlaps the current node's
+// work.
+template <class P, class F>
+__device__ __forceinline__ void for_nodes(const P& par, const DevSym& S, int l0, int l1, bool up,
+                                          F&& fn)
 {
     for (int li = l0; li < l1; ++li) {
         const int l = up ? li : l1 - 1 - (li - l0);
@@ -524,19 +602,25 @@ __device__ __forceinline__ void for_nodes(const DevSym& S, int l0, int l1, bool 
         const int beg = S.level_ptr[l];
         const int cnt = S.level_ptr[l + 1] - beg;
         const int gpb = blockDim.x / g;
-        const int grp = threadIdx.x / g;
+        const int step = gpb * par.size();
         const int lane = threadIdx.x & (g - 1);
-        int idx = grp;
+        int idx = par.rank() * gpb + threadIdx.x / g;
         NodeRec cur = idx < cnt ? load_rec(S, beg + idx) : NodeRec{};
         while (idx < cnt) {
-            const int nxt = idx + gpb;
+            const int nxt = idx + step;
             const NodeRec pre = nxt < cnt ? load_rec(S, beg + nxt) : NodeRec{};
             fn(beg + idx, cur, lane, g);
             cur = pre;
             idx = nxt;
         }
-        __syncthreads();
+        par.sync();
     }
+}
+
+template <class F>
+__device__ __forceinline__ void for_nodes(const DevSym& S, int l0, int l1, bool up, F&& fn)
+{
+    for_nodes(OneGroup{}, S, l0, l1, up, static_cast<F&&>(fn));
 }
 
 // Runs fn(jl, lane, g) over tail levels [t0, t1) (tail-local numbering).
@@ -1454,15 +1538,16 @@ struct CaseDesc {
 // order, NB per thread per step (blockDim apart), so that the admittance
 // rows, row pointers, positions and scheduled injections of a wavefront are
 // adjacent in memory; all loads of a step's buses are issued before any of
-// them is summed.
+// them is summed.  The buses are first, first + stride, ... (the thread's
+// index and count over the workgroups that share the case).
 template <bool SCALE, class EF, int NB = 2>
 __device__ __forceinline__ void mismatch_pass(const DevSym& S, const double* yv, const EF& ef,
                                               const View& wb, const Off& o, const PvMask& pvm,
                                               const double* Psp, const double* Qsp, double& mx,
-                                              int& nan)
+                                              int& nan, int first, int stride)
 {
-    const int bd = blockDim.x;
-    for (int i0 = threadIdx.x; i0 < S.n; i0 += NB * bd) {
+    const int bd = stride;
+    for (int i0 = first; i0 < S.n; i0 += NB * bd) {
         int ib[NB], pc[NB], q0[NB], q1[NB];
         bool has[NB], pv[NB];
         double sp[NB], sq[NB];
@@ -1511,6 +1596,16 @@ __device__ __forceinline__ void mismatch_pass(const DevSym& S, const double* yv,
             }
         }
     }
+}
+
+template <bool SCALE, class EF, int NB = 2>
+__device__ __forceinline__ void mismatch_pass(const DevSym& S, const double* yv, const EF& ef,
+                                              const View& wb, const Off& o, const PvMask& pvm,
+                                              const double* Psp, const double* Qsp, double& mx,
+                                              int& nan)
+{
+    mismatch_pass<SCALE, EF, NB>(S, yv, ef, wb, o, pvm, Psp, Qsp, mx, nan, (int)threadIdx.x,
+                                 (int)blockDim.x);
 }
 
 }  // namespace

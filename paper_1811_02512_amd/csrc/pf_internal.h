@@ -114,6 +114,9 @@ struct HostSym {
     int32_t max_width = 0;
     int32_t threads = 0;  // 0: chosen per launch from the batch size
     int32_t interleave = 4;  // cases per interleaved workspace group
+    // workgroups a one-case Newton launch spreads its wide phases over (the
+    // bus loops and the levels below the LDS tail); 0 or 1: one workgroup
+    int32_t spread = 0;
     // device copy
     DevSym dev{};
     bool uploaded = false;
@@ -133,11 +136,12 @@ struct HostSym {
         int64_t w = 8 * (int64_t)n + 2 * (int64_t)nn;  // bus records | rhs
         return (w + 31) & ~(int64_t)31;
     }
-    int64_t ws_doubles() const {
-        // vals | bus records (8 n) | rhs (2 nn)
-        int64_t w = vals_doubles() + 8 * (int64_t)n + 2 * (int64_t)nn;
-        return (w + 31) & ~(int64_t)31;
+    // vals | bus records (8 n) | rhs (2 nn) | grid-barrier words of a one-case
+    // launch spread over several workgroups (three 128-byte lines)
+    int64_t sync_off() const {
+        return (vals_doubles() + 8 * (int64_t)n + 2 * (int64_t)nn + 15) & ~(int64_t)15;
     }
+    int64_t ws_doubles() const { return (sync_off() + 48 + 31) & ~(int64_t)31; }
     size_t dev_bytes() const;
 };
 

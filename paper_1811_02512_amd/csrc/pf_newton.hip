@@ -19,35 +19,58 @@ using namespace pf::abi;
 
 namespace {
 
-// The whole Newton-Raphson loop of one case, run by one workgroup.  The
-// case's voltages and injections are copied into its bus records first and
-// the solution copied back at the end.
-__device__ __forceinline__ void newton_case(const DevSym& S, const double* yv, const int8_t* type,
-                            const double* Psp, const double* Qsp, double* Vm, double* Va,
-                            const View& w, const View& wb, double tol, int max_iter,
-                            int flags, int32_t* o_iters, double* o_norm, int32_t* o_status,
-                            int32_t* o_pivot)
+// The whole Newton-Raphson loop of one case, run by one workgroup (OneGroup)
+// or by every workgroup of a cooperative launch (Spread: the loops over
+// buses and the levels below the LDS tail are shared out, the tail runs on
+// workgroup 0).  The case's voltages and injections are copied into its bus
+// records first and the solution copied back at the end.
+template <class P>
+__device__ __forceinline__ void newton_case(const P& par, const DevSym& S, const double* yv,
+                                            const int8_t* type, const double* Psp,
+                                            const double* Qsp, double* Vm, double* Va,
+                                            const View& w, const View& wb, double tol,
+                                            int max_iter, int flags, int32_t* o_iters,
+                                            double* o_norm, int32_t* o_status, int32_t* o_pivot)
 {
     __shared__ int s_bad;
+    constexpr bool kOne = !P::kSpread;
+    int* bad = &s_bad;
+    if constexpr (P::kSpread) bad = par.marker();
+    const bool lead = par.rank() == 0;
+    // this thread's first bus and the stride of the loops over buses
+    auto t0 = [&]() { return par.rank() * (int)blockDim.x + (int)threadIdx.x; };
+    auto ts = [&]() { return par.size() * (int)blockDim.x; };
     const Off o = ws_off(S);
-    for (int i = threadIdx.x; i < S.n; i += blockDim.x) {
+    for (int i = t0(); i < S.n; i += ts()) {
         double sn, cs;
         const double vm = Vm[i], va = Va[i];
         sincos(va, &sn, &cs);
         wb.put(o.BUS + 8 * (int64_t)i, {vm * cs, vm * sn, vm, va});
     }
     pv_fill(S, type);
-    if (threadIdx.x == 0) s_bad = kNoPivot;
-    __syncthreads();
+    if (kOne && threadIdx.x == 0) s_bad = kNoPivot;
+    par.sync();
+    auto marker = [&]() {
+        if constexpr (P::kSpread)
+            return __hip_atomic_load(bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            return s_bad;
+    };
+    // the tail's results are read by the other workgroups of a spread launch
+    // only after a grid barrier (one workgroup's own barriers order them)
+    auto tail_done = [&]() {
+        if constexpr (P::kSpread) par.sync();
+    };
     const PvMask pvm{pv_words(S)};
-    // the global levels of the factorisation sweep read neighbours' (e, f)
-    // from the LDS copy the mismatch pass just made (the tail reuses that LDS
-    // afterwards and reads them from the bus records)
+    // one workgroup: the global levels of the factorisation sweep read
+    // neighbours' (e, f) from the LDS copy the mismatch pass just made (the
+    // tail reuses that LDS afterwards and reads them from the bus records),
+    // and the backward sweep keeps x in that LDS too (free again once the
+    // tail's backward substitution has read its values)
+    const bool efl = kOne && S.ef_lds;
     const SrcState src{yv, pvm, wb, o.BUS,
-                       S.ef_lds ? reinterpret_cast<const double2*>(pf_smem) : nullptr};
-    // the backward sweep keeps x in that LDS too (free again once the tail's
-    // backward substitution has read its values)
-    double2* const xs = (S.ef_lds && S.tail_nodes <= 4 * (int)blockDim.x)
+                       efl ? reinterpret_cast<const double2*>(pf_smem) : nullptr};
+    double2* const xs = (efl && S.tail_nodes <= 4 * (int)blockDim.x)
                             ? reinterpret_cast<double2*>(pf_smem)
                             : nullptr;
     const EFView ef{wb, o.BUS};
@@ -57,19 +80,44 @@ __device__ __forceinline__ void newton_case(const DevSym& S, const double* yv, c
     for (;;) {
         double mx = 0.0;
         int nan = 0;
-        if (S.ef_lds) {
+        if (efl) {
             // every bus's (e, f) into LDS (free until the tail), so that the
             // admittance rows' voltages are LDS reads
-            const EFLds efl{reinterpret_cast<double2*>(pf_smem)};
+            const EFLds el{reinterpret_cast<double2*>(pf_smem)};
             for (int i = threadIdx.x; i < S.n; i += blockDim.x)
-                efl.s[i] = wb.v2(o.BUS + 8 * (int64_t)i);
+                el.s[i] = wb.v2(o.BUS + 8 * (int64_t)i);
             __syncthreads();
-            mismatch_pass<false, EFLds, 4>(S, yv, efl, wb, o, pvm, Psp, Qsp, mx, nan);
+            mismatch_pass<false, EFLds, 4>(S, yv, el, wb, o, pvm, Psp, Qsp, mx, nan);
         } else {
-            mismatch_pass<false>(S, yv, ef, wb, o, pvm, Psp, Qsp, mx, nan);
+            mismatch_pass<false>(S, yv, ef, wb, o, pvm, Psp, Qsp, mx, nan, t0(), ts());
         }
         int any_nan = 0;
         nrm = block_max(mx, nan, any_nan);
+        if constexpr (P::kSpread) {
+            // every workgroup's maximum and NaN flag into this iteration's
+            // slots; after the barrier all read the same norm
+            const int sl = it & 1;
+            if (threadIdx.x == 0) {
+                if (any_nan)
+                    __hip_atomic_fetch_or(par.flags + 2 + sl, 1, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_max(par.maxbits + sl, (uint64_t)__double_as_longlong(nrm),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            par.sync();
+            any_nan = __hip_atomic_load(par.flags + 2 + sl, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+            nrm = __longlong_as_double((long long)__hip_atomic_load(
+                par.maxbits + sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            // the other slots were last read before the previous iteration's
+            // later barriers: clear them for the next iteration
+            if (lead && threadIdx.x == 0) {
+                __hip_atomic_store(par.flags + 3 - sl, 0, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(par.maxbits + 1 - sl, (uint64_t)0, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
         if (any_nan || !isfinite(nrm)) {
             st = ST_NONFINITE;
             break;
@@ -82,37 +130,50 @@ __device__ __forceinline__ void newton_case(const DevSym& S, const double* yv, c
             st = ST_NOT_CONVERGED;
             break;
         }
-        for_nodes(S, 0, S.tail_level, true, [&](int x, const NodeRec& r, int lane, int g) {
-            factor_node<SrcState, true, false>(S, src, x, r, lane, g, w, o.LU, wb, o.RHS, &s_bad);
+        for_nodes(par, S, 0, S.tail_level, true, [&](int x, const NodeRec& r, int lane, int g) {
+            factor_node<SrcState, true, false>(S, src, x, r, lane, g, w, o.LU, wb, o.RHS, bad);
         });
-        if (tail) tail_factor<SrcState, true, false>(S, src, w, o.LU, wb, o.RHS, &s_bad);
-        if (s_bad != kNoPivot) {
+        if (tail) {
+            if (lead) tail_factor<SrcState, true, false>(S, src, w, o.LU, wb, o.RHS, bad);
+            tail_done();
+        }
+        if (marker() != kNoPivot) {
             st = ST_ZERO_PIVOT;
             break;
         }
-        if (tail) tail_backward<true>(S, wb, o.RHS, o.BUS, pvm, xs);
-        for_nodes(S, 0, S.tail_level, false, [&](int, const NodeRec& r, int lane, int g) {
+        if (tail) {
+            if (lead) tail_backward<true>(S, wb, o.RHS, o.BUS, pvm, xs);
+            tail_done();
+        }
+        for_nodes(par, S, 0, S.tail_level, false, [&](int, const NodeRec& r, int lane, int g) {
             back_node<true>(S, r, lane, g, w, o.LU, wb, o.RHS, o.BUS, pvm, xs);
         });
         ++it;
     }
     if ((flags & PF_NEWTON_KEEP_FACTORS) && st == ST_OK) {
-        for_nodes(S, 0, S.tail_level, true, [&](int x, const NodeRec& r, int lane, int g) {
-            factor_node<SrcState, false, true>(S, src, x, r, lane, g, w, o.LU, wb, o.RHS, &s_bad);
+        for_nodes(par, S, 0, S.tail_level, true, [&](int x, const NodeRec& r, int lane, int g) {
+            factor_node<SrcState, false, true>(S, src, x, r, lane, g, w, o.LU, wb, o.RHS, bad);
         });
-        if (tail) tail_factor<SrcState, false, true>(S, src, w, o.LU, wb, o.RHS, &s_bad);
-        if (s_bad != kNoPivot) st = ST_ZERO_PIVOT;
+        if (tail) {
+            if (lead) tail_factor<SrcState, false, true>(S, src, w, o.LU, wb, o.RHS, bad);
+            tail_done();
+        }
+        if (marker() != kNoPivot) st = ST_ZERO_PIVOT;
     }
-    for (int i = threadIdx.x; i < S.n; i += blockDim.x) {
+    for (int i = t0(); i < S.n; i += ts()) {
         const Blk r = wb.blk(o.BUS + 8 * (int64_t)i);
         Vm[i] = r.c;
         Va[i] = r.d;
     }
-    if (threadIdx.x == 0) {
+    if (lead && threadIdx.x == 0) {
+        const int bad_at = marker();
+        if constexpr (P::kSpread) {
+            if (par.aborted()) st = PF_E_HIP;
+        }
         if (o_iters) *o_iters = it;
         if (o_norm) *o_norm = nrm;
         if (o_status) *o_status = st;
-        if (o_pivot) *o_pivot = s_bad == kNoPivot ? -1 : S.level_nodes[s_bad];
+        if (o_pivot) *o_pivot = bad_at == kNoPivot ? -1 : S.level_nodes[bad_at];
     }
 }
 
@@ -727,7 +788,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_newton(DevSym Sarg,
         const DevSym S = cd.sym;
         const View w = case_view(a.ws + cd.ws_off, 0, 1, 0);
         const View wb = case_bus_view(a.ws + cd.ws_off, 0, 1, 0, S.vals_doubles);
-        newton_case(S, a.yval + cd.y_off, a.type + cd.bus_off, a.Psp + cd.bus_off,
+        newton_case(OneGroup{}, S, a.yval + cd.y_off, a.type + cd.bus_off, a.Psp + cd.bus_off,
                     a.Qsp + cd.bus_off, a.Vm + cd.bus_off, a.Va + cd.bus_off, w, wb, a.tol,
                     a.max_iter, a.flags, a.iters ? a.iters + c : nullptr,
                     a.norm ? a.norm + c : nullptr, a.status ? a.status + c : nullptr,
@@ -737,12 +798,36 @@ __global__ __launch_bounds__(kLevelThreads) void k_newton(DevSym Sarg,
         if (c < 0) return;
         const View w = case_view(a.ws, a.ws_stride, a.interleave, c);
         const View wb = case_bus_view(a.ws, a.ws_stride, a.interleave, c, Sarg.vals_doubles);
-        newton_case(Sarg, a.yval + c * a.y_stride, a.type + c * a.type_stride,
+        newton_case(OneGroup{}, Sarg, a.yval + c * a.y_stride, a.type + c * a.type_stride,
                     a.Psp + c * a.inj_stride, a.Qsp + c * a.inj_stride, a.Vm + c * a.v_stride,
                     a.Va + c * a.v_stride, w, wb, a.tol, a.max_iter, a.flags,
                     a.iters ? a.iters + c : nullptr, a.norm ? a.norm + c : nullptr,
                     a.status ? a.status + c : nullptr, a.pivot ? a.pivot + c : nullptr);
     }
+}
+
+// One case over every workgroup of a cooperative launch; sync: the case's
+// grid-barrier words (three 128-byte lines, see Spread).
+__global__ __launch_bounds__(kLevelThreads) void k_newton_spread(DevSym S, NewtonArgs a,
+                                                               unsigned* sync)
+{
+    __shared__ unsigned s_count;
+    if (threadIdx.x == 0) s_count = 0;
+    const Spread par{sync, sync + 32, reinterpret_cast<int*>(sync + 64),
+                     reinterpret_cast<uint64_t*>(sync + 68), &s_count};
+    const View w = case_view(a.ws, a.ws_stride, 1, 0);
+    const View wb = case_bus_view(a.ws, a.ws_stride, 1, 0, S.vals_doubles);
+    newton_case(par, S, a.yval, a.type, a.Psp, a.Qsp, a.Vm, a.Va, w, wb, a.tol, a.max_iter,
+                a.flags, a.iters, a.norm, a.status, a.pivot);
+}
+
+// Clears the grid-barrier words before a spread launch (a kernel, not a
+// memset, so that the pair can be recorded into a graph); the pivot marker
+// starts at kNoPivot.
+__global__ void k_spread_init(unsigned* sync)
+{
+    const int i = threadIdx.x;
+    if (i < kSpreadWords) sync[i] = i == 65 ? (unsigned)kNoPivot : 0u;
 }
 
 __global__ void k_adj_rhs(DevSym S, const double* gVm, const double* gVa, int64_t v_stride,
@@ -914,6 +999,7 @@ void allow_big_lds()
     const void* kernels[] = {reinterpret_cast<const void*>(&k_adjoint<true>),
                              reinterpret_cast<const void*>(&k_newton<false>),
                              reinterpret_cast<const void*>(&k_newton<true>),
+                             reinterpret_cast<const void*>(&k_newton_spread),
                              reinterpret_cast<const void*>(&k_factor<false>),
                              reinterpret_cast<const void*>(&k_factor<true>),
                              reinterpret_cast<const void*>(&k_solve<false, true>),
@@ -927,6 +1013,51 @@ void allow_big_lds()
         }
     }
     (void)hipGetLastError();
+}
+
+// Workgroups of a one-case Newton launch spread over the device: the
+// symbolic's setting, capped by the workgroups the device keeps resident at
+// once (a cooperative launch needs every one of them at the same time); 0
+// selects the one-workgroup kernel, which also serves batches and every
+// launch recorded into a graph.
+int spread_blocks(const HostSym& h, int B, int threads, int lds, hipStream_t st)
+{
+    if (B != 1 || h.spread <= 1) return 0;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    int dev = 0, cus = 0, per = 0;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_newton_spread, threads, lds) !=
+            hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    const int G = std::min(h.spread, per * cus);
+    return G > 1 ? G : 0;
+}
+
+// The Newton launch of pf_newton and pf_newton_noalloc (arguments checked).
+int newton_launch(const HostSym& h, int B, int C, NewtonArgs a, hipStream_t st, const char* fn)
+{
+    allow_big_lds();
+    const int threads = launch_threads(h, B);
+    const int lds = newton_lds(h);
+    const int G = spread_blocks(h, B, threads, lds, st);
+    if (G > 1) {
+        unsigned* sync = reinterpret_cast<unsigned*>(a.ws + h.sync_off());
+        hipLaunchKernelGGL(k_spread_init, dim3(1), dim3(128), 0, st, sync);
+        if (const int e = launch_check(fn)) return e;
+        DevSym S = h.dev;
+        void* args[] = {&S, &a, &sync};
+        return hip_check(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_newton_spread),
+                                                    dim3(G), dim3(threads), args,
+                                                    (unsigned)lds, st),
+                         fn);
+    }
+    hipLaunchKernelGGL(k_newton<false>, dim3(grid_blocks(B, C)), dim3(threads), lds, st, h.dev,
+                       (const CaseDesc*)nullptr, (const int32_t*)nullptr, a);
+    return launch_check(fn);
 }
 
 }  // namespace
@@ -1130,11 +1261,7 @@ int pf_newton_noalloc(const pf_symbolic s, int B, const double* d_yval, int64_t 
     NewtonArgs a{d_yval, y_stride, d_type, type_stride, d_Psp, d_Qsp, inj_stride, d_Vm, d_Va,
                  v_stride, ws, ws_stride, tol, max_iter, 0, C, B, d_iters, d_norm, d_status,
                  d_pivot};
-    allow_big_lds();
-    hipLaunchKernelGGL(k_newton<false>, dim3(grid_blocks(B, C)), dim3(launch_threads(s->h, B)),
-                       newton_lds(s->h), as_stream(stream), s->h.dev, (const CaseDesc*)nullptr,
-                       (const int32_t*)nullptr, a);
-    return launch_check("pf_newton_noalloc");
+    return newton_launch(s->h, B, C, a, as_stream(stream), "pf_newton_noalloc");
 }
 
 int pf_newton(const pf_symbolic s, int B, const double* d_yval, int64_t y_stride,
@@ -1162,11 +1289,7 @@ int pf_newton(const pf_symbolic s, int B, const double* d_yval, int64_t y_stride
     NewtonArgs a{d_yval, y_stride, d_type, type_stride, d_Psp, d_Qsp, inj_stride, d_Vm, d_Va,
                  v_stride, d_ws, ws_stride, tol, max_iter, flags, C, B, d_iters, d_norm,
                  d_status, d_pivot};
-    allow_big_lds();
-    hipLaunchKernelGGL(k_newton<false>, dim3(grid_blocks(B, C)), dim3(launch_threads(s->h, B)),
-                       newton_lds(s->h), as_stream(stream), s->h.dev, (const CaseDesc*)nullptr,
-                       (const int32_t*)nullptr, a);
-    return launch_check("pf_newton");
+    return newton_launch(s->h, B, C, a, as_stream(stream), "pf_newton");
 }
 
 int pf_adjoint_params(const pf_symbolic s, int B, const double* d_lam, int64_t lam_stride,

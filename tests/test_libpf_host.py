@@ -212,3 +212,24 @@ def test_set_launch_checks_every_argument_before_changing_any(B):
     B.pf_symbolic_set_launch(h, 256, 65536, 2)
     assert B.pf_symbolic_info(h).ws_interleave == 2
     B.pf_symbolic_destroy(h)
+
+
+def test_spread_setting_is_checked_and_reported(B):
+    """The workgroups of a one-case launch: 0..1024, 0 and 1 both meaning one
+    workgroup; the workspace holds the grid-barrier words after the rhs."""
+    g = gridgen.make_grid(80, 3)
+    h = B.pf_analyze(g.n, g.f, g.t)
+    assert B.pf_symbolic_info(h).spread == 0
+    for bad in (-1, 1025):
+        with pytest.raises(B.PfError) as ei:
+            B.pf_symbolic_set_spread(h, bad)
+        assert ei.value.code == B.PF_E_INVALID
+    B.pf_symbolic_set_spread(h, 32)
+    assert B.pf_symbolic_info(h).spread == 32
+    B.pf_symbolic_set_spread(h, 1)
+    assert B.pf_symbolic_info(h).spread == 0
+    i = B.pf_symbolic_info(h)
+    rhs_end = i.vals_doubles + 8 * i.n + 2 * i.nn
+    sync = (rhs_end + 15) // 16 * 16  # three 128-byte lines on a 128-byte boundary
+    assert i.ws_doubles % 32 == 0 and i.ws_doubles >= sync + 48
+    B.pf_symbolic_destroy(h)
