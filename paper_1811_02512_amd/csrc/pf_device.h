@@ -547,6 +547,10 @@ struct Spread {
     int* flags;        // abort, pivot marker, NaN flag [2]
     uint64_t* maxbits; // [2]
     unsigned* count;   // LDS: barriers this workgroup has passed
+    // levels [back_lo, tail level) of the backward substitution run on
+    // workgroup 0 right after the tail's (narrow levels: workgroup barriers
+    // are cheaper there than grid barriers)
+    int back_lo;
     __device__ __forceinline__ int rank() const { return blockIdx.x; }
     __device__ __forceinline__ int size() const { return gridDim.x; }
     __device__ __forceinline__ int* marker() const { return flags + 1; }
@@ -589,9 +593,10 @@ struct Spread {
 // with a barrier of the split after every level: x indexes the level-ordered
 // node records, rec is x's record, and each node gets g lanes (the level's
 // mapping); the groups of g lanes of all the split's workgroups take the
-// level's nodes in turn.  The record of the group's next node in the level
-// is fetched before fn runs so that its latency overlaps the current node's
-// work.
+// level's nodes in turn, group k of every workgroup before group k + 1 of
+// any, so that a narrow level still reaches every workgroup.  The record of
+// the group's next node in the level is fetched before fn runs so that its
+// latency overlaps the current node's work.
 template <class P, class F>
 __device__ __forceinline__ void for_nodes(const P& par, const DevSym& S, int l0, int l1, bool up,
                                           F&& fn)
@@ -604,7 +609,7 @@ __device__ __forceinline__ void for_nodes(const P& par, const DevSym& S, int l0,
         const int gpb = blockDim.x / g;
         const int step = gpb * par.size();
         const int lane = threadIdx.x & (g - 1);
-        int idx = par.rank() * gpb + threadIdx.x / g;
+        int idx = (int)(threadIdx.x / g) * par.size() + par.rank();
         NodeRec cur = idx < cnt ? load_rec(S, beg + idx) : NodeRec{};
         while (idx < cnt) {
             const int nxt = idx + step;
@@ -1003,16 +1008,23 @@ __device__ __forceinline__ int clique_slot(int c0, int KC, int a, int b)
 //   pivot; row a is normalised (U_al = D_a^-1 V_al) during pivot a + 1,
 //   when nobody reads it any more.
 // WRITE stores the tail's factors to global memory.
-template <class SRC, bool FWD, bool WRITE>
+// With a Spread split, every workgroup of the launch takes a share of phase
+// A and leaves its results in the tail's own places in global memory (the
+// D blocks, rhs entries and slot records of the tail nodes, which nothing
+// else reads until the tail writes them); after a grid barrier workgroup 0
+// loads them into LDS and runs the rest, and the other workgroups return.
+template <class SRC, bool FWD, bool WRITE, class P = OneGroup>
 __device__ void tail_factor(const DevSym& S, const SRC& src, const View& w, int64_t lu,
-                            const View& wr, int64_t rhs, int* s_bad)
+                            const View& wr, int64_t rhs, int* s_bad, const P& par = P{})
 {
     const int K = S.tail_nodes, TS = S.tail_slots, KC = S.tail_clique;
     const int nT = S.nlev - S.tail_level;
     double* sLU = pf_smem;             // TS x 8: W, then V -> U
     double* sD = pf_smem + 8 * TS;     // K x 4: accumulated pivot, then D^-1
     double* sy = sD + 4 * K;           // K x 2: accumulated rhs, then y
-    for (int it = threadIdx.x; it < K + TS; it += blockDim.x) {
+    const int a0 = P::kSpread ? par.rank() * (int)blockDim.x + (int)threadIdx.x : threadIdx.x;
+    const int as = P::kSpread ? par.size() * (int)blockDim.x : blockDim.x;
+    for (int it = a0; it < K + TS; it += as) {
         if (it < K) {
             const int4 t0 = S.t_node[3 * it];
             const int4 t1 = S.t_node[3 * it + 1];
@@ -1063,9 +1075,14 @@ __device__ void tail_factor(const DevSym& S, const SRC& src, const View& w, int6
                     for (int k = 0; k < 4; ++k) e[k] = nx[k];
                 }
             }
-            bstore(sD + 4 * it, acc);
-            sy[2 * it] = z0;
-            sy[2 * it + 1] = z1;
+            if constexpr (P::kSpread) {
+                w.put(4 * (int64_t)t0.x, acc);
+                if (FWD) wr.put2(rhs + 2 * (int64_t)t0.x, make_double2(z0, z1));
+            } else {
+                bstore(sD + 4 * it, acc);
+                sy[2 * it] = z0;
+                sy[2 * it + 1] = z1;
+            }
         } else {
             const int t = it - K;
             const int4 a = S.t_slot[3 * t];
@@ -1074,8 +1091,31 @@ __device__ void tail_factor(const DevSym& S, const SRC& src, const View& w, int6
             Blk Wk, Vk;
             src.off(a.x, c.x, a.z, a.w, b.x, Wk, Vk);
             apply_updates(S.t_upd, b.y, b.z, w, lu, Wk, Vk);
-            bstore(sLU + 8 * t, Wk);
-            bstore(sLU + 8 * t + 4, Vk);
+            if constexpr (P::kSpread) {
+                w.put(lu + 8 * (int64_t)a.x, Wk);
+                w.put(lu + 8 * (int64_t)a.x + 4, Vk);
+            } else {
+                bstore(sLU + 8 * t, Wk);
+                bstore(sLU + 8 * t + 4, Vk);
+            }
+        }
+    }
+    if constexpr (P::kSpread) {
+        par.sync();
+        if (par.rank() != 0) return;
+        for (int it = threadIdx.x; it < K + TS; it += blockDim.x) {
+            if (it < K) {
+                const int j = S.t_node[3 * it].x;
+                bstore(sD + 4 * it, w.blk(4 * (int64_t)j));
+                const double2 z = FWD ? wr.v2(rhs + 2 * (int64_t)j) : make_double2(0.0, 0.0);
+                sy[2 * it] = z.x;
+                sy[2 * it + 1] = z.y;
+            } else {
+                const int t = it - K;
+                const int64_t sg = lu + 8 * (int64_t)S.t_slot[3 * t].x;
+                bstore(sLU + 8 * t, w.blk(sg));
+                bstore(sLU + 8 * t + 4, w.blk(sg + 4));
+            }
         }
     }
     __syncthreads();

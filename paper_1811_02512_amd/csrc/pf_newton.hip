@@ -57,7 +57,9 @@ __device__ __forceinline__ void newton_case(const P& par, const DevSym& S, const
             return s_bad;
     };
     // the tail's results are read by the other workgroups of a spread launch
-    // only after a grid barrier (one workgroup's own barriers order them)
+    // only after a grid barrier (one workgroup's own barriers order them);
+    // the tail's factorisation is entered by every workgroup (they share its
+    // first pass), its backward substitution by workgroup 0 alone
     auto tail_done = [&]() {
         if constexpr (P::kSpread) par.sync();
     };
@@ -134,20 +136,26 @@ __device__ __forceinline__ void newton_case(const P& par, const DevSym& S, const
             factor_node<SrcState, true, false>(S, src, x, r, lane, g, w, o.LU, wb, o.RHS, bad);
         });
         if (tail) {
-            if (lead) tail_factor<SrcState, true, false>(S, src, w, o.LU, wb, o.RHS, bad);
+            tail_factor<SrcState, true, false>(S, src, w, o.LU, wb, o.RHS, bad, par);
             tail_done();
         }
         if (marker() != kNoPivot) {
             st = ST_ZERO_PIVOT;
             break;
         }
-        if (tail) {
-            if (lead) tail_backward<true>(S, wb, o.RHS, o.BUS, pvm, xs);
+        auto back = [&](int, const NodeRec& r, int lane, int g) {
+            back_node<true>(S, r, lane, g, w, o.LU, wb, o.RHS, o.BUS, pvm, xs);
+        };
+        int lw = S.tail_level;
+        if constexpr (P::kSpread) lw = par.back_lo;
+        if (tail || lw < S.tail_level) {
+            if (lead) {
+                if (tail) tail_backward<true>(S, wb, o.RHS, o.BUS, pvm, xs);
+                if constexpr (P::kSpread) for_nodes(OneGroup{}, S, lw, S.tail_level, false, back);
+            }
             tail_done();
         }
-        for_nodes(par, S, 0, S.tail_level, false, [&](int, const NodeRec& r, int lane, int g) {
-            back_node<true>(S, r, lane, g, w, o.LU, wb, o.RHS, o.BUS, pvm, xs);
-        });
+        for_nodes(par, S, 0, lw, false, back);
         ++it;
     }
     if ((flags & PF_NEWTON_KEEP_FACTORS) && st == ST_OK) {
@@ -155,7 +163,7 @@ __device__ __forceinline__ void newton_case(const P& par, const DevSym& S, const
             factor_node<SrcState, false, true>(S, src, x, r, lane, g, w, o.LU, wb, o.RHS, bad);
         });
         if (tail) {
-            if (lead) tail_factor<SrcState, false, true>(S, src, w, o.LU, wb, o.RHS, bad);
+            tail_factor<SrcState, false, true>(S, src, w, o.LU, wb, o.RHS, bad, par);
             tail_done();
         }
         if (marker() != kNoPivot) st = ST_ZERO_PIVOT;
@@ -809,12 +817,12 @@ __global__ __launch_bounds__(kLevelThreads) void k_newton(DevSym Sarg,
 // One case over every workgroup of a cooperative launch; sync: the case's
 // grid-barrier words (three 128-byte lines, see Spread).
 __global__ __launch_bounds__(kLevelThreads) void k_newton_spread(DevSym S, NewtonArgs a,
-                                                               unsigned* sync)
+                                                               unsigned* sync, int back_lo)
 {
     __shared__ unsigned s_count;
     if (threadIdx.x == 0) s_count = 0;
     const Spread par{sync, sync + 32, reinterpret_cast<int*>(sync + 64),
-                     reinterpret_cast<uint64_t*>(sync + 68), &s_count};
+                     reinterpret_cast<uint64_t*>(sync + 68), &s_count, back_lo};
     const View w = case_view(a.ws, a.ws_stride, 1, 0);
     const View wb = case_bus_view(a.ws, a.ws_stride, 1, 0, S.vals_doubles);
     newton_case(par, S, a.yval, a.type, a.Psp, a.Qsp, a.Vm, a.Va, w, wb, a.tol, a.max_iter,
@@ -1049,7 +1057,12 @@ int newton_launch(const HostSym& h, int B, int C, NewtonArgs a, hipStream_t st, 
         hipLaunchKernelGGL(k_spread_init, dim3(1), dim3(128), 0, st, sync);
         if (const int e = launch_check(fn)) return e;
         DevSym S = h.dev;
-        void* args[] = {&S, &a, &sync};
+        // the narrow global levels (at most one node per thread of a
+        // workgroup) go with the tail's backward substitution
+        int back_lo = h.tail_level;
+        while (back_lo > 0 && h.level_ptr[back_lo] - h.level_ptr[back_lo - 1] <= threads)
+            --back_lo;
+        void* args[] = {&S, &a, &sync, &back_lo};
         return hip_check(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_newton_spread),
                                                     dim3(G), dim3(threads), args,
                                                     (unsigned)lds, st),
