@@ -1014,8 +1014,9 @@ __device__ __forceinline__ int clique_slot(int c0, int KC, int a, int b)
 // else reads until the tail writes them); after a grid barrier workgroup 0
 // loads them into LDS and runs the rest, and the other workgroups return.
 template <class SRC, bool FWD, bool WRITE, class P = OneGroup>
-__device__ void tail_factor(const DevSym& S, const SRC& src, const View& w, int64_t lu,
-                            const View& wr, int64_t rhs, int* s_bad, const P& par = P{})
+__device__ __forceinline__ void tail_factor(const DevSym& S, const SRC& src, const View& w,
+                                            int64_t lu, const View& wr, int64_t rhs, int* s_bad,
+                                            const P& par = P{})
 {
     const int K = S.tail_nodes, TS = S.tail_slots, KC = S.tail_clique;
     const int nT = S.nlev - S.tail_level;
@@ -1351,8 +1352,8 @@ __device__ __forceinline__ void apply_step(const View& w, int64_t rec, bool pv, 
 // x go there instead of the rhs: each thread takes its x into registers,
 // and writes them after a barrier.
 template <bool UPDATE>
-__device__ void tail_backward(const DevSym& S, const View& w, int64_t rhs, int64_t bus_off,
-                              PvMask type, double2* xs)
+__device__ __forceinline__ void tail_backward(const DevSym& S, const View& w, int64_t rhs,
+                                              int64_t bus_off, PvMask type, double2* xs)
 {
     const int K = S.tail_nodes, TS = S.tail_slots, KC = S.tail_clique;
     const int nT = S.nlev - S.tail_level;
