@@ -179,6 +179,11 @@ int pf_symbolic_set_launch(pf_symbolic sym, int threads, int64_t tail_lds_budget
  * (e, f).  A launch recorded into a graph (stream capture) and every batch
  * (B > 1) use the one-workgroup kernel.  Takes effect at the next call.    */
 int pf_symbolic_set_spread(pf_symbolic sym, int workgroups);
+/* The longest wait at a grid barrier of a spread launch before it gives up
+ * (every workgroup then stops waiting and runs to its end, and the case
+ * reports PF_E_HIP), in ticks of the device's 100 MHz constant clock;
+ * default 100000000 (one second).  Tests lower it to exercise that path.  */
+int pf_symbolic_set_spread_wait(pf_symbolic sym, uint64_t ticks);
 int pf_symbolic_get_mapping(const pf_symbolic sym, int32_t* lanes_per_level);
 /* Copies the integer structure into the caller's device buffer d_buf
  * (>= info.dev_bytes, 256-byte aligned) on stream s.  The buffer must stay

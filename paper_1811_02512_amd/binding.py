@@ -72,6 +72,7 @@ _SIGS = {
     "pf_symbolic_get_mapping": ([_vp, _vp], _i),
     "pf_symbolic_set_launch": ([_vp, _i, _i64, _i], _i),
     "pf_symbolic_set_spread": ([_vp, _i], _i),
+    "pf_symbolic_set_spread_wait": ([_vp, C.c_uint64], _i),
     "pf_newton_interleave": ([_vp, _i], _i),
     "pf_symbolic_upload": ([_vp, _vp, C.c_size_t, _vp], _i),
     "pf_symbolic_destroy": ([_vp], None),
@@ -198,6 +199,10 @@ def pf_symbolic_set_launch(h, threads=0, tail_lds_budget=65536, interleave=4):
 
 def pf_symbolic_set_spread(h, workgroups):
     check(lib.pf_symbolic_set_spread(h, int(workgroups)), "pf_symbolic_set_spread")
+
+
+def pf_symbolic_set_spread_wait(h, ticks):
+    check(lib.pf_symbolic_set_spread_wait(h, int(ticks)), "pf_symbolic_set_spread_wait")
 
 
 def pf_newton_interleave(h, B):

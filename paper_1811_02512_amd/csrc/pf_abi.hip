@@ -216,6 +216,13 @@ int pf_symbolic_set_spread(pf_symbolic s, int workgroups)
     return PF_OK;
 }
 
+int pf_symbolic_set_spread_wait(pf_symbolic s, uint64_t ticks)
+{
+    if (!s) return fail(PF_E_INVALID, "pf_symbolic_set_spread_wait: NULL symbolic");
+    s->h.spread_wait = ticks;
+    return PF_OK;
+}
+
 int pf_newton_interleave(const pf_symbolic s, int B)
 {
     if (!s || B < 0) return fail(PF_E_INVALID, "pf_newton_interleave: bad arguments"), -1;

@@ -534,10 +534,10 @@ struct OneGroup {
 // A workgroup makes its writes visible before it arrives and discards stale
 // cached lines after it is released (agent-scope fences), so what any
 // workgroup wrote before a barrier is what every workgroup reads after it.
-// A wait that lasts longer than kSpreadWaitTicks of the constant 100 MHz
-// clock sets the abort flag; from then on no barrier waits, so every
-// workgroup runs to its end and the case reports the failure.
-constexpr unsigned long long kSpreadWaitTicks = 100000000ull;  // one second
+// A wait that lasts longer than wait_ticks of the constant 100 MHz clock
+// (one second unless a caller lowers it) sets the abort flag; from then on
+// no barrier waits, so every workgroup runs to its end and the case reports
+// the failure.
 constexpr int kSpreadWords = 96;  // 32-bit words of the three lines
 
 struct Spread {
@@ -551,6 +551,7 @@ struct Spread {
     // workgroup 0 right after the tail's (narrow levels: workgroup barriers
     // are cheaper there than grid barriers)
     int back_lo;
+    unsigned long long wait_ticks;
     __device__ __forceinline__ int rank() const { return blockIdx.x; }
     __device__ __forceinline__ int size() const { return gridDim.x; }
     __device__ __forceinline__ int* marker() const { return flags + 1; }
@@ -574,7 +575,7 @@ struct Spread {
                     while (__hip_atomic_load(release, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT) < k) {
                         if (aborted()) break;
-                        if (wall_clock64() - t0 > kSpreadWaitTicks) {
+                        if (wall_clock64() - t0 > wait_ticks) {
                             __hip_atomic_store(flags, 1, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT);
                             break;

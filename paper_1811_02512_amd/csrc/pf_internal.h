@@ -117,6 +117,9 @@ struct HostSym {
     // workgroups a one-case Newton launch spreads its wide phases over (the
     // bus loops and the levels below the LDS tail); 0 or 1: one workgroup
     int32_t spread = 0;
+    // longest wait at a grid barrier of a spread launch, in ticks of the
+    // 100 MHz constant clock, before the launch gives up (one second)
+    uint64_t spread_wait = 100000000ull;
     // device copy
     DevSym dev{};
     bool uploaded = false;

@@ -50,11 +50,22 @@ __device__ __forceinline__ void newton_case(const P& par, const DevSym& S, const
     pv_fill(S, type);
     if (kOne && threadIdx.x == 0) s_bad = kNoPivot;
     par.sync();
+    // the zero-pivot marker; in a spread launch thread 0 reads it and hands
+    // it to its workgroup, so that every thread of a workgroup takes the
+    // same branch even if other workgroups have lost step (called by every
+    // thread of the workgroup)
+    __shared__ int s_mark;
     auto marker = [&]() {
-        if constexpr (P::kSpread)
-            return __hip_atomic_load(bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        else
+        if constexpr (P::kSpread) {
+            if (threadIdx.x == 0)
+                s_mark = __hip_atomic_load(bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+            const int v = s_mark;
+            __syncthreads();
+            return v;
+        } else {
             return s_bad;
+        }
     };
     // the tail's results are read by the other workgroups of a spread launch
     // only after a grid barrier (one workgroup's own barriers order them);
@@ -107,18 +118,27 @@ __device__ __forceinline__ void newton_case(const P& par, const DevSym& S, const
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             par.sync();
-            any_nan = __hip_atomic_load(par.flags + 2 + sl, __ATOMIC_RELAXED,
-                                        __HIP_MEMORY_SCOPE_AGENT);
-            nrm = __longlong_as_double((long long)__hip_atomic_load(
-                par.maxbits + sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-            // the other slots were last read before the previous iteration's
-            // later barriers: clear them for the next iteration
-            if (lead && threadIdx.x == 0) {
-                __hip_atomic_store(par.flags + 3 - sl, 0, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(par.maxbits + 1 - sl, (uint64_t)0, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+            // thread 0 reads the norm for its workgroup (as the marker)
+            __shared__ double s_nrm;
+            __shared__ int s_nan;
+            if (threadIdx.x == 0) {
+                s_nan = __hip_atomic_load(par.flags + 2 + sl, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+                s_nrm = __longlong_as_double((long long)__hip_atomic_load(
+                    par.maxbits + sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                // the other slots were last read before the previous
+                // iteration's later barriers: clear them for the next one
+                if (lead) {
+                    __hip_atomic_store(par.flags + 3 - sl, 0, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(par.maxbits + 1 - sl, (uint64_t)0, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                }
             }
+            __syncthreads();
+            any_nan = s_nan;
+            nrm = s_nrm;
+            __syncthreads();
         }
         if (any_nan || !isfinite(nrm)) {
             st = ST_NONFINITE;
@@ -173,8 +193,8 @@ __device__ __forceinline__ void newton_case(const P& par, const DevSym& S, const
         Vm[i] = r.c;
         Va[i] = r.d;
     }
+    const int bad_at = marker();
     if (lead && threadIdx.x == 0) {
-        const int bad_at = marker();
         if constexpr (P::kSpread) {
             if (par.aborted()) st = PF_E_HIP;
         }
@@ -817,12 +837,13 @@ __global__ __launch_bounds__(kLevelThreads) void k_newton(DevSym Sarg,
 // One case over every workgroup of a cooperative launch; sync: the case's
 // grid-barrier words (three 128-byte lines, see Spread).
 __global__ __launch_bounds__(kLevelThreads) void k_newton_spread(DevSym S, NewtonArgs a,
-                                                               unsigned* sync, int back_lo)
+                                                               unsigned* sync, int back_lo,
+                                                               unsigned long long wait_ticks)
 {
     __shared__ unsigned s_count;
     if (threadIdx.x == 0) s_count = 0;
-    const Spread par{sync, sync + 32, reinterpret_cast<int*>(sync + 64),
-                     reinterpret_cast<uint64_t*>(sync + 68), &s_count, back_lo};
+    const Spread par{sync,    sync + 32,  reinterpret_cast<int*>(sync + 64),
+                     reinterpret_cast<uint64_t*>(sync + 68), &s_count, back_lo, wait_ticks};
     const View w = case_view(a.ws, a.ws_stride, 1, 0);
     const View wb = case_bus_view(a.ws, a.ws_stride, 1, 0, S.vals_doubles);
     newton_case(par, S, a.yval, a.type, a.Psp, a.Qsp, a.Vm, a.Va, w, wb, a.tol, a.max_iter,
@@ -1062,7 +1083,8 @@ int newton_launch(const HostSym& h, int B, int C, NewtonArgs a, hipStream_t st, 
         int back_lo = h.tail_level;
         while (back_lo > 0 && h.level_ptr[back_lo] - h.level_ptr[back_lo - 1] <= threads)
             --back_lo;
-        void* args[] = {&S, &a, &sync, &back_lo};
+        unsigned long long wait = h.spread_wait;
+        void* args[] = {&S, &a, &sync, &back_lo, &wait};
         return hip_check(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_newton_spread),
                                                     dim3(G), dim3(threads), args,
                                                     (unsigned)lds, st),

@@ -188,3 +188,44 @@ def test_spread_under_graph_capture_takes_one_workgroup():
         torch.cuda.synchronize()
         assert st.item() == 0 and it.item() == it1, rep
         assert torch.equal(Vm[0], Vm1) and torch.equal(Va[0], Va1), rep
+
+
+def test_spread_gives_up_when_a_barrier_wait_runs_out():
+    """With a wait limit of zero ticks the first workgroup that has to wait at
+    a grid barrier gives up: no workgroup waits from then on, every one runs
+    to its end and the case reports PF_E_HIP.  The next launch with the
+    normal limit is whole again."""
+    B = _B()
+    s = Staged(grid(2000, 1))
+    B.pf_symbolic_set_spread_wait(s.sym.h, 0)
+    try:
+        r = solve(s, 32)
+    finally:
+        B.pf_symbolic_set_spread_wait(s.sym.h, 100_000_000)
+    log(f"[spread] zero wait limit: status {r[4]}")
+    assert r[4] == B.PF_E_HIP
+    good = solve(s, 32)
+    one = solve(s, 0)
+    assert good[4] == 0 and one[4] == 0 and good[2] == one[2]
+    assert (good[0] - one[0]).abs().max().item() < 1e-12
+
+
+def test_noalloc_takes_the_spread_launch_too():
+    """pf_newton_noalloc with a spread setting: its barrier words sit in the
+    library's scratch array; results equal pf_newton's spread launch."""
+    B = _B()
+    s = Staged(grid(2000, 2))
+    g = s.g
+    ref = solve(s, 32)
+    s.sym.set_spread(32)
+    Vm, Va = s.Vm0.clone()[None], s.Va0.clone()[None]
+    it = torch.full((1,), -9, dtype=torch.int32, device="cuda")
+    st = torch.full((1,), -9, dtype=torch.int32, device="cuda")
+    try:
+        B.pf_newton_noalloc(s.sym.h, 1, s.yval, 0, s.type, 0, s.Psp, s.Qsp, 0, Vm, Va, g.n,
+                            1e-8, 20, it, None, st)
+        torch.cuda.synchronize()
+    finally:
+        s.sym.set_spread(0)
+    assert st.item() == 0 and it.item() == ref[2]
+    assert torch.equal(Vm[0], ref[0]) and torch.equal(Va[0], ref[1])
