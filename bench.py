@@ -633,13 +633,15 @@ def leg_fdpf(W, steps):
     """Fast decoupled power flow on the workload's grid and scenarios: one
     step = B' and B'' built and factored once for the batch (shared
     impedances) + the batched decoupled iteration to 1e-8 + branch flows of
-    every case.  Also the one-case-per-launch rate."""
+    every case.  Also the one-case-per-launch rate.  Both run with the
+    batch's tuned launch shape (the one-case Newton tuning may pick a
+    workgroup size chosen for its spread launch)."""
     import torch
 
     from oracle import oracle as O
     from paper_1811_02512_amd import binding as B
 
-    g, sym, info = W.g, W.sym1, W.sym1.info
+    g, sym, info = W.g, W.sym, W.sym.info
     Bn = W.B
     dev = W.Vm.device
     mat = torch.empty(1, info.fd_mat_doubles, dtype=torch.float64, device=dev)
