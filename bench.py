@@ -434,9 +434,12 @@ def leg_plain(W, steps, label):
     Vm, Va = W.Vm[0].cpu().numpy(), W.Va[0].cpu().numpy()
     check = check_cases([(ref.iters == it, float(np.abs(ref.Vm - Vm).max()),
                           float(np.abs(ref.Va - Va).max()))])
-    spread = int(W.sym1.info.spread)
+    info1 = W.sym1.info
+    spread = int(info1.spread)
+    syncs = sync_counts(W.sym1, spread)
     log(f"[bench] {label} one case per launch: {ms * 1e3:.1f} us/solve, {it} iterations, "
-        f"{ms * 1e3 / max(it, 1):.1f} us/iteration, spread over {max(spread, 1)} workgroups")
+        f"{ms * 1e3 / max(it, 1):.1f} us/iteration, spread over {max(spread, 1)} workgroups, "
+        f"{syncs}")
     if spread > 1:
         launches = (3, f"k_ybus + k_spread_init + k_newton_spread (the whole NR loop in one "
                        f"cooperative launch of {spread} workgroups); two 16n-byte device copies "
@@ -446,7 +449,30 @@ def leg_plain(W, steps, label):
                        "device copies of the flat start")
     return dict(solves_per_s=1e3 / ms, ms_per_solve=ms, us_per_iteration=ms * 1e3 / max(it, 1),
                 iterations=it, workgroups=max(spread, 1), kernel_launches_per_solve=launches[0],
-                launches=launches[1], oracle_check=check)
+                launches=launches[1], syncs_per_iteration=syncs, oracle_check=check)
+
+
+def sync_counts(sym, spread):
+    """Barriers of one NR iteration of a one-case Newton launch, from the
+    partition: on one workgroup a workgroup barrier per level step (the
+    mismatch, every factorisation and backward level); spread, a grid barrier
+    after the mismatch, after each level below the LDS tail in the
+    factorisation and after each wide one in the backward sweep, and three
+    around the tail (its shared first pass, its factorisation, its backward
+    substitution together with the narrow global backward levels)."""
+    info = sym.info
+    widths = np.diff(sym.export()["level_ptr"])
+    nlev = int(info.nlevels)
+    below = nlev - int(info.tail_levels)
+    if spread <= 1:
+        return {"workgroup_barriers": 1 + 2 * nlev, "grid_barriers": 0}
+    threads = int(info.threads) or 512
+    back_lo = below
+    while back_lo > 0 and widths[back_lo - 1] <= threads:
+        back_lo -= 1
+    tail = 3 if info.tail_nodes > 0 else 0
+    return {"grid_barriers": 1 + below + tail + back_lo,
+            "levels_on_workgroup_0": int(info.tail_levels) * 2 + (below - back_lo)}
 
 
 def leg_c2_breakdown(W, steps):

@@ -6,6 +6,7 @@ import subprocess
 import sys
 from types import SimpleNamespace
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -62,3 +63,22 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=300)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_sync_counts_of_a_one_case_launch():
+    """Barriers per NR iteration: one workgroup takes a workgroup barrier per
+    level step; a spread launch a grid barrier per shared step."""
+    import gridgen
+    from paper_1811_02512_amd import api
+
+    g = gridgen.make_grid(2000, 1)
+    sym = api.Symbolic(g.n, g.f, g.t)
+    sym.set_launch(512, 0, 1)  # no tail: every level shared
+    info = sym.info
+    assert info.tail_levels == 0
+    one = bench.sync_counts(sym, 0)
+    assert one == {"workgroup_barriers": 1 + 2 * info.nlevels, "grid_barriers": 0}
+    spread = bench.sync_counts(sym, 16)
+    narrow = sum(1 for w in np.diff(sym.export()["level_ptr"]) if w <= 512)
+    assert spread["grid_barriers"] == 1 + info.nlevels + (info.nlevels - narrow)
+    assert spread["levels_on_workgroup_0"] == narrow
