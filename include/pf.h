@@ -476,8 +476,20 @@ int pf_adjoint(const pf_symbolic sym, int B, double* d_ws, int64_t ws_stride,
  * offsets: bus arrays (type, Psp, Qsp, Vm, Va: n of its grid), branch
  * arrays (r, x, b: m of its grid), admittance values (2*nnz_y doubles) and
  * workspace (ws_doubles).  Cases run largest first, one workgroup each, in
- * one launch.                                                              */
+ * one launch, unless pf_multi_set_spread gives the launch more workgroups
+ * than cases.                                                              */
 int pf_multi_create(int G, const pf_symbolic* syms, pf_multi* out);
+/* Workgroups of pf_newton_multi's launch (0 or up to G: one per case, the
+ * default; at most 65535).  The workgroups beyond one per case go one at a
+ * time to the case with the most estimated work per workgroup (a case takes
+ * at most one per 128 nodes of its widest level below its LDS tail, and
+ * 32), so the largest grids, which bound the launch, share their wide levels
+ * among several CUs as a spread one-case launch does (grid barriers within
+ * each case's group).  The launch is cooperative; when the device cannot
+ * keep every workgroup resident at once, or the stream is being captured,
+ * it falls back to one workgroup per case.  Changes the plan's device table:
+ * pf_multi_info's dev_bytes and pf_multi_upload again before the next call. */
+int pf_multi_set_spread(pf_multi plan, int workgroups);
 /* offsets: each int64[G+1] (prefix sums), any may be NULL.               */
 int pf_multi_info(const pf_multi plan, size_t* dev_bytes, int64_t* bus_off,
                   int64_t* branch_off, int64_t* y_off, int64_t* ws_off);

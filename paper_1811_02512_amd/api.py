@@ -177,6 +177,15 @@ class MultiPlan:
                 pass
             self.p = None
 
+    def set_spread(self, workgroups):
+        """Workgroups of the batch's Newton launch (0: one per case); the
+        plan's device table is rebuilt and uploaded again."""
+        B.pf_multi_set_spread(self.p, workgroups)
+        nbytes, _ = B.pf_multi_info(self.p, len(self.syms))
+        if self.buf.numel() < nbytes:
+            self.buf = torch.empty(nbytes, dtype=torch.uint8, device=self.buf.device)
+        B.pf_multi_upload(self.p, self.buf)
+
     def concat(self, arrays, key, dtype, device=None):
         """Concatenate per-case host arrays into one device tensor."""
         tot = int(self.offs[key][-1])

@@ -95,6 +95,7 @@ _SIGS = {
     "pf_multi_create": ([_i, _vp, C.POINTER(_vp)], _i),
     "pf_multi_info": ([_vp, C.POINTER(C.c_size_t), _vp, _vp, _vp, _vp], _i),
     "pf_multi_upload": ([_vp, _vp, C.c_size_t, _vp], _i),
+    "pf_multi_set_spread": ([_vp, _i], _i),
     "pf_build_ybus_multi": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], _i),
     "pf_newton_multi": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _d, _i, _i, _vp, _vp, _vp, _vp,
                          _vp, _vp], _i),
@@ -322,6 +323,10 @@ def pf_multi_info(p, G):
 def pf_multi_upload(p, buf, stream=None):
     check(lib.pf_multi_upload(p, ptr(buf), buf.numel() * buf.element_size(),
                               stream_ptr(stream)), "pf_multi_upload")
+
+
+def pf_multi_set_spread(p, workgroups):
+    check(lib.pf_multi_set_spread(p, int(workgroups)), "pf_multi_set_spread")
 
 
 def pf_build_ybus_multi(p, r, x, b, yval, ysh=None, stream=None):

@@ -521,8 +521,9 @@ struct OneGroup {
 };
 
 // Spread: the case's wide phases (loops over buses, the levels below the LDS
-// tail) over every workgroup of a cooperative launch, which meet at grid
-// barriers; the tail stays on workgroup 0 while the others wait.  The
+// tail) over the workgroups of a cooperative launch that own the case (all
+// of them, or a group in a batch of grids), which meet at grid barriers;
+// the tail stays on the group's first workgroup while the others wait.  The
 // barrier words live in three 128-byte lines of the case's workspace,
 // zeroed (the pivot marker set to kNoPivot) before the launch:
 //   line 0: arrivals (count of workgroups that reached a barrier, over all
@@ -552,8 +553,9 @@ struct Spread {
     // are cheaper there than grid barriers)
     int back_lo;
     unsigned long long wait_ticks;
-    __device__ __forceinline__ int rank() const { return blockIdx.x; }
-    __device__ __forceinline__ int size() const { return gridDim.x; }
+    int rk, sz;  // this workgroup's rank in the case's group, the group's size
+    __device__ __forceinline__ int rank() const { return rk; }
+    __device__ __forceinline__ int size() const { return sz; }
     __device__ __forceinline__ int* marker() const { return flags + 1; }
     __device__ __forceinline__ bool aborted() const
     {
@@ -568,7 +570,7 @@ struct Spread {
             const unsigned before =
                 __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (!aborted()) {
-                if (before == k * gridDim.x - 1) {
+                if (before == k * (unsigned)sz - 1) {
                     __hip_atomic_store(release, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 } else {
                     const unsigned long long t0 = wall_clock64();
@@ -1570,6 +1572,11 @@ struct AdjArgs {
 struct CaseDesc {
     DevSym sym;
     int64_t bus_off, br_off, y_off, ws_off;
+    // a batch of grids spread over more workgroups than cases: this case's
+    // workgroup count, its grid-barrier words (doubles after ws_off) and the
+    // first backward level left to its first workgroup
+    int64_t sync_off;
+    int32_t spread, back_lo;
 };
 
 // Mismatch pass of one case: F = calculated - scheduled (F_Q = 0 at PV buses)

@@ -290,6 +290,8 @@ __global__ void k_ybus(DevSym S, const double* __restrict__ r, const double* __r
     ybus_row(S, i, r + c * bstride, x + c * bstride, bc + c * bstride, sh, yval + c * ystride);
 }
 
+// Case blockIdx.x of a batch of grids; its rows are shared by the gridDim.y
+// workgroups of that case (a large grid's rows spread over many CUs).
 __global__ void k_ybus_multi(const CaseDesc* __restrict__ descs, const double* __restrict__ r,
                              const double* __restrict__ x, const double* __restrict__ bc,
                              const double* __restrict__ ysh, double* __restrict__ yval)
@@ -297,7 +299,7 @@ __global__ void k_ybus_multi(const CaseDesc* __restrict__ descs, const double* _
     const CaseDesc& cd = descs[blockIdx.x];
     const DevSym& S = cd.sym;
     const double2* sh = ysh ? reinterpret_cast<const double2*>(ysh) + cd.bus_off : nullptr;
-    for (int i = threadIdx.x; i < S.n; i += blockDim.x)
+    for (int i = blockIdx.y * blockDim.x + threadIdx.x; i < S.n; i += gridDim.y * blockDim.x)
         ybus_row(S, i, r + cd.br_off, x + cd.br_off, bc + cd.br_off, sh, yval + cd.y_off);
 }
 
@@ -842,12 +844,53 @@ __global__ __launch_bounds__(kLevelThreads) void k_newton_spread(DevSym S, Newto
 {
     __shared__ unsigned s_count;
     if (threadIdx.x == 0) s_count = 0;
-    const Spread par{sync,    sync + 32,  reinterpret_cast<int*>(sync + 64),
-                     reinterpret_cast<uint64_t*>(sync + 68), &s_count, back_lo, wait_ticks};
+    const Spread par{sync,    sync + 32,          reinterpret_cast<int*>(sync + 64),
+                     reinterpret_cast<uint64_t*>(sync + 68), &s_count, back_lo, wait_ticks,
+                     (int)blockIdx.x, (int)gridDim.x};
     const View w = case_view(a.ws, a.ws_stride, 1, 0);
     const View wb = case_bus_view(a.ws, a.ws_stride, 1, 0, S.vals_doubles);
     newton_case(par, S, a.yval, a.type, a.Psp, a.Qsp, a.Vm, a.Va, w, wb, a.tol, a.max_iter,
                 a.flags, a.iters, a.norm, a.status, a.pivot);
+}
+
+// A batch of grids (each case its own symbolic) in one cooperative launch
+// with more workgroups than cases: blocks[b] = (case, rank, group size) of
+// workgroup b.  A case with one workgroup runs as in k_newton<true>; a
+// larger group shares its case as a spread launch does, with grid barriers
+// among the group's workgroups only.
+__global__ __launch_bounds__(kLevelThreads) void k_newton_multi_spread(
+    const CaseDesc* __restrict__ descs, const int4* __restrict__ blocks, NewtonArgs a,
+    unsigned long long wait_ticks)
+{
+    __shared__ unsigned s_count;
+    const int4 bk = blocks[blockIdx.x];
+    const int c = bk.x;
+    const CaseDesc& cd = descs[c];
+    const DevSym S = cd.sym;
+    const View w = case_view(a.ws + cd.ws_off, 0, 1, 0);
+    const View wb = case_bus_view(a.ws + cd.ws_off, 0, 1, 0, S.vals_doubles);
+    const double* yv = a.yval + cd.y_off;
+    const int8_t* ty = a.type + cd.bus_off;
+    const double* P = a.Psp + cd.bus_off;
+    const double* Q = a.Qsp + cd.bus_off;
+    double* Vm = a.Vm + cd.bus_off;
+    double* Va = a.Va + cd.bus_off;
+    int32_t* o_it = a.iters ? a.iters + c : nullptr;
+    double* o_nrm = a.norm ? a.norm + c : nullptr;
+    int32_t* o_st = a.status ? a.status + c : nullptr;
+    int32_t* o_pv = a.pivot ? a.pivot + c : nullptr;
+    if (bk.z <= 1) {
+        newton_case(OneGroup{}, S, yv, ty, P, Q, Vm, Va, w, wb, a.tol, a.max_iter, a.flags, o_it,
+                    o_nrm, o_st, o_pv);
+        return;
+    }
+    if (threadIdx.x == 0) s_count = 0;
+    unsigned* sync = reinterpret_cast<unsigned*>(a.ws + cd.ws_off + cd.sync_off);
+    const Spread par{sync,    sync + 32, reinterpret_cast<int*>(sync + 64),
+                     reinterpret_cast<uint64_t*>(sync + 68), &s_count, cd.back_lo, wait_ticks,
+                     bk.y,    bk.z};
+    newton_case(par, S, yv, ty, P, Q, Vm, Va, w, wb, a.tol, a.max_iter, a.flags, o_it, o_nrm,
+                o_st, o_pv);
 }
 
 // Clears the grid-barrier words before a spread launch (a kernel, not a
@@ -855,6 +898,17 @@ __global__ __launch_bounds__(kLevelThreads) void k_newton_spread(DevSym S, Newto
 // starts at kNoPivot.
 __global__ void k_spread_init(unsigned* sync)
 {
+    const int i = threadIdx.x;
+    if (i < kSpreadWords) sync[i] = i == 65 ? (unsigned)kNoPivot : 0u;
+}
+
+// The same for every case of a batch of grids whose group has more than one
+// workgroup (block c: case c).
+__global__ void k_spread_init_multi(const CaseDesc* __restrict__ descs, double* ws)
+{
+    const CaseDesc& cd = descs[blockIdx.x];
+    if (cd.spread <= 1) return;
+    unsigned* sync = reinterpret_cast<unsigned*>(ws + cd.ws_off + cd.sync_off);
     const int i = threadIdx.x;
     if (i < kSpreadWords) sync[i] = i == 65 ? (unsigned)kNoPivot : 0u;
 }
@@ -992,10 +1046,18 @@ struct pf_multi_s {
 
     std::vector<pf_symbolic> syms;
     std::vector<int64_t> bus_off, br_off, y_off, ws_off;
-    std::vector<int32_t> order;
+    std::vector<int64_t> work;   // estimated one-workgroup work of each case
+    std::vector<int32_t> order;  // cases by decreasing work
     std::vector<uint64_t> gens;  // each symbolic's upload count when the plan was uploaded
+    // workgroups of pf_newton_multi's launch (0: one per case) and their
+    // assignment: counts[c] workgroups for case c; blocks: (case, rank,
+    // group size, 0) per workgroup
+    int spread = 0;
+    std::vector<int32_t> counts;
+    std::vector<int32_t> blocks;
     const CaseDesc* d_desc = nullptr;
     const int32_t* d_order = nullptr;
+    const int4* d_blocks = nullptr;
     bool uploaded = false;
 };
 
@@ -1029,6 +1091,7 @@ void allow_big_lds()
                              reinterpret_cast<const void*>(&k_newton<false>),
                              reinterpret_cast<const void*>(&k_newton<true>),
                              reinterpret_cast<const void*>(&k_newton_spread),
+                             reinterpret_cast<const void*>(&k_newton_multi_spread),
                              reinterpret_cast<const void*>(&k_factor<false>),
                              reinterpret_cast<const void*>(&k_factor<true>),
                              reinterpret_cast<const void*>(&k_solve<false, true>),
@@ -1093,6 +1156,63 @@ int newton_launch(const HostSym& h, int B, int C, NewtonArgs a, hipStream_t st, 
     hipLaunchKernelGGL(k_newton<false>, dim3(grid_blocks(B, C)), dim3(threads), lds, st, h.dev,
                        (const CaseDesc*)nullptr, (const int32_t*)nullptr, a);
     return launch_check(fn);
+}
+
+// Threads per workgroup of pf_newton_multi's launch: the largest setting of
+// the plan's symbolics, else 512 up to 512 cases and 256 beyond.
+int multi_threads(const pf_multi p)
+{
+    int threads = 0;
+    for (auto* sy : p->syms) threads = std::max(threads, sy->h.threads);
+    if (threads == 0) threads = (p->syms.size() <= 512) ? 512 : 256;
+    return threads;
+}
+
+// First level of the backward sweep left to a spread group's first
+// workgroup: the narrow global levels (at most one node per thread).
+int spread_back_lo(const HostSym& h, int threads)
+{
+    int lo = h.tail_level;
+    while (lo > 0 && h.level_ptr[lo] - h.level_ptr[lo - 1] <= threads) --lo;
+    return lo;
+}
+
+// Workgroups per case for a launch of `spread` workgroups in all: one each,
+// then the rest one at a time to the case with the most work per workgroup
+// (each case at most one per 128 nodes of its widest level below the tail,
+// and 32), so that the largest grids, which bound the launch, share theirs.
+void plan_blocks(pf_multi p)
+{
+    const int G = (int)p->syms.size();
+    p->counts.assign(G, 1);
+    std::vector<int> cap(G, 1);
+    for (int c = 0; c < G; ++c) {
+        const HostSym& h = p->syms[c]->h;
+        int widest = 0;
+        for (int l = 0; l < h.tail_level; ++l)
+            widest = std::max(widest, h.level_ptr[l + 1] - h.level_ptr[l]);
+        cap[c] = std::max(1, std::min(32, widest / 128));
+    }
+    int extra = std::max(0, p->spread - G);
+    while (extra > 0) {
+        int best = -1;
+        for (int c = 0; c < G; ++c) {
+            if (p->counts[c] >= cap[c]) continue;
+            // work per workgroup, compared without division
+            if (best < 0 || p->work[c] * p->counts[best] > p->work[best] * p->counts[c]) best = c;
+        }
+        if (best < 0) break;
+        ++p->counts[best];
+        --extra;
+    }
+    p->blocks.clear();
+    for (int c : p->order)
+        for (int r = 0; r < p->counts[c]; ++r) {
+            p->blocks.push_back(c);
+            p->blocks.push_back(r);
+            p->blocks.push_back(p->counts[c]);
+            p->blocks.push_back(0);
+        }
 }
 
 }  // namespace
@@ -1465,7 +1585,8 @@ int pf_multi_create(int G, const pf_symbolic* syms, pf_multi* out)
     p->br_off.assign(G + 1, 0);
     p->y_off.assign(G + 1, 0);
     p->ws_off.assign(G + 1, 0);
-    std::vector<int64_t> work(G);
+    std::vector<int64_t>& work = p->work;
+    work.assign(G, 0);
     for (int g = 0; g < G; ++g) {
         if (!syms[g]) {
             delete p;
@@ -1483,7 +1604,19 @@ int pf_multi_create(int G, const pf_symbolic* syms, pf_multi* out)
     std::iota(p->order.begin(), p->order.end(), 0);
     std::stable_sort(p->order.begin(), p->order.end(),
                      [&](int a, int b) { return work[a] > work[b]; });
+    plan_blocks(p);
     *out = p;
+    return PF_OK;
+}
+
+int pf_multi_set_spread(pf_multi p, int workgroups)
+{
+    if (!p) return fail(PF_E_INVALID, "pf_multi_set_spread: NULL plan");
+    if (workgroups < 0 || workgroups > 65535)
+        return fail(PF_E_INVALID, "pf_multi_set_spread: workgroups must be 0..65535");
+    p->spread = workgroups;
+    plan_blocks(p);
+    p->uploaded = false;  // the block table on the device is stale: upload again
     return PF_OK;
 }
 
@@ -1494,7 +1627,8 @@ int pf_multi_info(const pf_multi p, size_t* dev_bytes, int64_t* bus_off, int64_t
     size_t G = p->syms.size();
     if (dev_bytes)
         *dev_bytes = ((G * sizeof(CaseDesc) + 255) & ~(size_t)255) +
-                     ((std::max<size_t>(G, 1) * 4 + 255) & ~(size_t)255);
+                     ((std::max<size_t>(G, 1) * 4 + 255) & ~(size_t)255) +
+                     ((p->blocks.size() * 4 + 255) & ~(size_t)255);
     auto cp = [&](int64_t* dst, const std::vector<int64_t>& v) {
         if (dst) std::memcpy(dst, v.data(), v.size() * sizeof(int64_t));
     };
@@ -1527,9 +1661,15 @@ int pf_multi_upload(pf_multi p, void* d_buf, size_t bytes, void* stream)
         cd[g].br_off = p->br_off[g];
         cd[g].y_off = p->y_off[g];
         cd[g].ws_off = p->ws_off[g];
+        cd[g].sync_off = p->syms[g]->h.sync_off();
+        cd[g].spread = p->counts[g];
+        cd[g].back_lo = spread_back_lo(p->syms[g]->h, multi_threads(p));
     }
     size_t ooff = (G * sizeof(CaseDesc) + 255) & ~(size_t)255;
     if (G) std::memcpy(stage.data() + ooff, p->order.data(), G * sizeof(int32_t));
+    const size_t boff = ooff + ((std::max<size_t>(G, 1) * 4 + 255) & ~(size_t)255);
+    if (!p->blocks.empty())
+        std::memcpy(stage.data() + boff, p->blocks.data(), p->blocks.size() * sizeof(int32_t));
     int rc = hip_check(hipMemcpyAsync(d_buf, stage.data(), need, hipMemcpyHostToDevice,
                                       as_stream(stream)),
                        "pf_multi_upload: hipMemcpyAsync");
@@ -1538,6 +1678,7 @@ int pf_multi_upload(pf_multi p, void* d_buf, size_t bytes, void* stream)
     if (rc) return rc;
     p->d_desc = reinterpret_cast<const CaseDesc*>(d_buf);
     p->d_order = reinterpret_cast<const int32_t*>(static_cast<char*>(d_buf) + ooff);
+    p->d_blocks = reinterpret_cast<const int4*>(static_cast<char*>(d_buf) + boff);
     p->uploaded = true;
     return PF_OK;
 }
@@ -1569,8 +1710,12 @@ int pf_build_ybus_multi(const pf_multi p, const double* d_r, const double* d_x,
     if (d_ysh && (reinterpret_cast<uintptr_t>(d_ysh) & 15))
         return fail(PF_E_INVALID, "pf_build_ybus_multi: d_ysh must be 16-byte aligned");
     if (p->syms.empty()) return PF_OK;
-    hipLaunchKernelGGL(k_ybus_multi, dim3(p->syms.size()), dim3(256), 0, as_stream(stream),
-                       p->d_desc, d_r, d_x, d_b, d_ysh, d_yval);
+    // enough workgroups per case for the largest grid's rows, at most 64
+    int nmax = 0;
+    for (auto* sy : p->syms) nmax = std::max(nmax, sy->h.n);
+    const int per = std::max(1, std::min(64, (nmax + 255) / 256));
+    hipLaunchKernelGGL(k_ybus_multi, dim3((unsigned)p->syms.size(), per), dim3(256), 0,
+                       as_stream(stream), p->d_desc, d_r, d_x, d_b, d_ysh, d_yval);
     return launch_check("pf_build_ybus_multi");
 }
 
@@ -1589,15 +1734,44 @@ int pf_newton_multi(const pf_multi p, const double* d_yval, const int8_t* d_type
     NewtonArgs a{d_yval, 0, d_type, 0, d_Psp, d_Qsp, 0, d_Vm, d_Va, 0, d_ws, 0, tol, max_iter,
                  flags, 1, (int)p->syms.size(), d_iters, d_norm, d_status, d_pivot};
     DevSym none{};
-    int lds = 0, threads = 0;
+    int lds = 0;
+    uint64_t wait = 0;
     for (auto* sy : p->syms) {
         lds = std::max(lds, newton_lds(sy->h));
-        threads = std::max(threads, sy->h.threads);
+        wait = std::max<uint64_t>(wait, sy->h.spread_wait);
     }
-    if (threads == 0) threads = (p->syms.size() <= 512) ? 512 : 256;
+    const int threads = multi_threads(p);
     allow_big_lds();
-    hipLaunchKernelGGL(k_newton<true>, dim3(p->syms.size()), dim3(threads), lds,
-                       as_stream(stream), none, p->d_desc, p->d_order, a);
+    const int G = (int)p->syms.size();
+    const int nb = (int)p->blocks.size() / 4;
+    hipStream_t st = as_stream(stream);
+    if (nb > G) {
+        // more workgroups than cases: one cooperative launch, when the device
+        // keeps them all resident and the stream is not being captured
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        int dev = 0, cus = 0, per = 0;
+        const bool queried =
+            hipStreamIsCapturing(st, &cs) == hipSuccess && hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) ==
+                hipSuccess &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_newton_multi_spread, threads,
+                                                         lds) == hipSuccess;
+        if (!queried) (void)hipGetLastError();
+        if (queried && cs == hipStreamCaptureStatusNone && nb <= per * cus) {
+            hipLaunchKernelGGL(k_spread_init_multi, dim3(G), dim3(128), 0, st, p->d_desc, d_ws);
+            if (const int e = launch_check("pf_newton_multi")) return e;
+            const CaseDesc* descs = p->d_desc;
+            const int4* blocks = p->d_blocks;
+            unsigned long long w = wait;
+            void* args[] = {&descs, &blocks, &a, &w};
+            return hip_check(
+                hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_newton_multi_spread),
+                                           dim3(nb), dim3(threads), args, (unsigned)lds, st),
+                "pf_newton_multi");
+        }
+    }
+    hipLaunchKernelGGL(k_newton<true>, dim3(G), dim3(threads), lds, st, none, p->d_desc,
+                       p->d_order, a);
     return launch_check("pf_newton_multi");
 }
 

@@ -16,7 +16,7 @@ def _needs_gpu():
         pytest.skip("no GPU")
 
 
-def solve_multi(grids, tol=1e-8, max_iter=20, tail_budget=None):
+def solve_multi(grids, tol=1e-8, max_iter=20, tail_budget=None, spread=0):
     from paper_1811_02512_amd import api
     from paper_1811_02512_amd import binding as B
 
@@ -27,6 +27,8 @@ def solve_multi(grids, tol=1e-8, max_iter=20, tail_budget=None):
             s.set_launch(0, tail_budget)
         syms.append(s.upload())
     plan = api.MultiPlan(syms)
+    if spread:
+        plan.set_spread(spread)
     f64 = np.float64
     r = plan.concat([g.r for g in grids], "branch", f64)
     x = plan.concat([g.x for g in grids], "branch", f64)
@@ -157,3 +159,20 @@ def test_plan_refuses_members_changed_since_its_upload():
     B.pf_multi_upload(plan.p, plan.buf)
     B.pf_build_ybus_multi(plan.p, r, x, b, yv)
     torch.cuda.synchronize()
+
+
+def test_mixed_grids_with_spread_groups():
+    """More workgroups than grids: the 10k and 3k grids share their wide
+    levels among groups of workgroups (grid barriers per group) while the
+    small ones keep one each; every case matches the oracle and the
+    one-workgroup-per-case launch."""
+    grids = [grid(10000, 1), grid(200, 4), grid(3000, 2), grid(700, 3)]
+    Vms, Vas, it, st, _ = solve_multi(grids, tail_budget=161792, spread=96)
+    Vm1, Va1, it1, st1, _ = solve_multi(grids, tail_budget=161792)
+    log(f"[multi spread] iterations {it.tolist()} (one workgroup each: {it1.tolist()})")
+    assert st.tolist() == st1.tolist() == [0] * len(grids)
+    assert it.tolist() == it1.tolist()
+    for c in range(len(grids)):
+        assert np.abs(Vms[c] - Vm1[c]).max() < 1e-12
+        assert np.abs(Vas[c] - Va1[c]).max() < 1e-12
+    check_against_oracle(grids, Vms, Vas, it, st)

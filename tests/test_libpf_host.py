@@ -233,3 +233,31 @@ def test_spread_setting_is_checked_and_reported(B):
     sync = (rhs_end + 15) // 16 * 16  # three 128-byte lines on a 128-byte boundary
     assert i.ws_doubles % 32 == 0 and i.ws_doubles >= sync + 48
     B.pf_symbolic_destroy(h)
+
+
+def test_multi_plan_spread_setting(B):
+    """pf_multi_set_spread: 0..65535 workgroups; grids too small to share
+    their levels keep one workgroup each (the device table does not grow),
+    a 10k grid takes extra workgroups (it grows)."""
+    gs = [gridgen.make_grid(n, s) for n, s in [(40, 1), (90, 2)]]
+    hs = [B.pf_analyze(g.n, g.f, g.t) for g in gs]
+    p = B.pf_multi_create(hs)
+    base, _ = B.pf_multi_info(p, 2)
+    for bad in (-1, 65536):
+        with pytest.raises(B.PfError) as ei:
+            B.pf_multi_set_spread(p, bad)
+        assert ei.value.code == B.PF_E_INVALID
+    B.pf_multi_set_spread(p, 64)
+    assert B.pf_multi_info(p, 2)[0] == base
+    B.pf_multi_destroy(p)
+    big = gridgen.make_grid(10000, 1)
+    hb = B.pf_analyze(big.n, big.f, big.t)
+    p = B.pf_multi_create(hs + [hb])
+    base, _ = B.pf_multi_info(p, 3)
+    B.pf_multi_set_spread(p, 64)
+    assert B.pf_multi_info(p, 3)[0] > base
+    B.pf_multi_set_spread(p, 0)
+    assert B.pf_multi_info(p, 3)[0] == base
+    B.pf_multi_destroy(p)
+    for h in hs + [hb]:
+        B.pf_symbolic_destroy(h)
