@@ -541,13 +541,11 @@ def leg_c3(args, tuned_file):
                 step="Ybus + batched NR to 1e-8 (k_newton, one launch)")
 
 
-def bench_multi(grids, label, steps, check_idx, spreads=(0,), tune_largest=0):
+def bench_multi(grids, label, steps, check_idx, spreads=(0,), launches=((0, 161792),)):
     """One launch over cases with their own analyses; timing, host analysis
     time and an oracle check of the cases in check_idx.  spreads: workgroup
-    totals of the launch to try (0: one per case); the fastest is kept.
-    tune_largest: the lanes per level of that many of the largest grids are
-    autotuned first, each as one case spread over 32 workgroups (the group
-    the launch gives the largest grids)."""
+    totals of the launch to try (0: one per case); launches: (threads, LDS
+    budget) settings of the symbolics to try; the fastest pair is kept."""
     import torch
 
     from oracle import oracle as O
@@ -558,26 +556,14 @@ def bench_multi(grids, label, steps, check_idx, spreads=(0,), tune_largest=0):
     with ThreadPoolExecutor(host_threads()) as ex:
         syms = list(ex.map(lambda g: api.Symbolic(g.n, g.f, g.t), grids))
     t_an = time.time() - t0
-    for s in syms:
-        s.set_launch(0, 161792)  # the largest LDS tail: the launch waits for its largest grid
-        s.upload()
-    t_tune = 0.0
-    if tune_largest:
-        from paper_1811_02512_amd import autotune
 
-        t1 = time.time()
-        for c in np.argsort([-g.n for g in grids])[:tune_largest]:
-            g, s = grids[c], syms[c]
-            t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
-            y = s.build_ybus(t(g.r), t(g.x), t(g.b))
-            V0, A0 = (t(v)[None] for v in g.flat_start())
-            autotune.tune(s, y[0], t(g.bus_type.astype(np.int8)), t(g.Psp[None]),
-                          t(g.Qsp[None]), V0, A0, threads=(512,), budgets=(161792,),
-                          spreads=(32,))
-            s.set_launch(0, 161792)
-            s.set_spread(0)
-        t_tune = time.time() - t1
-    plan = api.MultiPlan(syms)
+    def make_plan(launch):
+        for s in syms:
+            s.set_launch(*launch)
+            s.upload()
+        return api.MultiPlan(syms)
+
+    plan = make_plan(launches[0])
     f64 = np.float64
     r = plan.concat([g.r for g in grids], "branch", f64)
     x = plan.concat([g.x for g in grids], "branch", f64)
@@ -601,10 +587,15 @@ def bench_multi(grids, label, steps, check_idx, spreads=(0,), tune_largest=0):
         B.pf_newton_multi(plan.p, yv, ty, P, Q, Vm, Va, 1e-8, 20, 0, ws, it, None, st)
 
     tried = {}
-    for sp in spreads:
-        plan.set_spread(sp)
-        tried[sp] = timed(step, steps, 1)
-    best = min(tried, key=tried.get)
+    for li, launch in enumerate(launches):
+        if li:
+            plan = make_plan(launch)
+        for sp in spreads:
+            plan.set_spread(sp)
+            tried[(launch, sp)] = timed(step, steps, 1)
+    (best_launch, best), _ = min(tried.items(), key=lambda kv: kv[1])
+    if best_launch != launches[-1]:
+        plan = make_plan(best_launch)
     plan.set_spread(best)
     ms = timed(step, steps, 1)
     sts = st.cpu().numpy()
@@ -620,11 +611,14 @@ def bench_multi(grids, label, steps, check_idx, spreads=(0,), tune_largest=0):
     with ThreadPoolExecutor(host_threads()) as ex:
         check = check_cases(list(ex.map(one, check_idx)))
     log(f"[bench] {label}: {G} cases, {ms:.2f} ms/launch, converged {ok}/{G}, host analysis "
-        f"{t_an:.2f}s; workgroups {max(best, G)} (tried {tried}); oracle check {check}")
+        f"{t_an:.2f}s; workgroups {max(best, G)}, launch {best_launch} (tried "
+        f"{ {f'{k[0]} x {max(k[1], G)}': round(v, 3) for k, v in tried.items()} }); "
+        f"oracle check {check}")
     # only converged cases count as solves
     return dict(solves_per_s=ok / ms * 1e3, ms=ms, cases=G, converged=ok,
-                workgroups=max(best, G), ms_by_workgroups={max(k, G): v for k, v in tried.items()},
-                mapping_tuned_grids=int(tune_largest), mapping_tuning_s=t_tune,
+                workgroups=max(best, G), threads_and_lds_budget=list(best_launch),
+                ms_tried={f"threads {k[0][0] or 'auto'}, lds {k[0][1]}, workgroups "
+                          f"{max(k[1], G)}": v for k, v in tried.items()},
                 host_analysis_s=t_an, host_threads=host_threads(),
                 solves_per_s_with_host_analysis=ok / (ms * 1e-3 + t_an),
                 buses=int(sum(g.n for g in grids)),
@@ -652,8 +646,7 @@ def leg_c4(W, args):
     # 64 grids leave most CUs idle: the launch may give the largest grids
     # groups of workgroups (one per CU at most)
     out["mixed_64_grids"] = bench_multi(mixed, "c4 mixed 64 grids 500-20k buses",
-                                        max(3, args.steps // 3), idx, spreads=(0, 128, 256),
-                                        tune_largest=0 if args.no_tune else 3)
+                                        max(3, args.steps // 3), idx, spreads=(0, 128, 256))
     return out
 
 

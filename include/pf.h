@@ -162,7 +162,9 @@ int pf_symbolic_set_mapping(pf_symbolic sym, const int32_t* lanes_per_level);
  * budget in bytes of the tail, the largest run of top levels whose values
  * (64 bytes per filled slot, 48 per node) are factorised and solved in LDS
  * (0 = none, at most 161792 so that 2 KB of LDS stay for reductions;
- * default 65536).  A new budget rebuilds the
+ * default 65536).  The Newton kernel's LDS copy of every bus's (e, f)
+ * (16 n bytes) is used only when it fits this budget too, so a budget of
+ * at most half the LDS lets two workgroups share a CU.  A new budget rebuilds the
  * tail and requires pf_symbolic_upload again.  interleave (1, 2, 4, 8;
  * default 4) is the case grouping of pf_newton's workspace.               */
 int pf_symbolic_set_launch(pf_symbolic sym, int threads, int64_t tail_lds_budget,

@@ -319,8 +319,12 @@ int pf_symbolic_upload(pf_symbolic s, void* d_buf, size_t bytes, void* stream)
             if (h.tail_lds + pv_mask_bytes(h.n) + 2048 > lds_max)
                 return fail(PF_E_WORKSPACE, "pf_symbolic_upload: LDS tail larger than the "
                                             "device's LDS; lower it with pf_symbolic_set_launch");
+            // the Newton kernel's LDS copy of every bus's (e, f), when it fits
+            // the device and the LDS budget the caller set (a small budget
+            // leaves room for a second workgroup per CU)
             const int64_t efb = 16 * (int64_t)h.n;
-            if (efb + pv_mask_bytes(h.n) + 2048 <= lds_max) ef_lds = (int32_t)efb;
+            if (efb + pv_mask_bytes(h.n) + 2048 <= lds_max && efb <= h.tail_budget)
+                ef_lds = (int32_t)efb;
         } else {
             (void)hipGetLastError();
         }
