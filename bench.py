@@ -422,9 +422,10 @@ def leg_autograd(W, steps):
                      "(pf_adjoint, branch gradients), buffers allocated per call by torch")
 
 
-def leg_plain(W, steps, label):
+def leg_plain(W, steps, label, adjoint=False):
     """One case per launch on W's grid: ms per solve and per iteration, and a
-    comparison with the oracle."""
+    comparison with the oracle; with adjoint, also one case per launch with
+    its gradient (the headline step at B = 1)."""
     ms = timed(lambda: W.step(adjoint=False, Bn=1), steps, 1)
     it = int(W.it[0].item())
     assert int(W.st[0].item()) == 0
@@ -447,9 +448,19 @@ def leg_plain(W, steps, label):
     else:
         launches = (2, "k_ybus + k_newton (the whole NR loop in one launch); two 16n-byte "
                        "device copies of the flat start")
-    return dict(solves_per_s=1e3 / ms, ms_per_solve=ms, us_per_iteration=ms * 1e3 / max(it, 1),
-                iterations=it, workgroups=max(spread, 1), kernel_launches_per_solve=launches[0],
-                launches=launches[1], syncs_per_iteration=syncs, oracle_check=check)
+    out = dict(solves_per_s=1e3 / ms, ms_per_solve=ms, us_per_iteration=ms * 1e3 / max(it, 1),
+               iterations=it, workgroups=max(spread, 1), kernel_launches_per_solve=launches[0],
+               launches=launches[1], syncs_per_iteration=syncs, oracle_check=check)
+    if adjoint:
+        ms_adj = timed(lambda: W.step(adjoint=True, Bn=1), steps, 1)
+        assert int(W.st[0].item()) == 0
+        check_adj = W.oracle_check([0], adjoint=True)
+        log(f"[bench] {label} one case per launch with its gradient: {ms_adj * 1e3:.1f} us "
+            f"(oracle check {check_adj})")
+        out["with_adjoint"] = dict(grads_per_s=1e3 / ms_adj, ms_per_solve=ms_adj,
+                                   step="Ybus + NR keeping the factors + pf_adjoint, one case",
+                                   oracle_check=check_adj)
+    return out
 
 
 def sync_counts(sym, spread):
@@ -958,10 +969,11 @@ def main():
         out["roofline"] = rf
         out["adjoint_roofline"] = adj
     if "c2" in legs or "c5" in legs:
-        plain = leg_plain(W, max(3, args.steps // 2), "c2 10k")
+        plain = leg_plain(W, max(3, args.steps // 2), "c2 10k", adjoint=True)
         out["plain_solves_per_s"] = plain["solves_per_s"]
         out["plain_ms_per_solve"] = plain["ms_per_solve"]
         out["plain_ms_per_iteration"] = plain["us_per_iteration"] * 1e-3
+        out["plain_adjoint_grads_per_s"] = plain["with_adjoint"]["grads_per_s"]
         out["c2_plain_10k"] = plain
         if "c2" in legs:
             plain.update(leg_c2_breakdown(W, max(5, args.steps)))
