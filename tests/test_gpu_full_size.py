@@ -2,7 +2,8 @@
 10,000 buses x 256 scenarios in the tuned launch (every case against the
 oracle's sparse adjoint, and central differences on the 10k grid), every
 case of 2,000 buses x 1,024 scenarios in the tuned launch, the full launch of
-the 64 mixed grids, and the 512 re-analysed N-1 outages of the 10k grid
+the 64 mixed grids (one workgroup per grid and 256 workgroups), and the 512
+re-analysed N-1 outages of the 10k grid
 (a seeded quarter of them against the oracle)."""
 import json
 import os
@@ -165,10 +166,10 @@ def test_every_case_of_2k_x1024_in_the_tuned_launch():
     assert worst < 1e-9
 
 
-def _solve_multi(grids, budget=161792):
+def _solve_multi(grids, budget=161792, spread=0):
     from test_gpu_batch import solve_multi
 
-    return solve_multi(grids, tail_budget=budget)
+    return solve_multi(grids, tail_budget=budget, spread=spread)
 
 
 def _check_all(grids, Vms, Vas, it, st, idx):
@@ -185,12 +186,17 @@ def _check_all(grids, Vms, Vas, it, st, idx):
     return max(r[1] for r in res)
 
 
-def test_full_launch_of_the_64_mixed_grids():
+@pytest.mark.parametrize("spread", [0, 256])
+def test_full_launch_of_the_64_mixed_grids(spread):
+    """Every grid of the 64-grid launch against the oracle, with one workgroup
+    per grid and with the benchmark's 256 workgroups (the largest grids in
+    groups)."""
     spec = json.load(open(os.path.join(ROOT, "tests", "golden", "mixed_batch.json")))
     jobs = [(x["n"], x["seed"], spec["load_scale"]) for x in spec["grids"]]
     grids = gridgen.make_grids(jobs, processes=THREADS)
-    log(f"[full] mixed: {len(grids)} grids, {sum(q.n for q in grids)} buses")
-    Vms, Vas, it, st, _ = _solve_multi(grids)
+    log(f"[full] mixed: {len(grids)} grids, {sum(q.n for q in grids)} buses, "
+        f"{spread or len(grids)} workgroups")
+    Vms, Vas, it, st, _ = _solve_multi(grids, spread=spread)
     worst = _check_all(grids, Vms, Vas, it, st, range(len(grids)))
     log(f"[full] mixed 64: worst |V|/theta difference {worst:.2e}")
     assert worst < 1e-9
