@@ -540,10 +540,11 @@ def leg_c3(args, tuned_file):
     its = W2.it.cpu().numpy()
     check = W2.oracle_check(pick_cases(W2.B, 16, 22), adjoint=False)
     plain = leg_plain(W2, max(3, args.steps // 2), "c3 2k")
+    graph = leg_graph(W2, max(3, args.steps // 2), adjoint=False)
     info = W2.sym.info
     b_it = newton_bytes_per_iter(info)
     log(f"[bench] c3 2k x 1024: {ms:.3f} ms/launch")
-    return dict(solves_per_s=W2.B / ms * 1e3, ms_per_step=ms, cases=W2.B,
+    return dict(solves_per_s=W2.B / ms * 1e3, ms_per_step=ms, cases=W2.B, graph_replay=graph,
                 mean_iterations=float(its.mean()),
                 speedup_vs_plain=(W2.B / ms) / plain["solves_per_s"] * 1e3,
                 plain_solves_per_s=plain["solves_per_s"],
@@ -661,32 +662,32 @@ def leg_c4(W, args):
     return out
 
 
-def leg_graph(W, steps):
-    """The whole step (Ybus, batched NR keeping the factors, adjoint) captured
-    once in a HIP graph and replayed; every replay's outputs are checked
-    against the eager step's."""
+def leg_graph(W, steps, adjoint=True):
+    """The whole step (Ybus, batched NR, with adjoint: keeping the factors and
+    the adjoint) captured once in a HIP graph and replayed; every replay's
+    outputs are checked against the eager step's."""
     import torch
 
-    W.step()
+    W.step(adjoint=adjoint)
     torch.cuda.synchronize()
-    ref = (W.Vm.clone(), W.gP.clone(), W.gx.clone())
+    outs = (W.Vm, W.Va, W.it) + ((W.gP, W.gx) if adjoint else ())
+    ref = tuple(t.clone() for t in outs)
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
-        W.step()  # warm the allocator on the capture stream
+        W.step(adjoint=adjoint)  # warm the allocator on the capture stream
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
-        W.step()
+        W.step(adjoint=adjoint)
     for _ in range(2):
         graph.replay()
         torch.cuda.synchronize()
-        same = (torch.equal(W.Vm, ref[0]) and torch.equal(W.gP, ref[1])
-                and torch.equal(W.gx, ref[2]))
-        assert same, "graph replay differs from the eager step"
+        assert all(torch.equal(a, b) for a, b in zip(outs, ref)), \
+            "graph replay differs from the eager step"
     ms = timed(graph.replay, steps, 1)
-    log(f"[bench] graph replay of the step: {ms:.3f} ms")
+    log(f"[bench] graph replay of the step ({W.g.n} buses x {W.B}): {ms:.3f} ms")
     return dict(solves_per_s=W.B / ms * 1e3, ms_per_step=ms, replays_checked=2)
 
 
