@@ -45,8 +45,10 @@ def solve_multi(grids, tol=1e-8, max_iter=20, tail_budget=None, spread=0):
     it = torch.full((G,), -1, dtype=torch.int32, device="cuda")
     nrm = torch.empty(G, dtype=torch.float64, device="cuda")
     st = torch.full((G,), -1, dtype=torch.int32, device="cuda")
-    B.pf_newton_multi(plan.p, yv, ty, P, Q, Vm, Va, tol, max_iter, 0, ws, it, nrm, st)
+    pv = torch.full((G,), -9, dtype=torch.int32, device="cuda")
+    B.pf_newton_multi(plan.p, yv, ty, P, Q, Vm, Va, tol, max_iter, 0, ws, it, nrm, st, pv)
     torch.cuda.synchronize()
+    plan.pivots = pv.cpu().numpy()
     return (plan.split(Vm, "bus"), plan.split(Va, "bus"), it.cpu().numpy(), st.cpu().numpy(),
             plan)
 
@@ -176,3 +178,32 @@ def test_mixed_grids_with_spread_groups():
         assert np.abs(Vms[c] - Vm1[c]).max() < 1e-12
         assert np.abs(Vas[c] - Va1[c]).max() < 1e-12
     check_against_oracle(grids, Vms, Vas, it, st)
+
+
+def test_spread_groups_keep_each_case_status_apart():
+    """In a batch with spread groups, a zero pivot in one grid (a bus cut off,
+    at a leaf of the shared levels) ends only that case, with its position,
+    while the grids around it, spread or not, converge; a plan whose spread
+    changed is refused until it is uploaded again."""
+    import test_gpu_failures as F
+    from oracle import oracle as O
+    from paper_1811_02512_amd import binding as B
+
+    g = grid(2000, 3)
+    s0 = Staged(g)
+    ex = s0.sym.export()
+    leaves, _, _ = F.regions(s0.info, ex)
+    bad, p = F.pick(O, g, leaves, ex["perm"], O.Sym(g.n, g.f, g.t))
+    grids = [grid(10000, 1), bad, grid(700, 3), g]
+    Vms, Vas, it, st, plan = solve_multi(grids, tail_budget=161792, spread=96)
+    log(f"[multi spread] statuses {st.tolist()} pivots {plan.pivots.tolist()} (position {p})")
+    assert st.tolist() == [0, B.PF_E_ZERO_PIVOT, 0, 0]
+    assert plan.pivots.tolist() == [-1, p, -1, -1]
+    ok = [grids[c] for c in (0, 2, 3)]
+    check_against_oracle(ok, [Vms[c] for c in (0, 2, 3)], [Vas[c] for c in (0, 2, 3)],
+                         it[[0, 2, 3]], st[[0, 2, 3]])
+    B.pf_multi_set_spread(plan.p, 64)
+    with pytest.raises(B.PfError) as ei:
+        B.pf_newton_multi(plan.p, plan.buf, plan.buf, plan.buf, plan.buf, plan.buf, plan.buf,
+                          1e-8, 20, 0, plan.buf)
+    assert ei.value.code == B.PF_E_INVALID and "not uploaded" in B.last_error()
