@@ -245,15 +245,22 @@ struct AsmPolar {
 // ===========================================================================
 // kernels
 // ===========================================================================
+// Threads per admittance row in the assembly kernels.
+constexpr int kYbusLanes = 4;
+
 // Row i of the admittance matrix (FormMatrixA): the diagonal starts from the
 // bus's shunt (ysh: (g, b) of bus i, or null), then every branch in the
 // entry's list adds y + jb/2 (diagonal) or -y (off-diagonal), in list order.
-__device__ __forceinline__ void ybus_row(const DevSym& S, int i, const double* __restrict__ rc,
+// Entries q0 + sub, q0 + sub + nsub, ... of the row are this thread's
+// (several threads per row, so that the rows' short chains of dependent
+// loads overlap).
+__device__ __forceinline__ void ybus_row(const DevSym& S, int i, int sub, int nsub,
+                                         const double* __restrict__ rc,
                                          const double* __restrict__ xc,
                                          const double* __restrict__ bcc,
                                          const double2* __restrict__ ysh, double* __restrict__ yc)
 {
-    for (int q = S.yptr[i]; q < S.yptr[i + 1]; ++q) {
+    for (int q = S.yptr[i] + sub; q < S.yptr[i + 1]; q += nsub) {
         const bool diag = S.ycol[q] == i;
         double G = 0.0, Bv = 0.0;
         if (diag && ysh) {
@@ -283,11 +290,13 @@ __global__ void k_ybus(DevSym S, const double* __restrict__ r, const double* __r
                        const double* __restrict__ ysh, int64_t sh_stride,
                        double* __restrict__ yval, int64_t ystride)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = t / kYbusLanes;
     const int c = blockIdx.y;
     if (i >= S.n) return;
     const double2* sh = ysh ? reinterpret_cast<const double2*>(ysh + c * sh_stride) : nullptr;
-    ybus_row(S, i, r + c * bstride, x + c * bstride, bc + c * bstride, sh, yval + c * ystride);
+    ybus_row(S, i, t % kYbusLanes, kYbusLanes, r + c * bstride, x + c * bstride,
+             bc + c * bstride, sh, yval + c * ystride);
 }
 
 // Case blockIdx.x of a batch of grids; its rows are shared by the gridDim.y
@@ -299,8 +308,11 @@ __global__ void k_ybus_multi(const CaseDesc* __restrict__ descs, const double* _
     const CaseDesc& cd = descs[blockIdx.x];
     const DevSym& S = cd.sym;
     const double2* sh = ysh ? reinterpret_cast<const double2*>(ysh) + cd.bus_off : nullptr;
-    for (int i = blockIdx.y * blockDim.x + threadIdx.x; i < S.n; i += gridDim.y * blockDim.x)
-        ybus_row(S, i, r + cd.br_off, x + cd.br_off, bc + cd.br_off, sh, yval + cd.y_off);
+    const int64_t n = (int64_t)S.n * kYbusLanes;
+    for (int64_t t = blockIdx.y * blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.y * blockDim.x)
+        ybus_row(S, (int)(t / kYbusLanes), (int)(t % kYbusLanes), kYbusLanes, r + cd.br_off,
+                 x + cd.br_off, bc + cd.br_off, sh, yval + cd.y_off);
 }
 
 __global__ __launch_bounds__(kMaxThreads) void k_mismatch(
@@ -1254,7 +1266,7 @@ int pf_build_ybus(const pf_symbolic s, int B, const double* d_r, const double* d
         return fail(PF_E_INVALID, "pf_build_ybus: ysh_stride must be 0 or even and >= 2*n, "
                                   "d_ysh 16-byte aligned");
     if (B == 0) return PF_OK;
-    dim3 grid((s->h.n + 255) / 256, B);
+    dim3 grid((unsigned)(((int64_t)s->h.n * kYbusLanes + 255) / 256), B);
     hipLaunchKernelGGL(k_ybus, grid, dim3(256), 0, as_stream(stream), s->h.dev, d_r, d_x, d_b,
                        branch_stride, d_ysh, ysh_stride, d_yval, y_stride);
     return launch_check("pf_build_ybus");
@@ -1710,10 +1722,11 @@ int pf_build_ybus_multi(const pf_multi p, const double* d_r, const double* d_x,
     if (d_ysh && (reinterpret_cast<uintptr_t>(d_ysh) & 15))
         return fail(PF_E_INVALID, "pf_build_ybus_multi: d_ysh must be 16-byte aligned");
     if (p->syms.empty()) return PF_OK;
-    // enough workgroups per case for the largest grid's rows, at most 64
+    // enough workgroups per case for the largest grid's rows, at most 256
     int nmax = 0;
     for (auto* sy : p->syms) nmax = std::max(nmax, sy->h.n);
-    const int per = std::max(1, std::min(64, (nmax + 255) / 256));
+    const int per = (int)std::max<int64_t>(
+        1, std::min<int64_t>(256, ((int64_t)nmax * kYbusLanes + 255) / 256));
     hipLaunchKernelGGL(k_ybus_multi, dim3((unsigned)p->syms.size(), per), dim3(256), 0,
                        as_stream(stream), p->d_desc, d_r, d_x, d_b, d_ysh, d_yval);
     return launch_check("pf_build_ybus_multi");
