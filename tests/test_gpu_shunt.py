@@ -1,6 +1,7 @@
 """Bus shunts (Sec. III-A: shunts on the vertices of the grid graph) through
 every GPU entry point that takes them, against the oracle on the same
-seeded shunted grids: admittance matrix, Newton-Raphson, batches with
+seeded shunted grids: admittance matrix, Newton-Raphson (one workgroup and,
+from 2,000 buses, one case spread over 32 workgroups), batches with
 per-case shunts, fast decoupled B'' and iteration, per-case-pattern
 batches, state estimation, the adjoint and N-1 screening."""
 import dataclasses
@@ -93,6 +94,20 @@ def test_newton_with_shunts(O, n, seed, shunt_seed):
     np.testing.assert_allclose(Va[0].cpu().numpy(), ref.Va, rtol=0, atol=1e-9)
     P, Q = O.injections(O.grid_ybus(g), Vm[0].cpu().numpy(), Va[0].cpu().numpy())
     assert O.mismatch(g.bus_type, P, Q, g.Psp, g.Qsp)[2] < 1e-8
+    if n < 2000:
+        return
+    # the same case spread over 32 workgroups (cooperative launch)
+    s.sym.set_spread(32)
+    try:
+        Vs, As, its, _, sts, _ = s.newton()
+        torch.cuda.synchronize()
+    finally:
+        s.sym.set_spread(0)
+    log(f"[shunt] spread newton n={n}: gpu iters={its.item()} status {sts.item()}")
+    assert sts.item() == 0 and its.item() == ref.iters
+    np.testing.assert_allclose(Vs[0].cpu().numpy(), ref.Vm, rtol=0, atol=1e-9)
+    np.testing.assert_allclose(As[0].cpu().numpy(), ref.Va, rtol=0, atol=1e-9)
+    assert (Vs - Vm).abs().max().item() < 1e-12 and (As - Va).abs().max().item() < 1e-12
 
 
 def test_newton_batch_with_per_case_shunts(O):
