@@ -3,7 +3,8 @@ graphs whose analysis degenerates (a star: no off-diagonal blocks and a
 single level; a path: one node per level; a spanning tree: no fill), a grid
 whose every non-slack bus is PV, the largest grid of the mixed-size range,
 and the full 10k-bus x 256-scenario batch in the launch configuration the
-benchmark times, every case checked."""
+benchmark times, every case checked; the degenerate grids and the largest
+one also as one case spread over several workgroups."""
 import dataclasses
 
 import numpy as np
@@ -103,6 +104,29 @@ def test_degenerate_structures(O, name, tail):
         np.testing.assert_allclose(Va[c].cpu().numpy(), ref.Va, rtol=0, atol=1e-9)
 
 
+@pytest.mark.parametrize("tail", [True, False])
+@pytest.mark.parametrize("name", ["star", "path", "tree", "all_pv"])
+def test_degenerate_structures_spread(O, name, tail):
+    """The same grids as one case over 8 workgroups (cooperative launch):
+    with the tail on the first workgroup, and without a tail (a path then
+    meets at a grid barrier after each of its one-node levels)."""
+    g = _topologies()[name]
+    s = Staged(g)
+    if not tail:
+        s.sym.set_launch(256, 0)
+    ref = O.solve_grid(g)
+    s.sym.set_spread(8)
+    try:
+        Vm, Va, iters, _, status, _ = s.newton()
+        torch.cuda.synchronize()
+    finally:
+        s.sym.set_spread(0)
+    log(f"[edges] {name} spread over 8: status {status.item()} iters {iters.item()}")
+    assert status.item() == 0 and iters.item() == ref.iters
+    np.testing.assert_allclose(Vm[0].cpu().numpy(), ref.Vm, rtol=0, atol=1e-9)
+    np.testing.assert_allclose(Va[0].cpu().numpy(), ref.Va, rtol=0, atol=1e-9)
+
+
 def test_empty_batch_is_a_no_op():
     """B = 0 is accepted by every batched entry point and touches nothing."""
     from paper_1811_02512_amd import binding as B
@@ -146,6 +170,16 @@ def test_largest_grid_of_the_mixed_range(O):
     for c in range(2):
         np.testing.assert_allclose(Vm[c].cpu().numpy(), ref.Vm, rtol=0, atol=1e-9)
         np.testing.assert_allclose(Va[c].cpu().numpy(), ref.Va, rtol=0, atol=1e-9)
+    # one case of it spread over 64 workgroups
+    s.sym.set_spread(64)
+    try:
+        Vs, As, its, _, sts, _ = s.newton()
+        torch.cuda.synchronize()
+    finally:
+        s.sym.set_spread(0)
+    assert sts.item() == 0 and its.item() == ref.iters
+    np.testing.assert_allclose(Vs[0].cpu().numpy(), ref.Vm, rtol=0, atol=1e-9)
+    np.testing.assert_allclose(As[0].cpu().numpy(), ref.Va, rtol=0, atol=1e-9)
 
 
 def test_full_batch_in_the_benchmark_launch(O):
