@@ -532,9 +532,13 @@ struct OneGroup {
 //           marker, then per parity of the iteration count a NaN flag and
 //           the bits of the mismatch maximum (a non-negative double, whose
 //           bit patterns order as unsigned integers do).
-// A workgroup makes its writes visible before it arrives and discards stale
-// cached lines after it is released (agent-scope fences), so what any
-// workgroup wrote before a barrier is what every workgroup reads after it.
+// A workgroup makes its writes visible before it arrives (an agent-scope
+// release fence: its XCD's L2 written back) and discards stale cached lines
+// after it is released (an agent-scope acquire fence), so what any workgroup
+// wrote before a barrier is what every workgroup reads after it: each
+// arrival is counted only after its writes have reached memory, the release
+// word is stored only after every arrival has been counted, and a workgroup
+// reads only after it has seen the release word and invalidated its caches.
 // A wait that lasts longer than wait_ticks of the constant 100 MHz clock
 // (one second unless a caller lowers it) sets the abort flag; from then on
 // no barrier waits, so every workgroup runs to its end and the case reports
@@ -566,7 +570,7 @@ struct Spread {
         __syncthreads();
         if (threadIdx.x == 0) {
             const unsigned k = ++*count;
-            __threadfence();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             const unsigned before =
                 __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (!aborted()) {
@@ -586,7 +590,7 @@ struct Spread {
                     }
                 }
             }
-            __threadfence();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         __syncthreads();
     }
