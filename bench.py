@@ -470,7 +470,9 @@ def sync_counts(sym, spread):
     after the mismatch, after each level below the LDS tail in the
     factorisation and after each wide one in the backward sweep, and three
     around the tail (its shared first pass, its factorisation, its backward
-    substitution together with the narrow global backward levels)."""
+    substitution together with the narrow global backward levels).  A
+    one-case launch shares its subtree levels too (only the groups of a
+    batch of grids run those per workgroup)."""
     info = sym.info
     widths = np.diff(sym.export()["level_ptr"])
     nlev = int(info.nlevels)
@@ -481,7 +483,9 @@ def sync_counts(sym, spread):
     back_lo = below
     while back_lo > 0 and widths[back_lo - 1] <= threads:
         back_lo -= 1
-    tail = 3 if info.tail_nodes > 0 else 0
+    # the tail's three, or without a tail the one after the narrow backward
+    # levels on workgroup 0
+    tail = 3 if info.tail_nodes > 0 else int(back_lo < below)
     return {"grid_barriers": 1 + below + tail + back_lo,
             "levels_on_workgroup_0": int(info.tail_levels) * 2 + (below - back_lo)}
 

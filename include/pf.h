@@ -123,6 +123,10 @@ typedef struct {
     int64_t fd_ws_doubles;   /* pf_fdpf workspace per case                   */
     int32_t spread;          /* workgroups of a one-case pf_newton launch    */
                              /* (0: one workgroup)                          */
+    int32_t sub_levels;      /* bottom levels that the groups of a spread    */
+                             /* batch of grids (pf_multi_set_spread) run as */
+                             /* whole subtrees per workgroup, without grid  */
+                             /* barriers (0: none)                          */
 } pf_info;
 
 /* ---- status ------------------------------------------------------------ */

@@ -39,7 +39,7 @@ class pf_info(C.Structure):
                 ("threads", C.c_int32), ("tail_clique", C.c_int32),
                 ("ws_interleave", C.c_int32), ("lu_offset", C.c_int64),
                 ("fd_mat_doubles", C.c_int64), ("fd_ws_doubles", C.c_int64),
-                ("spread", C.c_int32)]
+                ("spread", C.c_int32), ("sub_levels", C.c_int32)]
 
 
 if not os.path.exists(LIB_PATH):

@@ -53,7 +53,8 @@ size_t HostSym::dev_bytes() const
                                           &ydiag,     &Rp,        &Ri,      &Rs,     &level_ptr,
                                           &level_nodes, &level_g, &node_info, &slot_info, &rl,
                                           &upd,       &t_node,    &t_slot,  &t_rl,   &t_upd,
-                                          &t_lptr,    &t_pk,      &from,    &to};
+                                          &t_lptr,    &t_pk,      &from,    &to,     &sub_idx,
+                                          &sub_ptr,   &sub_cum};
     size_t total = 0;
     for (auto* a : arrs) total += align256(std::max<size_t>(a->size(), 1) * sizeof(int32_t));
     return total;
@@ -392,6 +393,7 @@ void build_tail(HostSym& s, int64_t budget)
     s.t_upd.clear();
     s.t_pk.clear();
     s.t_lptr.assign(1, 0);
+    build_subtrees(s);
     if (K == 0) return;
 
     // clique chain at the top of the tail: level nlev-1-d holds one node
@@ -505,6 +507,78 @@ void build_tail(HostSym& s, int64_t budget)
         int32_t* u = &s.t_slot[12 * (size_t)t];
         u[11] = pack(s.t_upd, u[6], u[7]);
     }
+}
+
+void build_subtrees(HostSym& s)
+{
+    const int nlev = (int)s.level_ptr.size() - 1;
+    const int nn = s.nn;
+    s.sub_cut = 0;
+    s.sub_roots = 0;
+    s.sub_idx.clear();
+    s.sub_ptr.clear();
+    s.sub_cum.clear();
+    const int top = std::min(s.tail_level, nlev);
+    if (top <= 0 || nn == 0) return;
+    // roots below cut c (levels 0-based here): nodes p with level(p) < c
+    // <= level(parent(p)), or without a parent; counted for every c at once
+    std::vector<int64_t> diff(nlev + 2, 0);
+    for (int p = 0; p < nn; ++p) {
+        const int lp = s.level[p] - 1;
+        const int hi = s.parent[p] >= 0 ? s.level[s.parent[p]] - 1 : nlev;
+        diff[lp + 1] += 1;
+        diff[hi + 1] -= 1;
+    }
+    int cut = 0;
+    int64_t run = 0;
+    for (int c = 1; c <= top; ++c) {
+        run += diff[c];
+        if (run >= kSubMinRoots) cut = c;
+    }
+    if (cut == 0) return;
+    // each node's root (its parent is on a higher level, so top-down works)
+    std::vector<int32_t> root(nn, -1);
+    for (int l = cut - 1; l >= 0; --l)
+        for (int x = s.level_ptr[l]; x < s.level_ptr[l + 1]; ++x) {
+            const int p = s.level_nodes[x];
+            const int q = s.parent[p];
+            root[p] = (q < 0 || s.level[q] - 1 >= cut) ? p : root[q];
+        }
+    std::vector<int32_t> rid(nn, -1);
+    int32_t R = 0;
+    for (int p = 0; p < nn; ++p)
+        if (root[p] == p) rid[p] = R++;
+    // work of a node: its record, descendant list and slots with their pairs
+    std::vector<int64_t> W(R, 0);
+    for (int p = 0; p < nn; ++p) {
+        if (root[p] < 0) continue;
+        int64_t w = 4 + (s.Rp[p + 1] - s.Rp[p]);
+        for (int q = s.Lp[p]; q < s.Lp[p + 1]; ++q) w += 2 + (s.Up[q + 1] - s.Up[q]);
+        W[rid[root[p]]] += w;
+    }
+    int64_t tot = 0;
+    for (int64_t w : W) tot += w;
+    if (tot >= ((int64_t)1 << 30)) return;
+    s.sub_cum.assign(R + 1, 0);
+    for (int k = 0; k < R; ++k) s.sub_cum[k + 1] = s.sub_cum[k] + (int32_t)W[k];
+    s.sub_idx.resize(s.level_ptr[cut]);
+    s.sub_ptr.assign((size_t)cut * (R + 1), 0);
+    for (int l = 0; l < cut; ++l) {
+        const int b = s.level_ptr[l], e = s.level_ptr[l + 1];
+        std::vector<int32_t> xs(e - b);
+        for (int x = b; x < e; ++x) xs[x - b] = x;
+        std::stable_sort(xs.begin(), xs.end(), [&](int32_t u, int32_t v) {
+            return rid[root[s.level_nodes[u]]] < rid[root[s.level_nodes[v]]];
+        });
+        int32_t* ptr = &s.sub_ptr[(size_t)l * (R + 1)];
+        for (int i = 0; i < e - b; ++i) {
+            s.sub_idx[b + i] = xs[i];
+            ++ptr[rid[root[s.level_nodes[xs[i]]]] + 1];
+        }
+        for (int k = 0; k < R; ++k) ptr[k + 1] += ptr[k];
+    }
+    s.sub_cut = cut;
+    s.sub_roots = R;
 }
 
 // Lanes per node: enough lanes for the widest per-node loop of the level

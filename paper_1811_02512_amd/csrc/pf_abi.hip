@@ -144,6 +144,7 @@ int pf_symbolic_info(const pf_symbolic s, pf_info* info)
     info->ws_interleave = h.interleave;
     info->threads = h.threads;
     info->spread = h.spread > 1 ? h.spread : 0;
+    info->sub_levels = h.sub_cut;
     return PF_OK;
 }
 
@@ -307,6 +308,11 @@ int pf_symbolic_upload(pf_symbolic s, void* d_buf, size_t bytes, void* stream)
     d.t_upd = reinterpret_cast<const int2*>(put(h.t_upd));
     d.t_lptr = put(h.t_lptr);
     d.t_pk = reinterpret_cast<const uint4*>(put(h.t_pk));
+    d.sub_cut = h.sub_cut;
+    d.sub_roots = h.sub_roots;
+    d.sub_idx = put(h.sub_idx);
+    d.sub_ptr = put(h.sub_ptr);
+    d.sub_cum = put(h.sub_cum);
     s->d_from = put(h.from);
     s->d_to = put(h.to);
     if (off > info.dev_bytes) return fail(PF_E_WORKSPACE, "pf_symbolic_upload: size mismatch");

@@ -515,6 +515,7 @@ __device__ __forceinline__ NodeRec load_rec(const DevSym& S, int x)
 // barriers.
 struct OneGroup {
     static constexpr bool kSpread = false;
+    static constexpr bool kSub = false;
     __device__ __forceinline__ int rank() const { return 0; }
     __device__ __forceinline__ int size() const { return 1; }
     __device__ __forceinline__ void sync() const { __syncthreads(); }
@@ -547,6 +548,7 @@ constexpr int kSpreadWords = 96;  // 32-bit words of the three lines
 
 struct Spread {
     static constexpr bool kSpread = true;
+    static constexpr bool kSub = false;  // every level below the tail shared
     unsigned* arrive;
     unsigned* release;
     int* flags;        // abort, pivot marker, NaN flag [2]
@@ -565,7 +567,7 @@ struct Spread {
     {
         return __hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
     }
-    __device__ void sync() const
+    __device__ __forceinline__ void sync() const
     {
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -594,6 +596,15 @@ struct Spread {
         }
         __syncthreads();
     }
+};
+
+// As Spread, with the levels below the subtree cut (DevSym::sub_cut) run by
+// each workgroup on whole subtrees of its own, workgroup barriers between
+// them: used by the groups of a batch of grids, where grid barriers contend
+// with the other groups for the XCDs they share.  (One case alone keeps
+// Spread: there the subtree levels measured slower than shared ones.)
+struct SpreadSub : Spread {
+    static constexpr bool kSub = true;
 };
 
 // Runs fn(x, rec, lane, g) for the nodes of levels [l0, l1), up or down,
@@ -633,6 +644,67 @@ template <class F>
 __device__ __forceinline__ void for_nodes(const DevSym& S, int l0, int l1, bool up, F&& fn)
 {
     for_nodes(OneGroup{}, S, l0, l1, up, static_cast<F&&>(fn));
+}
+
+// As for_nodes over levels [l0, l1) below the subtree cut, for the nodes of
+// this workgroup's subtrees only (roots [k0, k1)), with a workgroup barrier
+// after every level: a node's descendants belong to its own subtree, so no
+// other workgroup's results are needed until the cut.
+template <class F>
+__device__ __forceinline__ void for_sub_levels(const DevSym& S, int k0, int k1, int l0, int l1,
+                                               bool up, F&& fn)
+{
+    const int R1 = S.sub_roots + 1;
+    for (int li = l0; li < l1; ++li) {
+        const int l = up ? li : l1 - 1 - (li - l0);
+        const int g = S.level_g[l];
+        const int b = S.level_ptr[l];
+        const int e1 = b + S.sub_ptr[l * R1 + k1];
+        const int gpb = blockDim.x / g;
+        const int lane = threadIdx.x & (g - 1);
+        int e = b + S.sub_ptr[l * R1 + k0] + (int)threadIdx.x / g;
+        int x = e < e1 ? S.sub_idx[e] : 0;
+        NodeRec cur = e < e1 ? load_rec(S, x) : NodeRec{};
+        while (e < e1) {
+            const int en = e + gpb;
+            const int xn = en < e1 ? S.sub_idx[en] : 0;
+            const NodeRec pre = en < e1 ? load_rec(S, xn) : NodeRec{};
+            fn(x, cur, lane, g);
+            cur = pre;
+            x = xn;
+            e = en;
+        }
+        __syncthreads();
+    }
+}
+
+// The subtrees [k0, k1) of workgroup `rank` of `size`: the roots whose work
+// starts in its share [rank, rank + 1) / size of the total (every workgroup
+// of the group calls this; k0 = k1 = 0 without subtrees).
+template <class P>
+__device__ __forceinline__ void sub_share(const DevSym& S, const P& par, int& k0, int& k1)
+{
+    __shared__ int s_k[2];
+    k0 = k1 = 0;
+    if (S.sub_cut <= 0) return;
+    if (threadIdx.x < 2) s_k[threadIdx.x] = 0;
+    __syncthreads();
+    const int R = S.sub_roots;
+    const int64_t tot = S.sub_cum[R];
+    const int64_t a = tot * par.rank() / par.size();
+    const int64_t b = tot * (par.rank() + 1) / par.size();
+    int c0 = 0, c1 = 0;
+    for (int k = threadIdx.x; k < R; k += blockDim.x) {
+        const int64_t v = S.sub_cum[k];
+        c0 += v < a;
+        c1 += v < b;
+    }
+    if (c0) atomicAdd(&s_k[0], c0);
+    if (c1) atomicAdd(&s_k[1], c1);
+    __syncthreads();
+    k0 = s_k[0];
+    k1 = s_k[1];
+    __syncthreads();
 }
 
 // Runs fn(jl, lane, g) over tail levels [t0, t1) (tail-local numbering).
@@ -1490,7 +1562,7 @@ __device__ __forceinline__ void back_node(const DevSym& S, const NodeRec& rec, i
 }
 
 // Max over the workgroup with a NaN flag; every thread gets the result.
-__device__ double block_max(double v, int nan, int& any_nan)
+__device__ __forceinline__ double block_max(double v, int nan, int& any_nan)
 {
     __shared__ double s_v[kMaxThreads / 64 + 1];
     __shared__ int s_n[kMaxThreads / 64 + 1];

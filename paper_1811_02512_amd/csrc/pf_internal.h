@@ -94,6 +94,22 @@ struct DevSym {
     const int2* t_upd;
     const int32_t* t_lptr;   // nlev - tail_level + 1
     const uint4* t_pk;
+    // Subtrees below a cut level (the group of workgroups that a spread
+    // batch of grids gives a case hands each workgroup whole subtrees there,
+    // so those levels need workgroup barriers only; a one-case spread launch
+    // shares them and does not read these tables).  Roots: nodes of levels [0, sub_cut)
+    // whose parent lies at level sub_cut or above (or is absent), numbered
+    // by position.
+    //   sub_idx[x] for x < level_ptr[sub_cut]: the level-ordered node
+    //     records of each level again, grouped by root (ascending root,
+    //     then record)
+    //   sub_ptr[l (sub_roots + 1) + k]: entries of level l's group whose
+    //     root is below k
+    //   sub_cum[k]: work of the subtrees of roots below k (sub_roots + 1)
+    int32_t sub_cut, sub_roots;
+    const int32_t* sub_idx;
+    const int32_t* sub_ptr;
+    const int32_t* sub_cum;
 };
 
 struct HostSym {
@@ -110,6 +126,9 @@ struct HostSym {
     int32_t tail_level = 0, tail_nodes = 0, tail_slots = 0, tail_lds = 0, tail_clique = 0;
     int64_t tail_budget = 64 * 1024;
     std::vector<int32_t> t_node, t_slot, t_rl, t_upd, t_lptr, t_pk;
+    // subtrees below a cut level (DevSym); rebuilt with the tail
+    int32_t sub_cut = 0, sub_roots = 0;
+    std::vector<int32_t> sub_idx, sub_ptr, sub_cum;
     int32_t ef_lds = 0;  // set at upload: 16 n when it fits in the device's LDS, else 0
     int32_t max_width = 0;
     int32_t threads = 0;  // 0: chosen per launch from the batch size
@@ -161,7 +180,13 @@ int analyze(int n, int m, const int32_t* from, const int32_t* to, int slack, int
             HostSym& out, std::string& msg);
 // Default lanes-per-node for every level from a simple work model.
 void default_mapping(HostSym& s);
-// (Re)builds the LDS tail for an LDS budget in bytes (0 disables it).
+// (Re)builds the LDS tail for an LDS budget in bytes (0 disables it), and
+// the subtrees below the cut level under it.
 void build_tail(HostSym& s, int64_t budget);
+// Subtrees of the levels below the tail for spread launches: the highest cut
+// at or below the tail level with at least kSubMinRoots roots (none if no
+// such level).
+constexpr int kSubMinRoots = 768;
+void build_subtrees(HostSym& s);
 
 }  // namespace pf

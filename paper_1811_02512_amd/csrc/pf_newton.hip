@@ -41,6 +41,10 @@ __device__ __forceinline__ void newton_case(const P& par, const DevSym& S, const
     auto t0 = [&]() { return par.rank() * (int)blockDim.x + (int)threadIdx.x; };
     auto ts = [&]() { return par.size() * (int)blockDim.x; };
     const Off o = ws_off(S);
+    // the groups of a spread batch of grids: this workgroup's subtrees
+    // below the cut
+    int k0 = 0, k1 = 0;
+    if constexpr (P::kSub) sub_share(S, par, k0, k1);
     for (int i = t0(); i < S.n; i += ts()) {
         double sn, cs;
         const double vm = Vm[i], va = Va[i];
@@ -152,9 +156,18 @@ __device__ __forceinline__ void newton_case(const P& par, const DevSym& S, const
             st = ST_NOT_CONVERGED;
             break;
         }
-        for_nodes(par, S, 0, S.tail_level, true, [&](int x, const NodeRec& r, int lane, int g) {
+        auto fwd = [&](int x, const NodeRec& r, int lane, int g) {
             factor_node<SrcState, true, false>(S, src, x, r, lane, g, w, o.LU, wb, o.RHS, bad);
-        });
+        };
+        int lc = 0;  // first level shared among the workgroups
+        if constexpr (P::kSub) {
+            if (S.sub_cut > 0) {
+                for_sub_levels(S, k0, k1, 0, S.sub_cut, true, fwd);
+                par.sync();
+                lc = S.sub_cut;
+            }
+        }
+        for_nodes(par, S, lc, S.tail_level, true, fwd);
         if (tail) {
             tail_factor<SrcState, true, false>(S, src, w, o.LU, wb, o.RHS, bad, par);
             tail_done();
@@ -175,13 +188,31 @@ __device__ __forceinline__ void newton_case(const P& par, const DevSym& S, const
             }
             tail_done();
         }
-        for_nodes(par, S, 0, lw, false, back);
+        // below min(cut, lw): each workgroup its own subtrees, top-down
+        int lb = 0;
+        if constexpr (P::kSub) lb = S.sub_cut < lw ? S.sub_cut : lw;
+        for_nodes(par, S, lb, lw, false, back);
+        if constexpr (P::kSub) {
+            if (lb > 0) {
+                for_sub_levels(S, k0, k1, 0, lb, false, back);
+                par.sync();
+            }
+        }
         ++it;
     }
     if ((flags & PF_NEWTON_KEEP_FACTORS) && st == ST_OK) {
-        for_nodes(par, S, 0, S.tail_level, true, [&](int x, const NodeRec& r, int lane, int g) {
+        auto keep = [&](int x, const NodeRec& r, int lane, int g) {
             factor_node<SrcState, false, true>(S, src, x, r, lane, g, w, o.LU, wb, o.RHS, bad);
-        });
+        };
+        int lc = 0;
+        if constexpr (P::kSub) {
+            if (S.sub_cut > 0) {
+                for_sub_levels(S, k0, k1, 0, S.sub_cut, true, keep);
+                par.sync();
+                lc = S.sub_cut;
+            }
+        }
+        for_nodes(par, S, lc, S.tail_level, true, keep);
         if (tail) {
             tail_factor<SrcState, false, true>(S, src, w, o.LU, wb, o.RHS, bad, par);
             tail_done();
@@ -898,9 +929,9 @@ __global__ __launch_bounds__(kLevelThreads) void k_newton_multi_spread(
     }
     if (threadIdx.x == 0) s_count = 0;
     unsigned* sync = reinterpret_cast<unsigned*>(a.ws + cd.ws_off + cd.sync_off);
-    const Spread par{sync,    sync + 32, reinterpret_cast<int*>(sync + 64),
-                     reinterpret_cast<uint64_t*>(sync + 68), &s_count, cd.back_lo, wait_ticks,
-                     bk.y,    bk.z};
+    const SpreadSub par{{sync, sync + 32, reinterpret_cast<int*>(sync + 64),
+                         reinterpret_cast<uint64_t*>(sync + 68), &s_count, cd.back_lo,
+                         wait_ticks, bk.y, bk.z}};
     newton_case(par, S, yv, ty, P, Q, Vm, Va, w, wb, a.tol, a.max_iter, a.flags, o_it, o_nrm,
                 o_st, o_pv);
 }

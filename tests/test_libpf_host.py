@@ -261,3 +261,30 @@ def test_multi_plan_spread_setting(B):
     B.pf_multi_destroy(p)
     for h in hs + [hb]:
         B.pf_symbolic_destroy(h)
+
+
+def test_subtree_cut_of_the_spread_batch_groups():
+    """The cut below which the groups of a spread batch of grids run whole
+    subtrees per workgroup: the highest level at or below the LDS tail with
+    at least 768 subtree roots (nodes below it whose parent is at or above
+    it), recomputed here from the exported elimination tree."""
+    import gridgen
+    from paper_1811_02512_amd import api
+
+    for n, seed, budget in [(10000, 1, 161792), (10000, 1, 0), (2000, 2, 65536), (200, 1, 65536)]:
+        g = gridgen.make_grid(n, seed)
+        sym = api.Symbolic(g.n, g.f, g.t)
+        sym.set_launch(512, budget, 1)
+        info = sym.info
+        ex = sym.export()
+        lev = np.asarray(ex["level"]) - 1
+        par = np.asarray(ex["parent"])
+        top = info.nlevels - info.tail_levels
+        want = 0
+        for c in range(1, top + 1):
+            plev = np.where(par >= 0, lev[np.maximum(par, 0)], info.nlevels)
+            roots = int(((lev < c) & (plev >= c)).sum())
+            if roots >= 768:
+                want = c
+        assert info.sub_levels == want, (n, budget, info.sub_levels, want)
+    assert want == 0  # 200 buses: too few leaves
