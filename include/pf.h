@@ -491,7 +491,10 @@ int pf_multi_create(int G, const pf_symbolic* syms, pf_multi* out);
  * at most one per 128 nodes of its widest level below its LDS tail, and
  * 32), so the largest grids, which bound the launch, share their wide levels
  * among several CUs as a spread one-case launch does (grid barriers within
- * each case's group).  The launch is cooperative; when the device cannot
+ * each case's group); below the cut level that info.sub_levels reports,
+ * each workgroup of a group takes whole subtrees of the elimination tree
+ * (those with their work in its share of the case's) and runs those levels
+ * with workgroup barriers only.  The launch is cooperative; when the device cannot
  * keep every workgroup resident at once, or the stream is being captured,
  * it falls back to one workgroup per case.  Changes the plan's device table:
  * pf_multi_info's dev_bytes and pf_multi_upload again before the next call. */
